@@ -1,0 +1,254 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws random numbers (numpy ``Generator(PCG64(seed))``) and
+lays them out as columns.  It holds none of the join or aggregation
+arithmetic; both the GPU library's tests and the oracle consume its output.
+
+Workloads (paper section 6 evaluates LA and BI queries; the datasets it
+uses are not available, so these stand in for them by shape):
+
+* ``rmat_edges``      R-MAT graph, edges oriented (low, high), self-loops
+                      dropped, duplicates KEPT (a set-mode trie removes them).
+* ``sparse_matrix``   exactly ``nnz_per_row`` distinct uniform columns per row,
+                      values ``2*random()-1`` (multiples of 2^-53 in [-1, 1)).
+* ``zipf_degree_matrix`` power-law row degrees (rank law r^-s scaled to a
+                      target mean, clamped to [1, n], rows permuted).
+* ``batched_instances`` the mixed SpMV / SpGEMM batch.
+* ``star_schema``     fact table with Zipf foreign keys and four dimensions.
+* small graph families for closed-form tests.
+"""
+import math
+
+import numpy as np
+
+
+def rng_for(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform_pm1(rng, n):
+    """Uniform(-1, 1) as 2*random()-1: every value is a multiple of 2^-53."""
+    return 2.0 * rng.random(n) - 1.0
+
+
+# --------------------------------------------------------------------------
+# Graphs
+# --------------------------------------------------------------------------
+
+def rmat_edges(scale, n_samples, a=0.57, b=0.19, c=0.19, seed=2, chunk=1 << 22):
+    """R-MAT samples: at each of ``scale`` levels pick a quadrant with
+    probabilities (a, b, c, 1-a-b-c).  Returns (lo, hi) uint32 columns with
+    lo < hi; self-loops are dropped, duplicates are kept, no vertex
+    permutation is applied."""
+    rng = rng_for(seed)
+    t1 = np.uint32(round(a * 2**32))
+    t2 = np.uint32(min(round((a + b) * 2**32), 2**32 - 1))
+    t3 = np.uint32(min(round((a + b + c) * 2**32), 2**32 - 1))
+    los, his = [], []
+    done = 0
+    while done < n_samples:
+        m = min(chunk, n_samples - done)
+        u = np.zeros(m, dtype=np.uint32)
+        v = np.zeros(m, dtype=np.uint32)
+        for _ in range(scale):
+            r = rng.integers(0, 2**32, size=m, dtype=np.uint32)
+            bu = r >= t2               # quadrants c, d: source bit 1
+            bv = ((r >= t1) & (r < t2)) | (r >= t3)   # quadrants b, d: target bit 1
+            u = (u << np.uint32(1)) | bu.astype(np.uint32)
+            v = (v << np.uint32(1)) | bv.astype(np.uint32)
+        keep = u != v
+        u, v = u[keep], v[keep]
+        los.append(np.minimum(u, v))
+        his.append(np.maximum(u, v))
+        done += m
+    return np.concatenate(los), np.concatenate(his)
+
+
+def complete_graph(n):
+    i, j = np.triu_indices(n, 1)
+    return i.astype(np.uint32), j.astype(np.uint32)
+
+
+def complete_tripartite(a, b, c):
+    """K_{a,b,c}: parts [0,a), [a,a+b), [a+b,a+b+c); every cross-part pair."""
+    parts = [np.arange(0, a), np.arange(a, a + b), np.arange(a + b, a + b + c)]
+    lo, hi = [], []
+    for x in range(3):
+        for y in range(x + 1, 3):
+            p, q = np.meshgrid(parts[x], parts[y], indexing="ij")
+            lo.append(p.ravel())
+            hi.append(q.ravel())
+    lo = np.concatenate(lo)
+    hi = np.concatenate(hi)
+    return np.minimum(lo, hi).astype(np.uint32), np.maximum(lo, hi).astype(np.uint32)
+
+
+def wheel(n):
+    """Hub 0 joined to an n-cycle on vertices 1..n."""
+    rim = np.arange(1, n + 1)
+    nxt = np.roll(rim, -1)
+    lo = np.concatenate([np.zeros(n, dtype=np.int64), np.minimum(rim, nxt)])
+    hi = np.concatenate([rim, np.maximum(rim, nxt)])
+    return lo.astype(np.uint32), hi.astype(np.uint32)
+
+
+def cycle(n):
+    v = np.arange(n)
+    w = np.roll(v, -1)
+    return np.minimum(v, w).astype(np.uint32), np.maximum(v, w).astype(np.uint32)
+
+
+def random_bipartite(n_left, n_right, p, seed):
+    rng = rng_for(seed)
+    m = rng.random((n_left, n_right)) < p
+    i, j = np.nonzero(m)
+    return i.astype(np.uint32), (j + n_left).astype(np.uint32)
+
+
+def gnp(n, p, seed):
+    rng = rng_for(seed)
+    m = np.triu(rng.random((n, n)) < p, 1)
+    i, j = np.nonzero(m)
+    return i.astype(np.uint32), j.astype(np.uint32)
+
+
+# --------------------------------------------------------------------------
+# Sparse matrices
+# --------------------------------------------------------------------------
+
+def _distinct_columns(rng, deg, n):
+    """For each row r draw deg[r] distinct uniform columns in [0, n)."""
+    deg = np.asarray(deg, dtype=np.int64)
+    rows = np.repeat(np.arange(len(deg), dtype=np.int64), deg)
+    cols = np.empty(len(rows), dtype=np.int64)
+    start = np.concatenate([[0], np.cumsum(deg)])
+    dense = deg * 2 > n
+    sparse_mask = np.repeat(~dense, deg)
+    # dense rows: a random subset via a permutation
+    for r in np.nonzero(dense)[0]:
+        cols[start[r]:start[r + 1]] = rng.permutation(n)[: deg[r]]
+    idx = np.nonzero(sparse_mask)[0]
+    cols[idx] = rng.integers(0, n, size=len(idx))
+    while len(idx):
+        key = rows[idx] * n + cols[idx]
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        dup = np.zeros(len(ks), dtype=bool)
+        dup[1:] = ks[1:] == ks[:-1]
+        # also collide with entries already fixed in the same row
+        redo = idx[order[dup]]
+        if len(redo) == 0:
+            break
+        cols[redo] = rng.integers(0, n, size=len(redo))
+        # re-check every sparse entry of the affected rows
+        bad_rows = np.unique(rows[redo])
+        idx = idx[np.isin(rows[idx], bad_rows)]
+    return rows.astype(np.uint32), cols.astype(np.uint32)
+
+
+def sparse_matrix(n, nnz_per_row, seed):
+    """n x n, exactly nnz_per_row distinct uniform columns in every row."""
+    rng = rng_for(seed)
+    rows, cols = _distinct_columns(rng, np.full(n, nnz_per_row), n)
+    vals = uniform_pm1(rng, len(rows))
+    return rows, cols, vals
+
+
+def zipf_degrees(n, s, mean, rng):
+    """deg(r) = clamp(round(c * r^-s), 1, n) for ranks r = 1..n with c chosen
+    by bisection so that the mean degree is ``mean``; rows permuted."""
+    r = np.arange(1, n + 1, dtype=np.float64) ** (-s)
+
+    def mean_for(c):
+        return np.clip(np.round(c * r), 1, n).mean()
+
+    lo, hi = 0.0, float(mean) * n
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        if mean_for(mid) < mean:
+            lo = mid
+        else:
+            hi = mid
+    deg = np.clip(np.round(hi * r), 1, n).astype(np.int64)
+    return rng.permutation(deg)
+
+
+def zipf_degree_matrix(n, s, mean, rng):
+    deg = zipf_degrees(n, s, mean, rng)
+    rows, cols = _distinct_columns(rng, deg, n)
+    vals = uniform_pm1(rng, len(rows))
+    return rows, cols, vals
+
+
+def batched_instances(count=512, n_lo=1024, n_hi=65536, s=1.1, mean=16, seed=4):
+    """Half SpMV (y = A x, x dense) and half SpGEMM (C = A A), interleaved
+    by a seeded shuffle; n log-uniform in [n_lo, n_hi]."""
+    rng = rng_for(seed)
+    kinds = np.array(["spmv"] * (count // 2) + ["spgemm"] * (count - count // 2))
+    rng.shuffle(kinds)
+    out = []
+    for k in kinds:
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        rows, cols, vals = zipf_degree_matrix(n, s, mean, rng)
+        inst = {"kind": str(k), "n": n, "rows": rows, "cols": cols, "vals": vals}
+        if k == "spmv":
+            inst["x"] = uniform_pm1(rng, n)
+        out.append(inst)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Star schema
+# --------------------------------------------------------------------------
+
+def zipf_keys(rng, n_keys, s, size, chunk=1 << 23):
+    """P(rank r) proportional to r^-s over n_keys ranks; rank -> key through
+    a seeded permutation."""
+    w = np.arange(1, n_keys + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    perm = rng.permutation(n_keys).astype(np.uint32)
+    out = np.empty(size, dtype=np.uint32)
+    for i in range(0, size, chunk):
+        m = min(chunk, size - i)
+        u = rng.random(m)
+        rank = np.minimum(np.searchsorted(cdf, u, side="right"), n_keys - 1)
+        out[i:i + m] = perm[rank]
+    return out
+
+
+def star_schema(n_fact=60_000_000, dims=(2_000_000, 500_000, 100_000, 10_000), s=1.0, seed=3):
+    """Fact(k0..k3, ann) with ann = price * (1 - discount) computed once per
+    row (an expression over one relation becomes its annotation); four
+    dimensions keyed by dense ids:
+      D0: anno u ~ U[0,1)          (filter: u < 0.20)
+      D1: meta g in [0, 100)       (GROUP BY g)
+      D2: meta m in [0, 10)        (filter: m == 0)
+      D3: meta m in [0, 100)       (filter: m == 0)
+    """
+    rng = rng_for(seed)
+    fk = [zipf_keys(rng, d, s, n_fact) for d in dims]
+    price = rng.random(n_fact)
+    discount = rng.random(n_fact)
+    ann = price * (1.0 - discount)
+    d0 = {"key": np.arange(dims[0], dtype=np.uint32), "u": rng.random(dims[0])}
+    d1 = {"key": np.arange(dims[1], dtype=np.uint32), "g": rng.integers(0, 100, dims[1]).astype(np.uint32)}
+    d2 = {"key": np.arange(dims[2], dtype=np.uint32), "m": rng.integers(0, 10, dims[2]).astype(np.uint32)}
+    d3 = {"key": np.arange(dims[3], dtype=np.uint32), "m": rng.integers(0, 100, dims[3]).astype(np.uint32)}
+    return {"fact": {"k": fk, "ann": ann}, "dims": [d0, d1, d2, d3]}
+
+
+# --------------------------------------------------------------------------
+# Intersection micro-benchmark sets
+# --------------------------------------------------------------------------
+
+def set_pairs(card, universe, n_pairs, seed):
+    """n_pairs pairs of sorted distinct uint32 sets, each of size ``card``
+    drawn uniformly without replacement from [0, universe)."""
+    rng = rng_for(seed)
+    out = []
+    for _ in range(n_pairs):
+        a = np.sort(rng.choice(universe, card, replace=False)).astype(np.uint32)
+        b = np.sort(rng.choice(universe, card, replace=False)).astype(np.uint32)
+        out.append((a, b))
+    return out
