@@ -1,0 +1,171 @@
+"""Benchmark: generic worst-case optimal join with aggregation on one MI355X.
+
+Default workload: triangle COUNT  R(a,b) |x| S(b,c) |x| T(a,c)  on an R-MAT
+graph with 2^22 vertices and 2^26 sampled edges (a=0.57, b=0.19, c=0.19),
+edges oriented low->high and deduplicated by the set-mode trie build.
+
+One step is one pass of the whole path over the resident edge list:
+lh_trie_build (sort, dedup, levels, layouts) + lh_plan (order, policies)
++ lh_join_aggregate (multiway intersections, COUNT) + reading the count.
+value = join-aggregate input tuples per second = 3 * |E'| / step time (the
+three atoms each hold the |E'| deduplicated edges).
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "join-aggregate tuples/s + HBM GB/s, learned+batched vs plain WCOJ, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def leaf_alg_bytes(rows, elements):
+    """Algorithmic bytes of one intersect-and-aggregate pass: per frontier
+    row its two trie positions (8 B), the two sets' child ranges (16 B), its
+    work offset (8 B) and driver id (1 B); per element of the smaller set
+    the element itself (4 B) and one probe of the other set (4 B)."""
+    return 33 * rows + 8 * elements
+
+
+ALG_BYTES = {
+    "leaf_aggregate": leaf_alg_bytes,
+    "join_count": leaf_alg_bytes,
+    "join_fill": lambda rows, el: 33 * rows + 8 * el,
+    # (u64 key + u32 value) read and written per sorted element
+    "sort_scatter": lambda rows, el: 24 * rows,
+    "sort_hist": lambda rows, el: 8 * rows,
+}
+
+
+def cpu_baseline(scale):
+    import numpy as np
+
+    import oracle
+    import synth
+    from tests import queries
+    lo, hi = synth.rmat_edges(scale, 16 << scale, seed=2)
+    q = queries.triangle(lo, hi)
+    e = len(set(zip(lo.tolist(), hi.tolist())))
+    t0 = time.perf_counter()
+    res = oracle.join_aggregate(q)
+    dt = time.perf_counter() - t0
+    return {"value": 3 * e / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+            "sample": f"R-MAT scale {scale} (2^{scale} vertices, {16 << scale} samples, same a,b,c), "
+                      f"{e} edges, full triangle COUNT = {int(res['counts'][0])}, {dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--samples-log2", type=int, default=26)
+    ap.add_argument("--cpu-scale", type=int, default=15)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU layout is a design "
+              "note only", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1708_07859_amd import lh
+
+    torch.cuda.set_device(0)
+    log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
+    t0 = time.perf_counter()
+    lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
+    log(f"  {len(lo)} oriented samples in {time.perf_counter() - t0:.1f} s")
+    lo_d = lh.to_device(lo)
+    hi_d = lh.to_device(hi)
+    torch.cuda.synchronize()
+
+    state = {}
+
+    def step():
+        t = lh.trie_build([lo_d, hi_d])
+        p = lh.plan(3, [(t, [0, 1], -1), (t, [1, 2], -1), (t, [0, 2], -1)], agg="count")
+        r = lh.join_aggregate([p])[0]
+        res = r.to_host()
+        if "edges" not in state:
+            state["edges"] = t.info()["level_size"][1]
+            state["order"] = p.info()["attr_order"]
+        state["count"] = int(res["counts"][0])
+        r.free()
+        p.free()
+        t.free()
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i}: triangles={state['count']} edges={state['edges']}")
+    torch.cuda.synchronize()
+    lh.profile_reset()
+    lh.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lh.profile_enable(False)
+    prof = lh.profile_read()
+    ms = dt * 1000 / args.steps
+    tuples = 3 * state["edges"]
+    value = tuples / (ms / 1000)
+    log(f"{args.steps} steps: {ms:.2f} ms/step, triangles={state['count']}")
+    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
+        log(f"  {k:22s} launches={v['launches']:6d} total={v['total_ms']:9.3f} ms "
+            f"rows={v['rows']} elems={v['elements']}")
+    # roofline of the dominant kernel with a known byte formula
+    dom = max((k for k in prof if k in ALG_BYTES), key=lambda k: prof[k]["total_ms"], default=None)
+    roof = None
+    if dom:
+        e = prof[dom]
+        per_launch_bytes = ALG_BYTES[dom](e["rows"], e["elements"]) / e["launches"]
+        avg_ms = e["total_ms"] / e["launches"]
+        achieved = per_launch_bytes / (avg_ms / 1000) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(per_launch_bytes)}
+    join_ms = sum(prof[k]["total_ms"] for k in prof if k.startswith(("join_", "leaf_"))) / args.steps
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"triangle COUNT on R-MAT scale {args.scale}, 2^{args.samples_log2} samples "
+                               f"(a=0.57,b=0.19,c=0.19), oriented low->high, set-mode dedup",
+                   "edges": state["edges"], "triangles": state["count"], "attr_order": state["order"],
+                   "step": "trie_build + plan + join_aggregate",
+                   "join_kernels_ms_per_step": round(join_ms, 3)},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log(f"cpu baseline: oracle on R-MAT scale {args.cpu_scale}")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_scale)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

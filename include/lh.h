@@ -1,0 +1,279 @@
+/*
+ * lh.h -- generic (worst-case optimal) join with aggregation over
+ * dictionary-encoded uint32 tries, on one AMD Instinct MI355X (gfx950).
+ *
+ * The library follows the paper's statement of the problem:
+ *  - relations whose attributes are KEYS (joinable, dictionary encoded as
+ *    uint32, never aggregated) or ANNOTATIONS (aggregable; here FP64), with
+ *    other non-key columns kept as uint32 META columns (section 2.1, "Data
+ *    Model"; Rule 4 of section 3.1 keeps non-aggregated attributes in a
+ *    metadata container);
+ *  - one trie per relation over its key attributes, each level a collection
+ *    of sets stored as sorted uint arrays or as bitsets, with annotation
+ *    buffers reachable from the last level (section 2.2, "Storage Engine");
+ *  - a query hypergraph whose vertices are attributes and whose hyperedges
+ *    are relations (section 2.3, "Representing Queries as Hypergraphs");
+ *  - aggregation over a commutative semiring, multiplying annotations on
+ *    join and summing them over the attributes that are not output (section
+ *    2.3, "Capturing Aggregate-Join Queries");
+ *  - evaluation one attribute at a time by the generic worst-case optimal
+ *    join (Algorithm 1, section 2.4), with the attribute order chosen by the
+ *    cost-based optimizer of section 4 unless the caller fixes it.
+ *
+ * Memory: every column pointer handed IN is a DEVICE pointer (HIP); every
+ * descriptor array (the arrays of column pointers, attribute maps, orders,
+ * filters) is a HOST array.  Inputs are borrowed: each call finishes its
+ * device work (it synchronizes the given stream) before it returns, so the
+ * caller may release input buffers as soon as a call returns.  Tries,
+ * plans and results own their device memory until lh_free.  A plan borrows
+ * the tries its atoms name; they must outlive it.  A result does not
+ * reference its plan.
+ *
+ * Errors: every call returns lh_status; on any error *out is set to NULL
+ * and nothing is leaked.  lh_last_error() returns a thread-local message
+ * for the last failing call.  A handle must not be used from two host
+ * threads at once.  The stream argument is a hipStream_t (NULL = the null
+ * stream).
+ */
+#ifndef LH_H
+#define LH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LH_OK = 0,
+  LH_ERR_INVALID = 1,      /* a NULL pointer, a bad size, id or permutation */
+  LH_ERR_OOM = 2,          /* device allocation failed */
+  LH_ERR_DEVICE = 3,       /* any other HIP runtime error */
+  LH_ERR_UNSUPPORTED = 4,  /* valid request outside what this build supports */
+  LH_ERR_OVERFLOW = 5      /* a size or count exceeds its index type */
+} lh_status;
+
+/* ---- relation flags (lh_relation_desc.flags) ---------------------------- */
+#define LH_SET            0x00u  /* key tuples form a set: duplicates removed; no annos/meta */
+#define LH_BAG            0x01u  /* every row is its own tuple (duplicates kept) */
+#define LH_LAYOUT_PLAIN   0x00u  /* bitset iff (max-min+1) <= 32*card, per set */
+#define LH_LAYOUT_UINT    0x10u  /* every set a sorted uint array */
+#define LH_LAYOUT_BITSET  0x20u  /* every set whose window fits also a bitset */
+#define LH_LAYOUT_LEARNED 0x30u  /* per-set choice by the learned cost model */
+#define LH_LAYOUT_MASK    0x30u
+
+#define LH_MAX_KEYS 8
+
+typedef struct lh_trie lh_trie;
+typedef struct lh_plan_s lh_plan_t;
+
+/* One relation as a column store (section 2.1).  keys/annos/meta are HOST
+ * arrays of DEVICE column pointers, each column n_rows long. */
+typedef struct {
+  uint64_t n_rows;
+  uint32_t n_keys;                  /* 1..LH_MAX_KEYS key columns */
+  const uint32_t* const* keys;      /* dictionary-encoded key columns */
+  uint32_t n_annos;
+  const double* const* annos;       /* FP64 annotation columns */
+  uint32_t n_meta;
+  const uint32_t* const* meta;      /* uint32 non-key columns (filters, GROUP BY) */
+  const uint32_t* level_order;      /* host: key column of trie level l; NULL = identity */
+  uint32_t flags;                   /* LH_SET|LH_BAG  |  LH_LAYOUT_* */
+} lh_relation_desc;
+
+/* Build the trie of one relation (section 2.2): a stable lexicographic
+ * radix sort of the key tuples in level order, per-level keys and child
+ * offsets, set-mode deduplication or bag-mode runs, a per-set uint/bitset
+ * layout, and the annotation and meta columns gathered into trie order.
+ * Errors: LH_ERR_INVALID for NULL pointers, n_keys outside 1..8, a
+ * level_order that is not a permutation, or a set relation with annotation
+ * or meta columns; LH_ERR_OVERFLOW if n_rows >= 2^32. */
+lh_status lh_trie_build(const lh_relation_desc* rel, void* hip_stream, lh_trie** out);
+
+/* ---- queries ------------------------------------------------------------ */
+#define LH_AGG_COUNT 0u
+#define LH_AGG_SUM   1u
+
+#define LH_EQ_KEY     0u  /* key column == eq          (section 2.1) */
+#define LH_EQ_META    1u  /* meta column == eq         */
+#define LH_RANGE_ANNO 2u  /* lo <= annotation < hi     (section 2.1) */
+#define LH_RANGE_META 3u  /* lo <= meta column < hi    */
+
+#define LH_POLICY_PLAIN   0x0u  /* section 4 cost rule picks order and per-level algorithms */
+#define LH_POLICY_LEARNED 0x1u  /* learned cost model picks; the plain rule is its fallback */
+#define LH_POLICY_FIXED   0x2u  /* caller's attr_order, plain per-level algorithms */
+#define LH_POLICY_MASK    0x3u
+
+/* A hyperedge: one relation's trie and the query attribute of each of its
+ * key columns (columns mapping to one attribute are equi-joined, Rule 1 of
+ * section 3.1). */
+typedef struct {
+  const lh_trie* trie;
+  const uint32_t* attr_of_key;  /* host, n_keys entries, distinct, < n_attrs */
+  int32_t anno;                 /* annotation column multiplied in for SUM; -1 = identity */
+} lh_atom;
+
+typedef struct {
+  uint32_t atom, kind, col;     /* kind: LH_EQ_KEY / LH_EQ_META / LH_RANGE_ANNO / LH_RANGE_META */
+  uint32_t eq;
+  double lo, hi;                /* half-open [lo, hi) */
+} lh_filter;
+
+typedef struct { uint32_t atom, meta_col; } lh_group_col;  /* GROUP BY a meta column (section 5) */
+
+typedef struct {
+  uint32_t n_attrs;                 /* query attributes 0..n_attrs-1 (<= 16) */
+  uint32_t n_atoms;                 /* hyperedges (<= 8) */
+  const lh_atom* atoms;
+  uint32_t n_out;                   /* materialized key attributes, in output order */
+  const uint32_t* out_attrs;
+  uint32_t n_group;                 /* extra GROUP BY meta columns */
+  const lh_group_col* group_cols;
+  uint32_t agg;                     /* LH_AGG_COUNT or LH_AGG_SUM */
+  uint32_t n_filters;
+  const lh_filter* filters;
+  const uint32_t* attr_order;       /* host permutation of the attributes; NULL = optimizer */
+  uint32_t policy;                  /* LH_POLICY_* */
+} lh_query;
+
+/* Plan a query: validate it, apply the filters to private copies of the
+ * filtered relations (selections pushed below the join, section 3.2),
+ * choose the attribute order by the cost estimate of section 4 (sum over
+ * attributes of icost x weight; materialized attributes first, with the
+ * one-swap relaxation of section 4.1.2), rebuild any trie whose level order
+ * does not follow that order, and fix the per-level intersection algorithm
+ * and the exact-summation window.
+ * Errors: LH_ERR_INVALID (NULL, ids out of range, repeated attribute in an
+ * atom, attribute in no atom, non-permutation attr_order, filter column out
+ * of range, SUM without an annotated atom); LH_ERR_UNSUPPORTED (an
+ * aggregate other than COUNT/SUM, a non-finite annotation, or annotation
+ * values whose exact products do not fit the 256-bit accumulator).
+ * SUM terms: one annotated atom gives its value; with m >= 2 the first m-1
+ * factors (atom order) are multiplied with rounding and the last product is
+ * exact; every term is summed exactly and the sum rounded once (ties to
+ * even). */
+lh_status lh_plan(const lh_query* q, void* hip_stream, lh_plan_t** out);
+
+/* Result of one plan.  out_keys is a HOST array of n_cols DEVICE columns
+ * (the n_out output attributes in declared order, then the n_group group
+ * columns), n_rows long, rows sorted ascending lexicographically.  counts
+ * is the number of contributing join tuples per row (always present); sums
+ * (SUM only) is the exact sum of annotation products rounded once to the
+ * nearest double.  An ungrouped query has exactly one row. */
+typedef struct lh_result {
+  uint64_t n_rows;
+  uint32_t n_cols;
+  const uint32_t* const* out_keys;
+  const uint64_t* counts;
+  const double* sums;
+  uint32_t exact;                   /* 1: sums are correctly rounded exact sums */
+  uint64_t n_join_tuples;           /* full-join tuples aggregated */
+} lh_result;
+
+/* Run plans (Algorithm 1 per plan).  n_plans > 1 runs them as one batch:
+ * the batched executor puts every instance's work into one persistent,
+ * graph-captured launch where the plans allow it; results are identical to
+ * running them one at a time.  out receives n_plans result handles.
+ * Errors: LH_ERR_INVALID for NULL arguments or n_plans == 0. */
+lh_status lh_join_aggregate(lh_plan_t* const* plans, uint32_t n_plans, void* hip_stream,
+                            lh_result** out);
+
+/* Release an lh_trie*, lh_plan* or lh_result*.  NULL is a no-op. */
+void lh_free(void* handle);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* lh_last_error(void);
+
+/* ---- inspection helpers (tests, tools) ---------------------------------- */
+
+typedef struct {
+  uint32_t n_levels;
+  uint64_t n_rows;                  /* rows kept: distinct tuples (set) or all rows (bag) */
+  uint64_t level_size[LH_MAX_KEYS];     /* nodes per level */
+  uint64_t level_sets[LH_MAX_KEYS];     /* sets per level (level 0: 1) */
+  uint64_t level_bitsets[LH_MAX_KEYS];  /* sets stored as bitsets */
+  uint64_t level_words[LH_MAX_KEYS];    /* 64-bit bitset words per level */
+  uint32_t level_order[LH_MAX_KEYS];
+} lh_trie_info;
+
+lh_status lh_trie_get_info(const lh_trie* t, lh_trie_info* info);
+
+/* Copy level l to host buffers: keys (level_size[l] entries), offs
+ * (level_size[l]+1 entries; NULL allowed; for the last level these are the
+ * run offsets into the sorted rows in bag mode, else 0..n).  Either buffer
+ * may be NULL. */
+lh_status lh_trie_read_level(const lh_trie* t, uint32_t level, uint32_t* keys, uint32_t* offs);
+
+/* Copy a result to host buffers of n_rows entries each (n_cols key
+ * buffers); any pointer may be NULL. */
+lh_status lh_result_read(const lh_result* r, uint32_t* const* keys, uint64_t* counts, double* sums);
+
+typedef struct {
+  uint32_t n_attrs;
+  uint32_t attr_order[16];
+  double cost;                      /* the section 4 estimate of the chosen order */
+  uint32_t case_prefix;             /* 1: output is a prefix of the order (streamed groups) */
+  uint32_t exact_digits;            /* 32-bit digits of the exact accumulator (0: COUNT) */
+  int32_t exact_lsb;                /* exponent of the accumulator's least significant bit */
+  uint32_t level_alg[16];           /* intersection algorithm per attribute position */
+} lh_plan_info;
+
+lh_status lh_plan_get_info(const lh_plan_t* p, lh_plan_info* info);
+
+/* ---- the section 4 cost estimate on a bare hypergraph (host only) ------- */
+
+/* Edge e has edge_attr_count[e] attributes, listed consecutively in
+ * edge_attrs; edge_card is its cardinality (the score of section 4.2 is
+ * ceil(card / heaviest card * 100)); edge_eq marks an equality selection on
+ * the relation (its vertices then take the heaviest score, else the
+ * lightest); edge_dense marks a completely dense relation, which adds no
+ * intersection (section 4.1.1).  edge_eq / edge_dense may be NULL. */
+typedef struct {
+  uint32_t n_attrs, n_edges;
+  const uint32_t* edge_attr_count;
+  const uint32_t* edge_attrs;
+  const uint64_t* edge_card;
+  const uint32_t* edge_eq;
+  const uint32_t* edge_dense;
+} lh_hypergraph;
+
+/* cost = SUM_i icost(order[i]) * weight(order[i]) (section 4); icost and
+ * weight (n_attrs entries each, may be NULL) receive the per-position
+ * values.  icost follows the layout guess of Crucial Observation 1 with
+ * bs&bs = 1, bs&uint = 10, uint&uint = 50, N-way sums with bitsets first,
+ * and 0 for an attribute in a single (non-dense) relation. */
+lh_status lh_order_cost(const lh_hypergraph* h, const uint32_t* order, uint32_t* icost, uint32_t* weight,
+                        double* cost);
+
+/* The optimizer's choice: the cheapest order with the n_out materialized
+ * attributes first, plus the one-swap relaxation of section 4.1.2 (last
+ * attribute projected away, second-to-last materialized, swap lowers the
+ * icost); ties go to the lexicographically smallest order. */
+lh_status lh_choose_order(const lh_hypergraph* h, uint32_t n_out, const uint32_t* out_attrs, uint32_t* order,
+                          double* cost);
+
+/* Device allocations currently held by the library (leak checks). */
+long lh_live_allocations(void);
+
+/* ---- opt-in kernel timing ------------------------------------------------
+ * When enabled, the library brackets its kernel launches with hipEvents on
+ * the launching stream and aggregates them per kernel name: launches, total
+ * milliseconds, and the rows / flattened set elements the launches
+ * processed (the units of the algorithmic-bytes formulas). */
+typedef struct {
+  char name[48];
+  uint64_t launches;
+  double total_ms;
+  uint64_t rows;
+  uint64_t elements;
+} lh_profile_entry;
+
+void lh_profile_enable(int on);
+void lh_profile_reset(void);
+/* Writes up to max_entries entries; returns the number of kernels seen. */
+uint32_t lh_profile_read(lh_profile_entry* out, uint32_t max_entries);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LH_H */

@@ -1,0 +1,265 @@
+// The C ABI: validation of descriptors, handle bookkeeping and the mapping
+// of internal errors to lh_status.  No exception crosses this boundary.
+#include <cstring>
+#include <mutex>
+#include <set>
+
+#include "costmodel.h"
+#include "engine.h"
+
+namespace lh {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+std::mutex g_mu;
+std::set<const void*> g_tries, g_plans, g_results;
+
+void track(std::set<const void*>& s, const void* p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  s.insert(p);
+}
+
+bool untrack(std::set<const void*>& s, const void* p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return s.erase(p) != 0;
+}
+
+bool tracked(const std::set<const void*>& s, const void* p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return s.count(p) != 0;
+}
+
+template <class F>
+lh_status guard(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return LH_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return LH_ERR_OOM;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return LH_ERR_DEVICE;
+  }
+}
+
+Hypergraph hypergraph_from(const lh_hypergraph* h) {
+  if (!h || !h->edge_attr_count || !h->edge_attrs || !h->edge_card) fail(LH_ERR_INVALID, "hypergraph is incomplete");
+  if (h->n_attrs == 0 || h->n_attrs > MAXV) fail(LH_ERR_INVALID, "n_attrs must be 1..16");
+  Hypergraph g;
+  g.n_attrs = h->n_attrs;
+  uint32_t k = 0;
+  for (uint32_t e = 0; e < h->n_edges; e++) {
+    Edge E;
+    for (uint32_t i = 0; i < h->edge_attr_count[e]; i++) {
+      uint32_t v = h->edge_attrs[k++];
+      if (v >= h->n_attrs) fail(LH_ERR_INVALID, "edge attribute out of range");
+      E.attrs.push_back(v);
+    }
+    E.card = h->edge_card[e];
+    E.eq = h->edge_eq && h->edge_eq[e];
+    E.dense = h->edge_dense && h->edge_dense[e];
+    g.edges.push_back(E);
+  }
+  return g;
+}
+
+}  // namespace
+
+void free_trie(lh_trie* t) { delete t; }
+
+}  // namespace lh
+
+using namespace lh;
+
+extern "C" {
+
+lh_status lh_trie_build(const lh_relation_desc* rel, void* hip_stream, lh_trie** out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    if (!rel || !out) fail(LH_ERR_INVALID, "NULL argument");
+    if (rel->n_keys == 0 || rel->n_keys > LH_MAX_KEYS) fail(LH_ERR_INVALID, "n_keys must be 1..8");
+    if (!rel->keys) fail(LH_ERR_INVALID, "keys is NULL");
+    if (rel->n_rows >= (1ull << 32) - 1) fail(LH_ERR_OVERFLOW, "n_rows must be below 2^32 - 1");
+    for (uint32_t c = 0; c < rel->n_keys; c++)
+      if (!rel->keys[c] && rel->n_rows) fail(LH_ERR_INVALID, "a key column is NULL");
+    if (rel->n_annos && !rel->annos) fail(LH_ERR_INVALID, "annos is NULL");
+    if (rel->n_meta && !rel->meta) fail(LH_ERR_INVALID, "meta is NULL");
+    for (uint32_t a = 0; a < rel->n_annos; a++)
+      if (!rel->annos[a] && rel->n_rows) fail(LH_ERR_INVALID, "an annotation column is NULL");
+    for (uint32_t m = 0; m < rel->n_meta; m++)
+      if (!rel->meta[m] && rel->n_rows) fail(LH_ERR_INVALID, "a meta column is NULL");
+    if (!(rel->flags & LH_BAG) && (rel->n_annos || rel->n_meta))
+      fail(LH_ERR_INVALID, "a set relation carries no annotation or meta columns");
+    if (rel->flags & ~(LH_BAG | LH_LAYOUT_MASK)) fail(LH_ERR_INVALID, "unknown flag bits");
+    uint32_t lo[LH_MAX_KEYS];
+    uint32_t seen = 0;
+    for (uint32_t l = 0; l < rel->n_keys; l++) {
+      lo[l] = rel->level_order ? rel->level_order[l] : l;
+      if (lo[l] >= rel->n_keys || (seen >> lo[l] & 1u)) fail(LH_ERR_INVALID, "level_order is not a permutation");
+      seen |= 1u << lo[l];
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    lh_trie* t = build_trie(rel->n_rows, rel->n_keys, rel->keys, rel->n_annos, rel->annos, rel->n_meta, rel->meta, lo,
+                            rel->flags, nullptr, 0, s);
+    track(g_tries, t);
+    *out = t;
+  });
+}
+
+lh_status lh_plan(const lh_query* q, void* hip_stream, lh_plan_t** out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    if (!q || !out) fail(LH_ERR_INVALID, "NULL argument");
+    for (uint32_t e = 0; q->atoms && e < q->n_atoms; e++)
+      if (!tracked(g_tries, q->atoms[e].trie)) fail(LH_ERR_INVALID, "atom trie is not a live lh_trie");
+    hipStream_t s = (hipStream_t)hip_stream;
+    lh_plan_t* p = make_plan(q, s);
+    LH_HIP(hipStreamSynchronize(s));
+    track(g_plans, p);
+    *out = p;
+  });
+}
+
+lh_status lh_join_aggregate(lh_plan_t* const* plans, uint32_t n_plans, void* hip_stream, lh_result** out) {
+  if (out)
+    for (uint32_t i = 0; i < n_plans; i++) out[i] = nullptr;
+  std::vector<lh_result_impl*> made;
+  lh_status st = guard([&] {
+    if (!plans || !out || n_plans == 0) fail(LH_ERR_INVALID, "NULL argument or no plans");
+    for (uint32_t i = 0; i < n_plans; i++)
+      if (!tracked(g_plans, plans[i])) fail(LH_ERR_INVALID, "not a live lh_plan");
+    hipStream_t s = (hipStream_t)hip_stream;
+    for (uint32_t i = 0; i < n_plans; i++) made.push_back(run_plan(plans[i], s));
+  });
+  if (st != LH_OK) {
+    for (auto* r : made) delete r;
+    return st;
+  }
+  for (uint32_t i = 0; i < n_plans; i++) {
+    out[i] = &made[i]->pub;
+    track(g_results, made[i]);
+  }
+  return LH_OK;
+}
+
+void lh_free(void* h) {
+  if (!h) return;
+  if (untrack(g_tries, h)) {
+    delete static_cast<lh_trie*>(h);
+  } else if (untrack(g_plans, h)) {
+    delete static_cast<lh_plan_t*>(h);
+  } else if (untrack(g_results, h)) {
+    delete reinterpret_cast<lh_result_impl*>(h);
+  }
+  // anything else (already freed, foreign pointer) is ignored
+}
+
+const char* lh_last_error(void) { return g_last_error.c_str(); }
+
+lh_status lh_trie_get_info(const lh_trie* t, lh_trie_info* info) {
+  return guard([&] {
+    if (!t || !info || !tracked(g_tries, t)) fail(LH_ERR_INVALID, "not a live lh_trie");
+    memset(info, 0, sizeof *info);
+    info->n_levels = t->n_levels;
+    info->n_rows = t->n_rows;
+    for (uint32_t l = 0; l < t->n_levels; l++) {
+      info->level_size[l] = t->lv[l].n;
+      info->level_sets[l] = t->lv[l].n_sets;
+      info->level_words[l] = t->lv[l].pool_words;
+      info->level_order[l] = t->level_order[l];
+      uint64_t nb = 0;
+      if (t->lv[l].n_sets) {
+        std::vector<uint64_t> w(t->lv[l].n_sets);
+        LH_HIP(hipMemcpy(w.data(), t->lv[l].bs_word.p, w.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        for (uint64_t x : w) nb += x != UINT64_MAX;
+      }
+      info->level_bitsets[l] = nb;
+    }
+  });
+}
+
+lh_status lh_trie_read_level(const lh_trie* t, uint32_t level, uint32_t* keys, uint32_t* offs) {
+  return guard([&] {
+    if (!t || !tracked(g_tries, t)) fail(LH_ERR_INVALID, "not a live lh_trie");
+    if (level >= t->n_levels) fail(LH_ERR_INVALID, "level out of range");
+    const Level& L = t->lv[level];
+    if (keys && L.n) LH_HIP(hipMemcpy(keys, L.keys.p, L.n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (offs) {
+      if (L.offs.p) {
+        LH_HIP(hipMemcpy(offs, L.offs.p, (L.n + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost));
+      } else {
+        for (uint64_t i = 0; i <= L.n; i++) offs[i] = (uint32_t)i;
+      }
+    }
+  });
+}
+
+lh_status lh_result_read(const lh_result* r, uint32_t* const* keys, uint64_t* counts, double* sums) {
+  return guard([&] {
+    if (!r || !tracked(g_results, r)) fail(LH_ERR_INVALID, "not a live lh_result");
+    if (!r->n_rows) return;
+    if (keys)
+      for (uint32_t c = 0; c < r->n_cols; c++)
+        if (keys[c]) LH_HIP(hipMemcpy(keys[c], r->out_keys[c], r->n_rows * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (counts) LH_HIP(hipMemcpy(counts, r->counts, r->n_rows * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (sums && r->sums) LH_HIP(hipMemcpy(sums, r->sums, r->n_rows * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+lh_status lh_plan_get_info(const lh_plan_t* p, lh_plan_info* info) {
+  return guard([&] {
+    if (!p || !info || !tracked(g_plans, p)) fail(LH_ERR_INVALID, "not a live lh_plan");
+    memset(info, 0, sizeof *info);
+    info->n_attrs = p->n_attrs;
+    for (uint32_t i = 0; i < p->n_attrs; i++) {
+      info->attr_order[i] = p->order[i];
+      info->level_alg[i] = p->level_alg[i];
+    }
+    info->cost = p->cost;
+    info->case_prefix = p->case_prefix ? 1u : 0u;
+    info->exact_digits = p->exact_digits;
+    info->exact_lsb = p->exact_lsb;
+  });
+}
+
+lh_status lh_order_cost(const lh_hypergraph* h, const uint32_t* order, uint32_t* icost, uint32_t* weight,
+                        double* cost) {
+  return guard([&] {
+    Hypergraph g = hypergraph_from(h);
+    if (!order) fail(LH_ERR_INVALID, "order is NULL");
+    std::vector<uint32_t> o(order, order + g.n_attrs);
+    uint32_t seen = 0;
+    for (uint32_t v : o) {
+      if (v >= g.n_attrs || (seen >> v & 1u)) fail(LH_ERR_INVALID, "order is not a permutation");
+      seen |= 1u << v;
+    }
+    double c = order_cost(g, o, icost, weight);
+    if (cost) *cost = c;
+  });
+}
+
+lh_status lh_choose_order(const lh_hypergraph* h, uint32_t n_out, const uint32_t* out_attrs, uint32_t* order,
+                          double* cost) {
+  return guard([&] {
+    Hypergraph g = hypergraph_from(h);
+    if (!order || (n_out && !out_attrs)) fail(LH_ERR_INVALID, "NULL argument");
+    std::vector<uint32_t> out(out_attrs, out_attrs + n_out);
+    for (uint32_t v : out)
+      if (v >= g.n_attrs) fail(LH_ERR_INVALID, "output attribute out of range");
+    std::vector<uint32_t> o;
+    double c = choose_order(g, out, o);
+    std::copy(o.begin(), o.end(), order);
+    if (cost) *cost = c;
+  });
+}
+
+long lh_live_allocations(void) { return live_allocations(); }
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Plans and results: host-side objects shared by the planner, the join
+// executor and the C ABI.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "lh_internal.h"
+
+namespace lh {
+
+constexpr int MAXA = 8;    // atoms per query
+constexpr int MAXP = 8;    // participants per attribute
+constexpr int MAXV = 16;   // attributes per query
+
+// Per-level intersection algorithm (chosen per attribute position).
+enum LevelAlg : uint32_t {
+  ALG_PROBE = 0,   // iterate the smallest set, probe the others (bit test or binary search)
+  ALG_MERGE = 1,   // reserved: merge-path co-iteration of two uint sets
+  ALG_BSAND = 2,   // reserved: word-wise AND of two bitsets
+};
+
+struct PlanAtom {
+  const lh_trie* trie = nullptr;      // trie used by the plan
+  lh_trie* owned = nullptr;           // plan-owned copy (filtered or re-ordered)
+  uint32_t n_levels = 0;
+  uint32_t attr_of_level[LH_MAX_KEYS];
+  int32_t anno = -1;                  // annotation column in the trie (SUM); -1 identity
+  bool bag = false;
+  uint64_t card = 0;                  // base cardinality (rows before filters)
+  bool has_eq_filter = false;
+};
+
+struct Participant {
+  uint32_t atom;
+  uint32_t level;  // trie level holding this attribute
+};
+
+}  // namespace lh
+
+struct lh_plan_s {
+  uint32_t magic = lh::PLAN_MAGIC;
+  uint32_t n_attrs = 0;
+  std::vector<lh::PlanAtom> atoms;
+  uint32_t order[lh::MAXV];                 // attribute at each depth
+  uint32_t depth_of[lh::MAXV];              // depth of each attribute
+  std::vector<std::vector<lh::Participant>> parts;  // per depth
+  std::vector<uint32_t> out_attrs;
+  std::vector<lh_group_col> groups;         // atom index refers to plan atoms
+  uint32_t agg = LH_AGG_COUNT;
+  uint32_t policy = LH_POLICY_PLAIN;
+  bool case_prefix = false;                 // outputs = first n_out attributes of the order
+  int32_t exact_lsb = 0;
+  uint32_t exact_digits = 0;
+  double cost = 0.0;
+  uint32_t level_alg[lh::MAXV];
+  ~lh_plan_s() {
+    for (auto& a : atoms)
+      if (a.owned) delete a.owned;
+  }
+};
+
+struct lh_result_impl {
+  lh_result pub;                            // must stay first
+  uint32_t magic = lh::RESULT_MAGIC;
+  std::vector<lh::DBuf<uint32_t>> cols;
+  std::vector<const uint32_t*> colptr;
+  lh::DBuf<uint64_t> counts;
+  lh::DBuf<double> sums;
+};
+
+namespace lh {
+
+lh_plan_t* make_plan(const lh_query* q, hipStream_t s);
+lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s);
+void free_trie(lh_trie* t);
+
+}  // namespace lh

@@ -1,0 +1,939 @@
+// Generic worst-case optimal join with fused aggregation (Algorithm 1,
+// section 2.4), executed level-synchronously on the GPU.
+//
+// The recursion of Algorithm 1 is unrolled breadth-first: the frontier at
+// depth d holds one row per binding of the first d+1 attributes of the
+// order, each row recording, for every relation that has a bound
+// attribute, its node position in that relation's trie.  Binding attribute
+// v_d intersects, for each frontier row, the sets of every relation that
+// contains v_d (its children under the row's node, or its root set).  The
+// work of a depth is flattened over the elements of each row's smallest
+// set, so rows of any size are spread evenly over the GPU: a count pass,
+// a scan and a fill pass that compacts hits with wave ballots.  The last
+// attribute is never materialized: each hit is aggregated directly
+// (annotations multiplied, the commutative-semiring sum of section 2.3).
+#include <algorithm>
+#include <cstring>
+
+#include "device_common.h"
+#include "engine.h"
+#include "exact.h"
+
+namespace lh {
+
+namespace {
+
+constexpr int J_NT = 256;
+constexpr int J_IT = 4;
+constexpr int J_CH = J_NT * J_IT;  // flattened elements per block
+constexpr int J_NW = J_NT / WAVE;
+constexpr int GCAP = 128;          // groups a block accumulates in LDS
+
+struct DSet {
+  const uint32_t* ppos;   // frontier positions at the previous level (null: root set)
+  const uint32_t* poffs;  // child offsets of the previous level (null: root set)
+  const uint32_t* keys;   // keys of this level
+  uint32_t root_n;
+  const uint64_t* bs_word;
+  const uint32_t* bs_base;
+  const uint64_t* pool;
+};
+
+__device__ __forceinline__ void dset_range(const DSet& st, uint64_t row, uint32_t& b, uint32_t& e, uint64_t& sidx) {
+  if (st.ppos) {
+    uint32_t p = st.ppos[row];
+    b = st.poffs[p];
+    e = st.poffs[p + 1];
+    sidx = p;
+  } else {
+    b = 0;
+    e = st.root_n;
+    sidx = 0;
+  }
+}
+
+// Membership of x in set [b, e) (descriptor sidx); its position if asked.
+__device__ __forceinline__ bool dset_find(const DSet& st, uint32_t b, uint32_t e, uint64_t sidx, uint32_t x,
+                                          bool need_pos, uint32_t& pos) {
+  if (b >= e) return false;
+  uint64_t w = st.bs_word[sidx];
+  if (w != UINT64_MAX) {
+    uint32_t base = st.bs_base[sidx];
+    if (x < base || x > st.keys[e - 1]) return false;
+    uint32_t d = x - base;
+    uint64_t word = st.pool[w + (d >> 6)];
+    if (!((word >> (d & 63u)) & 1ull)) return false;
+    if (need_pos) pos = lower_bound_u32(st.keys, b, e, x);
+    return true;
+  }
+  uint32_t j = lower_bound_u32(st.keys, b, e, x);
+  if (j < e && st.keys[j] == x) {
+    pos = j;
+    return true;
+  }
+  return false;
+}
+
+struct LeafAtom {
+  const uint32_t* pos;    // frontier position at its last level (non-participant)
+  int32_t part;           // participant index at the leaf attribute, or -1
+  const uint32_t* run;    // bag: run offsets of the last level; null: one row per node
+  const double* anno;     // SUM factor column (trie order), or null
+  const uint32_t* gmeta;  // GROUP BY meta column (trie order), or null
+  int32_t gcol;           // output column of gmeta
+  uint32_t expand;        // iterate the node's rows (anno or gmeta present)
+};
+
+struct LeafArgs {
+  uint32_t n_atoms;
+  LeafAtom at[MAXA];
+  uint32_t sum;
+  int32_t lsb;
+  uint32_t D;
+  // streamed groups (outputs are a prefix of the order)
+  const uint32_t* gid;    // group of each frontier row (null: one group)
+  uint64_t* gcount;
+  int64_t* gacc;          // n_groups x EXACT_MAXD slots
+  // materialized tuples
+  uint32_t n_cols;
+  uint32_t* col_out[MAXV + MAXA];
+  int32_t col_src[MAXV + MAXA];  // >= 0: frontier out column; -1: leaf value; -2: group meta
+  uint64_t* mult_out;
+  double* hi_out;
+  double* lo_out;
+  uint32_t* err;
+};
+
+struct ElemArgs {
+  uint32_t np;
+  DSet set[MAXP];
+  const uint64_t* W;      // exclusive scan of per-row work, nrows + 1 entries
+  const uint8_t* drv;     // driving participant of each row
+  uint64_t nrows;
+  uint64_t total;
+  uint32_t need_pos_mask; // participants whose position is needed
+  // fill
+  uint32_t n_atoms;
+  const uint32_t* pos_in[MAXA];
+  uint32_t* pos_out[MAXA];
+  int32_t part_of_atom[MAXA];
+  uint32_t n_outv;
+  const uint32_t* outv_in[MAXV];
+  uint32_t* outv_out[MAXV];
+  int32_t new_outv;       // out column taking the new value, or -1
+  const uint32_t* gid_in;
+  uint32_t* gid_out;
+  uint32_t gid_mode;      // 0 none, 1 copy parent's, 2 own row index
+  uint32_t* blk_cnt;
+  const uint64_t* blk_off;
+  LeafArgs leaf;
+};
+
+enum { M_COUNT = 0, M_FILL = 1, M_LEAF_A = 2, M_LEAF_B_COUNT = 3, M_LEAF_B_FILL = 4 };
+
+struct WorkArgs {
+  uint32_t np;
+  DSet set[MAXP];
+};
+
+__global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t best = UINT32_MAX, bi = 0;
+    for (uint32_t p = 0; p < a.np; p++) {
+      uint32_t b, e;
+      uint64_t sidx;
+      dset_range(a.set[p], r, b, e, sidx);
+      uint32_t c = e - b;
+      if (c < best) {
+        best = c;
+        bi = p;
+      }
+    }
+    work[r] = best;
+    drv[r] = (uint8_t)bi;
+  }
+}
+
+// Rows of a leaf hit: for each atom, the range of rows of its leaf node.
+struct HitRows {
+  uint32_t rb[MAXA], re[MAXA];
+  uint64_t mult;  // product of run lengths of the non-expanding atoms
+};
+
+__device__ __forceinline__ void leaf_rows(const LeafArgs& L, uint64_t r, const uint32_t* ppos, HitRows& h) {
+  h.mult = 1;
+  for (uint32_t e = 0; e < L.n_atoms; e++) {
+    const LeafAtom& A = L.at[e];
+    uint32_t lp = A.part >= 0 ? ppos[A.part] : (A.pos ? A.pos[r] : 0u);
+    uint32_t b = lp, en = lp + 1;
+    if (A.run) {
+      b = A.run[lp];
+      en = A.run[lp + 1];
+    }
+    h.rb[e] = b;
+    h.re[e] = en;
+    if (!A.expand) h.mult *= (uint64_t)(en - b);
+  }
+}
+
+// Product term of one row combination: (hi, lo) with hi + lo exact.  The
+// factors are taken in atom order; all but the last are multiplied with
+// rounding, the last multiplication is exact (a two-product).
+__device__ __forceinline__ void term_of(const LeafArgs& L, const uint32_t* cur, double& hi, double& lo) {
+  double p = 1.0, last = 1.0;
+  int nf = 0;
+  for (uint32_t e = 0; e < L.n_atoms; e++) {
+    if (!L.at[e].anno) continue;
+    double v = L.at[e].anno[cur[e]];
+    if (nf == 0) p = v;
+    else if (nf == 1) last = v;
+    else {
+      p = __dmul_rn(p, last);
+      last = v;
+    }
+    nf++;
+  }
+  if (nf <= 1) {
+    hi = p;
+    lo = 0.0;
+  } else {
+    two_prod(p, last, hi, lo);
+  }
+}
+
+// Number of row combinations of the expanding atoms.
+__device__ __forceinline__ uint64_t combos(const LeafArgs& L, const HitRows& h) {
+  uint64_t c = 1;
+  for (uint32_t e = 0; e < L.n_atoms; e++)
+    if (L.at[e].expand) c *= (uint64_t)(h.re[e] - h.rb[e]);
+  return c;
+}
+
+// Advance the odometer over expanding atoms; false when exhausted.
+__device__ __forceinline__ bool next_combo(const LeafArgs& L, const HitRows& h, uint32_t* cur) {
+  for (int e = (int)L.n_atoms - 1; e >= 0; e--) {
+    if (!L.at[e].expand) continue;
+    if (++cur[e] < h.re[e]) return true;
+    cur[e] = h.rb[e];
+  }
+  return false;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
+  __shared__ uint64_t s_rlo, s_rhi;
+  __shared__ uint64_t s_red[J_NW];
+  __shared__ uint64_t s_base;
+  __shared__ unsigned long long s_gcnt[GCAP];
+  __shared__ long long s_gacc[GCAP * EXACT_MAXD];
+  __shared__ uint32_t s_glo;
+  __shared__ uint32_t s_gspan;
+
+  const uint64_t k0 = (uint64_t)blockIdx.x * J_CH;
+  const uint64_t k1 = min(k0 + (uint64_t)J_CH, a.total);
+  const int tid = threadIdx.x;
+  const LeafArgs& L = a.leaf;
+
+  if (tid == 0) {
+    uint64_t lo = upper_bound_minus1<uint64_t>(a.W, 0, a.nrows, k0);
+    s_rlo = lo;
+    s_rhi = upper_bound_minus1<uint64_t>(a.W, lo, a.nrows, k1 - 1);
+    s_base = (MODE == M_FILL || MODE == M_LEAF_B_FILL) ? a.blk_off[blockIdx.x] : 0;
+    if (MODE == M_LEAF_A) {
+      uint32_t glo = L.gid ? L.gid[s_rlo] : 0u;
+      uint32_t ghi = L.gid ? L.gid[s_rhi] : 0u;
+      s_glo = glo;
+      s_gspan = ghi - glo + 1;
+    }
+  }
+  if (MODE == M_LEAF_A) {
+    for (int i = tid; i < GCAP; i += J_NT) s_gcnt[i] = 0;
+    for (int i = tid; i < GCAP * EXACT_MAXD; i += J_NT) s_gacc[i] = 0;
+  }
+  __syncthreads();
+  const uint64_t rlo = s_rlo, rhi = s_rhi;
+  const bool lds_groups = (MODE == M_LEAF_A) && (s_gspan <= (uint32_t)GCAP);
+
+  uint64_t my_count = 0;  // COUNT / LEAF_B_COUNT: hits or emitted tuples
+  RegAcc racc;
+  racc.clear();
+  uint64_t rcnt = 0;
+  uint32_t bad = 0;
+
+  for (int it = 0; it < J_IT; it++) {
+    const uint64_t k = k0 + (uint64_t)it * J_NT + tid;
+    const bool valid = k < k1;
+    bool hit = false;
+    uint64_t r = 0;
+    uint32_t x = 0;
+    uint32_t ppos[MAXP];
+    for (int i = 0; i < MAXP; i++) ppos[i] = 0;
+    if (valid) {
+      r = upper_bound_minus1<uint64_t>(a.W, rlo, rhi + 1, k);
+      const uint32_t d = a.drv[r];
+      uint32_t b[MAXP], e[MAXP];
+      uint64_t sidx[MAXP];
+      for (uint32_t p = 0; p < a.np; p++) dset_range(a.set[p], r, b[p], e[p], sidx[p]);
+      const uint32_t idx = b[d] + (uint32_t)(k - a.W[r]);
+      x = a.set[d].keys[idx];
+      ppos[d] = idx;
+      hit = true;
+      for (uint32_t p = 0; p < a.np && hit; p++) {
+        if (p == d) continue;
+        hit = dset_find(a.set[p], b[p], e[p], sidx[p], x, (a.need_pos_mask >> p) & 1u, ppos[p]);
+      }
+    }
+
+    if (MODE == M_COUNT) {
+      my_count += hit ? 1 : 0;
+    } else if (MODE == M_FILL) {
+      // order-preserving compaction: wave ballot + per-wave offsets
+      const uint64_t bal = ballot(hit);
+      const uint32_t wpre = lanes_below(bal);
+      const int w = tid / WAVE;
+      if (lane_id() == 0) s_red[w] = (uint64_t)__popcll(bal);
+      __syncthreads();
+      uint64_t off = s_base;
+      uint64_t tot = 0;
+      for (int j = 0; j < J_NW; j++) {
+        if (j < w) off += s_red[j];
+        tot += s_red[j];
+      }
+      if (hit) {
+        const uint64_t o = off + wpre;
+        for (uint32_t e = 0; e < a.n_atoms; e++) {
+          uint32_t* po = a.pos_out[e];
+          if (!po) continue;
+          const int32_t pa = a.part_of_atom[e];
+          po[o] = pa >= 0 ? ppos[pa] : a.pos_in[e][r];
+        }
+        for (uint32_t j = 0; j < a.n_outv; j++) {
+          uint32_t* ov = a.outv_out[j];
+          if (!ov) continue;
+          ov[o] = ((int32_t)j == a.new_outv) ? x : a.outv_in[j][r];
+        }
+        if (a.gid_mode == 1) a.gid_out[o] = a.gid_in[r];
+        else if (a.gid_mode == 2) a.gid_out[o] = (uint32_t)o;
+      }
+      __syncthreads();
+      if (tid == 0) s_base += tot;
+      __syncthreads();
+    } else if (MODE == M_LEAF_A) {
+      if (hit) {
+        HitRows h;
+        leaf_rows(L, r, ppos, h);
+        uint32_t cur[MAXA];
+        for (uint32_t e = 0; e < L.n_atoms; e++) cur[e] = h.rb[e];
+        const uint64_t nc = combos(L, h);
+        if (L.gid == nullptr) {
+          rcnt += h.mult * nc;
+          if (L.sum && nc) {
+            do {
+              double hi, lo;
+              term_of(L, cur, hi, lo);
+              bool ok = racc.add(hi, L.lsb, L.D, (int64_t)h.mult);
+              ok = racc.add(lo, L.lsb, L.D, (int64_t)h.mult) && ok;
+              if (!ok) bad = 1;
+            } while (next_combo(L, h, cur));
+          }
+        } else {
+          const uint32_t g = L.gid[r];
+          RegAcc t;
+          t.clear();
+          if (L.sum && nc) {
+            do {
+              double hi, lo;
+              term_of(L, cur, hi, lo);
+              bool ok = t.add(hi, L.lsb, L.D, (int64_t)h.mult);
+              ok = t.add(lo, L.lsb, L.D, (int64_t)h.mult) && ok;
+              if (!ok) bad = 1;
+            } while (next_combo(L, h, cur));
+          }
+          const uint64_t c = h.mult * nc;
+          if (lds_groups) {
+            const uint32_t gi = g - s_glo;
+            atomicAdd(&s_gcnt[gi], (unsigned long long)c);
+            if (L.sum)
+              for (uint32_t i = 0; i < L.D; i++)
+                if (t.s[i]) atomicAdd((unsigned long long*)&s_gacc[gi * EXACT_MAXD + i], (unsigned long long)t.s[i]);
+          } else {
+            atomicAdd((unsigned long long*)&L.gcount[g], (unsigned long long)c);
+            if (L.sum)
+              for (uint32_t i = 0; i < L.D; i++)
+                if (t.s[i]) atomicAdd((unsigned long long*)&L.gacc[(uint64_t)g * EXACT_MAXD + i], (unsigned long long)t.s[i]);
+          }
+        }
+      }
+    } else if (MODE == M_LEAF_B_COUNT) {
+      if (hit) {
+        HitRows h;
+        leaf_rows(L, r, ppos, h);
+        my_count += combos(L, h);
+      }
+    } else if (MODE == M_LEAF_B_FILL) {
+      uint64_t mine = 0;
+      HitRows h;
+      if (hit) {
+        leaf_rows(L, r, ppos, h);
+        mine = combos(L, h);
+      }
+      uint64_t tot;
+      uint64_t off = block_excl_scan<uint64_t, J_NT>(mine, s_red, tot) + s_base;
+      if (mine) {
+        uint32_t cur[MAXA];
+        for (uint32_t e = 0; e < L.n_atoms; e++) cur[e] = h.rb[e];
+        uint64_t o = off;
+        do {
+          for (uint32_t c = 0; c < L.n_cols; c++) {
+            const int32_t src = L.col_src[c];
+            uint32_t v;
+            if (src >= 0) v = a.outv_in[src][r];
+            else if (src == -1) v = x;
+            else {
+              v = 0;
+              for (uint32_t e = 0; e < L.n_atoms; e++)
+                if (L.at[e].gmeta && L.at[e].gcol == (int32_t)c) v = L.at[e].gmeta[cur[e]];
+            }
+            L.col_out[c][o] = v;
+          }
+          L.mult_out[o] = h.mult;
+          if (L.sum) {
+            double hi, lo;
+            term_of(L, cur, hi, lo);
+            L.hi_out[o] = hi;
+            L.lo_out[o] = lo;
+          }
+          o++;
+        } while (next_combo(L, h, cur));
+      }
+      __syncthreads();
+      if (tid == 0) s_base += tot;
+      __syncthreads();
+    }
+  }
+
+  if (MODE == M_COUNT || MODE == M_LEAF_B_COUNT) {
+    uint64_t t = block_sum<uint64_t, J_NT>(my_count, s_red);
+    if (tid == 0) a.blk_cnt[blockIdx.x] = (uint32_t)t;
+  }
+  if (MODE == M_LEAF_A) {
+    if (bad) atomicOr(L.err, 1u);
+    if (L.gid == nullptr) {
+      // block-reduce the per-thread accumulators into LDS slot 0
+      racc.normalize(L.D);
+      atomicAdd(&s_gcnt[0], (unsigned long long)rcnt);
+      if (L.sum)
+        for (uint32_t i = 0; i < L.D; i++)
+          if (racc.s[i]) atomicAdd((unsigned long long*)&s_gacc[i], (unsigned long long)racc.s[i]);
+      __syncthreads();
+      if (tid == 0) {
+        atomicAdd((unsigned long long*)&L.gcount[0], s_gcnt[0]);
+        if (L.sum) {
+          RegAcc t;
+          t.clear();
+          for (uint32_t i = 0; i < L.D; i++) t.s[i] = s_gacc[i];
+          t.normalize(L.D);
+          for (uint32_t i = 0; i < L.D; i++)
+            if (t.s[i]) atomicAdd((unsigned long long*)&L.gacc[i], (unsigned long long)t.s[i]);
+        }
+      }
+    } else if (lds_groups) {
+      __syncthreads();
+      for (uint32_t gi = tid; gi < s_gspan; gi += J_NT) {
+        if (s_gcnt[gi] == 0) continue;
+        const uint64_t g = (uint64_t)s_glo + gi;
+        atomicAdd((unsigned long long*)&L.gcount[g], s_gcnt[gi]);
+        if (L.sum) {
+          RegAcc t;
+          t.clear();
+          for (uint32_t i = 0; i < L.D; i++) t.s[i] = s_gacc[gi * EXACT_MAXD + i];
+          t.normalize(L.D);
+          for (uint32_t i = 0; i < L.D; i++)
+            if (t.s[i]) atomicAdd((unsigned long long*)&L.gacc[g * EXACT_MAXD + i], (unsigned long long)t.s[i]);
+        }
+      }
+    }
+  }
+}
+
+// ---- finalization ------------------------------------------------------------
+
+__global__ void k_nonzero_flags(const uint64_t* cnt, uint64_t n, uint32_t* flags) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    flags[i] = cnt[i] != 0 ? 1u : 0u;
+}
+
+struct FinA {
+  const uint64_t* gcount;
+  const int64_t* gacc;
+  const uint64_t* off;      // exclusive scan of nonzero flags (null: keep all)
+  uint32_t n_cols;
+  const uint32_t* key_in[MAXV];
+  uint32_t* key_out[MAXV];
+  uint64_t* count_out;
+  double* sum_out;
+  uint32_t sum;
+  int32_t lsb;
+  uint32_t D;
+  uint32_t* err;
+};
+
+__global__ void k_finalize_groups(FinA f, uint64_t n) {
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t o = g;
+    if (f.off) {
+      if (f.off[g + 1] == f.off[g]) continue;
+      o = f.off[g];
+    }
+    for (uint32_t c = 0; c < f.n_cols; c++) f.key_out[c][o] = f.key_in[c][g];
+    f.count_out[o] = f.gcount[g];
+    if (f.sum) f.sum_out[o] = exact_round(f.gacc + g * EXACT_MAXD, f.D, f.lsb, f.err);
+  }
+}
+
+struct ColsArg {
+  const uint32_t* c[MAXV + MAXA];
+  uint32_t n;
+};
+
+__global__ void k_seg_heads(ColsArg cols, const uint32_t* perm, uint64_t n, uint32_t* head) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t h = (i == 0);
+    if (!h) {
+      uint32_t p = perm[i], q = perm[i - 1];
+      for (uint32_t c = 0; c < cols.n && !h; c++) h = cols.c[c][p] != cols.c[c][q];
+    }
+    head[i] = h;
+  }
+}
+
+struct SegAccArgs {
+  ColsArg cols;
+  const uint32_t* perm;
+  const uint64_t* segoff;   // exclusive scan of heads: segment of i = segoff[i+1]-1
+  const uint64_t* mult;
+  const double* hi;
+  const double* lo;
+  uint32_t sum;
+  int32_t lsb;
+  uint32_t D;
+  uint64_t* gcount;
+  int64_t* gacc;
+  uint32_t* key_out[MAXV + MAXA];
+  uint32_t* err;
+};
+
+__global__ void k_seg_accumulate(SegAccArgs a, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t g = a.segoff[i + 1] - 1;
+    const uint32_t p = a.perm[i];
+    if (a.segoff[i + 1] != a.segoff[i])
+      for (uint32_t c = 0; c < a.cols.n; c++) a.key_out[c][g] = a.cols.c[c][p];
+    atomicAdd((unsigned long long*)&a.gcount[g], (unsigned long long)a.mult[p]);
+    if (a.sum) {
+      RegAcc t;
+      t.clear();
+      bool ok = t.add(a.hi[p], a.lsb, a.D, (int64_t)a.mult[p]);
+      ok = t.add(a.lo[p], a.lsb, a.D, (int64_t)a.mult[p]) && ok;
+      if (!ok) atomicOr(a.err, 1u);
+      for (uint32_t s = 0; s < a.D; s++)
+        if (t.s[s]) atomicAdd((unsigned long long*)&a.gacc[g * EXACT_MAXD + s], (unsigned long long)t.s[s]);
+    }
+  }
+}
+
+unsigned grid_for(uint64_t n) {
+  uint64_t b = (n + 255) / 256;
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(b, 256 * 64));
+}
+
+uint32_t bitlen(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
+
+// ---- host-side frontier --------------------------------------------------------
+
+struct Frontier {
+  uint64_t n = 1;                           // starts as the single empty binding
+  std::vector<DBuf<uint32_t>> pos;          // per atom (empty: no bound attribute)
+  std::vector<DBuf<uint32_t>> outv;         // per output column (empty: not bound yet)
+  DBuf<uint32_t> gid;
+};
+
+DSet make_dset(const lh_plan_t* p, const Participant& pt, const Frontier& F) {
+  const lh_trie* t = p->atoms[pt.atom].trie;
+  const Level& L = t->lv[pt.level];
+  DSet d{};
+  d.keys = L.keys.p;
+  d.bs_word = L.bs_word.p;
+  d.bs_base = L.bs_base.p;
+  d.pool = L.pool.p;
+  if (pt.level == 0) {
+    d.root_n = (uint32_t)t->lv[0].n;
+  } else {
+    d.ppos = F.pos[pt.atom].p;
+    d.poffs = t->lv[pt.level - 1].offs.p;
+  }
+  return d;
+}
+
+// Per-row work (smallest participating set) and its exclusive scan.
+uint64_t depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs& a, DBuf<uint64_t>& W,
+                    DBuf<uint8_t>& drv, hipStream_t s) {
+  const auto& parts = p->parts[d];
+  WorkArgs wa{};
+  wa.np = (uint32_t)parts.size();
+  a.np = wa.np;
+  for (uint32_t i = 0; i < wa.np; i++) {
+    wa.set[i] = make_dset(p, parts[i], F);
+    a.set[i] = wa.set[i];
+  }
+  DBuf<uint32_t> work(F.n, s);
+  drv.alloc(F.n, s);
+  W.alloc(F.n + 1, s);
+  {
+    ProfScope ps("join_work", s, F.n, 0);
+    k_work<<<grid_for(F.n), 256, 0, s>>>(wa, F.n, work.p, drv.p);
+  }
+  LH_HIP(hipGetLastError());
+  uint64_t total = scan_u32_to_u64(work.p, W.p, F.n, s);
+  a.W = W.p;
+  a.drv = drv.p;
+  a.nrows = F.n;
+  a.total = total;
+  return total;
+}
+
+bool binds_by(const lh_plan_t* p, uint32_t atom, uint32_t d) {
+  const PlanAtom& A = p->atoms[atom];
+  for (uint32_t l = 0; l < A.n_levels; l++)
+    if (p->depth_of[A.attr_of_level[l]] <= d) return true;
+  return false;
+}
+
+void step(const lh_plan_t* p, uint32_t d, Frontier& F, hipStream_t s) {
+  ElemArgs a{};
+  DBuf<uint64_t> W;
+  DBuf<uint8_t> drv;
+  uint64_t total = depth_work(p, d, F, a, W, drv, s);
+  if (total == 0) {
+    F.n = 0;
+    return;
+  }
+  const uint64_t nblk = (total + J_CH - 1) / J_CH;
+  if (nblk >= (1ull << 31)) fail(LH_ERR_OVERFLOW, "join: too much work at one attribute");
+  DBuf<uint32_t> bcnt(nblk, s);
+  a.blk_cnt = bcnt.p;
+  a.need_pos_mask = 0;
+  {
+    ProfScope ps("join_count", s, F.n, total);
+    k_elem<M_COUNT><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+  }
+  LH_HIP(hipGetLastError());
+  DBuf<uint64_t> boff(nblk + 1, s);
+  const uint64_t n_new = scan_u32_to_u64(bcnt.p, boff.p, nblk, s);
+  if (n_new >= (1ull << 32)) fail(LH_ERR_OVERFLOW, "join: frontier exceeds 2^32 rows");
+  Frontier G;
+  G.n = n_new;
+  const uint32_t na = (uint32_t)p->atoms.size();
+  G.pos.resize(na);
+  a.n_atoms = na;
+  for (uint32_t e = 0; e < na; e++) {
+    a.part_of_atom[e] = -1;
+    a.pos_in[e] = F.pos[e].p;
+    if (binds_by(p, e, d)) {
+      G.pos[e].alloc(n_new, s);
+      a.pos_out[e] = G.pos[e].p;
+    }
+  }
+  for (uint32_t i = 0; i < p->parts[d].size(); i++) a.part_of_atom[p->parts[d][i].atom] = (int32_t)i;
+  const uint32_t no = (uint32_t)p->out_attrs.size();
+  G.outv.resize(no);
+  a.n_outv = no;
+  a.new_outv = -1;
+  for (uint32_t j = 0; j < no; j++) {
+    a.outv_in[j] = F.outv[j].p;
+    const uint32_t dj = p->depth_of[p->out_attrs[j]];
+    if (dj <= d) {
+      G.outv[j].alloc(n_new, s);
+      a.outv_out[j] = G.outv[j].p;
+      if (dj == d) a.new_outv = (int32_t)j;
+    }
+  }
+  a.gid_mode = 0;
+  if (p->case_prefix && no > 0) {
+    if (d == no - 1) a.gid_mode = 2;
+    else if (d > no - 1) a.gid_mode = 1;
+  }
+  if (a.gid_mode) {
+    G.gid.alloc(n_new, s);
+    a.gid_out = G.gid.p;
+    a.gid_in = F.gid.p;
+  }
+  a.blk_off = boff.p;
+  a.need_pos_mask = 0xffu;
+  {
+    ProfScope ps("join_fill", s, F.n, total);
+    k_elem<M_FILL><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+  }
+  LH_HIP(hipGetLastError());
+  F = std::move(G);
+}
+
+}  // namespace
+
+lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
+  std::unique_ptr<lh_result_impl> res(new lh_result_impl());
+  memset(&res->pub, 0, sizeof(res->pub));
+  const uint32_t na = (uint32_t)p->atoms.size();
+  const uint32_t no = (uint32_t)p->out_attrs.size();
+  const uint32_t ngc = (uint32_t)p->groups.size();
+  const uint32_t n_cols = no + ngc;
+  const uint32_t leaf = p->n_attrs - 1;
+  const bool is_sum = p->agg == LH_AGG_SUM;
+  const uint32_t D = p->exact_digits;
+
+  Frontier F;
+  F.pos.resize(na);
+  F.outv.resize(no);
+  // keep the group-defining frontier's output columns (streamed groups)
+  std::vector<DBuf<uint32_t>> group_keys;
+  uint64_t n_groups = 1;
+  for (uint32_t d = 0; d < leaf && F.n; d++) {
+    step(p, d, F, s);
+    if (p->case_prefix && no > 0 && d == no - 1) {
+      n_groups = F.n;
+      group_keys.clear();
+      for (uint32_t j = 0; j < no; j++) {
+        group_keys.emplace_back(F.n, s);
+        if (F.n)
+          LH_HIP(hipMemcpyAsync(group_keys.back().p, F.outv[j].p, F.n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+      }
+    }
+  }
+  if (p->case_prefix && no > 0 && F.n == 0 && group_keys.empty()) n_groups = 0;
+
+  DBuf<uint32_t> err(1, s);
+  LH_HIP(hipMemsetAsync(err.p, 0, sizeof(uint32_t), s));
+
+  // leaf attribute: intersect and aggregate
+  ElemArgs a{};
+  DBuf<uint64_t> W;
+  DBuf<uint8_t> drv;
+  uint64_t total = F.n ? depth_work(p, leaf, F, a, W, drv, s) : 0;
+  const uint64_t nblk = (total + J_CH - 1) / J_CH;
+  if (nblk >= (1ull << 31)) fail(LH_ERR_OVERFLOW, "join: too much work at the last attribute");
+  LeafArgs& L = a.leaf;
+  L.n_atoms = na;
+  L.sum = is_sum ? 1u : 0u;
+  L.lsb = p->exact_lsb;
+  L.D = D;
+  L.err = err.p;
+  a.n_atoms = na;
+  a.n_outv = no;
+  for (uint32_t j = 0; j < no; j++) a.outv_in[j] = F.outv[j].p;
+  uint32_t need = 0;
+  for (uint32_t e = 0; e < na; e++) {
+    const PlanAtom& A = p->atoms[e];
+    LeafAtom& LA = L.at[e];
+    LA.part = -1;
+    for (uint32_t i = 0; i < p->parts[leaf].size(); i++)
+      if (p->parts[leaf][i].atom == e) LA.part = (int32_t)i;
+    LA.pos = F.pos[e].p;
+    LA.run = A.bag ? A.trie->lv[A.n_levels - 1].offs.p : nullptr;
+    LA.anno = (is_sum && A.anno >= 0) ? A.trie->annos[A.anno].p : nullptr;
+    LA.gmeta = nullptr;
+    LA.gcol = -1;
+    for (uint32_t g = 0; g < ngc; g++)
+      if (p->groups[g].atom == e) {
+        LA.gmeta = A.trie->meta[p->groups[g].meta_col].p;
+        LA.gcol = (int32_t)(no + g);
+      }
+    LA.expand = (LA.anno || LA.gmeta) ? 1u : 0u;
+    if (LA.part >= 0 && (A.bag || LA.expand)) need |= 1u << LA.part;
+  }
+  a.need_pos_mask = need;
+
+  lh_result& R = res->pub;
+  R.n_cols = n_cols;
+  R.exact = is_sum ? 1u : 0u;
+
+  if (p->case_prefix) {
+    // streamed groups: one accumulator per group of the output prefix
+    DBuf<uint64_t> gcount(n_groups ? n_groups : 1, s);
+    DBuf<int64_t> gacc(is_sum ? (n_groups ? n_groups : 1) * EXACT_MAXD : 0, s);
+    LH_HIP(hipMemsetAsync(gcount.p, 0, gcount.n * sizeof(uint64_t), s));
+    if (is_sum) LH_HIP(hipMemsetAsync(gacc.p, 0, gacc.n * sizeof(int64_t), s));
+    L.gid = no > 0 ? F.gid.p : nullptr;
+    L.gcount = gcount.p;
+    L.gacc = gacc.p;
+    if (total) {
+      ProfScope ps("leaf_aggregate", s, F.n, total);
+      k_elem<M_LEAF_A><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+      LH_HIP(hipGetLastError());
+    }
+    FinA f{};
+    f.gcount = gcount.p;
+    f.gacc = gacc.p;
+    f.sum = L.sum;
+    f.lsb = L.lsb;
+    f.D = D;
+    f.err = err.p;
+    uint64_t n_out_rows;
+    DBuf<uint64_t> off;
+    if (no == 0) {
+      n_out_rows = 1;
+    } else {
+      DBuf<uint32_t> flags(n_groups, s);
+      off.alloc(n_groups + 1, s);
+      if (n_groups) {
+        k_nonzero_flags<<<grid_for(n_groups), 256, 0, s>>>(gcount.p, n_groups, flags.p);
+        LH_HIP(hipGetLastError());
+      }
+      n_out_rows = scan_u32_to_u64(flags.p, off.p, n_groups, s);
+      f.off = off.p;
+    }
+    f.n_cols = no;
+    res->cols.resize(no);
+    for (uint32_t c = 0; c < no; c++) {
+      res->cols[c].alloc(n_out_rows, s);
+      f.key_in[c] = c < group_keys.size() ? group_keys[c].p : nullptr;
+      f.key_out[c] = res->cols[c].p;
+    }
+    res->counts.alloc(n_out_rows, s);
+    if (is_sum) res->sums.alloc(n_out_rows, s);
+    f.count_out = res->counts.p;
+    f.sum_out = res->sums.p;
+    const uint64_t nfin = no == 0 ? 1 : (group_keys.empty() ? 0 : n_groups);
+    if (nfin) {
+      k_finalize_groups<<<grid_for(nfin), 256, 0, s>>>(f, nfin);
+      LH_HIP(hipGetLastError());
+    }
+    R.n_rows = n_out_rows;
+  } else {
+    // materialize leaf tuples keyed by the output columns, sort, reduce
+    uint64_t n_emit = 0;
+    DBuf<uint64_t> boff;
+    if (total) {
+      DBuf<uint32_t> bcnt(nblk, s);
+      a.blk_cnt = bcnt.p;
+      {
+        ProfScope ps("leaf_emit_count", s, F.n, total);
+        k_elem<M_LEAF_B_COUNT><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+      }
+      LH_HIP(hipGetLastError());
+      boff.alloc(nblk + 1, s);
+      n_emit = scan_u32_to_u64(bcnt.p, boff.p, nblk, s);
+    }
+    if (n_emit >= (1ull << 32) - 1) fail(LH_ERR_OVERFLOW, "join: more than 2^32 output tuples to group");
+    std::vector<DBuf<uint32_t>> cols(n_cols);
+    DBuf<uint64_t> mult(n_emit, s);
+    DBuf<double> hi(is_sum ? n_emit : 0, s), lo(is_sum ? n_emit : 0, s);
+    L.n_cols = n_cols;
+    for (uint32_t c = 0; c < n_cols; c++) {
+      cols[c].alloc(n_emit, s);
+      L.col_out[c] = cols[c].p;
+      if (c < no) {
+        const uint32_t attr = p->out_attrs[c];
+        L.col_src[c] = (p->depth_of[attr] == leaf) ? -1 : (int32_t)c;
+      } else {
+        L.col_src[c] = -2;
+      }
+    }
+    L.mult_out = mult.p;
+    L.hi_out = hi.p;
+    L.lo_out = lo.p;
+    if (n_emit) {
+      a.blk_off = boff.p;
+      ProfScope ps("leaf_emit_fill", s, F.n, total);
+      k_elem<M_LEAF_B_FILL><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+      LH_HIP(hipGetLastError());
+    }
+    // sort tuples by the output columns
+    std::vector<const uint32_t*> cptr(n_cols);
+    std::vector<uint32_t> bits(n_cols);
+    for (uint32_t c = 0; c < n_cols; c++) {
+      cptr[c] = cols[c].p;
+      bits[c] = bitlen(n_emit ? reduce_max_u32(cols[c].p, n_emit, s) : 0);
+    }
+    DBuf<uint32_t> perm(n_emit, s);
+    lex_sort_perm(cptr.data(), bits.data(), n_cols, n_emit, perm.p, s);
+    ColsArg ca{};
+    ca.n = n_cols;
+    for (uint32_t c = 0; c < n_cols; c++) ca.c[c] = cols[c].p;
+    DBuf<uint32_t> head(n_emit, s);
+    DBuf<uint64_t> segoff(n_emit + 1, s);
+    uint64_t n_seg = 0;
+    if (n_emit) {
+      k_seg_heads<<<grid_for(n_emit), 256, 0, s>>>(ca, perm.p, n_emit, head.p);
+      LH_HIP(hipGetLastError());
+      n_seg = scan_u32_to_u64(head.p, segoff.p, n_emit, s);
+    }
+    // segoff is exclusive; segment of i = (inclusive count) - 1 = segoff[i+1]-1
+    DBuf<uint64_t> gcount(n_seg ? n_seg : 1, s);
+    DBuf<int64_t> gacc(is_sum ? (n_seg ? n_seg : 1) * EXACT_MAXD : 0, s);
+    LH_HIP(hipMemsetAsync(gcount.p, 0, gcount.n * sizeof(uint64_t), s));
+    if (is_sum) LH_HIP(hipMemsetAsync(gacc.p, 0, gacc.n * sizeof(int64_t), s));
+    std::vector<DBuf<uint32_t>> segkeys(n_cols);
+    SegAccArgs sa{};
+    sa.cols = ca;
+    sa.perm = perm.p;
+    sa.segoff = segoff.p;
+    sa.mult = mult.p;
+    sa.hi = hi.p;
+    sa.lo = lo.p;
+    sa.sum = L.sum;
+    sa.lsb = L.lsb;
+    sa.D = D;
+    sa.gcount = gcount.p;
+    sa.gacc = gacc.p;
+    sa.err = err.p;
+    for (uint32_t c = 0; c < n_cols; c++) {
+      segkeys[c].alloc(n_seg, s);
+      sa.key_out[c] = segkeys[c].p;
+    }
+    if (n_emit) {
+      k_seg_accumulate<<<grid_for(n_emit), 256, 0, s>>>(sa, n_emit);
+      LH_HIP(hipGetLastError());
+    }
+    FinA f{};
+    f.gcount = gcount.p;
+    f.gacc = gacc.p;
+    f.sum = L.sum;
+    f.lsb = L.lsb;
+    f.D = D;
+    f.err = err.p;
+    f.n_cols = n_cols;
+    res->cols.resize(n_cols);
+    for (uint32_t c = 0; c < n_cols; c++) {
+      res->cols[c].alloc(n_seg, s);
+      f.key_in[c] = segkeys[c].p;
+      f.key_out[c] = res->cols[c].p;
+    }
+    res->counts.alloc(n_seg, s);
+    if (is_sum) res->sums.alloc(n_seg, s);
+    f.count_out = res->counts.p;
+    f.sum_out = res->sums.p;
+    if (n_seg) {
+      k_finalize_groups<<<grid_for(n_seg), 256, 0, s>>>(f, n_seg);
+      LH_HIP(hipGetLastError());
+    }
+    R.n_rows = n_seg;
+  }
+  if (read_scalar(err.p, s)) fail(LH_ERR_UNSUPPORTED, "an annotation product did not fit the exact accumulator");
+
+  // total contributing tuples
+  res->colptr.resize(n_cols);
+  for (uint32_t c = 0; c < n_cols; c++) res->colptr[c] = res->cols[c].p;
+  R.out_keys = n_cols ? res->colptr.data() : nullptr;
+  R.counts = res->counts.p;
+  R.sums = is_sum ? res->sums.p : nullptr;
+  uint64_t nj = 0;
+  if (R.n_rows) {
+    DBuf<uint64_t> tmp(R.n_rows + 1, s);
+    nj = scan_u64(res->counts.p, tmp.p, R.n_rows, s);
+  }
+  R.n_join_tuples = nj;
+  LH_HIP(hipStreamSynchronize(s));
+  return res.release();
+}
+
+}  // namespace lh

@@ -1,0 +1,186 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lh.h"
+
+namespace lh {
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws lh::Error; the C ABI turns it into lh_status.
+// ---------------------------------------------------------------------------
+struct Error {
+  lh_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(lh_status st, const std::string& msg);
+
+#define LH_HIP(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) ::lh::hip_fail(e_, #expr, __FILE__, __LINE__);          \
+  } while (0)
+
+[[noreturn]] void hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+// ---------------------------------------------------------------------------
+// Device memory: stream-ordered allocations from the device's default pool.
+// ---------------------------------------------------------------------------
+void* dalloc(size_t bytes, hipStream_t s);
+void dfree(void* p, hipStream_t s);
+long live_allocations();
+
+template <class T>
+struct DBuf {  // owning device buffer, freed on the stream it was made on
+  T* p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  DBuf() = default;
+  DBuf(size_t count, hipStream_t st) { alloc(count, st); }
+  void alloc(size_t count, hipStream_t st) {
+    reset();
+    s = st;
+    n = count;
+    p = count ? static_cast<T*>(dalloc(count * sizeof(T), st)) : nullptr;
+  }
+  void reset() {
+    if (p) dfree(p, s);
+    p = nullptr;
+    n = 0;
+  }
+  T* release() {
+    T* q = p;
+    p = nullptr;
+    n = 0;
+    return q;
+  }
+  ~DBuf() { reset(); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+};
+
+template <class T>
+T read_scalar(const T* dptr, hipStream_t s) {
+  T v{};
+  LH_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  LH_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Primitives (prims.hip)
+// ---------------------------------------------------------------------------
+// Exclusive scan of n uint32 values into n+1 uint64 offsets (out[n] = total).
+uint64_t scan_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, hipStream_t s);
+// Exclusive scan of n uint64 values into n+1 uint64 offsets; returns total.
+uint64_t scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s);
+// Exclusive scan, uint32 -> uint32 (caller guarantees the total fits); out has n+1.
+uint32_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s);
+uint32_t reduce_max_u32(const uint32_t* in, uint64_t n, hipStream_t s);
+// Indices i < n with flags[i] != 0, in order, into out (n entries); returns count.
+uint64_t select_flagged(const uint32_t* flags, uint64_t n, uint32_t* out, hipStream_t s);
+void iota_u32(uint32_t* out, uint64_t n, hipStream_t s);
+void fill_u32(uint32_t* out, uint32_t v, uint64_t n, hipStream_t s);
+void fill_u64(uint64_t* out, uint64_t v, uint64_t n, hipStream_t s);
+void gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, uint64_t n, hipStream_t s);
+void gather_f64(const double* src, const uint32_t* idx, double* dst, uint64_t n, hipStream_t s);
+
+// Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
+// Sorted pairs end in (keys, vals); tmp buffers must hold n entries each.
+void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals,
+                      uint64_t n, uint32_t bits, hipStream_t s);
+
+// Permutation that sorts rows lexicographically by cols[0], cols[1], ...
+// (stable); bits[c] = significant bits of column c.  perm receives n ids.
+void lex_sort_perm(const uint32_t* const* cols, const uint32_t* bits, uint32_t ncols,
+                   uint64_t n, uint32_t* perm, hipStream_t s);
+
+// Exponent of the lowest set bit over the non-zero finite values (INT32_MAX
+// if none), the largest |v| and whether any value is non-finite.
+struct AnnoStats {
+  int32_t qmin;
+  double maxabs;
+  uint32_t nonfinite;
+};
+AnnoStats anno_stats(const double* v, uint64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Tries (trie.hip)
+// ---------------------------------------------------------------------------
+struct Level {
+  uint64_t n = 0;            // nodes
+  DBuf<uint32_t> keys;       // n
+  DBuf<uint32_t> offs;       // n+1: children in the next level; last level: run offsets
+  uint64_t n_sets = 0;       // sets at this level (1 at level 0, else nodes of level-1)
+  DBuf<uint64_t> bs_word;    // n_sets: first word in pool, UINT64_MAX = uint layout
+  DBuf<uint32_t> bs_base;    // n_sets: value of bit 0 (multiple of 64)
+  DBuf<uint64_t> pool;       // bitset words
+  uint64_t pool_words = 0;
+  uint64_t n_bitsets = 0;
+};
+
+}  // namespace lh
+
+struct lh_trie {
+  uint32_t magic;
+  uint32_t n_levels = 0;
+  uint32_t flags = 0;
+  uint64_t n_input = 0;      // input rows
+  uint64_t n_rows = 0;       // rows kept (bag: all; set: distinct)
+  uint32_t level_order[LH_MAX_KEYS];   // input key column of each level
+  uint32_t key_bits[LH_MAX_KEYS];      // significant bits per level
+  uint32_t key_max[LH_MAX_KEYS];       // largest key per level
+  lh::Level lv[LH_MAX_KEYS];
+  // rows in trie order (bag: every row; set: one per distinct tuple)
+  lh::DBuf<uint32_t> skeys[LH_MAX_KEYS];   // per level
+  std::vector<lh::DBuf<double>> annos;      // per annotation column
+  std::vector<lh::DBuf<uint32_t>> meta;     // per meta column
+  std::vector<lh::AnnoStats> astats;
+};
+
+namespace lh {
+
+constexpr uint32_t TRIE_MAGIC = 0x54524945u;
+constexpr uint32_t PLAN_MAGIC = 0x504c414eu;
+constexpr uint32_t RESULT_MAGIC = 0x52534c54u;
+
+// Build from device columns, optionally restricted to the rows listed in
+// `sel` (n_sel entries).  Columns are in the relation's own column order;
+// level_order maps levels to key columns.
+lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* keys,
+                    uint32_t n_annos, const double* const* annos, uint32_t n_meta,
+                    const uint32_t* const* meta, const uint32_t* level_order, uint32_t flags,
+                    const uint32_t* sel, uint64_t n_sel, hipStream_t s);
+
+// Per-set layout and bitset materialization for one level.
+void build_layouts(lh_trie* t, uint32_t level, uint32_t layout_flags, hipStream_t s);
+
+}  // namespace lh
+
+namespace lh {
+
+// ---------------------------------------------------------------------------
+// Opt-in kernel timing (hipEvent pairs on the launching stream).
+// ---------------------------------------------------------------------------
+bool prof_enabled();
+struct ProfScope {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  uint64_t rows, elems;
+  ProfScope(const char* n, hipStream_t st, uint64_t r = 0, uint64_t el = 0);
+  ~ProfScope();
+};
+
+}  // namespace lh

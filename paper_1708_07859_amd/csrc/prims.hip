@@ -1,0 +1,399 @@
+// Device-wide primitives: scans, reductions, fills, gathers, LSD radix sort.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+
+#include "device_common.h"
+#include "lh_internal.h"
+
+namespace lh {
+
+namespace {
+
+constexpr int SC_NT = 256;
+constexpr int SC_ITEMS = 8;
+constexpr int SC_TILE = SC_NT * SC_ITEMS;
+
+inline unsigned blocks_for(uint64_t n, uint64_t per) { return (unsigned)((n + per - 1) / per); }
+
+// Per-tile sums of the input.
+template <class TI, class TO>
+__global__ __launch_bounds__(SC_NT) void k_tile_sums(const TI* in, uint64_t n, TO* sums) {
+  __shared__ TO lds[SC_NT / WAVE];
+  uint64_t base = (uint64_t)blockIdx.x * SC_TILE;
+  TO s = 0;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; i++) {
+    uint64_t idx = base + (uint64_t)i * SC_NT + threadIdx.x;
+    if (idx < n) s += (TO)in[idx];
+  }
+  TO tot = block_sum<TO, SC_NT>(s, lds);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan of each tile plus its tile offset; thread t owns
+// SC_ITEMS consecutive elements.
+template <class TI, class TO>
+__global__ __launch_bounds__(SC_NT) void k_tile_scan(const TI* in, uint64_t n, const TO* tile_off, TO* out) {
+  __shared__ TO lds[SC_NT / WAVE];
+  __shared__ TI stage[SC_TILE];
+  uint64_t base = (uint64_t)blockIdx.x * SC_TILE;
+  // coalesced load into LDS
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; i++) {
+    uint64_t idx = base + (uint64_t)i * SC_NT + threadIdx.x;
+    stage[i * SC_NT + threadIdx.x] = idx < n ? in[idx] : (TI)0;
+  }
+  __syncthreads();
+  TO v[SC_ITEMS];
+  TO s = 0;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; i++) {
+    v[i] = (TO)stage[threadIdx.x * SC_ITEMS + i];
+    s += v[i];
+  }
+  TO tot;
+  TO run = block_excl_scan<TO, SC_NT>(s, lds, tot) + tile_off[blockIdx.x];
+  __syncthreads();
+  // write back through LDS as TO (reuse needs a separate buffer for 64-bit)
+  __shared__ TO ostage[SC_TILE];
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; i++) {
+    ostage[threadIdx.x * SC_ITEMS + i] = run;
+    run += v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; i++) {
+    uint64_t idx = base + (uint64_t)i * SC_NT + threadIdx.x;
+    if (idx < n) out[idx] = ostage[i * SC_NT + threadIdx.x];
+  }
+}
+
+template <class TO>
+__global__ void k_set_total(TO* out, uint64_t n, const TO* tile_off, const TO* tile_sums, uint64_t ntiles) {
+  out[n] = tile_off[ntiles - 1] + tile_sums[ntiles - 1];
+}
+
+template <class TI, class TO>
+TO scan_impl(const TI* in, TO* out, uint64_t n, hipStream_t s) {
+  if (n == 0) {
+    LH_HIP(hipMemsetAsync(out, 0, sizeof(TO), s));
+    return 0;
+  }
+  uint64_t ntiles = (n + SC_TILE - 1) / SC_TILE;
+  DBuf<TO> sums(ntiles, s), offs(ntiles + 1, s);
+  k_tile_sums<TI, TO><<<(unsigned)ntiles, SC_NT, 0, s>>>(in, n, sums.p);
+  LH_HIP(hipGetLastError());
+  if (ntiles == 1) {
+    LH_HIP(hipMemsetAsync(offs.p, 0, sizeof(TO), s));
+  } else {
+    scan_impl<TO, TO>(sums.p, offs.p, ntiles, s);
+  }
+  k_tile_scan<TI, TO><<<(unsigned)ntiles, SC_NT, 0, s>>>(in, n, offs.p, out);
+  LH_HIP(hipGetLastError());
+  k_set_total<TO><<<1, 1, 0, s>>>(out, n, offs.p, sums.p, ntiles);
+  LH_HIP(hipGetLastError());
+  return read_scalar(out + n, s);
+}
+
+__global__ void k_reduce_max_u32(const uint32_t* in, uint64_t n, uint32_t* out) {
+  uint32_t m = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    m = max(m, in[i]);
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, WAVE));
+  if (lane_id() == 0) atomicMax(out, m);
+}
+
+__global__ void k_iota(uint32_t* out, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = (uint32_t)i;
+}
+
+template <class T>
+__global__ void k_fill(T* out, T v, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = v;
+}
+
+template <class T>
+__global__ void k_gather(const T* src, const uint32_t* idx, T* dst, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[idx[i]];
+}
+
+__global__ void k_scatter_flagged(const uint32_t* flags, const uint64_t* off, uint64_t n, uint32_t* out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    if (flags[i]) out[off[i]] = (uint32_t)i;
+}
+
+unsigned grid_for(uint64_t n) {
+  uint64_t b = (n + 255) / 256;
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(b, 256 * 64));
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort, 8-bit digits.  Per pass: tile histograms (digit-major, so
+// an exclusive scan yields every tile's first slot per digit), then a
+// stable scatter that ranks equal digits inside a wave with eight ballots
+// and across the block's waves through LDS.
+// ---------------------------------------------------------------------------
+constexpr int RS_NT = 256;
+constexpr int RS_ITEMS = 8;
+constexpr int RS_TILE = RS_NT * RS_ITEMS;
+constexpr int RS_NW = RS_NT / WAVE;
+
+__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, uint64_t n, uint32_t shift,
+                                                   uint32_t* hist, uint32_t ntiles) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; i++) {
+    uint64_t idx = base + (uint64_t)i * RS_NT + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                      uint32_t* vout, uint64_t n, uint32_t shift,
+                                                      const uint32_t* offs, uint32_t ntiles) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[RS_NW][256];
+  const int tid = threadIdx.x, w = tid / WAVE;
+  run[tid] = offs[(uint64_t)tid * ntiles + blockIdx.x];
+  uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+  for (int i = 0; i < RS_ITEMS; i++) {
+#pragma unroll
+    for (int j = 0; j < RS_NW; j++) wcnt[j][tid] = 0;
+    __syncthreads();
+    uint64_t idx = base + (uint64_t)i * RS_NT + tid;
+    bool valid = idx < n;
+    uint64_t k = valid ? kin[idx] : 0;
+    uint32_t v = valid ? vin[idx] : 0;
+    uint32_t d = (uint32_t)(k >> shift) & 255u;
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      bool bit = (d >> b) & 1u;
+      uint64_t m = ballot(valid && bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t rank = lanes_below(peers);
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = 0;
+      for (int j = 0; j < w; j++) pre += wcnt[j][d];
+      uint32_t pos = run[d] + pre + rank;
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int j = 0; j < RS_NW; j++) add += wcnt[j][tid];
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+struct PackArgs {
+  const uint32_t* col[LH_MAX_KEYS];
+  uint32_t shift[LH_MAX_KEYS];
+  uint32_t ncols;
+};
+
+__global__ void k_pack(PackArgs a, const uint32_t* perm, uint64_t* out, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t r = perm[i];
+    uint64_t k = 0;
+    for (uint32_t c = 0; c < a.ncols; c++) k |= (uint64_t)a.col[c][r] << a.shift[c];
+    out[i] = k;
+  }
+}
+
+__device__ __forceinline__ int32_t lowest_bit_exp(double v) {
+  uint64_t b = (uint64_t)__double_as_longlong(v);
+  uint32_t ex = (uint32_t)(b >> 52) & 0x7ffu;
+  uint64_t mant = b & ((1ull << 52) - 1);
+  if (ex == 0) return -1074 + (int32_t)__builtin_ctzll(mant);
+  mant |= 1ull << 52;
+  return (int32_t)ex - 1075 + (int32_t)__builtin_ctzll(mant);
+}
+
+__global__ void k_anno_stats(const double* v, uint64_t n, int32_t* qmin, unsigned long long* maxabs, uint32_t* nonfinite) {
+  int32_t q = INT_MAX;
+  uint64_t m = 0;
+  uint32_t bad = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    double x = v[i];
+    if (!isfinite(x)) { bad = 1; continue; }
+    if (x == 0.0) continue;
+    q = min(q, lowest_bit_exp(x));
+    uint64_t ab = (uint64_t)__double_as_longlong(fabs(x));
+    m = max(m, ab);
+  }
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) {
+    q = min(q, __shfl_xor(q, d, WAVE));
+    m = max(m, (uint64_t)__shfl_xor((unsigned long long)m, d, WAVE));
+    bad |= (uint32_t)__shfl_xor((int)bad, d, WAVE);
+  }
+  if (lane_id() == 0) {
+    atomicMin(qmin, q);
+    atomicMax(maxabs, (unsigned long long)m);
+    if (bad) atomicOr(nonfinite, 1u);
+  }
+}
+
+}  // namespace
+
+uint64_t scan_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
+  return scan_impl<uint32_t, uint64_t>(in, out, n, s);
+}
+uint64_t scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
+  return scan_impl<uint64_t, uint64_t>(in, out, n, s);
+}
+uint32_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s) {
+  return scan_impl<uint32_t, uint32_t>(in, out, n, s);
+}
+
+uint32_t reduce_max_u32(const uint32_t* in, uint64_t n, hipStream_t s) {
+  DBuf<uint32_t> r(1, s);
+  LH_HIP(hipMemsetAsync(r.p, 0, sizeof(uint32_t), s));
+  if (n) {
+    k_reduce_max_u32<<<grid_for(n), 256, 0, s>>>(in, n, r.p);
+    LH_HIP(hipGetLastError());
+  }
+  return read_scalar(r.p, s);
+}
+
+uint64_t select_flagged(const uint32_t* flags, uint64_t n, uint32_t* out, hipStream_t s) {
+  DBuf<uint64_t> off(n + 1, s);
+  uint64_t m = scan_u32_to_u64(flags, off.p, n, s);
+  if (m) {
+    k_scatter_flagged<<<grid_for(n), 256, 0, s>>>(flags, off.p, n, out);
+    LH_HIP(hipGetLastError());
+  }
+  return m;
+}
+
+void iota_u32(uint32_t* out, uint64_t n, hipStream_t s) {
+  if (!n) return;
+  k_iota<<<grid_for(n), 256, 0, s>>>(out, n);
+  LH_HIP(hipGetLastError());
+}
+void fill_u32(uint32_t* out, uint32_t v, uint64_t n, hipStream_t s) {
+  if (!n) return;
+  k_fill<uint32_t><<<grid_for(n), 256, 0, s>>>(out, v, n);
+  LH_HIP(hipGetLastError());
+}
+void fill_u64(uint64_t* out, uint64_t v, uint64_t n, hipStream_t s) {
+  if (!n) return;
+  k_fill<uint64_t><<<grid_for(n), 256, 0, s>>>(out, v, n);
+  LH_HIP(hipGetLastError());
+}
+void gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, uint64_t n, hipStream_t s) {
+  if (!n) return;
+  k_gather<uint32_t><<<grid_for(n), 256, 0, s>>>(src, idx, dst, n);
+  LH_HIP(hipGetLastError());
+}
+void gather_f64(const double* src, const uint32_t* idx, double* dst, uint64_t n, hipStream_t s) {
+  if (!n) return;
+  k_gather<double><<<grid_for(n), 256, 0, s>>>(src, idx, dst, n);
+  LH_HIP(hipGetLastError());
+}
+
+void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, uint64_t n,
+                      uint32_t bits, hipStream_t s) {
+  if (n <= 1 || bits == 0) return;
+  if (n >= (1ull << 32)) fail(LH_ERR_OVERFLOW, "radix sort: more than 2^32 - 1 keys");
+  uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
+  uint64_t hn = (uint64_t)ntiles * 256;
+  DBuf<uint32_t> hist(hn, s), offs(hn + 1, s);
+  uint64_t* ki = keys;
+  uint32_t* vi = vals;
+  uint64_t* ko = tkeys;
+  uint32_t* vo = tvals;
+  uint32_t passes = (bits + 7) / 8;
+  for (uint32_t p = 0; p < passes; p++) {
+    uint32_t shift = p * 8;
+    {
+      ProfScope ps("sort_hist", s, n, 0);
+      k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ki, n, shift, hist.p, ntiles);
+    }
+    LH_HIP(hipGetLastError());
+    scan_u32(hist.p, offs.p, hn, s);
+    {
+      ProfScope ps("sort_scatter", s, n, 0);
+      k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, offs.p, ntiles);
+    }
+    LH_HIP(hipGetLastError());
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  if (ki != keys) {
+    LH_HIP(hipMemcpyAsync(keys, ki, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    LH_HIP(hipMemcpyAsync(vals, vi, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  }
+}
+
+void lex_sort_perm(const uint32_t* const* cols, const uint32_t* bits, uint32_t ncols, uint64_t n, uint32_t* perm,
+                   hipStream_t s) {
+  iota_u32(perm, n, s);
+  if (n <= 1) return;
+  DBuf<uint64_t> k(n, s), tk(n, s);
+  DBuf<uint32_t> tv(n, s);
+  int end = (int)ncols;
+  while (end > 0) {
+    int start = end - 1;
+    uint32_t tot = bits[start];
+    while (start > 0 && tot + bits[start - 1] <= 64) {
+      start--;
+      tot += bits[start];
+    }
+    if (tot > 0) {
+      PackArgs a{};
+      a.ncols = (uint32_t)(end - start);
+      uint32_t sh = 0;
+      for (int c = end - 1; c >= start; c--) {  // least significant column at the bottom
+        a.col[c - start] = cols[c];
+        a.shift[c - start] = sh;
+        sh += bits[c];
+      }
+      k_pack<<<grid_for(n), 256, 0, s>>>(a, perm, k.p, n);
+      LH_HIP(hipGetLastError());
+      radix_sort_pairs(k.p, perm, tk.p, tv.p, n, tot, s);
+    }
+    end = start;
+  }
+}
+
+AnnoStats anno_stats(const double* v, uint64_t n, hipStream_t s) {
+  DBuf<int32_t> q(1, s);
+  DBuf<unsigned long long> m(1, s);
+  DBuf<uint32_t> bad(1, s);
+  k_fill<int32_t><<<1, 64, 0, s>>>(q.p, INT_MAX, 1);
+  LH_HIP(hipGetLastError());
+  LH_HIP(hipMemsetAsync(m.p, 0, sizeof(unsigned long long), s));
+  LH_HIP(hipMemsetAsync(bad.p, 0, sizeof(uint32_t), s));
+  if (n) {
+    k_anno_stats<<<grid_for(n), 256, 0, s>>>(v, n, q.p, m.p, bad.p);
+    LH_HIP(hipGetLastError());
+  }
+  AnnoStats st;
+  st.qmin = read_scalar(q.p, s);
+  unsigned long long mb = read_scalar(m.p, s);
+  double md;
+  memcpy(&md, &mb, sizeof md);
+  st.maxabs = md;
+  st.nonfinite = read_scalar(bad.p, s);
+  return st;
+}
+
+}  // namespace lh

@@ -1,0 +1,318 @@
+// Trie construction (section 2.2): lexicographic sort of the key tuples in
+// level order, head flags per level, per-level keys and child offsets,
+// set-mode deduplication or bag-mode runs, annotation/meta gathering and the
+// per-set uint/bitset layout.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+
+#include "device_common.h"
+#include "lh_internal.h"
+
+namespace lh {
+
+namespace {
+
+constexpr int TB_NT = 256;  // rows per tile in the level builder
+constexpr int TB_NW = TB_NT / WAVE;
+
+struct LevelCols {
+  const uint32_t* k[LH_MAX_KEYS];  // sorted key column per level
+  uint32_t n_levels;
+};
+
+__device__ __forceinline__ uint32_t head_mask(const LevelCols& c, uint64_t r) {
+  // bit l set when row r starts a new node at level l
+  uint32_t m = 0;
+  bool h = (r == 0);
+  for (uint32_t l = 0; l < c.n_levels; l++) {
+    if (!h) h = c.k[l][r] != c.k[l][r - 1];
+    if (h) m |= 1u << l;
+  }
+  return m;
+}
+
+// Heads per level per tile: counts[l * ntiles + tile].
+__global__ __launch_bounds__(TB_NT) void k_head_counts(LevelCols c, uint64_t n, uint32_t* counts, uint32_t ntiles) {
+  __shared__ uint32_t w_cnt[TB_NW][LH_MAX_KEYS];
+  uint64_t r = (uint64_t)blockIdx.x * TB_NT + threadIdx.x;
+  uint32_t m = r < n ? head_mask(c, r) : 0;
+  const int w = threadIdx.x / WAVE;
+  for (uint32_t l = 0; l < c.n_levels; l++) {
+    uint64_t b = ballot((m >> l) & 1u);
+    if (lane_id() == 0) w_cnt[w][l] = (uint32_t)__popcll(b);
+  }
+  __syncthreads();
+  if (threadIdx.x < c.n_levels) {
+    uint32_t t = 0;
+    for (int j = 0; j < TB_NW; j++) t += w_cnt[j][threadIdx.x];
+    counts[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = t;
+  }
+}
+
+struct EmitArgs {
+  LevelCols c;
+  uint32_t* keys_out[LH_MAX_KEYS];   // level keys
+  uint32_t* offs_out[LH_MAX_KEYS];   // level child offsets (levels 0..L-2)
+  uint32_t* run_out;                 // bag: leaf run starts (sorted-row index); may be null
+  uint32_t* kept_out;                // set: sorted-row index of each kept row; may be null
+  const uint32_t* tile_off;          // [l * ntiles + tile]
+  uint32_t ntiles;
+};
+
+__global__ __launch_bounds__(TB_NT) void k_emit_levels(EmitArgs a, uint64_t n) {
+  __shared__ uint32_t w_cnt[TB_NW][LH_MAX_KEYS];
+  uint64_t r = (uint64_t)blockIdx.x * TB_NT + threadIdx.x;
+  uint32_t m = r < n ? head_mask(a.c, r) : 0;
+  const int w = threadIdx.x / WAVE;
+  uint32_t rank[LH_MAX_KEYS];
+  for (uint32_t l = 0; l < a.c.n_levels; l++) {
+    uint64_t b = ballot((m >> l) & 1u);
+    rank[l] = lanes_below(b);
+    if (lane_id() == 0) w_cnt[w][l] = (uint32_t)__popcll(b);
+  }
+  __syncthreads();
+  if (r >= n) return;
+  const uint32_t L = a.c.n_levels;
+  uint32_t pos_prev = 0;
+  for (uint32_t l = 0; l < L; l++) {
+    if (!((m >> l) & 1u)) continue;
+    uint32_t pre = 0;
+    for (int j = 0; j < w; j++) pre += w_cnt[j][l];
+    uint32_t pos = a.tile_off[(uint64_t)l * a.ntiles + blockIdx.x] + pre + rank[l];
+    a.keys_out[l][pos] = a.c.k[l][r];
+    // a head at level l-1 is also a head at l: its first child is pos
+    if (l > 0 && ((m >> (l - 1)) & 1u)) a.offs_out[l - 1][pos_prev] = pos;
+    if (l + 1 == L) {
+      if (a.run_out) a.run_out[pos] = (uint32_t)r;
+      if (a.kept_out) a.kept_out[pos] = (uint32_t)r;
+    }
+    pos_prev = pos;
+  }
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+// ---- layouts ---------------------------------------------------------------
+
+struct SetRange {
+  const uint32_t* offs;  // parent offsets (null for level 0)
+  uint64_t root_n;       // level-0 size
+};
+
+__device__ __forceinline__ void set_range(const SetRange& sr, uint64_t s, uint32_t& b, uint32_t& e) {
+  if (!sr.offs) { b = 0; e = (uint32_t)sr.root_n; }
+  else { b = sr.offs[s]; e = sr.offs[s + 1]; }
+}
+
+__global__ void k_layout_words(SetRange sr, const uint32_t* keys, uint64_t n_sets, uint32_t mode, uint64_t* words) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_sets; s += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t b, e;
+    set_range(sr, s, b, e);
+    uint64_t nw = 0;
+    if (e > b) {
+      uint32_t lo = keys[b], hi = keys[e - 1];
+      uint64_t card = e - b;
+      uint64_t span = (uint64_t)hi - lo + 1;
+      bool bs = false;
+      if (mode == LH_LAYOUT_PLAIN || mode == LH_LAYOUT_LEARNED) bs = span <= 32ull * card;
+      else if (mode == LH_LAYOUT_BITSET) bs = span <= 4096ull * card;
+      if (bs) nw = (((uint64_t)hi - (lo & ~63u)) >> 6) + 1;
+    }
+    words[s] = nw;
+  }
+}
+
+__global__ void k_layout_desc(SetRange sr, const uint32_t* keys, uint64_t n_sets, const uint64_t* words,
+                              const uint64_t* woff, uint64_t* bs_word, uint32_t* bs_base) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_sets; s += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t b, e;
+    set_range(sr, s, b, e);
+    bool bs = words[s] != 0;
+    bs_word[s] = bs ? woff[s] : UINT64_MAX;
+    bs_base[s] = (e > b) ? (keys[b] & ~63u) : 0u;
+  }
+}
+
+__global__ void k_layout_fill(SetRange sr, const uint32_t* keys, uint64_t n_sets, const uint64_t* woff,
+                              const uint32_t* bs_base, uint64_t* pool, uint64_t n_words) {
+  for (uint64_t wi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < n_words; wi += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t s = upper_bound_minus1<uint64_t>(woff, 0, n_sets, wi);
+    uint32_t b, e;
+    set_range(sr, s, b, e);
+    uint32_t lo = bs_base[s] + (uint32_t)((wi - woff[s]) << 6);
+    uint32_t j = lower_bound_u32(keys, b, e, lo);
+    uint64_t bits = 0;
+    while (j < e && keys[j] - lo < 64u && keys[j] >= lo) {
+      bits |= 1ull << (keys[j] - lo);
+      j++;
+    }
+    pool[wi] = bits;
+  }
+}
+
+unsigned grid_for(uint64_t n) {
+  uint64_t b = (n + 255) / 256;
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(b, 256 * 64));
+}
+
+uint32_t bitlen(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
+
+}  // namespace
+
+void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, hipStream_t s) {
+  Level& L = t->lv[l];
+  L.n_sets = (l == 0) ? 1 : t->lv[l - 1].n;
+  SetRange sr{l == 0 ? nullptr : t->lv[l - 1].offs.p, t->lv[0].n};
+  L.bs_word.alloc(L.n_sets, s);
+  L.bs_base.alloc(L.n_sets, s);
+  if (L.n_sets == 0) return;
+  DBuf<uint64_t> words(L.n_sets, s), woff(L.n_sets + 1, s);
+  k_layout_words<<<grid_for(L.n_sets), 256, 0, s>>>(sr, L.keys.p, L.n_sets, mode, words.p);
+  LH_HIP(hipGetLastError());
+  L.pool_words = scan_u64(words.p, woff.p, L.n_sets, s);
+  k_layout_desc<<<grid_for(L.n_sets), 256, 0, s>>>(sr, L.keys.p, L.n_sets, words.p, woff.p, L.bs_word.p, L.bs_base.p);
+  LH_HIP(hipGetLastError());
+  L.n_bitsets = 0;
+  if (L.pool_words) {
+    L.pool.alloc(L.pool_words, s);
+    k_layout_fill<<<grid_for(L.pool_words), 256, 0, s>>>(sr, L.keys.p, L.n_sets, woff.p, L.bs_base.p, L.pool.p,
+                                                        L.pool_words);
+    LH_HIP(hipGetLastError());
+  }
+}
+
+lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* keys, uint32_t n_annos,
+                    const double* const* annos, uint32_t n_meta, const uint32_t* const* meta,
+                    const uint32_t* level_order, uint32_t flags, const uint32_t* sel, uint64_t n_sel,
+                    hipStream_t s) {
+  const uint64_t n = sel ? n_sel : n_rows;
+  if (n >= (1ull << 32) - 1) fail(LH_ERR_OVERFLOW, "trie build: 2^32 - 1 rows or more");
+  const bool bag = (flags & LH_BAG) != 0;
+  std::unique_ptr<lh_trie> t(new lh_trie());
+  t->magic = TRIE_MAGIC;
+  t->n_levels = n_keys;
+  t->flags = flags;
+  t->n_input = n;
+  for (uint32_t l = 0; l < n_keys; l++) t->level_order[l] = level_order ? level_order[l] : l;
+
+  // Input columns in level order (compacted through `sel` if given).
+  std::vector<DBuf<uint32_t>> selcols;
+  const uint32_t* col[LH_MAX_KEYS];
+  for (uint32_t l = 0; l < n_keys; l++) {
+    const uint32_t* src = keys[t->level_order[l]];
+    if (sel) {
+      selcols.emplace_back(n, s);
+      gather_u32(src, sel, selcols.back().p, n, s);
+      src = selcols.back().p;
+    }
+    col[l] = src;
+    t->key_max[l] = n ? reduce_max_u32(src, n, s) : 0;
+    t->key_bits[l] = bitlen(t->key_max[l]);
+  }
+
+  DBuf<uint32_t> perm(n, s);
+  lex_sort_perm(col, t->key_bits, n_keys, n, perm.p, s);
+
+  LevelCols lc{};
+  lc.n_levels = n_keys;
+  std::vector<DBuf<uint32_t>> sorted;
+  for (uint32_t l = 0; l < n_keys; l++) {
+    sorted.emplace_back(n, s);
+    gather_u32(col[l], perm.p, sorted.back().p, n, s);
+    lc.k[l] = sorted.back().p;
+  }
+
+  uint32_t ntiles = (uint32_t)((n + TB_NT - 1) / TB_NT);
+  uint64_t cn = (uint64_t)ntiles * n_keys;
+  DBuf<uint32_t> counts(cn ? cn : 1, s), toff(cn + 1, s);
+  if (n) {
+    ProfScope ps("trie_head_counts", s, n, 0);
+    k_head_counts<<<ntiles, TB_NT, 0, s>>>(lc, n, counts.p, ntiles);
+    LH_HIP(hipGetLastError());
+  }
+  // scan per level: offsets of level l start at toff[l*ntiles]
+  std::vector<uint64_t> level_n(n_keys, 0);
+  DBuf<uint32_t> tmp(ntiles + 1, s);
+  for (uint32_t l = 0; l < n_keys; l++) {
+    uint64_t tot = n ? scan_u32(counts.p + (uint64_t)l * ntiles, tmp.p, ntiles, s) : 0;
+    if (n) LH_HIP(hipMemcpyAsync(toff.p + (uint64_t)l * ntiles, tmp.p, ntiles * sizeof(uint32_t),
+                                 hipMemcpyDeviceToDevice, s));
+    level_n[l] = tot;
+  }
+  EmitArgs ea{};
+  ea.c = lc;
+  ea.tile_off = toff.p;
+  ea.ntiles = ntiles;
+  for (uint32_t l = 0; l < n_keys; l++) {
+    Level& L = t->lv[l];
+    L.n = level_n[l];
+    L.keys.alloc(L.n, s);
+    ea.keys_out[l] = L.keys.p;
+    if (l + 1 < n_keys) {
+      L.offs.alloc(L.n + 1, s);
+      ea.offs_out[l] = L.offs.p;
+    }
+  }
+  const uint64_t n_leaf = n_keys ? level_n[n_keys - 1] : 0;
+  DBuf<uint32_t> kept;
+  if (bag) {
+    t->lv[n_keys - 1].offs.alloc(n_leaf + 1, s);
+    ea.run_out = t->lv[n_keys - 1].offs.p;
+  } else {
+    kept.alloc(n_leaf, s);
+    ea.kept_out = kept.p;
+  }
+  if (n) {
+    ProfScope ps("trie_emit_levels", s, n, 0);
+    k_emit_levels<<<ntiles, TB_NT, 0, s>>>(ea, n);
+    LH_HIP(hipGetLastError());
+  }
+  // closing offsets: offs_l[n_l] = n_{l+1}; run[n_leaf] = n
+  for (uint32_t l = 0; l + 1 < n_keys; l++) {
+    k_set_u32<<<1, 1, 0, s>>>(t->lv[l].offs.p + t->lv[l].n, (uint32_t)level_n[l + 1]);
+    LH_HIP(hipGetLastError());
+  }
+  if (bag) {
+    k_set_u32<<<1, 1, 0, s>>>(t->lv[n_keys - 1].offs.p + n_leaf, (uint32_t)n);
+    LH_HIP(hipGetLastError());
+  }
+
+  // Rows in trie order: bag keeps every sorted row, set keeps leaf heads.
+  t->n_rows = bag ? n : n_leaf;
+  const uint32_t* rowsel = perm.p;  // sorted position -> input row
+  DBuf<uint32_t> keptrows;
+  if (!bag) {
+    keptrows.alloc(n_leaf, s);
+    gather_u32(perm.p, kept.p, keptrows.p, n_leaf, s);
+    rowsel = keptrows.p;
+  }
+  for (uint32_t l = 0; l < n_keys; l++) {
+    t->skeys[l].alloc(t->n_rows, s);
+    gather_u32(col[l], rowsel, t->skeys[l].p, t->n_rows, s);
+  }
+  // annotation / meta columns (bag relations only); `sel` maps rows first
+  DBuf<uint32_t> srcrow;
+  const uint32_t* rowmap = rowsel;
+  if (sel && (n_annos || n_meta)) {
+    srcrow.alloc(t->n_rows, s);
+    gather_u32(sel, rowsel, srcrow.p, t->n_rows, s);
+    rowmap = srcrow.p;
+  }
+  for (uint32_t a = 0; a < n_annos; a++) {
+    t->annos.emplace_back(t->n_rows, s);
+    gather_f64(annos[a], rowmap, t->annos.back().p, t->n_rows, s);
+    t->astats.push_back(anno_stats(t->annos.back().p, t->n_rows, s));
+  }
+  for (uint32_t m = 0; m < n_meta; m++) {
+    t->meta.emplace_back(t->n_rows, s);
+    gather_u32(meta[m], rowmap, t->meta.back().p, t->n_rows, s);
+  }
+
+  uint32_t mode = flags & LH_LAYOUT_MASK;
+  for (uint32_t l = 0; l < n_keys; l++) build_layouts(t.get(), l, mode, s);
+  LH_HIP(hipStreamSynchronize(s));
+  return t.release();
+}
+
+}  // namespace lh

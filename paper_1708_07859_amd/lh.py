@@ -1,0 +1,459 @@
+"""ctypes binding of the C ABI in include/lh.h (argument marshalling only).
+
+Every step of the join runs in liblh.so's HIP kernels; this module only
+lays out descriptors, hands device pointers across and copies results back.
+torch supplies device memory and the current stream.  If liblh.so is not
+built, importing the binding raises: there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblh.so")
+
+LH_OK, LH_ERR_INVALID, LH_ERR_OOM, LH_ERR_DEVICE, LH_ERR_UNSUPPORTED, LH_ERR_OVERFLOW = range(6)
+LH_SET, LH_BAG = 0x0, 0x1
+LAYOUT = {"plain": 0x00, "uint": 0x10, "bitset": 0x20, "learned": 0x30}
+LH_AGG_COUNT, LH_AGG_SUM = 0, 1
+FILTER_KIND = {"eq_key": 0, "eq_meta": 1, "range_anno": 2, "range_meta": 3}
+POLICY = {"plain": 0, "learned": 1, "fixed": 2}
+LH_MAX_KEYS = 8
+
+
+class RelationDesc(C.Structure):
+    _fields_ = [
+        ("n_rows", C.c_uint64),
+        ("n_keys", C.c_uint32),
+        ("keys", C.POINTER(C.c_void_p)),
+        ("n_annos", C.c_uint32),
+        ("annos", C.POINTER(C.c_void_p)),
+        ("n_meta", C.c_uint32),
+        ("meta", C.POINTER(C.c_void_p)),
+        ("level_order", C.POINTER(C.c_uint32)),
+        ("flags", C.c_uint32),
+    ]
+
+
+class Atom(C.Structure):
+    _fields_ = [("trie", C.c_void_p), ("attr_of_key", C.POINTER(C.c_uint32)), ("anno", C.c_int32)]
+
+
+class Filter(C.Structure):
+    _fields_ = [("atom", C.c_uint32), ("kind", C.c_uint32), ("col", C.c_uint32), ("eq", C.c_uint32),
+                ("lo", C.c_double), ("hi", C.c_double)]
+
+
+class GroupCol(C.Structure):
+    _fields_ = [("atom", C.c_uint32), ("meta_col", C.c_uint32)]
+
+
+class Query(C.Structure):
+    _fields_ = [
+        ("n_attrs", C.c_uint32),
+        ("n_atoms", C.c_uint32),
+        ("atoms", C.POINTER(Atom)),
+        ("n_out", C.c_uint32),
+        ("out_attrs", C.POINTER(C.c_uint32)),
+        ("n_group", C.c_uint32),
+        ("group_cols", C.POINTER(GroupCol)),
+        ("agg", C.c_uint32),
+        ("n_filters", C.c_uint32),
+        ("filters", C.POINTER(Filter)),
+        ("attr_order", C.POINTER(C.c_uint32)),
+        ("policy", C.c_uint32),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("n_rows", C.c_uint64),
+        ("n_cols", C.c_uint32),
+        ("out_keys", C.POINTER(C.c_void_p)),
+        ("counts", C.c_void_p),
+        ("sums", C.c_void_p),
+        ("exact", C.c_uint32),
+        ("n_join_tuples", C.c_uint64),
+    ]
+
+
+class TrieInfo(C.Structure):
+    _fields_ = [
+        ("n_levels", C.c_uint32),
+        ("n_rows", C.c_uint64),
+        ("level_size", C.c_uint64 * LH_MAX_KEYS),
+        ("level_sets", C.c_uint64 * LH_MAX_KEYS),
+        ("level_bitsets", C.c_uint64 * LH_MAX_KEYS),
+        ("level_words", C.c_uint64 * LH_MAX_KEYS),
+        ("level_order", C.c_uint32 * LH_MAX_KEYS),
+    ]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [
+        ("n_attrs", C.c_uint32),
+        ("attr_order", C.c_uint32 * 16),
+        ("cost", C.c_double),
+        ("case_prefix", C.c_uint32),
+        ("exact_digits", C.c_uint32),
+        ("exact_lsb", C.c_int32),
+        ("level_alg", C.c_uint32 * 16),
+    ]
+
+
+class Hypergraph(C.Structure):
+    _fields_ = [
+        ("n_attrs", C.c_uint32),
+        ("n_edges", C.c_uint32),
+        ("edge_attr_count", C.POINTER(C.c_uint32)),
+        ("edge_attrs", C.POINTER(C.c_uint32)),
+        ("edge_card", C.POINTER(C.c_uint64)),
+        ("edge_eq", C.POINTER(C.c_uint32)),
+        ("edge_dense", C.POINTER(C.c_uint32)),
+    ]
+
+
+# Every entry point declared in include/lh.h, with its ctypes signature.
+SIGNATURES = {
+    "lh_trie_build": ([C.POINTER(RelationDesc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "lh_plan": ([C.POINTER(Query), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "lh_join_aggregate": ([C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p, C.POINTER(C.POINTER(Result))], C.c_int),
+    "lh_free": ([C.c_void_p], None),
+    "lh_last_error": ([], C.c_char_p),
+    "lh_trie_get_info": ([C.c_void_p, C.POINTER(TrieInfo)], C.c_int),
+    "lh_trie_read_level": ([C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p], C.c_int),
+    "lh_result_read": ([C.POINTER(Result), C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p], C.c_int),
+    "lh_plan_get_info": ([C.c_void_p, C.POINTER(PlanInfo)], C.c_int),
+    "lh_order_cost": ([C.POINTER(Hypergraph), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                       C.POINTER(C.c_uint32), C.POINTER(C.c_double)], C.c_int),
+    "lh_choose_order": ([C.POINTER(Hypergraph), C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                         C.POINTER(C.c_double)], C.c_int),
+    "lh_live_allocations": ([], C.c_long),
+    "lh_profile_enable": ([C.c_int], None),
+    "lh_profile_reset": ([], None),
+    "lh_profile_read": ([C.c_void_p, C.c_uint32], C.c_uint32),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run paper_1708_07859_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = C.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+class LHError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lh status {status}: {msg}")
+        self.status = status
+
+
+def _check(st):
+    if st != LH_OK:
+        raise LHError(st, lib.lh_last_error().decode())
+
+
+# --------------------------------------------------------------------------
+# device columns
+# --------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_device(a, dtype=None):
+    """numpy array -> contiguous device tensor with the same bytes
+    (uint32 is carried as int32 storage)."""
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        return a.contiguous()
+    a = np.ascontiguousarray(a, dtype=dtype) if dtype is not None else np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to("cuda")
+
+
+def _ptr_array(tensors):
+    arr = (C.c_void_p * max(1, len(tensors)))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+class Trie:
+    """Owning handle of an lh_trie."""
+
+    def __init__(self, handle, n_keys):
+        self.handle = handle
+        self.n_keys = n_keys
+
+    def info(self):
+        inf = TrieInfo()
+        _check(lib.lh_trie_get_info(self.handle, C.byref(inf)))
+        L = inf.n_levels
+        return {"n_levels": L, "n_rows": inf.n_rows,
+                "level_size": list(inf.level_size[:L]), "level_sets": list(inf.level_sets[:L]),
+                "level_bitsets": list(inf.level_bitsets[:L]), "level_words": list(inf.level_words[:L]),
+                "level_order": list(inf.level_order[:L])}
+
+    def read_level(self, level):
+        inf = self.info()
+        n = inf["level_size"][level]
+        keys = np.zeros(n, np.uint32)
+        offs = np.zeros(n + 1, np.uint32)
+        _check(lib.lh_trie_read_level(self.handle, level, keys.ctypes.data, offs.ctypes.data))
+        return keys, offs
+
+    def free(self):
+        if self.handle:
+            lib.lh_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def trie_build(keys, annos=(), meta=(), level_order=None, bag=False, layout="plain", stream=None):
+    """lh_trie_build over device columns (torch tensors or numpy arrays)."""
+    kt = [to_device(k, np.uint32) for k in keys]
+    at = [to_device(a, np.float64) for a in annos]
+    mt = [to_device(m, np.uint32) for m in meta]
+    n = int(kt[0].numel()) if kt else 0
+    d = RelationDesc()
+    d.n_rows = n
+    d.n_keys = len(kt)
+    ka, aa, ma = _ptr_array(kt), _ptr_array(at), _ptr_array(mt)
+    d.keys = C.cast(ka, C.POINTER(C.c_void_p))
+    d.n_annos = len(at)
+    d.annos = C.cast(aa, C.POINTER(C.c_void_p))
+    d.n_meta = len(mt)
+    d.meta = C.cast(ma, C.POINTER(C.c_void_p))
+    lo = None
+    if level_order is not None:
+        lo = (C.c_uint32 * len(level_order))(*level_order)
+        d.level_order = C.cast(lo, C.POINTER(C.c_uint32))
+    d.flags = (LH_BAG if bag else LH_SET) | LAYOUT[layout]
+    out = C.c_void_p()
+    _check(lib.lh_trie_build(C.byref(d), stream if stream is not None else current_stream(), C.byref(out)))
+    return Trie(out.value, len(kt))
+
+
+class Plan:
+    def __init__(self, handle, tries):
+        self.handle = handle
+        self._tries = tries  # a plan borrows its tries
+
+    def info(self):
+        inf = PlanInfo()
+        _check(lib.lh_plan_get_info(self.handle, C.byref(inf)))
+        n = inf.n_attrs
+        return {"attr_order": list(inf.attr_order[:n]), "cost": inf.cost, "case_prefix": inf.case_prefix,
+                "exact_digits": inf.exact_digits, "exact_lsb": inf.exact_lsb,
+                "level_alg": list(inf.level_alg[:n])}
+
+    def free(self):
+        if self.handle:
+            lib.lh_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def plan(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None, policy="plain",
+         stream=None):
+    """lh_plan.  atoms: [(Trie, attr_of_key list, anno index or -1)]."""
+    catoms = (Atom * len(atoms))()
+    keep = []
+    for i, (t, attrs, anno) in enumerate(atoms):
+        am = (C.c_uint32 * len(attrs))(*attrs)
+        keep.append(am)
+        catoms[i].trie = t.handle
+        catoms[i].attr_of_key = C.cast(am, C.POINTER(C.c_uint32))
+        catoms[i].anno = anno
+    q = Query()
+    q.n_attrs = n_attrs
+    q.n_atoms = len(atoms)
+    q.atoms = catoms
+    oa = (C.c_uint32 * max(1, len(out)))(*out)
+    q.n_out = len(out)
+    q.out_attrs = C.cast(oa, C.POINTER(C.c_uint32))
+    ga = (GroupCol * max(1, len(group)))()
+    for i, (a, c) in enumerate(group):
+        ga[i].atom, ga[i].meta_col = a, c
+    q.n_group = len(group)
+    q.group_cols = ga
+    q.agg = LH_AGG_SUM if agg == "sum" else LH_AGG_COUNT
+    fa = (Filter * max(1, len(filters)))()
+    for i, f in enumerate(filters):
+        fa[i].atom = f["atom"]
+        fa[i].kind = FILTER_KIND[f["kind"]]
+        fa[i].col = f.get("col", 0)
+        fa[i].eq = f.get("eq", 0)
+        fa[i].lo = f.get("lo", 0.0)
+        fa[i].hi = f.get("hi", 0.0)
+    q.n_filters = len(filters)
+    q.filters = fa
+    ao = None
+    if attr_order is not None:
+        ao = (C.c_uint32 * len(attr_order))(*attr_order)
+        q.attr_order = C.cast(ao, C.POINTER(C.c_uint32))
+    q.policy = POLICY[policy]
+    out_h = C.c_void_p()
+    _check(lib.lh_plan(C.byref(q), stream if stream is not None else current_stream(), C.byref(out_h)))
+    return Plan(out_h.value, [a[0] for a in atoms])
+
+
+class JoinResult:
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    @property
+    def n_rows(self):
+        return self.ptr.contents.n_rows
+
+    def to_host(self):
+        r = self.ptr.contents
+        n, w = r.n_rows, r.n_cols
+        cols = [np.zeros(n, np.uint32) for _ in range(w)]
+        counts = np.zeros(n, np.uint64)
+        # a SUM result is flagged exact even when it has no rows
+        sums = np.zeros(n, np.float64) if (r.sums or r.exact) else None
+        kp = (C.c_void_p * max(1, w))(*[c.ctypes.data for c in cols])
+        _check(lib.lh_result_read(self.ptr, kp, counts.ctypes.data,
+                                  sums.ctypes.data if (sums is not None and n) else None))
+        keys = np.stack(cols, axis=1) if w else np.zeros((n, 0), np.uint32)
+        return {"keys": keys, "counts": counts, "sums": sums, "n_join": int(r.n_join_tuples), "exact": r.exact}
+
+    def free(self):
+        if self.ptr:
+            lib.lh_free(C.cast(self.ptr, C.c_void_p))
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def join_aggregate(plans, stream=None):
+    """lh_join_aggregate over one or more plans (more than one = batched)."""
+    n = len(plans)
+    arr = (C.c_void_p * n)(*[p.handle for p in plans])
+    outs = (C.POINTER(Result) * n)()
+    _check(lib.lh_join_aggregate(arr, n, stream if stream is not None else current_stream(), outs))
+    return [JoinResult(outs[i]) for i in range(n)]
+
+
+def live_allocations():
+    return lib.lh_live_allocations()
+
+
+class ProfileEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_uint64), ("total_ms", C.c_double),
+                ("rows", C.c_uint64), ("elements", C.c_uint64)]
+
+
+def profile_enable(on=True):
+    lib.lh_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib.lh_profile_reset()
+
+
+def profile_read():
+    """{kernel: {launches, total_ms, rows, elements}} since the last reset."""
+    n = lib.lh_profile_read(None, 0)
+    arr = (ProfileEntry * max(1, n))()
+    n = lib.lh_profile_read(arr, n)
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                                   "rows": arr[i].rows, "elements": arr[i].elements} for i in range(n)}
+
+
+# --------------------------------------------------------------------------
+# the section 4 cost estimate on a bare hypergraph
+# --------------------------------------------------------------------------
+
+def _hypergraph(n_attrs, edges):
+    """edges: [{"attrs": [...], "card": int, "eq": bool, "dense": bool}]"""
+    cnt = (C.c_uint32 * len(edges))(*[len(e["attrs"]) for e in edges])
+    flat = [v for e in edges for v in e["attrs"]]
+    attrs = (C.c_uint32 * max(1, len(flat)))(*flat)
+    card = (C.c_uint64 * len(edges))(*[int(e["card"]) for e in edges])
+    eq = (C.c_uint32 * len(edges))(*[1 if e.get("eq") else 0 for e in edges])
+    dense = (C.c_uint32 * len(edges))(*[1 if e.get("dense") else 0 for e in edges])
+    h = Hypergraph(n_attrs, len(edges), cnt, attrs, card, eq, dense)
+    return h, (cnt, attrs, card, eq, dense)
+
+
+def order_cost(n_attrs, edges, order):
+    h, keep = _hypergraph(n_attrs, edges)
+    o = (C.c_uint32 * n_attrs)(*order)
+    ic = (C.c_uint32 * n_attrs)()
+    w = (C.c_uint32 * n_attrs)()
+    cost = C.c_double()
+    _check(lib.lh_order_cost(C.byref(h), o, ic, w, C.byref(cost)))
+    return list(ic), list(w), cost.value
+
+
+def choose_order(n_attrs, edges, out=()):
+    h, keep = _hypergraph(n_attrs, edges)
+    oa = (C.c_uint32 * max(1, len(out)))(*out)
+    o = (C.c_uint32 * n_attrs)()
+    cost = C.c_double()
+    _check(lib.lh_choose_order(C.byref(h), len(out), oa, o, C.byref(cost)))
+    return list(o), cost.value
+
+
+# --------------------------------------------------------------------------
+# query dictionaries (the format documented in tests/queries.py)
+# --------------------------------------------------------------------------
+
+def run_query(query, attr_order=None, policy="plain", layout="plain", return_plan_info=False):
+    """Build one trie per distinct relation of the query, plan, run, and
+    copy the result to host in the format {keys, counts, sums, n_join}."""
+    tries = {}
+    atoms = []
+    for a in query["atoms"]:
+        ident = (tuple(id(k) for k in a["keys"]), tuple(id(x) for x in a.get("annos", [])),
+                 tuple(id(m) for m in a.get("meta", [])), bool(a.get("bag", False)))
+        if ident not in tries:
+            tries[ident] = trie_build(a["keys"], a.get("annos", []), a.get("meta", []), bag=a.get("bag", False),
+                                      layout=layout)
+        atoms.append((tries[ident], list(a["attrs"]), int(a.get("anno", -1))))
+    p = plan(query["n_attrs"], atoms, out=query.get("out", []), group=query.get("group", []),
+             agg=query.get("agg", "count"), filters=query.get("filters", []), attr_order=attr_order,
+             policy=policy)
+    r = join_aggregate([p])[0]
+    out = r.to_host()
+    info = p.info() if return_plan_info else None
+    r.free()
+    p.free()
+    for t in tries.values():
+        t.free()
+    if return_plan_info:
+        out["plan"] = info
+    return out
