@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--samples-log2", type=int, default=26)
     ap.add_argument("--cpu-scale", type=int, default=15)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--layout", default="plain", choices=["plain", "uint", "bitset", "learned"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU layout is a design "
@@ -96,7 +97,7 @@ def main():
     state = {}
 
     def step():
-        t = lh.trie_build([lo_d, hi_d])
+        t = lh.trie_build([lo_d, hi_d], layout=args.layout)
         p = lh.plan(3, [(t, [0, 1], -1), (t, [1, 2], -1), (t, [0, 2], -1)], agg="count")
         r = lh.join_aggregate([p])[0]
         res = r.to_host()
@@ -157,7 +158,7 @@ def main():
         "config": {"workload": f"triangle COUNT on R-MAT scale {args.scale}, 2^{args.samples_log2} samples "
                                f"(a=0.57,b=0.19,c=0.19), oriented low->high, set-mode dedup",
                    "edges": state["edges"], "triangles": state["count"], "attr_order": state["order"],
-                   "step": "trie_build + plan + join_aggregate",
+                   "step": "trie_build + plan + join_aggregate", "layout": args.layout,
                    "join_kernels_ms_per_step": round(join_ms, 3)},
         "roofline": roof,
     }

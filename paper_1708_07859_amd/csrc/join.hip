@@ -23,11 +23,10 @@ namespace lh {
 
 namespace {
 
-constexpr int J_NT = 256;
-constexpr int J_IT = 4;
-constexpr int J_CH = J_NT * J_IT;  // flattened elements per block
+constexpr int J_NT = 256;          // 4 waves per block, one work unit per wave
 constexpr int J_NW = J_NT / WAVE;
-constexpr int GCAP = 128;          // groups a block accumulates in LDS
+constexpr int U_IT = 4;            // elements per lane per unit
+constexpr int U_EL = WAVE * U_IT;  // driver elements per unit
 
 struct DSet {
   const uint32_t* ppos;   // frontier positions at the previous level (null: root set)
@@ -111,6 +110,10 @@ struct ElemArgs {
   const uint8_t* drv;     // driving participant of each row
   uint64_t nrows;
   uint64_t total;
+  const uint64_t* U;      // exclusive scan of per-row work units, nrows + 1 entries
+  const uint32_t* urow;   // row of each unit
+  uint64_t total_units;
+  uint64_t nvblk;         // virtual blocks of J_NW units
   uint32_t need_pos_mask; // participants whose position is needed
   // fill
   uint32_t n_atoms;
@@ -129,14 +132,14 @@ struct ElemArgs {
   LeafArgs leaf;
 };
 
-enum { M_COUNT = 0, M_FILL = 1, M_LEAF_A = 2, M_LEAF_B_COUNT = 3, M_LEAF_B_FILL = 4 };
+enum { M_COUNT = 0, M_FILL = 1, M_LEAF_A = 2, M_LEAF_B_COUNT = 3, M_LEAF_B_FILL = 4, M_LEAF_COUNT = 5 };
 
 struct WorkArgs {
   uint32_t np;
   DSet set[MAXP];
 };
 
-__global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv) {
+__global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv, uint32_t* units) {
   for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t best = UINT32_MAX, bi = 0;
     for (uint32_t p = 0; p < a.np; p++) {
@@ -151,6 +154,7 @@ __global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv)
     }
     work[r] = best;
     drv[r] = (uint8_t)bi;
+    units[r] = (best + U_EL - 1) / U_EL;
   }
 }
 
@@ -162,9 +166,18 @@ struct HitRows {
 
 __device__ __forceinline__ void leaf_rows(const LeafArgs& L, uint64_t r, const uint32_t* ppos, HitRows& h) {
   h.mult = 1;
-  for (uint32_t e = 0; e < L.n_atoms; e++) {
+#pragma unroll
+  for (int e = 0; e < MAXA; e++) {
+    if (e >= (int)L.n_atoms) break;
     const LeafAtom& A = L.at[e];
-    uint32_t lp = A.part >= 0 ? ppos[A.part] : (A.pos ? A.pos[r] : 0u);
+    uint32_t lp = 0;
+    if (A.part >= 0) {
+#pragma unroll
+      for (int q = 0; q < MAXP; q++)
+        if (q == A.part) lp = ppos[q];
+    } else if (A.pos) {
+      lp = A.pos[r];
+    }
     uint32_t b = lp, en = lp + 1;
     if (A.run) {
       b = A.run[lp];
@@ -182,7 +195,9 @@ __device__ __forceinline__ void leaf_rows(const LeafArgs& L, uint64_t r, const u
 __device__ __forceinline__ void term_of(const LeafArgs& L, const uint32_t* cur, double& hi, double& lo) {
   double p = 1.0, last = 1.0;
   int nf = 0;
-  for (uint32_t e = 0; e < L.n_atoms; e++) {
+#pragma unroll
+  for (int e = 0; e < MAXA; e++) {
+    if (e >= (int)L.n_atoms) break;
     if (!L.at[e].anno) continue;
     double v = L.at[e].anno[cur[e]];
     if (nf == 0) p = v;
@@ -204,256 +219,315 @@ __device__ __forceinline__ void term_of(const LeafArgs& L, const uint32_t* cur, 
 // Number of row combinations of the expanding atoms.
 __device__ __forceinline__ uint64_t combos(const LeafArgs& L, const HitRows& h) {
   uint64_t c = 1;
-  for (uint32_t e = 0; e < L.n_atoms; e++)
+#pragma unroll
+  for (int e = 0; e < MAXA; e++) {
+    if (e >= (int)L.n_atoms) break;
     if (L.at[e].expand) c *= (uint64_t)(h.re[e] - h.rb[e]);
+  }
   return c;
 }
 
 // Advance the odometer over expanding atoms; false when exhausted.
 __device__ __forceinline__ bool next_combo(const LeafArgs& L, const HitRows& h, uint32_t* cur) {
-  for (int e = (int)L.n_atoms - 1; e >= 0; e--) {
-    if (!L.at[e].expand) continue;
-    if (++cur[e] < h.re[e]) return true;
-    cur[e] = h.rb[e];
+  bool carry = true;
+#pragma unroll
+  for (int e = MAXA - 1; e >= 0; e--) {
+    if (!carry) break;
+    if (e >= (int)L.n_atoms || !L.at[e].expand) continue;
+    if (++cur[e] < h.re[e]) {
+      carry = false;
+    } else {
+      cur[e] = h.rb[e];
+    }
   }
-  return false;
+  return !carry;
 }
 
 template <int MODE>
 __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
-  __shared__ uint64_t s_rlo, s_rhi;
+  __shared__ uint64_t s_wcnt[J_NW];
   __shared__ uint64_t s_red[J_NW];
-  __shared__ uint64_t s_base;
-  __shared__ unsigned long long s_gcnt[GCAP];
-  __shared__ long long s_gacc[GCAP * EXACT_MAXD];
-  __shared__ uint32_t s_glo;
-  __shared__ uint32_t s_gspan;
+  __shared__ unsigned long long s_cnt;
+  __shared__ long long s_acc[EXACT_MAXD];
 
-  const uint64_t k0 = (uint64_t)blockIdx.x * J_CH;
-  const uint64_t k1 = min(k0 + (uint64_t)J_CH, a.total);
   const int tid = threadIdx.x;
+  const int w = tid / WAVE;
+  const int lane = lane_id();
   const LeafArgs& L = a.leaf;
+  constexpr bool NEED_POS = !(MODE == M_COUNT || MODE == M_LEAF_COUNT);
+  constexpr bool LEAF_AGG = (MODE == M_LEAF_A || MODE == M_LEAF_COUNT);
+  const bool one_group = LEAF_AGG && L.gid == nullptr;
 
-  if (tid == 0) {
-    uint64_t lo = upper_bound_minus1<uint64_t>(a.W, 0, a.nrows, k0);
-    s_rlo = lo;
-    s_rhi = upper_bound_minus1<uint64_t>(a.W, lo, a.nrows, k1 - 1);
-    s_base = (MODE == M_FILL || MODE == M_LEAF_B_FILL) ? a.blk_off[blockIdx.x] : 0;
-    if (MODE == M_LEAF_A) {
-      uint32_t glo = L.gid ? L.gid[s_rlo] : 0u;
-      uint32_t ghi = L.gid ? L.gid[s_rhi] : 0u;
-      s_glo = glo;
-      s_gspan = ghi - glo + 1;
-    }
+  if (LEAF_AGG && tid == 0) {
+    s_cnt = 0;
+    for (int i = 0; i < EXACT_MAXD; i++) s_acc[i] = 0;
   }
-  if (MODE == M_LEAF_A) {
-    for (int i = tid; i < GCAP; i += J_NT) s_gcnt[i] = 0;
-    for (int i = tid; i < GCAP * EXACT_MAXD; i += J_NT) s_gacc[i] = 0;
-  }
-  __syncthreads();
-  const uint64_t rlo = s_rlo, rhi = s_rhi;
-  const bool lds_groups = (MODE == M_LEAF_A) && (s_gspan <= (uint32_t)GCAP);
-
-  uint64_t my_count = 0;  // COUNT / LEAF_B_COUNT: hits or emitted tuples
-  RegAcc racc;
-  racc.clear();
-  uint64_t rcnt = 0;
+  // one-group aggregation is carried across the block's virtual blocks
+  uint64_t run_cnt = 0;
+  RegAcc run_acc;
+  run_acc.clear();
   uint32_t bad = 0;
 
-  for (int it = 0; it < J_IT; it++) {
-    const uint64_t k = k0 + (uint64_t)it * J_NT + tid;
-    const bool valid = k < k1;
-    bool hit = false;
+  // The grid is capped (a dispatch holds < 2^32 work-items); each block
+  // walks virtual blocks of J_NW units.
+  for (uint64_t vb = blockIdx.x; vb < a.nvblk; vb += gridDim.x) {
+    const uint64_t u = vb * J_NW + w;
+    const bool wave_valid = u < a.total_units;
+
+    // the wave's row and chunk (uniform across the wave)
     uint64_t r = 0;
-    uint32_t x = 0;
-    uint32_t ppos[MAXP];
-    for (int i = 0; i < MAXP; i++) ppos[i] = 0;
-    if (valid) {
-      r = upper_bound_minus1<uint64_t>(a.W, rlo, rhi + 1, k);
-      const uint32_t d = a.drv[r];
-      uint32_t b[MAXP], e[MAXP];
-      uint64_t sidx[MAXP];
-      for (uint32_t p = 0; p < a.np; p++) dset_range(a.set[p], r, b[p], e[p], sidx[p]);
-      const uint32_t idx = b[d] + (uint32_t)(k - a.W[r]);
-      x = a.set[d].keys[idx];
-      ppos[d] = idx;
-      hit = true;
-      for (uint32_t p = 0; p < a.np && hit; p++) {
-        if (p == d) continue;
-        hit = dset_find(a.set[p], b[p], e[p], sidx[p], x, (a.need_pos_mask >> p) & 1u, ppos[p]);
+    uint32_t chunk = 0, work = 0, d = 0;
+    if (wave_valid) {
+      r = a.urow[u];
+      chunk = (uint32_t)(u - a.U[r]);
+      work = (uint32_t)(a.W[r + 1] - a.W[r]);
+      d = a.drv[r];
+    }
+    uint32_t b[MAXP], e[MAXP];
+    uint64_t sidx[MAXP];
+    uint32_t bd = 0;
+    const uint32_t* dkeys = nullptr;
+#pragma unroll
+    for (int p = 0; p < MAXP; p++) {
+      b[p] = e[p] = 0;
+      sidx[p] = 0;
+      if (p < (int)a.np && wave_valid) dset_range(a.set[p], r, b[p], e[p], sidx[p]);
+      if (p == (int)d) {
+        bd = b[p];
+        dkeys = a.set[p].keys;
       }
     }
 
-    if (MODE == M_COUNT) {
-      my_count += hit ? 1 : 0;
+    bool hit[U_IT];
+    uint32_t x[U_IT];
+    uint32_t ppos[U_IT][NEED_POS ? MAXP : 1];
+#pragma unroll
+    for (int it = 0; it < U_IT; it++) {
+      const uint32_t i = chunk * U_EL + it * WAVE + lane;
+      const bool valid = wave_valid && i < work;
+      hit[it] = valid;
+      x[it] = valid ? dkeys[bd + i] : 0u;
+      if constexpr (NEED_POS) {
+#pragma unroll
+        for (int p = 0; p < MAXP; p++) ppos[it][p] = (p == (int)d) ? bd + i : 0u;
+      }
+    }
+    // probe the other sets; iterations are independent, so their loads overlap
+#pragma unroll
+    for (int p = 0; p < MAXP; p++) {
+      if (p >= (int)a.np) break;
+      if (p == (int)d) continue;
+      const bool np_ = NEED_POS && ((a.need_pos_mask >> p) & 1u);
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        uint32_t dummy;
+        if (hit[it])
+          hit[it] = dset_find(a.set[p], b[p], e[p], sidx[p], x[it], np_, NEED_POS ? ppos[it][NEED_POS ? p : 0] : dummy);
+      }
+    }
+
+    if (MODE == M_LEAF_COUNT) {
+      // every hit is one tuple (set relations, COUNT)
+      uint64_t c = 0;
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) c += hit[it] ? 1 : 0;
+      if (one_group) {
+        run_cnt += c;
+      } else {
+        c = wave_sum(c);
+        if (wave_valid && lane == 0 && c) atomicAdd((unsigned long long*)&L.gcount[L.gid[r]], (unsigned long long)c);
+      }
+    } else if (MODE == M_COUNT) {
+      uint64_t c = 0;
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) c += hit[it] ? 1 : 0;
+      uint64_t t = block_sum<uint64_t, J_NT>(c, s_red);
+      if (tid == 0) a.blk_cnt[vb] = (uint32_t)t;
     } else if (MODE == M_FILL) {
-      // order-preserving compaction: wave ballot + per-wave offsets
-      const uint64_t bal = ballot(hit);
-      const uint32_t wpre = lanes_below(bal);
-      const int w = tid / WAVE;
-      if (lane_id() == 0) s_red[w] = (uint64_t)__popcll(bal);
+      // order: units in block order, elements in order inside a unit
+      uint32_t wc = 0;
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) wc += (uint32_t)__popcll(ballot(hit[it]));
+      if (lane == 0) s_wcnt[w] = wc;
       __syncthreads();
-      uint64_t off = s_base;
-      uint64_t tot = 0;
-      for (int j = 0; j < J_NW; j++) {
-        if (j < w) off += s_red[j];
-        tot += s_red[j];
-      }
-      if (hit) {
-        const uint64_t o = off + wpre;
-        for (uint32_t e = 0; e < a.n_atoms; e++) {
-          uint32_t* po = a.pos_out[e];
-          if (!po) continue;
-          const int32_t pa = a.part_of_atom[e];
-          po[o] = pa >= 0 ? ppos[pa] : a.pos_in[e][r];
+      uint64_t off = a.blk_off[vb];
+      for (int j = 0; j < w; j++) off += s_wcnt[j];
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        const uint64_t bal = ballot(hit[it]);
+        if (hit[it]) {
+          const uint64_t o = off + lanes_below(bal);
+#pragma unroll
+          for (int at = 0; at < MAXA; at++) {
+            if (at >= (int)a.n_atoms) break;
+            uint32_t* po = a.pos_out[at];
+            if (!po) continue;
+            const int32_t pa = a.part_of_atom[at];
+            uint32_t v = 0;
+            if (pa >= 0) {
+#pragma unroll
+              for (int q = 0; q < MAXP; q++)
+                if (q == pa) v = ppos[it][q];
+            } else {
+              v = a.pos_in[at][r];
+            }
+            po[o] = v;
+          }
+          for (uint32_t j = 0; j < a.n_outv; j++) {
+            uint32_t* ov = a.outv_out[j];
+            if (!ov) continue;
+            ov[o] = ((int32_t)j == a.new_outv) ? x[it] : a.outv_in[j][r];
+          }
+          if (a.gid_mode == 1) a.gid_out[o] = a.gid_in[r];
+          else if (a.gid_mode == 2) a.gid_out[o] = (uint32_t)o;
         }
-        for (uint32_t j = 0; j < a.n_outv; j++) {
-          uint32_t* ov = a.outv_out[j];
-          if (!ov) continue;
-          ov[o] = ((int32_t)j == a.new_outv) ? x : a.outv_in[j][r];
-        }
-        if (a.gid_mode == 1) a.gid_out[o] = a.gid_in[r];
-        else if (a.gid_mode == 2) a.gid_out[o] = (uint32_t)o;
+        off += (uint64_t)__popcll(bal);
       }
-      __syncthreads();
-      if (tid == 0) s_base += tot;
       __syncthreads();
     } else if (MODE == M_LEAF_A) {
-      if (hit) {
+      uint64_t cnt = 0;
+      RegAcc acc;
+      acc.clear();
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        if (!hit[it]) continue;
         HitRows h;
-        leaf_rows(L, r, ppos, h);
-        uint32_t cur[MAXA];
-        for (uint32_t e = 0; e < L.n_atoms; e++) cur[e] = h.rb[e];
+        leaf_rows(L, r, ppos[it], h);
         const uint64_t nc = combos(L, h);
-        if (L.gid == nullptr) {
-          rcnt += h.mult * nc;
-          if (L.sum && nc) {
-            do {
-              double hi, lo;
-              term_of(L, cur, hi, lo);
-              bool ok = racc.add(hi, L.lsb, L.D, (int64_t)h.mult);
-              ok = racc.add(lo, L.lsb, L.D, (int64_t)h.mult) && ok;
-              if (!ok) bad = 1;
-            } while (next_combo(L, h, cur));
-          }
-        } else {
-          const uint32_t g = L.gid[r];
-          RegAcc t;
-          t.clear();
-          if (L.sum && nc) {
-            do {
-              double hi, lo;
-              term_of(L, cur, hi, lo);
-              bool ok = t.add(hi, L.lsb, L.D, (int64_t)h.mult);
-              ok = t.add(lo, L.lsb, L.D, (int64_t)h.mult) && ok;
-              if (!ok) bad = 1;
-            } while (next_combo(L, h, cur));
-          }
-          const uint64_t c = h.mult * nc;
-          if (lds_groups) {
-            const uint32_t gi = g - s_glo;
-            atomicAdd(&s_gcnt[gi], (unsigned long long)c);
-            if (L.sum)
-              for (uint32_t i = 0; i < L.D; i++)
-                if (t.s[i]) atomicAdd((unsigned long long*)&s_gacc[gi * EXACT_MAXD + i], (unsigned long long)t.s[i]);
-          } else {
-            atomicAdd((unsigned long long*)&L.gcount[g], (unsigned long long)c);
-            if (L.sum)
-              for (uint32_t i = 0; i < L.D; i++)
-                if (t.s[i]) atomicAdd((unsigned long long*)&L.gacc[(uint64_t)g * EXACT_MAXD + i], (unsigned long long)t.s[i]);
-          }
+        cnt += h.mult * nc;
+        if (L.sum && nc) {
+          uint32_t cur[MAXA];
+#pragma unroll
+          for (int at = 0; at < MAXA; at++) cur[at] = h.rb[at];
+          do {
+            double hi, lo;
+            term_of(L, cur, hi, lo);
+            bool ok = acc.add(hi, L.lsb, L.D, (int64_t)h.mult);
+            ok = acc.add(lo, L.lsb, L.D, (int64_t)h.mult) && ok;
+            if (!ok) bad = 1;
+          } while (next_combo(L, h, cur));
+        }
+      }
+      if (L.sum) acc.normalize(L.D);
+      if (one_group) {
+        run_cnt += cnt;
+#pragma unroll
+        for (int i = 0; i < EXACT_MAXD; i++) run_acc.s[i] += acc.s[i];
+        if (L.sum) run_acc.normalize(L.D);
+      } else {
+        // the wave's unit belongs to one row, hence to one group
+        cnt = wave_sum(cnt);
+        if (wave_valid) {
+          const uint64_t g = L.gid[r];
+          if (lane == 0 && cnt) atomicAdd((unsigned long long*)&L.gcount[g], (unsigned long long)cnt);
+          if (L.sum)
+            for (uint32_t i = 0; i < L.D; i++) {
+              int64_t v = wave_sum(acc.s[i]);
+              if (lane == 0 && v) atomicAdd((unsigned long long*)&L.gacc[g * EXACT_MAXD + i], (unsigned long long)v);
+            }
         }
       }
     } else if (MODE == M_LEAF_B_COUNT) {
-      if (hit) {
+      uint64_t c = 0;
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        if (!hit[it]) continue;
         HitRows h;
-        leaf_rows(L, r, ppos, h);
-        my_count += combos(L, h);
+        leaf_rows(L, r, ppos[it], h);
+        c += combos(L, h);
       }
+      uint64_t t = block_sum<uint64_t, J_NT>(c, s_red);
+      if (tid == 0) a.blk_cnt[vb] = (uint32_t)t;
     } else if (MODE == M_LEAF_B_FILL) {
-      uint64_t mine = 0;
-      HitRows h;
-      if (hit) {
-        leaf_rows(L, r, ppos, h);
-        mine = combos(L, h);
+      uint64_t m[U_IT];
+      uint64_t wtot = 0;
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        m[it] = 0;
+        if (hit[it]) {
+          HitRows h;
+          leaf_rows(L, r, ppos[it], h);
+          m[it] = combos(L, h);
+        }
+        wtot += wave_sum(m[it]);
       }
-      uint64_t tot;
-      uint64_t off = block_excl_scan<uint64_t, J_NT>(mine, s_red, tot) + s_base;
-      if (mine) {
-        uint32_t cur[MAXA];
-        for (uint32_t e = 0; e < L.n_atoms; e++) cur[e] = h.rb[e];
-        uint64_t o = off;
-        do {
-          for (uint32_t c = 0; c < L.n_cols; c++) {
-            const int32_t src = L.col_src[c];
-            uint32_t v;
-            if (src >= 0) v = a.outv_in[src][r];
-            else if (src == -1) v = x;
-            else {
-              v = 0;
-              for (uint32_t e = 0; e < L.n_atoms; e++)
-                if (L.at[e].gmeta && L.at[e].gcol == (int32_t)c) v = L.at[e].gmeta[cur[e]];
-            }
-            L.col_out[c][o] = v;
-          }
-          L.mult_out[o] = h.mult;
-          if (L.sum) {
-            double hi, lo;
-            term_of(L, cur, hi, lo);
-            L.hi_out[o] = hi;
-            L.lo_out[o] = lo;
-          }
-          o++;
-        } while (next_combo(L, h, cur));
-      }
+      if (lane == 0) s_wcnt[w] = wtot;
       __syncthreads();
-      if (tid == 0) s_base += tot;
+      uint64_t off = a.blk_off[vb];
+      for (int j = 0; j < w; j++) off += s_wcnt[j];
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        const uint64_t incl = wave_incl_scan(m[it]);
+        const uint64_t tot = __shfl(incl, WAVE - 1, WAVE);
+        if (m[it]) {
+          HitRows h;
+          leaf_rows(L, r, ppos[it], h);
+          uint32_t cur[MAXA];
+#pragma unroll
+          for (int at = 0; at < MAXA; at++) cur[at] = h.rb[at];
+          uint64_t o = off + incl - m[it];
+          do {
+            for (uint32_t c = 0; c < L.n_cols; c++) {
+              const int32_t src = L.col_src[c];
+              uint32_t v;
+              if (src >= 0) v = a.outv_in[src][r];
+              else if (src == -1) v = x[it];
+              else {
+                v = 0;
+#pragma unroll
+                for (int at = 0; at < MAXA; at++)
+                  if (at < (int)L.n_atoms && L.at[at].gmeta && L.at[at].gcol == (int32_t)c) v = L.at[at].gmeta[cur[at]];
+              }
+              L.col_out[c][o] = v;
+            }
+            L.mult_out[o] = h.mult;
+            if (L.sum) {
+              double hi, lo;
+              term_of(L, cur, hi, lo);
+              L.hi_out[o] = hi;
+              L.lo_out[o] = lo;
+            }
+            o++;
+          } while (next_combo(L, h, cur));
+        }
+        off += tot;
+      }
       __syncthreads();
     }
   }
 
-  if (MODE == M_COUNT || MODE == M_LEAF_B_COUNT) {
-    uint64_t t = block_sum<uint64_t, J_NT>(my_count, s_red);
-    if (tid == 0) a.blk_cnt[blockIdx.x] = (uint32_t)t;
-  }
-  if (MODE == M_LEAF_A) {
+  if (LEAF_AGG) {
     if (bad) atomicOr(L.err, 1u);
-    if (L.gid == nullptr) {
-      // block-reduce the per-thread accumulators into LDS slot 0
-      racc.normalize(L.D);
-      atomicAdd(&s_gcnt[0], (unsigned long long)rcnt);
-      if (L.sum)
-        for (uint32_t i = 0; i < L.D; i++)
-          if (racc.s[i]) atomicAdd((unsigned long long*)&s_gacc[i], (unsigned long long)racc.s[i]);
+    if (one_group) {
+      // reduce the block into LDS, one flush per block
+      __syncthreads();
+      const uint64_t c = wave_sum(run_cnt);
+      if (lane == 0 && c) atomicAdd(&s_cnt, (unsigned long long)c);
+      if (MODE == M_LEAF_A && L.sum)
+        for (uint32_t i = 0; i < L.D; i++) {
+          int64_t v = wave_sum(run_acc.s[i]);
+          if (lane == 0 && v) atomicAdd((unsigned long long*)&s_acc[i], (unsigned long long)v);
+        }
       __syncthreads();
       if (tid == 0) {
-        atomicAdd((unsigned long long*)&L.gcount[0], s_gcnt[0]);
-        if (L.sum) {
+        if (s_cnt) atomicAdd((unsigned long long*)&L.gcount[0], s_cnt);
+        if (MODE == M_LEAF_A && L.sum) {
           RegAcc t;
           t.clear();
-          for (uint32_t i = 0; i < L.D; i++) t.s[i] = s_gacc[i];
+          for (uint32_t i = 0; i < L.D; i++) t.s[i] = s_acc[i];
           t.normalize(L.D);
           for (uint32_t i = 0; i < L.D; i++)
             if (t.s[i]) atomicAdd((unsigned long long*)&L.gacc[i], (unsigned long long)t.s[i]);
         }
       }
-    } else if (lds_groups) {
-      __syncthreads();
-      for (uint32_t gi = tid; gi < s_gspan; gi += J_NT) {
-        if (s_gcnt[gi] == 0) continue;
-        const uint64_t g = (uint64_t)s_glo + gi;
-        atomicAdd((unsigned long long*)&L.gcount[g], s_gcnt[gi]);
-        if (L.sum) {
-          RegAcc t;
-          t.clear();
-          for (uint32_t i = 0; i < L.D; i++) t.s[i] = s_gacc[gi * EXACT_MAXD + i];
-          t.normalize(L.D);
-          for (uint32_t i = 0; i < L.D; i++)
-            if (t.s[i]) atomicAdd((unsigned long long*)&L.gacc[g * EXACT_MAXD + i], (unsigned long long)t.s[i]);
-        }
-      }
     }
   }
+}
+
+// Row of every work unit.
+__global__ void k_unit_rows(const uint64_t* U, uint64_t nrows, uint32_t* urow) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x)
+    for (uint64_t u = U[r]; u < U[r + 1]; u++) urow[u] = (uint32_t)r;
 }
 
 // ---- finalization ------------------------------------------------------------
@@ -542,6 +616,10 @@ __global__ void k_seg_accumulate(SegAccArgs a, uint64_t n) {
   }
 }
 
+// A dispatch counts work-items in 32 bits: cap the grid and let blocks
+// stride over virtual blocks.
+unsigned elem_grid(uint64_t nvblk) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nvblk, 32768)); }
+
 unsigned grid_for(uint64_t n) {
   uint64_t b = (n + 255) / 256;
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(b, 256 * 64));
@@ -575,9 +653,16 @@ DSet make_dset(const lh_plan_t* p, const Participant& pt, const Frontier& F) {
   return d;
 }
 
-// Per-row work (smallest participating set) and its exclusive scan.
-uint64_t depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs& a, DBuf<uint64_t>& W,
-                    DBuf<uint8_t>& drv, hipStream_t s) {
+// Per-row work (smallest participating set), its exclusive scan, and the
+// cut of every row into work units of U_EL elements.
+struct DepthWork {
+  DBuf<uint64_t> W, U;
+  DBuf<uint8_t> drv;
+  DBuf<uint32_t> urow;
+  uint64_t total = 0, units = 0, nblk = 0;
+};
+
+void depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs& a, DepthWork& dw, hipStream_t s) {
   const auto& parts = p->parts[d];
   WorkArgs wa{};
   wa.np = (uint32_t)parts.size();
@@ -586,20 +671,32 @@ uint64_t depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs&
     wa.set[i] = make_dset(p, parts[i], F);
     a.set[i] = wa.set[i];
   }
-  DBuf<uint32_t> work(F.n, s);
-  drv.alloc(F.n, s);
-  W.alloc(F.n + 1, s);
+  DBuf<uint32_t> work(F.n, s), units(F.n, s);
+  dw.drv.alloc(F.n, s);
+  dw.W.alloc(F.n + 1, s);
+  dw.U.alloc(F.n + 1, s);
   {
     ProfScope ps("join_work", s, F.n, 0);
-    k_work<<<grid_for(F.n), 256, 0, s>>>(wa, F.n, work.p, drv.p);
+    k_work<<<grid_for(F.n), 256, 0, s>>>(wa, F.n, work.p, dw.drv.p, units.p);
   }
   LH_HIP(hipGetLastError());
-  uint64_t total = scan_u32_to_u64(work.p, W.p, F.n, s);
-  a.W = W.p;
-  a.drv = drv.p;
+  dw.total = scan_u32_to_u64(work.p, dw.W.p, F.n, s);
+  dw.units = scan_u32_to_u64(units.p, dw.U.p, F.n, s);
+  if (dw.units >= (1ull << 32)) fail(LH_ERR_OVERFLOW, "join: more than 2^32 work units at one attribute");
+  dw.urow.alloc(dw.units, s);
+  if (dw.units) {
+    k_unit_rows<<<grid_for(F.n), 256, 0, s>>>(dw.U.p, F.n, dw.urow.p);
+    LH_HIP(hipGetLastError());
+  }
+  dw.nblk = (dw.units + J_NW - 1) / J_NW;
+  a.nvblk = dw.nblk;
+  a.W = dw.W.p;
+  a.drv = dw.drv.p;
   a.nrows = F.n;
-  a.total = total;
-  return total;
+  a.total = dw.total;
+  a.U = dw.U.p;
+  a.urow = dw.urow.p;
+  a.total_units = dw.units;
 }
 
 bool binds_by(const lh_plan_t* p, uint32_t atom, uint32_t d) {
@@ -611,21 +708,21 @@ bool binds_by(const lh_plan_t* p, uint32_t atom, uint32_t d) {
 
 void step(const lh_plan_t* p, uint32_t d, Frontier& F, hipStream_t s) {
   ElemArgs a{};
-  DBuf<uint64_t> W;
-  DBuf<uint8_t> drv;
-  uint64_t total = depth_work(p, d, F, a, W, drv, s);
+  DepthWork dw;
+  depth_work(p, d, F, a, dw, s);
+  const uint64_t total = dw.total;
   if (total == 0) {
     F.n = 0;
     return;
   }
-  const uint64_t nblk = (total + J_CH - 1) / J_CH;
+  const uint64_t nblk = dw.nblk;
   if (nblk >= (1ull << 31)) fail(LH_ERR_OVERFLOW, "join: too much work at one attribute");
   DBuf<uint32_t> bcnt(nblk, s);
   a.blk_cnt = bcnt.p;
   a.need_pos_mask = 0;
   {
     ProfScope ps("join_count", s, F.n, total);
-    k_elem<M_COUNT><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+    k_elem<M_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
   }
   LH_HIP(hipGetLastError());
   DBuf<uint64_t> boff(nblk + 1, s);
@@ -672,7 +769,7 @@ void step(const lh_plan_t* p, uint32_t d, Frontier& F, hipStream_t s) {
   a.need_pos_mask = 0xffu;
   {
     ProfScope ps("join_fill", s, F.n, total);
-    k_elem<M_FILL><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+    k_elem<M_FILL><<<elem_grid(nblk), J_NT, 0, s>>>(a);
   }
   LH_HIP(hipGetLastError());
   F = std::move(G);
@@ -716,10 +813,10 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
 
   // leaf attribute: intersect and aggregate
   ElemArgs a{};
-  DBuf<uint64_t> W;
-  DBuf<uint8_t> drv;
-  uint64_t total = F.n ? depth_work(p, leaf, F, a, W, drv, s) : 0;
-  const uint64_t nblk = (total + J_CH - 1) / J_CH;
+  DepthWork dw;
+  if (F.n) depth_work(p, leaf, F, a, dw, s);
+  const uint64_t total = dw.total;
+  const uint64_t nblk = dw.nblk;
   if (nblk >= (1ull << 31)) fail(LH_ERR_OVERFLOW, "join: too much work at the last attribute");
   LeafArgs& L = a.leaf;
   L.n_atoms = na;
@@ -766,8 +863,11 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
     L.gcount = gcount.p;
     L.gacc = gacc.p;
     if (total) {
+      bool all_set = !is_sum;
+      for (const auto& A : p->atoms) all_set = all_set && !A.bag;
       ProfScope ps("leaf_aggregate", s, F.n, total);
-      k_elem<M_LEAF_A><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+      if (all_set) k_elem<M_LEAF_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+      else k_elem<M_LEAF_A><<<elem_grid(nblk), J_NT, 0, s>>>(a);
       LH_HIP(hipGetLastError());
     }
     FinA f{};
@@ -817,7 +917,7 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
       a.blk_cnt = bcnt.p;
       {
         ProfScope ps("leaf_emit_count", s, F.n, total);
-        k_elem<M_LEAF_B_COUNT><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+        k_elem<M_LEAF_B_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
       }
       LH_HIP(hipGetLastError());
       boff.alloc(nblk + 1, s);
@@ -844,7 +944,7 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
     if (n_emit) {
       a.blk_off = boff.p;
       ProfScope ps("leaf_emit_fill", s, F.n, total);
-      k_elem<M_LEAF_B_FILL><<<(unsigned)nblk, J_NT, 0, s>>>(a);
+      k_elem<M_LEAF_B_FILL><<<elem_grid(nblk), J_NT, 0, s>>>(a);
       LH_HIP(hipGetLastError());
     }
     // sort tuples by the output columns

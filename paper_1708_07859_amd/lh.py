@@ -137,6 +137,9 @@ SIGNATURES = {
 
 
 def _load():
+    # torch brings its own HIP runtime (same soname as the one liblh.so
+    # links); loading torch first makes the process use exactly one.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run paper_1708_07859_amd/build.py "
                           "(or __graft_entry__.build()) first")
