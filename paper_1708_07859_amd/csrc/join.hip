@@ -141,17 +141,46 @@ struct WorkArgs {
 
 __global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv, uint32_t* units) {
   for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t best = UINT32_MAX, bi = 0;
-    for (uint32_t p = 0; p < a.np; p++) {
+    // Driver: the set whose elements are cheapest to stream and probe into
+    // the others; probing a bitset costs one word load, probing a sorted
+    // uint array a binary search of ~log2(card) loads.
+    uint32_t card[MAXP];
+    float probe[MAXP];
+    uint32_t bi = 0;
+#pragma unroll
+    for (int p = 0; p < MAXP; p++) {
+      card[p] = 0;
+      probe[p] = 1.0f;
+      if (p >= (int)a.np) continue;
       uint32_t b, e;
       uint64_t sidx;
       dset_range(a.set[p], r, b, e, sidx);
-      uint32_t c = e - b;
-      if (c < best) {
-        best = c;
-        bi = p;
+      card[p] = e - b;
+      const bool bs = card[p] && a.set[p].bs_word[sidx] != UINT64_MAX;
+      probe[p] = bs ? 1.0f : 2.0f + log2f((float)card[p] + 1.0f);
+    }
+    float best_cost = 3.0e38f;
+#pragma unroll
+    for (int p = 0; p < MAXP; p++) {
+      if (p >= (int)a.np) continue;
+      float c = 0.0f;
+#pragma unroll
+      for (int q = 0; q < MAXP; q++)
+        if (q < (int)a.np && q != p) c += probe[q];
+      c = (float)card[p] * (c + 1.0f);
+      if (c < best_cost) {
+        best_cost = c;
+        bi = (uint32_t)p;
       }
     }
+    uint32_t best = 0;
+    bool empty = false;
+#pragma unroll
+    for (int p = 0; p < MAXP; p++) {
+      if (p == (int)bi) best = card[p];
+      if (p < (int)a.np && card[p] == 0) empty = true;
+    }
+    if (empty) best = 0;
     work[r] = best;
     drv[r] = (uint8_t)bi;
     units[r] = (best + U_EL - 1) / U_EL;
@@ -530,6 +559,109 @@ __global__ void k_unit_rows(const uint64_t* U, uint64_t nrows, uint32_t* urow) {
     for (uint64_t u = U[r]; u < U[r + 1]; u++) urow[u] = (uint32_t)r;
 }
 
+// ---- two-set COUNT leaf with per-unit descriptors ----------------------------
+// For the common leaf of two participating sets and set semantics, every
+// work unit is described once (driver key range, probed set range and
+// layout), so a wave needs one descriptor load before streaming its keys.
+struct UnitDesc {
+  uint32_t dstart;   // first driver element (index into the driver's level keys)
+  uint32_t dcount;   // driver elements in this unit (<= U_EL)
+  uint32_t pb, pe;   // probed set range in its level keys
+  uint64_t pword;    // probed set's first bitset word, or UINT64_MAX
+  uint32_t pbase;    // probed set's bitset base value
+  uint32_t drv;      // driving participant (0 or 1)
+};
+
+__global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint8_t* drv, uint64_t nrows, UnitDesc* desc) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t u0 = U[r], u1 = U[r + 1];
+    if (u0 == u1) continue;
+    uint32_t b[2], e[2];
+    uint64_t sidx[2];
+    dset_range(wa.set[0], r, b[0], e[0], sidx[0]);
+    dset_range(wa.set[1], r, b[1], e[1], sidx[1]);
+    const uint32_t d = drv[r];
+    const uint32_t q = 1 - d;
+    const uint32_t db = d ? b[1] : b[0], de = d ? e[1] : e[0];
+    UnitDesc t;
+    t.pb = q ? b[1] : b[0];
+    t.pe = q ? e[1] : e[0];
+    const uint64_t sq = q ? sidx[1] : sidx[0];
+    t.pword = (t.pe > t.pb) ? wa.set[q].bs_word[sq] : UINT64_MAX;
+    t.pbase = (t.pword != UINT64_MAX) ? wa.set[q].bs_base[sq] : 0u;
+    t.drv = d;
+    for (uint64_t u = u0; u < u1; u++) {
+      t.dstart = db + (uint32_t)(u - u0) * U_EL;
+      t.dcount = min((uint32_t)U_EL, de - t.dstart);
+      desc[u] = t;
+    }
+  }
+}
+
+struct Leaf2Args {
+  const uint32_t* keys[2];
+  const uint64_t* pool[2];
+  const UnitDesc* desc;
+  const uint32_t* urow;   // grouped only
+  const uint32_t* gid;    // null: one group
+  uint64_t* gcount;
+  uint64_t units;
+  uint64_t nvblk;
+};
+
+__global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
+  __shared__ unsigned long long s_cnt;
+  const int tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+  if (tid == 0) s_cnt = 0;
+  uint64_t run = 0;
+  for (uint64_t vb = blockIdx.x; vb < a.nvblk; vb += gridDim.x) {
+    const uint64_t u = vb * J_NW + w;
+    if (u >= a.units) continue;  // wave-uniform; no barrier inside the loop
+    const UnitDesc t = a.desc[u];
+    const uint32_t* dk = t.drv ? a.keys[1] : a.keys[0];
+    const uint32_t* pk = t.drv ? a.keys[0] : a.keys[1];
+    const uint64_t* pool = t.drv ? a.pool[0] : a.pool[1];
+    uint32_t x[U_IT];
+    bool v[U_IT];
+#pragma unroll
+    for (int it = 0; it < U_IT; it++) {
+      const uint32_t i = it * WAVE + lane;
+      v[it] = i < t.dcount;
+      x[it] = v[it] ? dk[t.dstart + i] : 0u;
+    }
+    uint32_t c = 0;
+    if (t.pword != UINT64_MAX) {
+      const uint32_t hi = pk[t.pe - 1];
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        if (!v[it] || x[it] < t.pbase || x[it] > hi) continue;
+        const uint32_t dd = x[it] - t.pbase;
+        c += (uint32_t)((pool[t.pword + (dd >> 6)] >> (dd & 63u)) & 1ull);
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        if (!v[it]) continue;
+        const uint32_t j = lower_bound_u32(pk, t.pb, t.pe, x[it]);
+        c += (j < t.pe && pk[j] == x[it]) ? 1u : 0u;
+      }
+    }
+    if (a.gid) {
+      const uint64_t s = wave_sum((uint64_t)c);
+      if (lane == 0 && s) atomicAdd((unsigned long long*)&a.gcount[a.gid[a.urow[u]]], (unsigned long long)s);
+    } else {
+      run += c;
+    }
+  }
+  if (!a.gid) {
+    __syncthreads();
+    const uint64_t s = wave_sum(run);
+    if (lane == 0 && s) atomicAdd(&s_cnt, (unsigned long long)s);
+    __syncthreads();
+    if (tid == 0 && s_cnt) atomicAdd((unsigned long long*)&a.gcount[0], s_cnt);
+  }
+}
+
 // ---- finalization ------------------------------------------------------------
 
 __global__ void k_nonzero_flags(const uint64_t* cnt, uint64_t n, uint32_t* flags) {
@@ -866,7 +998,28 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
       bool all_set = !is_sum;
       for (const auto& A : p->atoms) all_set = all_set && !A.bag;
       ProfScope ps("leaf_aggregate", s, F.n, total);
-      if (all_set) k_elem<M_LEAF_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+      if (all_set && a.np == 2) {
+        // two sets, set semantics: per-unit descriptors, one load per wave
+        DBuf<UnitDesc> desc(dw.units, s);
+        WorkArgs wa{};
+        wa.np = 2;
+        wa.set[0] = a.set[0];
+        wa.set[1] = a.set[1];
+        k_unit_desc<<<grid_for(F.n), 256, 0, s>>>(wa, dw.U.p, dw.drv.p, F.n, desc.p);
+        LH_HIP(hipGetLastError());
+        Leaf2Args l2{};
+        l2.keys[0] = a.set[0].keys;
+        l2.keys[1] = a.set[1].keys;
+        l2.pool[0] = a.set[0].pool;
+        l2.pool[1] = a.set[1].pool;
+        l2.desc = desc.p;
+        l2.urow = dw.urow.p;
+        l2.gid = L.gid;
+        l2.gcount = L.gcount;
+        l2.units = dw.units;
+        l2.nvblk = nblk;
+        k_leaf2_count<<<elem_grid(nblk), J_NT, 0, s>>>(l2);
+      } else if (all_set) k_elem<M_LEAF_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
       else k_elem<M_LEAF_A><<<elem_grid(nblk), J_NT, 0, s>>>(a);
       LH_HIP(hipGetLastError());
     }
