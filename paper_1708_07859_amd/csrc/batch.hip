@@ -1,0 +1,794 @@
+// Batched execution of many join-aggregate instances of uneven size in one
+// persistent, graph-captured launch.
+//
+// Handled shape ("row union"): two annotated relations A(i, j) and E(j)
+// or E(j, k) under the order i, j[, k] with output [i] or [i, k] -- the
+// sparse matrix-vector and matrix-matrix products the paper expresses as
+// join-aggregate queries (the order i, j, k is the relaxed order of section
+// 4.1.2, whose last attribute is materialized by a GROUP BY on a key,
+// section 5).  Every row i of every instance is a work item:
+//  * light rows (few products) are taken by one wave, which sums exactly
+//    into a private LDS hash keyed by k;
+//  * heavy rows are taken by a whole block, which sums into a dense LDS
+//    window of k values, window after window.
+// Workers pull items from two device queues (heavy rows first, longest
+// first), so one launch balances thousands of instances.  The launch and
+// its queue resets are captured once in a hipGraph and replayed.  Sums are
+// exact (the same accumulator as the single-plan path), so every instance's
+// result is bit-identical to running its plan alone.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+
+#include "device_common.h"
+#include "engine.h"
+#include "exact.h"
+
+namespace lh {
+
+namespace {
+
+constexpr int B_NT = 256;
+constexpr int B_NW = B_NT / WAVE;
+constexpr int HS = 256;                       // hash slots per wave
+constexpr uint32_t EMPTY_KEY = 0xffffffffu;
+
+struct BInst {
+  uint32_t kind;             // 0: E(j) (vector), 1: E(j, k) (matrix)
+  uint32_t n_rows;           // nodes of A's first level (the rows i)
+  const uint32_t* a_i;       // A level 0 keys
+  const uint32_t* a_off;     // A level 0 child offsets
+  const uint32_t* a_j;       // A level 1 keys
+  const uint32_t* a_run;     // A bag runs of level 1 (null: one row per node)
+  const double* a_val;       // A annotation in trie order (null for COUNT)
+  const uint32_t* e_j;       // E level 0 keys
+  uint32_t e_n0;
+  uint64_t e_bsw;            // E root set bitset word (UINT64_MAX: uint layout)
+  uint32_t e_bsb;
+  const uint64_t* e_pool;
+  const uint32_t* e_off;     // matrix: E level 0 child offsets
+  const uint32_t* e_k;       // matrix: E level 1 keys
+  const uint32_t* e_run;     // bag runs of E's last level (null: one row per node)
+  const double* e_val;
+  int32_t lsb;
+  uint32_t D;
+  uint32_t sum;
+  uint32_t n_k;              // matrix: largest k + 1
+  uint64_t row_base;         // first batch row of this instance
+};
+
+__device__ __forceinline__ bool find_j(const BInst& I, uint32_t j, uint32_t& pos) {
+  if (I.e_n0 == 0) return false;
+  if (I.e_bsw != UINT64_MAX) {
+    if (j < I.e_bsb || j > I.e_j[I.e_n0 - 1]) return false;
+    const uint32_t d = j - I.e_bsb;
+    if (!((I.e_pool[I.e_bsw + (d >> 6)] >> (d & 63u)) & 1ull)) return false;
+  }
+  const uint32_t q = lower_bound_u32(I.e_j, 0, I.e_n0, j);
+  if (q < I.e_n0 && I.e_j[q] == j) {
+    pos = q;
+    return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ void rows_of(const uint32_t* run, uint32_t node, uint32_t& b, uint32_t& e) {
+  if (run) {
+    b = run[node];
+    e = run[node + 1];
+  } else {
+    b = node;
+    e = node + 1;
+  }
+}
+
+// ---- setup: per-row product bounds and classes ----------------------------
+
+__global__ void k_row_setup(const BInst* inst, const uint64_t* inst_row0, uint32_t n_inst, uint64_t R,
+                            uint32_t light_max, uint32_t* row_inst, uint64_t* prod, uint32_t* ub, uint32_t* is_heavy,
+                            uint32_t* is_light) {
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < R; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t ii = (uint32_t)upper_bound_minus1<uint64_t>(inst_row0, 0, n_inst, t);
+    const BInst& I = inst[ii];
+    const uint32_t p = (uint32_t)(t - inst_row0[ii]);
+    row_inst[t] = ii;
+    uint64_t u = 0;
+    for (uint32_t q = I.a_off[p]; q < I.a_off[p + 1]; q++) {
+      uint32_t pe;
+      if (!find_j(I, I.a_j[q], pe)) continue;
+      uint32_t ab, ae, eb, ee;
+      rows_of(I.a_run, q, ab, ae);
+      if (I.kind == 0) {
+        rows_of(I.e_run, pe, eb, ee);
+        u += (uint64_t)(ae - ab) * (ee - eb);
+      } else {
+        u += (uint64_t)(ae - ab) * (I.e_off[pe + 1] - I.e_off[pe]);
+      }
+    }
+    prod[t] = u;
+    const bool heavy = I.kind == 1 && u > light_max;
+    ub[t] = I.kind == 0 ? 1u : (uint32_t)min<uint64_t>(u, I.n_k);
+    is_heavy[t] = heavy ? 1u : 0u;
+    is_light[t] = heavy ? 0u : 1u;
+  }
+}
+
+__global__ void k_fill_u32_dev(uint32_t* p, uint32_t v, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---- the persistent kernel -------------------------------------------------------
+
+struct BatchArgs {
+  const BInst* inst;
+  const uint32_t* row_inst;
+  const uint64_t* inst_row0;
+  const uint64_t* ub_off;    // per batch row: first upper-bound output slot
+  const uint32_t* heavy;     // heavy rows, longest first
+  uint64_t n_heavy;
+  const uint32_t* light;     // light rows
+  uint64_t n_light;
+  uint32_t* qhead;           // [0] heavy queue, [1] light queue
+  uint32_t* row_nnz;         // outputs per row
+  uint32_t* ub_k;
+  uint64_t* ub_cnt;
+  double* ub_sum;
+  uint32_t* err;
+};
+
+// Exact sum held in slots (EXACT_MAXD stride) of one accumulator: add t.
+__device__ __forceinline__ bool lds_add_term(long long* slots, double v, int32_t lsb, uint32_t D, int64_t mult) {
+  if (v == 0.0) return true;
+  int32_t k0;
+  int64_t d0, d1, d2;
+  bool neg;
+  if (!split_to_digits(v, lsb, k0, d0, d1, d2, neg)) return false;
+  if (neg) mult = -mult;
+  const int64_t dd[3] = {d0 * mult, d1 * mult, d2 * mult};
+  bool ok = true;
+  for (int q = 0; q < 3; q++) {
+    if (dd[q] == 0) continue;
+    const int32_t k = k0 + q;
+    if (k >= (int32_t)D) {
+      ok = false;
+      continue;
+    }
+    atomicAdd((unsigned long long*)&slots[k], (unsigned long long)dd[q]);
+  }
+  return ok;
+}
+
+template <int WIN>
+__global__ __launch_bounds__(B_NT) void k_batch(BatchArgs a) {
+  // LDS: heavy phase uses a dense window, light phase per-wave hashes
+  constexpr int HEAVY_BYTES = WIN * (8 + 8 * EXACT_MAXD);
+  constexpr int LIGHT_BYTES = B_NW * HS * (4 + 8 + 8 * EXACT_MAXD + 2);
+  constexpr int LDS_BYTES = HEAVY_BYTES > LIGHT_BYTES ? HEAVY_BYTES : LIGHT_BYTES;
+  __shared__ __align__(16) unsigned char lds[LDS_BYTES];
+  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_wsum[B_NW];
+  const int tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+  uint32_t bad = 0;
+
+  // ---- heavy rows: one block per row, dense windows of k ----
+  unsigned long long* wcnt = (unsigned long long*)lds;
+  long long* wdig = (long long*)(lds + WIN * 8);
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(&a.qhead[0], 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    __syncthreads();
+    if (item >= a.n_heavy) break;
+    const uint32_t t = a.heavy[item];
+    const BInst I = a.inst[a.row_inst[t]];
+    const uint32_t p = t - (uint32_t)a.inst_row0[a.row_inst[t]];
+    const uint32_t qb = I.a_off[p], qe = I.a_off[p + 1];
+    uint64_t out = a.ub_off[t];
+    uint32_t nnz = 0;
+    for (uint32_t w0 = 0; w0 < I.n_k; w0 += WIN) {
+      for (int s = tid; s < WIN; s += B_NT) wcnt[s] = 0;
+      for (int s = tid; s < WIN * EXACT_MAXD; s += B_NT) wdig[s] = 0;
+      __syncthreads();
+      for (uint32_t q = qb + tid; q < qe; q += B_NT) {
+        uint32_t pe;
+        if (!find_j(I, I.a_j[q], pe)) continue;
+        uint32_t ab, ae;
+        rows_of(I.a_run, q, ab, ae);
+        const uint32_t kb = lower_bound_u32(I.e_k, I.e_off[pe], I.e_off[pe + 1], w0);
+        const uint32_t kend = lower_bound_u32(I.e_k, kb, I.e_off[pe + 1], min(w0 + (uint32_t)WIN, I.n_k));
+        for (uint32_t kp = kb; kp < kend; kp++) {
+          const uint32_t slot = I.e_k[kp] - w0;
+          uint32_t eb, ee;
+          rows_of(I.e_run, kp, eb, ee);
+          atomicAdd(&wcnt[slot], (unsigned long long)(ae - ab) * (ee - eb));
+          if (I.sum)
+            for (uint32_t ra = ab; ra < ae; ra++)
+              for (uint32_t re = eb; re < ee; re++) {
+                double hi, lo;
+                two_prod(I.a_val[ra], I.e_val[re], hi, lo);
+                bool ok = lds_add_term(wdig + slot * EXACT_MAXD, hi, I.lsb, I.D, 1);
+                ok = lds_add_term(wdig + slot * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
+                if (!ok) bad = 1;
+              }
+        }
+      }
+      __syncthreads();
+      // emit the window's non-empty slots in k order
+      constexpr int PER = WIN / B_NT;
+      uint32_t flags = 0, c = 0;
+#pragma unroll
+      for (int i = 0; i < PER; i++)
+        if (wcnt[tid * PER + i]) {
+          flags |= 1u << i;
+          c++;
+        }
+      uint32_t tot;
+      uint32_t pre = block_excl_scan<uint32_t, B_NT>(c, s_wsum, tot);
+#pragma unroll
+      for (int i = 0; i < PER; i++) {
+        if (!((flags >> i) & 1u)) continue;
+        const int s = tid * PER + i;
+        const uint64_t o = out + nnz + pre;
+        a.ub_k[o] = w0 + (uint32_t)s;
+        a.ub_cnt[o] = wcnt[s];
+        if (I.sum) a.ub_sum[o] = exact_round((const int64_t*)(wdig + s * EXACT_MAXD), I.D, I.lsb, a.err);
+        pre++;
+      }
+      nnz += tot;
+      __syncthreads();
+    }
+    if (tid == 0) a.row_nnz[t] = nnz;
+  }
+
+  // ---- light rows: one wave per row, private LDS hash ----
+  uint32_t* hk = (uint32_t*)(lds + w * HS * (4 + 8 + 8 * EXACT_MAXD + 2));
+  unsigned long long* hc = (unsigned long long*)(hk + HS);
+  long long* hd = (long long*)(hc + HS);
+  uint16_t* hl = (uint16_t*)(hd + HS * EXACT_MAXD);
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = atomicAdd(&a.qhead[1], 1u);
+    item = __shfl(item, 0, WAVE);
+    if (item >= a.n_light) break;
+    const uint32_t t = a.light[item];
+    const BInst I = a.inst[a.row_inst[t]];
+    const uint32_t p = t - (uint32_t)a.inst_row0[a.row_inst[t]];
+    const uint32_t qb = I.a_off[p], qe = I.a_off[p + 1];
+    const uint64_t out = a.ub_off[t];
+    if (I.kind == 0) {
+      // vector: one output per row, reduced across the wave
+      RegAcc acc;
+      acc.clear();
+      uint64_t cnt = 0;
+      for (uint32_t q = qb + lane; q < qe; q += WAVE) {
+        uint32_t pe;
+        if (!find_j(I, I.a_j[q], pe)) continue;
+        uint32_t ab, ae, eb, ee;
+        rows_of(I.a_run, q, ab, ae);
+        rows_of(I.e_run, pe, eb, ee);
+        cnt += (uint64_t)(ae - ab) * (ee - eb);
+        if (I.sum)
+          for (uint32_t ra = ab; ra < ae; ra++)
+            for (uint32_t re = eb; re < ee; re++) {
+              double hi, lo;
+              two_prod(I.a_val[ra], I.e_val[re], hi, lo);
+              bool ok = acc.add(hi, I.lsb, I.D, 1);
+              ok = acc.add(lo, I.lsb, I.D, 1) && ok;
+              if (!ok) bad = 1;
+            }
+      }
+      if (I.sum) acc.normalize(I.D);
+      cnt = wave_sum(cnt);
+      int64_t tot[EXACT_MAXD];
+#pragma unroll
+      for (int s = 0; s < EXACT_MAXD; s++) tot[s] = wave_sum(acc.s[s]);
+      if (lane == 0) {
+        if (cnt) {
+          a.ub_k[out] = 0;
+          a.ub_cnt[out] = cnt;
+          if (I.sum) a.ub_sum[out] = exact_round(tot, I.D, I.lsb, a.err);
+        }
+        a.row_nnz[t] = cnt ? 1u : 0u;
+      }
+      continue;
+    }
+    // matrix: hash the row's products by k
+    for (int s = lane; s < HS; s += WAVE) {
+      hk[s] = EMPTY_KEY;
+      hc[s] = 0;
+#pragma unroll
+      for (int d = 0; d < EXACT_MAXD; d++) hd[s * EXACT_MAXD + d] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t q = qb + lane; q < qe; q += WAVE) {
+      uint32_t pe;
+      if (!find_j(I, I.a_j[q], pe)) continue;
+      uint32_t ab, ae;
+      rows_of(I.a_run, q, ab, ae);
+      for (uint32_t kp = I.e_off[pe]; kp < I.e_off[pe + 1]; kp++) {
+        const uint32_t k = I.e_k[kp];
+        uint32_t slot = (k * 2654435761u) >> 24;  // HS = 256
+        for (;;) {
+          const uint32_t prev = atomicCAS(&hk[slot], EMPTY_KEY, k);
+          if (prev == EMPTY_KEY || prev == k) break;
+          slot = (slot + 1) & (HS - 1);
+        }
+        uint32_t eb, ee;
+        rows_of(I.e_run, kp, eb, ee);
+        atomicAdd(&hc[slot], (unsigned long long)(ae - ab) * (ee - eb));
+        if (I.sum)
+          for (uint32_t ra = ab; ra < ae; ra++)
+            for (uint32_t re = eb; re < ee; re++) {
+              double hi, lo;
+              two_prod(I.a_val[ra], I.e_val[re], hi, lo);
+              bool ok = lds_add_term(hd + slot * EXACT_MAXD, hi, I.lsb, I.D, 1);
+              ok = lds_add_term(hd + slot * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
+              if (!ok) bad = 1;
+            }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // list the occupied slots, then place each by its rank in k order
+    uint32_t m = 0;
+    for (int s0 = 0; s0 < HS; s0 += WAVE) {
+      const bool occ = hk[s0 + lane] != EMPTY_KEY;
+      const uint64_t bal = ballot(occ);
+      if (occ) hl[m + lanes_below(bal)] = (uint16_t)(s0 + lane);
+      m += (uint32_t)__popcll(bal);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t e = lane; e < m; e += WAVE) {
+      const uint32_t s = hl[e];
+      const uint32_t k = hk[s];
+      uint32_t rank = 0;
+      for (uint32_t f = 0; f < m; f++) rank += hk[hl[f]] < k ? 1u : 0u;
+      const uint64_t o = out + rank;
+      a.ub_k[o] = k;
+      a.ub_cnt[o] = hc[s];
+      if (I.sum) a.ub_sum[o] = exact_round((const int64_t*)(hd + s * EXACT_MAXD), I.D, I.lsb, a.err);
+    }
+    if (lane == 0) a.row_nnz[t] = m;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (bad) atomicOr(a.err, 1u);
+}
+
+// Copy each row's outputs from its upper-bound slots to the packed result.
+struct PackArgs2 {
+  const BInst* inst;
+  const uint32_t* row_inst;
+  const uint64_t* inst_row0;
+  const uint64_t* ub_off;
+  const uint64_t* out_off;   // exclusive scan of row_nnz
+  const uint32_t* ub_k;
+  const uint64_t* ub_cnt;
+  const double* ub_sum;
+  uint32_t* out_i;
+  uint32_t* out_k;
+  uint64_t* out_cnt;
+  double* out_sum;
+  uint64_t R;
+};
+
+__global__ void k_pack_rows(PackArgs2 a) {
+  const int lane = lane_id();
+  const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / WAVE);
+  for (uint64_t t = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; t < a.R; t += nw) {
+    const uint64_t o0 = a.out_off[t], n = a.out_off[t + 1] - o0;
+    if (!n) continue;
+    const uint32_t ii = a.row_inst[t];
+    const BInst& I = a.inst[ii];
+    const uint32_t i = I.a_i[t - a.inst_row0[ii]];
+    const uint64_t u0 = a.ub_off[t];
+    for (uint64_t e = lane; e < n; e += WAVE) {
+      a.out_i[o0 + e] = i;
+      if (I.kind == 1) a.out_k[o0 + e] = a.ub_k[u0 + e];
+      a.out_cnt[o0 + e] = a.ub_cnt[u0 + e];
+      if (I.sum) a.out_sum[o0 + e] = a.ub_sum[u0 + e];
+    }
+  }
+}
+
+// Join tuples per instance: the sum of its output counts.
+__global__ void k_inst_sums(const uint64_t* cnt, const uint64_t* lo, const uint64_t* hi, uint64_t* out) {
+  __shared__ uint64_t red[B_NW];
+  uint64_t s = 0;
+  for (uint64_t e = lo[blockIdx.x] + threadIdx.x; e < hi[blockIdx.x]; e += blockDim.x) s += cnt[e];
+  s = block_sum<uint64_t, B_NT>(s, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+unsigned grid_for(uint64_t n) {
+  uint64_t b = (n + 255) / 256;
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(b, 256 * 64));
+}
+
+// ---- host side ----------------------------------------------------------------
+
+struct Tuning {
+  uint32_t light_max = 128;   // products above which a matrix row is heavy
+  uint32_t win = 1024;        // dense window of the heavy path
+  uint32_t blocks_per_cu = 2; // persistent grid
+};
+
+// Everything one batch needs; kept across calls with the same plans so the
+// graph is replayed rather than rebuilt.
+struct BatchState {
+  std::vector<const lh_plan_t*> plans;
+  Tuning tune;
+  uint64_t R = 0, UB = 0;
+  hipStream_t s = nullptr;
+  DBuf<BInst> inst;
+  DBuf<uint64_t> inst_row0, prod, ub_off;
+  DBuf<uint32_t> row_inst, ub, heavy_f, light_f, heavy, light, qhead, row_nnz, ub_k, err;
+  DBuf<uint64_t> ub_cnt;
+  DBuf<double> ub_sum;
+  uint64_t n_heavy = 0, n_light = 0;
+  std::vector<uint64_t> h_inst_row0;
+  std::vector<BInst> h_inst;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  ~BatchState() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+std::mutex g_batch_mu;
+std::unique_ptr<BatchState> g_batch;
+
+BInst describe(const lh_plan_t* p) {
+  const PlanAtom& A = p->atoms[0];
+  const PlanAtom& E = p->atoms[1];
+  const lh_trie* ta = A.trie;
+  const lh_trie* te = E.trie;
+  BInst b{};
+  b.kind = E.n_levels == 1 ? 0u : 1u;
+  b.n_rows = (uint32_t)ta->lv[0].n;
+  b.a_i = ta->lv[0].keys.p;
+  b.a_off = ta->lv[0].offs.p;
+  b.a_j = ta->lv[1].keys.p;
+  b.a_run = A.bag ? ta->lv[1].offs.p : nullptr;
+  b.sum = p->agg == LH_AGG_SUM ? 1u : 0u;
+  b.a_val = (b.sum && A.anno >= 0) ? ta->annos[A.anno].p : nullptr;
+  b.e_j = te->lv[0].keys.p;
+  b.e_n0 = (uint32_t)te->lv[0].n;
+  b.e_pool = te->lv[0].pool.p;
+  b.e_bsw = UINT64_MAX;
+  b.e_bsb = 0;
+  if (b.e_n0) {
+    LH_HIP(hipMemcpy(&b.e_bsw, te->lv[0].bs_word.p, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    LH_HIP(hipMemcpy(&b.e_bsb, te->lv[0].bs_base.p, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  }
+  if (b.kind == 1) {
+    b.e_off = te->lv[0].offs.p;
+    b.e_k = te->lv[1].keys.p;
+    b.n_k = te->key_max[1] + 1;
+  }
+  b.e_run = E.bag ? te->lv[E.n_levels - 1].offs.p : nullptr;
+  b.e_val = (b.sum && E.anno >= 0) ? te->annos[E.anno].p : nullptr;
+  b.lsb = p->exact_lsb;
+  b.D = p->exact_digits;
+  return b;
+}
+
+std::string cache_path() {
+  const char* e = std::getenv("LH_AUTOTUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = std::getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/lh_autotune.txt";
+}
+
+std::string signature(const BatchState& b) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&prop, dev);
+  std::ostringstream os;
+  uint64_t rows_log = 0, ub_log = 0;
+  while ((1ull << rows_log) < b.R) rows_log++;
+  while ((1ull << ub_log) < b.UB) ub_log++;
+  os << prop.gcnArchName << "_cu" << prop.multiProcessorCount << "_inst" << b.plans.size() << "_r" << rows_log << "_u"
+     << ub_log;
+  return os.str();
+}
+
+bool load_tuning(const std::string& sig, Tuning& t) {
+  std::ifstream f(cache_path());
+  std::string key;
+  Tuning x;
+  while (f >> key >> x.light_max >> x.win >> x.blocks_per_cu) {
+    if (key == sig) {
+      t = x;
+      return true;
+    }
+  }
+  return false;
+}
+
+void save_tuning(const std::string& sig, const Tuning& t) {
+  std::string path = cache_path();
+  std::string dir = path.substr(0, path.find_last_of('/'));
+  (void)std::system(("mkdir -p '" + dir + "' 2>/dev/null").c_str());
+  std::ofstream f(path, std::ios::app);
+  f << sig << " " << t.light_max << " " << t.win << " " << t.blocks_per_cu << "\n";
+}
+
+void setup(BatchState& b, hipStream_t s) {
+  const uint32_t n = (uint32_t)b.plans.size();
+  b.s = s;
+  b.h_inst.resize(n);
+  b.h_inst_row0.assign(n + 1, 0);
+  for (uint32_t i = 0; i < n; i++) {
+    b.h_inst[i] = describe(b.plans[i]);
+    b.h_inst[i].row_base = b.h_inst_row0[i];
+    b.h_inst_row0[i + 1] = b.h_inst_row0[i] + b.h_inst[i].n_rows;
+  }
+  b.R = b.h_inst_row0[n];
+  if (b.R >= (1ull << 32)) fail(LH_ERR_OVERFLOW, "batch: more than 2^32 rows");
+  b.inst.alloc(n, s);
+  LH_HIP(hipMemcpyAsync(b.inst.p, b.h_inst.data(), n * sizeof(BInst), hipMemcpyHostToDevice, s));
+  b.inst_row0.alloc(n + 1, s);
+  LH_HIP(hipMemcpyAsync(b.inst_row0.p, b.h_inst_row0.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  b.row_inst.alloc(b.R, s);
+  b.prod.alloc(b.R, s);
+  b.ub.alloc(b.R, s);
+  b.heavy_f.alloc(b.R, s);
+  b.light_f.alloc(b.R, s);
+  if (b.R) {
+    k_row_setup<<<grid_for(b.R), 256, 0, s>>>(b.inst.p, b.inst_row0.p, n, b.R, b.tune.light_max, b.row_inst.p, b.prod.p,
+                                              b.ub.p, b.heavy_f.p, b.light_f.p);
+    LH_HIP(hipGetLastError());
+  }
+  b.ub_off.alloc(b.R + 1, s);
+  b.UB = scan_u32_to_u64(b.ub.p, b.ub_off.p, b.R, s);
+  b.heavy.alloc(b.R, s);
+  b.light.alloc(b.R, s);
+  b.n_heavy = select_flagged(b.heavy_f.p, b.R, b.heavy.p, s);
+  b.n_light = select_flagged(b.light_f.p, b.R, b.light.p, s);
+  // heavy rows longest first (LPT): sort their ids by descending product count
+  if (b.n_heavy > 1) {
+    DBuf<uint64_t> key(b.n_heavy, s), tk(b.n_heavy, s);
+    DBuf<uint32_t> tv(b.n_heavy, s);
+    std::vector<uint32_t> hrows(b.n_heavy);
+    std::vector<uint64_t> hp(b.R);
+    LH_HIP(hipMemcpyAsync(hrows.data(), b.heavy.p, b.n_heavy * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    LH_HIP(hipMemcpyAsync(hp.data(), b.prod.p, b.R * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    LH_HIP(hipStreamSynchronize(s));
+    std::stable_sort(hrows.begin(), hrows.end(), [&](uint32_t x, uint32_t y) { return hp[x] > hp[y]; });
+    LH_HIP(hipMemcpyAsync(b.heavy.p, hrows.data(), b.n_heavy * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  }
+  b.qhead.alloc(2, s);
+  b.row_nnz.alloc(b.R, s);
+  b.ub_k.alloc(b.UB, s);
+  b.ub_cnt.alloc(b.UB, s);
+  b.ub_sum.alloc(b.UB, s);
+  b.err.alloc(1, s);
+  LH_HIP(hipStreamSynchronize(s));
+}
+
+void launch_compute(BatchState& b, hipStream_t s) {
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  k_fill_u32_dev<<<1, 64, 0, s>>>(b.qhead.p, 0u, 2);
+  k_fill_u32_dev<<<1, 64, 0, s>>>(b.err.p, 0u, 1);
+  BatchArgs a{};
+  a.inst = b.inst.p;
+  a.row_inst = b.row_inst.p;
+  a.inst_row0 = b.inst_row0.p;
+  a.ub_off = b.ub_off.p;
+  a.heavy = b.heavy.p;
+  a.n_heavy = b.n_heavy;
+  a.light = b.light.p;
+  a.n_light = b.n_light;
+  a.qhead = b.qhead.p;
+  a.row_nnz = b.row_nnz.p;
+  a.ub_k = b.ub_k.p;
+  a.ub_cnt = b.ub_cnt.p;
+  a.ub_sum = b.ub_sum.p;
+  a.err = b.err.p;
+  const unsigned grid = (unsigned)(cus * b.tune.blocks_per_cu);
+  if (b.tune.win == 512) k_batch<512><<<grid, B_NT, 0, s>>>(a);
+  else k_batch<1024><<<grid, B_NT, 0, s>>>(a);
+}
+
+void build_graph(BatchState& b) {
+  if (!b.cap) LH_HIP(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+  LH_HIP(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
+  launch_compute(b, b.cap);
+  hipError_t e = hipStreamEndCapture(b.cap, &b.graph);
+  if (e != hipSuccess) hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+  LH_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+}
+
+float time_replay(BatchState& b, hipStream_t s) {
+  hipEvent_t e0, e1;
+  LH_HIP(hipEventCreate(&e0));
+  LH_HIP(hipEventCreate(&e1));
+  LH_HIP(hipEventRecord(e0, s));
+  LH_HIP(hipGraphLaunch(b.exec, s));
+  LH_HIP(hipEventRecord(e1, s));
+  LH_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  LH_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+// The project's autotuner: time each candidate's graph twice, keep the
+// fastest, remember it per device and batch signature.
+void autotune(std::unique_ptr<BatchState>& cur, lh_plan_t* const* plans, uint32_t n, hipStream_t s) {
+  const std::string sig = signature(*cur);
+  Tuning t;
+  if (load_tuning(sig, t)) {
+    if (t.light_max != cur->tune.light_max || t.win != cur->tune.win || t.blocks_per_cu != cur->tune.blocks_per_cu) {
+      auto nb = std::make_unique<BatchState>();
+      nb->plans = cur->plans;
+      nb->tune = t;
+      setup(*nb, s);
+      build_graph(*nb);
+      cur = std::move(nb);
+    }
+    return;
+  }
+  const uint32_t lights[] = {64, 128};
+  const uint32_t wins[] = {512, 1024};
+  const uint32_t bpcs[] = {1, 2, 4};
+  float best = 3.0e38f;
+  std::unique_ptr<BatchState> winner;
+  for (uint32_t lm : lights)
+    for (uint32_t wn : wins)
+      for (uint32_t bp : bpcs) {
+        auto cand = std::make_unique<BatchState>();
+        cand->plans = cur->plans;
+        cand->tune = Tuning{lm, wn, bp};
+        setup(*cand, s);
+        build_graph(*cand);
+        (void)time_replay(*cand, s);
+        float ms = std::min(time_replay(*cand, s), time_replay(*cand, s));
+        if (ms < best) {
+          best = ms;
+          winner = std::move(cand);
+        }
+      }
+  save_tuning(sig, winner->tune);
+  cur = std::move(winner);
+}
+
+struct SharedOut {
+  DBuf<uint32_t> out_i, out_k;
+  DBuf<uint64_t> out_cnt;
+  DBuf<double> out_sum;
+};
+
+}  // namespace
+
+int row_union_kind(const lh_plan_t* p) {
+  if (p->atoms.size() != 2 || !p->groups.empty()) return -1;
+  const PlanAtom& A = p->atoms[0];
+  const PlanAtom& E = p->atoms[1];
+  if (A.n_levels != 2) return -1;
+  // attribute roles: i = A's first level, j = A's second level
+  const uint32_t i = A.attr_of_level[0], j = A.attr_of_level[1];
+  if (p->order[0] != i || p->order[1] != j) return -1;
+  if (E.n_levels == 1) {
+    if (p->n_attrs != 2 || E.attr_of_level[0] != j) return -1;
+    if (p->out_attrs.size() != 1 || p->out_attrs[0] != i) return -1;
+    return 0;
+  }
+  if (E.n_levels == 2) {
+    if (p->n_attrs != 3 || E.attr_of_level[0] != j) return -1;
+    const uint32_t k = E.attr_of_level[1];
+    if (p->order[2] != k) return -1;
+    if (p->out_attrs.size() != 2 || p->out_attrs[0] != i || p->out_attrs[1] != k) return -1;
+    return 1;
+  }
+  return -1;
+}
+
+bool run_batch(lh_plan_t* const* plans, uint32_t n, hipStream_t s, std::vector<lh_result_impl*>& out) {
+  for (uint32_t i = 0; i < n; i++)
+    if (row_union_kind(plans[i]) < 0) return false;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  std::vector<const lh_plan_t*> pv(plans, plans + n);
+  if (!g_batch || g_batch->plans != pv) {
+    g_batch.reset();
+    auto b = std::make_unique<BatchState>();
+    b->plans = pv;
+    setup(*b, s);
+    build_graph(*b);
+    autotune(b, plans, n, s);
+    g_batch = std::move(b);
+  }
+  BatchState& b = *g_batch;
+  {
+    ProfScope ps("batch_graph", s, b.R, b.UB);
+    LH_HIP(hipGraphLaunch(b.exec, s));
+  }
+  // pack: scan the per-row output counts, one shared output block
+  DBuf<uint64_t> out_off(b.R + 1, s);
+  const uint64_t total = scan_u32_to_u64(b.row_nnz.p, out_off.p, b.R, s);
+  if (read_scalar(b.err.p, s)) fail(LH_ERR_UNSUPPORTED, "an annotation product did not fit the exact accumulator");
+  auto sh = std::make_shared<SharedOut>();
+  sh->out_i.alloc(total, s);
+  sh->out_k.alloc(total, s);
+  sh->out_cnt.alloc(total, s);
+  sh->out_sum.alloc(total, s);
+  PackArgs2 pa{};
+  pa.inst = b.inst.p;
+  pa.row_inst = b.row_inst.p;
+  pa.inst_row0 = b.inst_row0.p;
+  pa.ub_off = b.ub_off.p;
+  pa.out_off = out_off.p;
+  pa.ub_k = b.ub_k.p;
+  pa.ub_cnt = b.ub_cnt.p;
+  pa.ub_sum = b.ub_sum.p;
+  pa.out_i = sh->out_i.p;
+  pa.out_k = sh->out_k.p;
+  pa.out_cnt = sh->out_cnt.p;
+  pa.out_sum = sh->out_sum.p;
+  pa.R = b.R;
+  if (b.R) {
+    ProfScope ps("batch_pack", s, b.R, total);
+    k_pack_rows<<<grid_for(b.R * WAVE), 256, 0, s>>>(pa);
+    LH_HIP(hipGetLastError());
+  }
+  std::vector<uint64_t> offs(b.R + 1);
+  LH_HIP(hipMemcpyAsync(offs.data(), out_off.p, (b.R + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  LH_HIP(hipStreamSynchronize(s));
+  std::vector<uint64_t> lo(n), hi(n), nj(n, 0);
+  for (uint32_t i = 0; i < n; i++) {
+    lo[i] = offs[b.h_inst_row0[i]];
+    hi[i] = offs[b.h_inst_row0[i + 1]];
+  }
+  {
+    DBuf<uint64_t> dlo(n, s), dhi(n, s), dnj(n, s);
+    LH_HIP(hipMemcpyAsync(dlo.p, lo.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    LH_HIP(hipMemcpyAsync(dhi.p, hi.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    k_inst_sums<<<n, B_NT, 0, s>>>(sh->out_cnt.p, dlo.p, dhi.p, dnj.p);
+    LH_HIP(hipGetLastError());
+    LH_HIP(hipMemcpyAsync(nj.data(), dnj.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    LH_HIP(hipStreamSynchronize(s));
+  }
+  for (uint32_t i = 0; i < n; i++) {
+    const BInst& I = b.h_inst[i];
+    const uint64_t o0 = lo[i], o1 = hi[i];
+    auto* r = new lh_result_impl();
+    memset(&r->pub, 0, sizeof(r->pub));
+    r->shared = sh;
+    r->colptr.push_back(sh->out_i.p ? sh->out_i.p + o0 : nullptr);
+    if (I.kind == 1) r->colptr.push_back(sh->out_k.p ? sh->out_k.p + o0 : nullptr);
+    r->pub.n_rows = o1 - o0;
+    r->pub.n_cols = (uint32_t)r->colptr.size();
+    r->pub.out_keys = r->colptr.data();
+    r->pub.counts = sh->out_cnt.p ? sh->out_cnt.p + o0 : nullptr;
+    r->pub.sums = I.sum ? (sh->out_sum.p ? sh->out_sum.p + o0 : nullptr) : nullptr;
+    r->pub.exact = I.sum;
+    r->pub.n_join_tuples = nj[i];
+    out.push_back(r);
+  }
+  return true;
+}
+
+void batch_forget_plan(const lh_plan_t* p) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  if (g_batch && std::find(g_batch->plans.begin(), g_batch->plans.end(), p) != g_batch->plans.end()) g_batch.reset();
+}
+
+}  // namespace lh

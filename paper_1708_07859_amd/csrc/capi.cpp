@@ -136,7 +136,8 @@ lh_status lh_join_aggregate(lh_plan_t* const* plans, uint32_t n_plans, void* hip
     for (uint32_t i = 0; i < n_plans; i++)
       if (!tracked(g_plans, plans[i])) fail(LH_ERR_INVALID, "not a live lh_plan");
     hipStream_t s = (hipStream_t)hip_stream;
-    for (uint32_t i = 0; i < n_plans; i++) made.push_back(run_plan(plans[i], s));
+    if (n_plans == 1 || !run_batch(plans, n_plans, s, made))
+      for (uint32_t i = 0; i < n_plans; i++) made.push_back(run_plan(plans[i], s));
   });
   if (st != LH_OK) {
     for (auto* r : made) delete r;
@@ -154,6 +155,7 @@ void lh_free(void* h) {
   if (untrack(g_tries, h)) {
     delete static_cast<lh_trie*>(h);
   } else if (untrack(g_plans, h)) {
+    batch_forget_plan(static_cast<lh_plan_t*>(h));
     delete static_cast<lh_plan_t*>(h);
   } else if (untrack(g_results, h)) {
     delete reinterpret_cast<lh_result_impl*>(h);

@@ -67,12 +67,20 @@ struct lh_result_impl {
   std::vector<const uint32_t*> colptr;
   lh::DBuf<uint64_t> counts;
   lh::DBuf<double> sums;
+  std::shared_ptr<void> shared;             // batched results share one output block
 };
 
 namespace lh {
 
 lh_plan_t* make_plan(const lh_query* q, hipStream_t s);
 lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s);
+// Batched execution of many plans; returns false (and does nothing) when
+// the plans are not all of a shape the batched executor handles.
+bool run_batch(lh_plan_t* const* plans, uint32_t n, hipStream_t s, std::vector<lh_result_impl*>& out);
+// Row-union shape: A(i,j) with E(j) (SpMV) or E(j,k) (SpGEMM), order i,j[,k].
+int row_union_kind(const lh_plan_t* p);
+// Drop the cached batch (and its graph) if it refers to this plan.
+void batch_forget_plan(const lh_plan_t* p);
 void free_trie(lh_trie* t);
 
 }  // namespace lh
