@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=15)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--layout", default="plain", choices=["plain", "uint", "bitset", "learned"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch"])
+    ap.add_argument("--instances", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU layout is a design "
@@ -86,6 +88,8 @@ def main():
     from paper_1708_07859_amd import lh
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return bench_batch(args, lh, torch, synth)
     log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
     t0 = time.perf_counter()
     lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
@@ -165,6 +169,85 @@ def main():
     if not args.no_cpu:
         log(f"cpu baseline: oracle on R-MAT scale {args.cpu_scale}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_scale)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, lh, torch, synth):
+    """512 SpMV / SpGEMM join-aggregate instances (n log-uniform in [1k, 64k],
+    Zipf(1.1) row degrees with mean 16): one batched lh_join_aggregate call
+    (persistent, graph-captured launch) against the same plans run one call
+    per plan.  Tries and plans are built once, outside the timed region."""
+    import numpy as np
+    log(f"generating {args.instances} instances")
+    t0 = time.perf_counter()
+    insts = synth.batched_instances(count=args.instances)
+    log(f"  {sum(i['n'] for i in insts)} rows, {sum(len(i['rows']) for i in insts)} nonzeros "
+        f"in {time.perf_counter() - t0:.1f} s")
+    tries, plans = [], []
+    tuples = 0
+    for inst in insts:
+        ta = lh.trie_build([inst["rows"], inst["cols"]], [inst["vals"]], bag=True)
+        tries.append(ta)
+        nnz = len(inst["rows"])
+        if inst["kind"] == "spmv":
+            n = inst["n"]
+            tx = lh.trie_build([np.arange(n, dtype=np.uint32)], [inst["x"]], bag=True)
+            tries.append(tx)
+            plans.append(lh.plan(2, [(ta, [0, 1], 0), (tx, [1], 0)], out=[0], agg="sum"))
+            tuples += nnz + n
+        else:
+            plans.append(lh.plan(3, [(ta, [0, 1], 0), (ta, [1, 2], 0)], out=[0, 2], agg="sum"))
+            tuples += 2 * nnz
+    torch.cuda.synchronize()
+    # sequential: one call per plan
+    log("sequential")
+    lh.join_aggregate([plans[0]])[0].free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_rows = 0
+    for p in plans:
+        r = lh.join_aggregate([p])[0]
+        seq_rows += r.n_rows
+        r.free()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1000
+    log(f"  {seq_ms:.1f} ms, {seq_rows} output rows")
+    # batched: first call builds, tunes and captures; then replays
+    log("batched: setup + autotune")
+    t0 = time.perf_counter()
+    for r in lh.join_aggregate(plans):
+        r.free()
+    log(f"  first call {time.perf_counter() - t0:.1f} s")
+    for _ in range(args.warmup):
+        for r in lh.join_aggregate(plans):
+            r.free()
+    torch.cuda.synchronize()
+    lh.profile_reset()
+    lh.profile_enable(True)
+    t0 = time.perf_counter()
+    bat_rows = 0
+    for _ in range(args.steps):
+        rs = lh.join_aggregate(plans)
+        bat_rows = sum(r.n_rows for r in rs)
+        for r in rs:
+            r.free()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000 / args.steps
+    lh.profile_enable(False)
+    prof = lh.profile_read()
+    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
+        log(f"  {k:22s} launches={v['launches']:6d} total={v['total_ms']:9.3f} ms")
+    assert bat_rows == seq_rows
+    out = {
+        "metric": METRIC, "value": tuples / (ms / 1000), "unit": "tuples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.instances} SpMV/SpGEMM instances, n log-uniform [1k,64k], Zipf(1.1) "
+                               "degrees mean 16, FP64 U(-1,1)",
+                   "step": "lh_join_aggregate over all plans (batched)",
+                   "sequential_ms": seq_ms, "batched_ms": ms, "batched_over_sequential": seq_ms / ms,
+                   "output_rows": bat_rows},
+    }
     print(json.dumps(out), flush=True)
 
 

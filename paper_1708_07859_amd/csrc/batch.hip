@@ -647,27 +647,50 @@ void autotune(std::unique_ptr<BatchState>& cur, lh_plan_t* const* plans, uint32_
     }
     return;
   }
+  // The light/heavy split changes the setup; window and grid only change
+  // the captured launch, so they are tried on one setup each.
   const uint32_t lights[] = {64, 128};
   const uint32_t wins[] = {512, 1024};
-  const uint32_t bpcs[] = {1, 2, 4};
+  const uint32_t bpcs[] = {1, 2};
   float best = 3.0e38f;
   std::unique_ptr<BatchState> winner;
-  for (uint32_t lm : lights)
+  Tuning best_t = cur->tune;
+  for (uint32_t lm : lights) {
+    std::unique_ptr<BatchState> cand;
+    if (lm == cur->tune.light_max) {
+      cand = std::move(cur);
+    } else {
+      cand = std::make_unique<BatchState>();
+      cand->plans = winner ? winner->plans : std::vector<const lh_plan_t*>(plans, plans + n);
+      cand->tune.light_max = lm;
+      setup(*cand, s);
+    }
     for (uint32_t wn : wins)
       for (uint32_t bp : bpcs) {
-        auto cand = std::make_unique<BatchState>();
-        cand->plans = cur->plans;
-        cand->tune = Tuning{lm, wn, bp};
-        setup(*cand, s);
+        if (cand->exec) (void)hipGraphExecDestroy(cand->exec);
+        if (cand->graph) (void)hipGraphDestroy(cand->graph);
+        cand->exec = nullptr;
+        cand->graph = nullptr;
+        cand->tune.win = wn;
+        cand->tune.blocks_per_cu = bp;
         build_graph(*cand);
-        (void)time_replay(*cand, s);
-        float ms = std::min(time_replay(*cand, s), time_replay(*cand, s));
+        float ms = time_replay(*cand, s);
         if (ms < best) {
           best = ms;
-          winner = std::move(cand);
+          best_t = cand->tune;
         }
       }
-  save_tuning(sig, winner->tune);
+    if (!winner || best_t.light_max == lm) winner = std::move(cand);
+  }
+  if (winner->tune.win != best_t.win || winner->tune.blocks_per_cu != best_t.blocks_per_cu) {
+    (void)hipGraphExecDestroy(winner->exec);
+    (void)hipGraphDestroy(winner->graph);
+    winner->exec = nullptr;
+    winner->graph = nullptr;
+    winner->tune = best_t;
+    build_graph(*winner);
+  }
+  save_tuning(sig, best_t);
   cur = std::move(winner);
 }
 
