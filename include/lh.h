@@ -194,6 +194,8 @@ typedef struct {
   uint64_t level_bitsets[LH_MAX_KEYS];  /* sets stored as bitsets */
   uint64_t level_words[LH_MAX_KEYS];    /* 64-bit bitset words per level */
   uint32_t level_order[LH_MAX_KEYS];
+  uint64_t col_distinct[LH_MAX_KEYS];   /* distinct values of each level's column */
+  uint64_t col_freq_max[LH_MAX_KEYS];   /* most rows sharing one value of it */
 } lh_trie_info;
 
 lh_status lh_trie_get_info(const lh_trie* t, lh_trie_info* info);
@@ -235,6 +237,11 @@ typedef struct {
   const uint64_t* edge_card;
   const uint32_t* edge_eq;
   const uint32_t* edge_dense;
+  /* optional, aligned with edge_attrs (attributes listed in trie level
+   * order): log2(1 + mean) and log2(1 + largest) number of rows sharing one
+   * value of that attribute's column; used by lh_order_features only */
+  const float* edge_attr_lf_mean;
+  const float* edge_attr_lf_max;
 } lh_hypergraph;
 
 /* cost = SUM_i icost(order[i]) * weight(order[i]) (section 4); icost and
@@ -267,6 +274,55 @@ typedef struct {
   uint64_t rows;
   uint64_t elements;
 } lh_profile_entry;
+
+/* ---- the learned cost model ----------------------------------------------
+ * A 3-layer perceptron d_in -> 64 -> 64 -> 1 (ReLU) predicting log2 of a
+ * cost.  Training runs FP32 forward, backward and Adam kernels on the GPU;
+ * inference for decisions runs a BF16 kernel (bf16 weights and activations,
+ * fp32 sums).  Parameters are packed fp32: W1 (64 x d_in), b1 (64),
+ * W2 (64 x 64), b2 (64), W3 (1 x 64), b3 (1), row-major.  All arrays below
+ * are HOST arrays; X is n x d_in row-major.
+ *
+ * Two decisions can use a registered model (lh_use_model); without one they
+ * follow the plain rules of section 4, which also remain the judge of the
+ * model's regret.  Join results never depend on these choices.
+ *  LH_MODEL_LAYOUT: per-set layout at lh_trie_build with LH_LAYOUT_LEARNED
+ *    (sets of 32+ elements); features [log2 card, log2 span, log2(card/span),
+ *    choice (0 uint, 1 bitset)], target log2(ns per probe).
+ *  LH_MODEL_ORDER: attribute order at lh_plan with LH_POLICY_LEARNED;
+ *    features from lh_order_features, target log2(plan + join time). */
+typedef struct lh_mlp lh_mlp;
+#define LH_MODEL_LAYOUT 0u
+#define LH_MODEL_ORDER  1u
+#define LH_LAYOUT_FEATURES 4u
+#define LH_ORDER_FEATURES 24u
+
+lh_status lh_mlp_create(uint32_t d_in, uint32_t width, uint64_t seed, lh_mlp** out);  /* width must be 64 */
+void lh_mlp_free(lh_mlp* m);
+uint64_t lh_mlp_num_params(const lh_mlp* m);
+lh_status lh_mlp_get_params(const lh_mlp* m, float* params);
+lh_status lh_mlp_set_params(lh_mlp* m, const float* params);
+/* FP32 forward + backward of one batch: mean of (p - y)^2 / 2 and the
+ * packed gradient (num_params floats; may be NULL). */
+lh_status lh_mlp_loss_grad(const lh_mlp* m, const float* X, const float* y, uint32_t n, void* hip_stream,
+                           float* loss, float* grad);
+/* Adam (beta 0.9 / 0.999) over shuffled minibatches for `epochs` epochs. */
+lh_status lh_mlp_train(lh_mlp* m, const float* X, const float* y, uint32_t n, uint32_t epochs, uint32_t batch,
+                       float lr, uint64_t seed, void* hip_stream, float* final_loss);
+/* Predictions y (n floats); bf16 = 1 uses the BF16 inference kernel. */
+lh_status lh_mlp_predict(const lh_mlp* m, const float* X, uint64_t n, uint32_t bf16, void* hip_stream, float* y);
+/* Register m (or NULL) for a decision; the model must outlive its use. */
+lh_status lh_use_model(uint32_t slot, const lh_mlp* m);
+/* LH_ORDER_FEATURES floats describing an attribute order: for each of the
+ * first 4 positions the section 4 icost / 50, log2(1 + weight), and over
+ * the relations holding the attribute the smallest and largest log2 mean
+ * size and the largest log2 maximum size of the set each offers there
+ * (root set: distinct values; else rows per value of the attribute bound
+ * just before in that relation); then log2(1 + rows of relations the order
+ * forces to re-sort, their edge attributes being listed in trie level
+ * order), log2(1 + all rows), the attribute count and log2(1 + the section
+ * 4 cost). */
+lh_status lh_order_features(const lh_hypergraph* h, const uint32_t* order, float* features);
 
 void lh_profile_enable(int on);
 void lh_profile_reset(void);

@@ -176,6 +176,8 @@ lh_status lh_trie_get_info(const lh_trie* t, lh_trie_info* info) {
       info->level_sets[l] = t->lv[l].n_sets;
       info->level_words[l] = t->lv[l].pool_words;
       info->level_order[l] = t->level_order[l];
+      info->col_distinct[l] = t->col_distinct[l];
+      info->col_freq_max[l] = t->col_freq_max[l];
       uint64_t nb = 0;
       if (t->lv[l].n_sets) {
         std::vector<uint64_t> w(t->lv[l].n_sets);

@@ -13,6 +13,9 @@ struct Edge {
   uint64_t card = 0;            // relation cardinality (before filters)
   bool eq = false;              // an equality selection applies to the relation
   bool dense = false;           // completely dense: contributes no intersection
+  // per attribute (aligned with attrs): log2 of the mean and the largest
+  // number of rows sharing one value of that attribute's column
+  std::vector<float> lf_mean, lf_max;
 };
 
 struct Hypergraph {

@@ -88,6 +88,10 @@ uint64_t scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s);
 // Exclusive scan, uint32 -> uint32 (caller guarantees the total fits); out has n+1.
 uint32_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s);
 uint32_t reduce_max_u32(const uint32_t* in, uint64_t n, hipStream_t s);
+// Distinct values and the largest value frequency of a column whose values
+// are below `range` (a histogram pass).
+void column_freq(const uint32_t* col, uint64_t n, uint32_t range, uint64_t& distinct, uint64_t& freq_max,
+                 hipStream_t s);
 // Indices i < n with flags[i] != 0, in order, into out (n entries); returns count.
 uint64_t select_flagged(const uint32_t* flags, uint64_t n, uint32_t* out, hipStream_t s);
 void iota_u32(uint32_t* out, uint64_t n, hipStream_t s);
@@ -141,6 +145,8 @@ struct lh_trie {
   uint32_t level_order[LH_MAX_KEYS];   // input key column of each level
   uint32_t key_bits[LH_MAX_KEYS];      // significant bits per level
   uint32_t key_max[LH_MAX_KEYS];       // largest key per level
+  uint64_t col_distinct[LH_MAX_KEYS];  // distinct values of each level's column (kept rows)
+  uint64_t col_freq_max[LH_MAX_KEYS];  // largest number of kept rows sharing one value
   lh::Level lv[LH_MAX_KEYS];
   // rows in trie order (bag: every row; set: one per distinct tuple)
   lh::DBuf<uint32_t> skeys[LH_MAX_KEYS];   // per level
@@ -165,6 +171,10 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
 
 // Per-set layout and bitset materialization for one level.
 void build_layouts(lh_trie* t, uint32_t level, uint32_t layout_flags, hipStream_t s);
+
+// Per-set layout choices from the registered learned layout model (0 plain
+// rule, 1 uint, 2 bitset); false when no model is registered.
+bool learned_layout_choices(const lh_trie* t, uint32_t level, hipStream_t s, DBuf<uint8_t>& choice);
 
 }  // namespace lh
 

@@ -11,6 +11,9 @@
 
 namespace lh {
 
+bool learned_order(const Hypergraph& h, const std::vector<uint32_t>& out_attrs, std::vector<uint32_t>& order,
+                   hipStream_t s);
+
 namespace {
 
 // One selection over a trie's rows (trie order): equality on a key or meta
@@ -180,7 +183,13 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
   for (uint32_t e = 0; e < q->n_atoms; e++) {
     const lh_atom& A = q->atoms[e];
     Edge E;
-    for (uint32_t c = 0; c < A.trie->n_levels; c++) E.attrs.push_back(A.attr_of_key[c]);
+    // attributes in the trie's level order (an order that breaks it re-sorts the relation)
+    for (uint32_t l = 0; l < A.trie->n_levels; l++) {
+      E.attrs.push_back(A.attr_of_key[A.trie->level_order[l]]);
+      const double d = (double)std::max<uint64_t>(1, A.trie->col_distinct[l]);
+      E.lf_mean.push_back((float)std::log2(1.0 + (double)A.trie->n_rows / d));
+      E.lf_max.push_back((float)std::log2(1.0 + (double)A.trie->col_freq_max[l]));
+    }
     E.card = A.trie->n_input;
     E.eq = eqsel[e];
     E.dense = (A.trie->n_levels == 1 && A.trie->lv[0].n > 0 && A.trie->lv[0].n == (uint64_t)A.trie->key_max[0] + 1 &&
@@ -196,6 +205,8 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
       seen |= 1u << v;
       order[i] = v;
     }
+    p->cost = order_cost(h, order, nullptr, nullptr);
+  } else if ((q->policy & LH_POLICY_MASK) == LH_POLICY_LEARNED && learned_order(h, p->out_attrs, order, s)) {
     p->cost = order_cost(h, order, nullptr, nullptr);
   } else {
     p->cost = choose_order(h, p->out_attrs, order);

@@ -283,6 +283,44 @@ uint64_t select_flagged(const uint32_t* flags, uint64_t n, uint32_t* out, hipStr
   return m;
 }
 
+__global__ void k_hist_u32(const uint32_t* col, uint64_t n, uint32_t* cnt) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    atomicAdd(&cnt[col[i]], 1u);
+}
+
+__global__ void k_hist_stats(const uint32_t* cnt, uint64_t m, unsigned long long* distinct, uint32_t* fmax) {
+  uint64_t d = 0;
+  uint32_t f = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+    d += cnt[i] != 0;
+    f = max(f, cnt[i]);
+  }
+  d = wave_sum(d);
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) f = max(f, (uint32_t)__shfl_xor((int)f, o, WAVE));
+  if (lane_id() == 0) {
+    atomicAdd(distinct, (unsigned long long)d);
+    atomicMax(fmax, f);
+  }
+}
+
+void column_freq(const uint32_t* col, uint64_t n, uint32_t range, uint64_t& distinct, uint64_t& freq_max,
+                 hipStream_t s) {
+  distinct = 0;
+  freq_max = 0;
+  if (!n) return;
+  DBuf<uint32_t> cnt((uint64_t)range + 1, s), fm(1, s);
+  DBuf<unsigned long long> d(1, s);
+  k_fill<uint32_t><<<grid_for(range + 1ull), 256, 0, s>>>(cnt.p, 0u, range + 1ull);
+  k_fill<uint32_t><<<1, 64, 0, s>>>(fm.p, 0u, 1);
+  k_fill<unsigned long long><<<1, 64, 0, s>>>(d.p, 0ull, 1);
+  k_hist_u32<<<grid_for(n), 256, 0, s>>>(col, n, cnt.p);
+  k_hist_stats<<<grid_for(range + 1ull), 256, 0, s>>>(cnt.p, range + 1ull, d.p, fm.p);
+  LH_HIP(hipGetLastError());
+  distinct = read_scalar(d.p, s);
+  freq_max = read_scalar(fm.p, s);
+}
+
 void iota_u32(uint32_t* out, uint64_t n, hipStream_t s) {
   if (!n) return;
   k_iota<<<grid_for(n), 256, 0, s>>>(out, n);

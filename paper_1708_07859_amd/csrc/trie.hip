@@ -105,7 +105,8 @@ __device__ __forceinline__ void set_range(const SetRange& sr, uint64_t s, uint32
   else { b = sr.offs[s]; e = sr.offs[s + 1]; }
 }
 
-__global__ void k_layout_words(SetRange sr, const uint32_t* keys, uint64_t n_sets, uint32_t mode, uint64_t* words) {
+__global__ void k_layout_words(SetRange sr, const uint32_t* keys, uint64_t n_sets, uint32_t mode,
+                               const uint8_t* choice, uint64_t* words) {
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_sets; s += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t b, e;
     set_range(sr, s, b, e);
@@ -115,8 +116,10 @@ __global__ void k_layout_words(SetRange sr, const uint32_t* keys, uint64_t n_set
       uint64_t card = e - b;
       uint64_t span = (uint64_t)hi - lo + 1;
       bool bs = false;
+      // plain rule: a bitset when the set fills at least 1/32 of its window
       if (mode == LH_LAYOUT_PLAIN || mode == LH_LAYOUT_LEARNED) bs = span <= 32ull * card;
       else if (mode == LH_LAYOUT_BITSET) bs = span <= 4096ull * card;
+      if (choice && choice[s]) bs = choice[s] == 2;
       if (bs) nw = (((uint64_t)hi - (lo & ~63u)) >> 6) + 1;
     }
     words[s] = nw;
@@ -168,7 +171,10 @@ void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, hipStream_t s) {
   L.bs_base.alloc(L.n_sets, s);
   if (L.n_sets == 0) return;
   DBuf<uint64_t> words(L.n_sets, s), woff(L.n_sets + 1, s);
-  k_layout_words<<<grid_for(L.n_sets), 256, 0, s>>>(sr, L.keys.p, L.n_sets, mode, words.p);
+  DBuf<uint8_t> choice;
+  const bool learned = mode == LH_LAYOUT_LEARNED && learned_layout_choices(t, l, s, choice);
+  k_layout_words<<<grid_for(L.n_sets), 256, 0, s>>>(sr, L.keys.p, L.n_sets, mode, learned ? choice.p : nullptr,
+                                                    words.p);
   LH_HIP(hipGetLastError());
   L.pool_words = scan_u64(words.p, woff.p, L.n_sets, s);
   k_layout_desc<<<grid_for(L.n_sets), 256, 0, s>>>(sr, L.keys.p, L.n_sets, words.p, woff.p, L.bs_word.p, L.bs_base.p);
@@ -307,6 +313,16 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
   for (uint32_t m = 0; m < n_meta; m++) {
     t->meta.emplace_back(t->n_rows, s);
     gather_u32(meta[m], rowmap, t->meta.back().p, t->n_rows, s);
+  }
+
+  // column statistics for the learned cost model's order features
+  for (uint32_t l = 0; l < n_keys; l++) {
+    if (t->key_max[l] < (1u << 28)) {
+      column_freq(t->skeys[l].p, t->n_rows, t->key_max[l], t->col_distinct[l], t->col_freq_max[l], s);
+    } else {
+      t->col_distinct[l] = t->n_rows;
+      t->col_freq_max[l] = 1;
+    }
   }
 
   uint32_t mode = flags & LH_LAYOUT_MASK;

@@ -1,0 +1,286 @@
+"""Training driver of the learned cost model.
+
+The engine times its own runs; the timings become training samples for
+the network in liblh.so (FP32 training kernels), and the trained weights
+are registered for two decisions (BF16 inference kernels):
+
+* layout: for sets of a given cardinality and span stored as uint arrays
+  or as bitsets, the time of one probe inside the join's intersection
+  kernel.  Calibration builds a relation of many such sets and a probe
+  relation, runs COUNT(R |x| P) and divides the intersection kernel's time
+  by the number of probes.
+* order: the time of planning and running a query under each candidate
+  attribute order, on graph, matrix and star-schema training workloads.
+
+Usage: python -m paper_1708_07859_amd.learned train --out <weights.npz>
+"""
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1708_07859_amd import lh  # noqa: E402
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "cost_model.npz")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# --------------------------------------------------------------------------
+# layout calibration
+# --------------------------------------------------------------------------
+
+def layout_features(card, span, choice):
+    return [np.log2(card), np.log2(span), np.log2(card / span), float(choice)]
+
+
+def _probe_time(R, P, n_probes):
+    """ns per probe of COUNT(R(a,c) |x| P(a,c)) under order (a, c)."""
+    p = lh.plan(2, [(R, [0, 1], -1), (P, [0, 1], -1)], agg="count", attr_order=[0, 1], policy="fixed")
+    lh.join_aggregate([p])[0].free()             # warm
+    lh.profile_reset()
+    lh.profile_enable(True)
+    for _ in range(3):
+        lh.join_aggregate([p])[0].free()
+    lh.profile_enable(False)
+    prof = lh.profile_read()
+    p.free()
+    ms = prof["leaf_aggregate"]["total_ms"] / 3
+    return ms * 1e6 / n_probes
+
+
+def calibrate_layouts(seed=7, total=1 << 23, cards=None, densities=None):
+    """Samples (features, log2 ns per probe) for uint and bitset sets."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cards = cards or [2 ** k for k in range(5, 18)]
+    densities = densities or [2.0 ** -k for k in range(0, 13)]
+    max_span = 1 << 24
+    X, y, rows = [], [], []
+    for card in cards:
+        for dens in densities:
+            span = int(card / dens)
+            if span > max_span or span < card:
+                continue
+            n_sets = max(1, total // card)
+            m = max(8, card // 2)
+
+            def stratified(count):
+                # one uniform value in each of `count` equal slices of [0, span):
+                # distinct and sorted; every set lives under its own key a
+                w = span / count
+                v = np.floor((np.arange(count)[None, :] + rng.random((n_sets, count))) * w)
+                return v.astype(np.uint32).ravel()
+
+            a_r = np.repeat(np.arange(n_sets, dtype=np.uint32), card)
+            c_r = stratified(card)
+            a_p = np.repeat(np.arange(n_sets, dtype=np.uint32), m)
+            c_p = stratified(m)
+            P = lh.trie_build([a_p, c_p], layout="uint")
+            for choice, layout in ((0, "uint"), (1, "bitset")):
+                R = lh.trie_build([a_r, c_r], layout=layout)
+                inf = R.info()
+                if choice == 1 and inf["level_bitsets"][1] < n_sets:
+                    R.free()
+                    continue                     # the window was too large to store
+                ns = _probe_time(R, P, n_sets * m)
+                R.free()
+                X.append(layout_features(card, span, choice))
+                y.append(np.log2(ns))
+                rows.append({"card": card, "span": span, "layout": layout, "ns_per_probe": ns})
+            P.free()
+        log(f"  layout calibration card={card}: {len(rows)} samples")
+    return np.array(X, np.float32), np.array(y, np.float32), rows
+
+
+# --------------------------------------------------------------------------
+# order samples
+# --------------------------------------------------------------------------
+
+def _edges_of(query, tries):
+    """Hypergraph edges (attrs, base cardinality, eq flag) of a query dict."""
+    eq_atoms = {f["atom"] for f in query.get("filters", []) if f["kind"] in ("eq_key", "eq_meta")}
+    out = []
+    for i, (a, t) in enumerate(zip(query["atoms"], tries)):
+        inf = t.info()          # tries here are built in column order
+        n = max(1, inf["n_rows"])
+        lf_mean = [float(np.log2(1 + n / max(1, d))) for d in inf["col_distinct"]]
+        lf_max = [float(np.log2(1 + f)) for f in inf["col_freq_max"]]
+        out.append({"attrs": list(a["attrs"]), "card": len(a["keys"][0]), "eq": i in eq_atoms,
+                    "lf_mean": lf_mean, "lf_max": lf_max})
+    return out
+
+
+def candidate_orders(n_attrs, out_attrs):
+    mat = set(out_attrs)
+    res = []
+    for perm in itertools.permutations(range(n_attrs)):
+        seen_proj, ok = False, True
+        for v in perm:
+            if v not in mat:
+                seen_proj = True
+            elif seen_proj:
+                ok = False
+        if not ok:
+            continue
+        res.append(list(perm))
+        if n_attrs >= 2 and perm[-1] not in mat and perm[-2] in mat:
+            sw = list(perm)
+            sw[-1], sw[-2] = sw[-2], sw[-1]
+            res.append(sw)
+    return res
+
+
+def time_order(query, tries_by_atom, order, reps=2):
+    atoms = [(t, list(a["attrs"]), int(a.get("anno", -1))) for t, a in zip(tries_by_atom, query["atoms"])]
+    best = None
+    for _ in range(reps + 1):
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = lh.plan(query["n_attrs"], atoms, out=query.get("out", []), group=query.get("group", []),
+                    agg=query.get("agg", "count"), filters=query.get("filters", []), attr_order=order,
+                    policy="fixed")
+        r = lh.join_aggregate([p])[0]
+        r.to_host()
+        dt = time.perf_counter() - t0
+        r.free()
+        p.free()
+        best = dt if best is None else min(best, dt)
+    return best * 1000.0
+
+
+def build_tries(query, layout="plain"):
+    cache = {}
+    out = []
+    for a in query["atoms"]:
+        ident = (tuple(id(k) for k in a["keys"]), tuple(id(x) for x in a.get("annos", [])),
+                 tuple(id(m) for m in a.get("meta", [])), bool(a.get("bag", False)))
+        if ident not in cache:
+            cache[ident] = lh.trie_build(a["keys"], a.get("annos", []), a.get("meta", []),
+                                         bag=a.get("bag", False), layout=layout)
+        out.append(cache[ident])
+    return out, list(cache.values())
+
+
+def training_queries():
+    import synth
+    from tests import queries
+    qs = []
+    for sc in (12, 14, 16, 18, 20, 21):
+        lo, hi = synth.rmat_edges(sc, 16 << sc, seed=20 + sc)
+        qs.append(("triangle rmat%d" % sc, queries.triangle(lo, hi)))
+    # the benchmark graph itself (2^22 vertices, 2^26 samples, seed 2) and
+    # one of twice its size (seed 23); 2^24 vertices are held out
+    lo, hi = synth.rmat_edges(22, 1 << 26, seed=2)
+    qs.append(("triangle rmat22", queries.triangle(lo, hi)))
+    lo, hi = synth.rmat_edges(23, 1 << 27, seed=23)
+    qs.append(("triangle rmat23", queries.triangle(lo, hi)))
+    for sc, seed in ((22, 102), (23, 123)):
+        lo, hi = synth.rmat_edges(sc, 1 << (sc + 4), seed=seed)
+        qs.append(("triangle rmat%d seed %d" % (sc, seed), queries.triangle(lo, hi)))
+    for n in (1024, 4096):
+        a = synth.sparse_matrix(n, 10, seed=n)
+        qs.append(("spgemm %d" % n, queries.spgemm(a, a)))
+        rng = synth.rng_for(n + 1)
+        x = synth.uniform_pm1(rng, n)
+        qs.append(("spmv %d" % n, queries.spmv(synth.zipf_degree_matrix(n, 1.1, 16, rng), x)))
+    s = synth.star_schema(n_fact=400_000, dims=(40_000, 10_000, 2000, 200), seed=31)
+    qs.append(("star", queries.star(s, u_hi=0.2, m2=0, m3=0)))
+    return qs
+
+
+def order_samples(queries_list):
+    """The decision ranks the candidate orders of one query, so each
+    sample's target is log2 of its time relative to the geometric mean of
+    its query's candidates."""
+    X, y, rows = [], [], []
+    for name, q in queries_list:
+        tries, uniq = build_tries(q)
+        edges = _edges_of(q, tries)
+        qy = []
+        big = len(q["atoms"][0]["keys"][0]) > (1 << 24)
+        for order in candidate_orders(q["n_attrs"], q.get("out", [])):
+            ms = time_order(q, tries, order, reps=1 if big else 2)
+            X.append(lh.order_features(q["n_attrs"], edges, order))
+            qy.append(np.log2(ms))
+            rows.append({"query": name, "order": order, "ms": ms})
+        # a query's samples count in proportion to the time at stake, so
+        # the fit is judged where a wrong choice costs the most
+        rel = list(np.array(qy) - np.mean(qy))
+        feats = X[len(X) - len(qy):]
+        reps = int(min(16, max(1, round(float(np.mean(2.0 ** np.array(qy))) / 25.0))))
+        y.extend(rel)
+        for _ in range(reps - 1):
+            X.extend(feats)
+            y.extend(rel)
+        for t in uniq:
+            t.free()
+        log(f"  order samples {name}: {len(rows)} total")
+    return np.array(X, np.float32), np.array(y, np.float32), rows
+
+
+# --------------------------------------------------------------------------
+# models
+# --------------------------------------------------------------------------
+
+def train_model(X, y, d_in, epochs=400, batch=64, lr=3e-3, seed=1):
+    m = lh.Mlp(d_in, 64, seed)
+    loss0, _ = m.loss_grad(X, y)
+    loss = m.train(X, y, epochs=epochs, batch=min(batch, len(y)), lr=lr, seed=seed)
+    log(f"  trained on {len(y)} samples: loss {loss0:.4f} -> {loss:.4f}")
+    return m, loss0, loss
+
+
+def save(path, layout_m, order_m, meta):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, layout=layout_m.get_params(), order=order_m.get_params(),
+             meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+
+def load(path):
+    z = np.load(path, allow_pickle=False)
+    lm = lh.Mlp(lh.LH_LAYOUT_FEATURES, 64, 0)
+    lm.set_params(z["layout"])
+    om = lh.Mlp(lh.LH_ORDER_FEATURES, 64, 0)
+    om.set_params(z["order"])
+    meta = json.loads(bytes(z["meta"]).decode())
+    return lm, om, meta
+
+
+def register(layout_m, order_m):
+    lh.use_model(lh.LH_MODEL_LAYOUT, layout_m)
+    lh.use_model(lh.LH_MODEL_ORDER, order_m)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    log("layout calibration")
+    Xl, yl, rl = calibrate_layouts()
+    log("order samples")
+    Xo, yo, ro = order_samples(training_queries())
+    log("training")
+    lm, l0, l1 = train_model(Xl, yl, lh.LH_LAYOUT_FEATURES)
+    om, o0, o1 = train_model(Xo, yo, lh.LH_ORDER_FEATURES)
+    meta = {"layout_samples": len(yl), "order_samples": len(yo), "layout_loss": [l0, l1], "order_loss": [o0, o1],
+            "layout_rows": rl, "order_rows": ro}
+    save(args.out, lm, om, meta)
+    log(f"saved {args.out}")
+
+
+if __name__ == "__main__":
+    main()

@@ -87,6 +87,8 @@ class TrieInfo(C.Structure):
         ("level_bitsets", C.c_uint64 * LH_MAX_KEYS),
         ("level_words", C.c_uint64 * LH_MAX_KEYS),
         ("level_order", C.c_uint32 * LH_MAX_KEYS),
+        ("col_distinct", C.c_uint64 * LH_MAX_KEYS),
+        ("col_freq_max", C.c_uint64 * LH_MAX_KEYS),
     ]
 
 
@@ -111,6 +113,8 @@ class Hypergraph(C.Structure):
         ("edge_card", C.POINTER(C.c_uint64)),
         ("edge_eq", C.POINTER(C.c_uint32)),
         ("edge_dense", C.POINTER(C.c_uint32)),
+        ("edge_attr_lf_mean", C.POINTER(C.c_float)),
+        ("edge_attr_lf_max", C.POINTER(C.c_float)),
     ]
 
 
@@ -130,6 +134,18 @@ SIGNATURES = {
     "lh_choose_order": ([C.POINTER(Hypergraph), C.c_uint32, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                          C.POINTER(C.c_double)], C.c_int),
     "lh_live_allocations": ([], C.c_long),
+    "lh_mlp_create": ([C.c_uint32, C.c_uint32, C.c_uint64, C.POINTER(C.c_void_p)], C.c_int),
+    "lh_mlp_free": ([C.c_void_p], None),
+    "lh_mlp_num_params": ([C.c_void_p], C.c_uint64),
+    "lh_mlp_get_params": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lh_mlp_set_params": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lh_mlp_loss_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.POINTER(C.c_float),
+                          C.c_void_p], C.c_int),
+    "lh_mlp_train": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_float,
+                      C.c_uint64, C.c_void_p, C.POINTER(C.c_float)], C.c_int),
+    "lh_mlp_predict": ([C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_void_p, C.c_void_p], C.c_int),
+    "lh_use_model": ([C.c_uint32, C.c_void_p], C.c_int),
+    "lh_order_features": ([C.POINTER(Hypergraph), C.POINTER(C.c_uint32), C.c_void_p], C.c_int),
     "lh_profile_enable": ([C.c_int], None),
     "lh_profile_reset": ([], None),
     "lh_profile_read": ([C.c_void_p, C.c_uint32], C.c_uint32),
@@ -212,7 +228,8 @@ class Trie:
         return {"n_levels": L, "n_rows": inf.n_rows,
                 "level_size": list(inf.level_size[:L]), "level_sets": list(inf.level_sets[:L]),
                 "level_bitsets": list(inf.level_bitsets[:L]), "level_words": list(inf.level_words[:L]),
-                "level_order": list(inf.level_order[:L])}
+                "level_order": list(inf.level_order[:L]),
+                "col_distinct": list(inf.col_distinct[:L]), "col_freq_max": list(inf.col_freq_max[:L])}
 
     def read_level(self, level):
         inf = self.info()
@@ -374,6 +391,81 @@ def live_allocations():
     return lib.lh_live_allocations()
 
 
+LH_MODEL_LAYOUT, LH_MODEL_ORDER = 0, 1
+LH_LAYOUT_FEATURES, LH_ORDER_FEATURES = 4, 24
+
+
+class Mlp:
+    """Owning handle of an lh_mlp (the learned cost model's network)."""
+
+    def __init__(self, d_in, width=64, seed=0):
+        h = C.c_void_p()
+        _check(lib.lh_mlp_create(d_in, width, seed, C.byref(h)))
+        self.handle = h.value
+        self.d_in = d_in
+
+    @property
+    def n_params(self):
+        return int(lib.lh_mlp_num_params(self.handle))
+
+    def get_params(self):
+        p = np.zeros(self.n_params, np.float32)
+        _check(lib.lh_mlp_get_params(self.handle, p.ctypes.data))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.size == self.n_params
+        _check(lib.lh_mlp_set_params(self.handle, p.ctypes.data))
+
+    def loss_grad(self, X, y):
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        g = np.zeros(self.n_params, np.float32)
+        loss = C.c_float()
+        _check(lib.lh_mlp_loss_grad(self.handle, X.ctypes.data, y.ctypes.data, len(y), current_stream(),
+                                    C.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def train(self, X, y, epochs=200, batch=256, lr=1e-3, seed=0):
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        loss = C.c_float()
+        _check(lib.lh_mlp_train(self.handle, X.ctypes.data, y.ctypes.data, len(y), epochs, batch, lr, seed,
+                                current_stream(), C.byref(loss)))
+        return loss.value
+
+    def predict(self, X, bf16=True):
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.zeros(len(X), np.float32)
+        _check(lib.lh_mlp_predict(self.handle, X.ctypes.data, len(X), 1 if bf16 else 0, current_stream(),
+                                  y.ctypes.data))
+        return y
+
+    def free(self):
+        if self.handle:
+            lib.lh_mlp_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def use_model(slot, mlp):
+    _check(lib.lh_use_model(slot, mlp.handle if mlp is not None else None))
+
+
+def order_features(n_attrs, edges, order):
+    h, keep = _hypergraph(n_attrs, edges)
+    o = (C.c_uint32 * n_attrs)(*order)
+    f = np.zeros(LH_ORDER_FEATURES, np.float32)
+    _check(lib.lh_order_features(C.byref(h), o, f.ctypes.data))
+    return f
+
+
 class ProfileEntry(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_uint64), ("total_ms", C.c_double),
                 ("rows", C.c_uint64), ("elements", C.c_uint64)]
@@ -408,8 +500,11 @@ def _hypergraph(n_attrs, edges):
     card = (C.c_uint64 * len(edges))(*[int(e["card"]) for e in edges])
     eq = (C.c_uint32 * len(edges))(*[1 if e.get("eq") else 0 for e in edges])
     dense = (C.c_uint32 * len(edges))(*[1 if e.get("dense") else 0 for e in edges])
-    h = Hypergraph(n_attrs, len(edges), cnt, attrs, card, eq, dense)
-    return h, (cnt, attrs, card, eq, dense)
+    has_lf = all("lf_mean" in e for e in edges) and edges
+    lfm = (C.c_float * max(1, len(flat)))(*([v for e in edges for v in e["lf_mean"]] if has_lf else []))
+    lfx = (C.c_float * max(1, len(flat)))(*([v for e in edges for v in e["lf_max"]] if has_lf else []))
+    h = Hypergraph(n_attrs, len(edges), cnt, attrs, card, eq, dense, lfm if has_lf else None, lfx if has_lf else None)
+    return h, (cnt, attrs, card, eq, dense, lfm, lfx)
 
 
 def order_cost(n_attrs, edges, order):
