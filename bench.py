@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=15)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--layout", default="plain", choices=["plain", "uint", "bitset", "learned"])
-    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
     args = ap.parse_args()
@@ -93,6 +93,8 @@ def main():
         return bench_batch(args, lh, torch, synth)
     if args.workload == "learned":
         return bench_learned(args, lh, torch, synth)
+    if args.workload == "copy":
+        return bench_copy(args, torch)
     log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
     t0 = time.perf_counter()
     lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
@@ -243,6 +245,32 @@ def bench_learned(args, lh, torch, synth):
                    "regret_plain": t_plain / best - 1, "regret_learned": t_learn / best - 1,
                    "best_candidate_ms": best, "candidates_ms": cands},
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_copy(args, torch):
+    """A plain device-to-device copy of 1 GiB: the known-size kernel that
+    hardware byte counters (FETCH_SIZE, WRITE_SIZE) are scaled against, and
+    the achievable-bandwidth line next to the 8 TB/s peak."""
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    gbs = 2 * n / (ms / 1000) / 1e9
+    out = {"metric": "device copy GB/s (read + write)", "value": gbs, "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "copy of 1 GiB, device to device", "bytes_read": n, "bytes_written": n,
+                      "frac_of_peak": gbs / HBM_PEAK_GBS}}
     print(json.dumps(out), flush=True)
 
 

@@ -561,40 +561,64 @@ __global__ void k_unit_rows(const uint64_t* U, uint64_t nrows, uint32_t* urow) {
 
 // ---- two-set COUNT leaf with per-unit descriptors ----------------------------
 // For the common leaf of two participating sets and set semantics, every
-// work unit is described once (driver key range, probed set range and
-// layout), so a wave needs one descriptor load before streaming its keys.
+// work unit is described once: its driver key range, and either the probed
+// set's bitset window or the part of the probed sorted keys that the unit's
+// driver values can meet.  A wave then needs one descriptor load before it
+// streams its driver keys and that key range side by side.
 struct UnitDesc {
   uint32_t dstart;   // first driver element (index into the driver's level keys)
-  uint32_t dcount;   // driver elements in this unit (<= U_EL)
-  uint32_t pb, pe;   // probed set range in its level keys
-  uint64_t pword;    // probed set's first bitset word, or UINT64_MAX
-  uint32_t pbase;    // probed set's bitset base value
+  uint32_t dcount;   // driver elements in this unit (1..U_EL)
+  uint32_t plo;      // uint: first probed key index; bitset: window base value
+  uint32_t phi;      // uint: end of probed keys (UINT32_MAX: next unit's plo); bitset: largest value
+  uint64_t pword;    // probed set's first bitset word, or UINT64_MAX (sorted keys)
   uint32_t drv;      // driving participant (0 or 1)
+  uint32_t pad;
 };
 
-__global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint8_t* drv, uint64_t nrows, UnitDesc* desc) {
-  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x) {
+// First index in [lo, hi) whose value is > x (hi if none).
+__device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t x) {
+  while (lo < hi) {
+    uint32_t mid = lo + (hi - lo) / 2;
+    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// One thread per unit.  Consecutive units of a row split the driver into
+// chunks of U_EL sorted keys; a chunk can only meet probed keys from the
+// lower bound of its first key up to the lower bound of the next chunk's
+// first key (the last chunk: the upper bound of its last key).
+__global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow, const uint8_t* drv, uint64_t units,
+                            UnitDesc* desc) {
+  for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = urow[u];
     const uint64_t u0 = U[r], u1 = U[r + 1];
-    if (u0 == u1) continue;
     uint32_t b[2], e[2];
     uint64_t sidx[2];
     dset_range(wa.set[0], r, b[0], e[0], sidx[0]);
     dset_range(wa.set[1], r, b[1], e[1], sidx[1]);
     const uint32_t d = drv[r];
-    const uint32_t q = 1 - d;
     const uint32_t db = d ? b[1] : b[0], de = d ? e[1] : e[0];
+    const uint32_t pb = d ? b[0] : b[1], pe = d ? e[0] : e[1];
+    const uint64_t sq = d ? sidx[0] : sidx[1];
+    const uint32_t* dk = d ? wa.set[1].keys : wa.set[0].keys;
+    const uint32_t* pk = d ? wa.set[0].keys : wa.set[1].keys;
+    const uint64_t* bsw = d ? wa.set[0].bs_word : wa.set[1].bs_word;
+    const uint32_t* bsb = d ? wa.set[0].bs_base : wa.set[1].bs_base;
     UnitDesc t;
-    t.pb = q ? b[1] : b[0];
-    t.pe = q ? e[1] : e[0];
-    const uint64_t sq = q ? sidx[1] : sidx[0];
-    t.pword = (t.pe > t.pb) ? wa.set[q].bs_word[sq] : UINT64_MAX;
-    t.pbase = (t.pword != UINT64_MAX) ? wa.set[q].bs_base[sq] : 0u;
     t.drv = d;
-    for (uint64_t u = u0; u < u1; u++) {
-      t.dstart = db + (uint32_t)(u - u0) * U_EL;
-      t.dcount = min((uint32_t)U_EL, de - t.dstart);
-      desc[u] = t;
+    t.pad = 0;
+    t.dstart = db + (uint32_t)(u - u0) * U_EL;
+    t.dcount = min((uint32_t)U_EL, de - t.dstart);
+    t.pword = (pe > pb) ? bsw[sq] : UINT64_MAX;
+    if (t.pword != UINT64_MAX) {
+      t.plo = bsb[sq];
+      t.phi = pk[pe - 1];
+    } else {
+      t.plo = lower_bound_u32(pk, pb, pe, dk[t.dstart]);
+      t.phi = (u + 1 == u1) ? upper_bound_u32(pk, t.plo, pe, dk[t.dstart + t.dcount - 1]) : UINT32_MAX;
     }
+    desc[u] = t;
   }
 }
 
@@ -609,18 +633,62 @@ struct Leaf2Args {
   uint64_t nvblk;
 };
 
+#ifndef LH_L2_CAP
+#define LH_L2_CAP 1024
+#endif
+constexpr int L2_CAP = LH_L2_CAP;  // probed keys a wave stages in LDS
+#ifndef LH_L2_RATIO
+#define LH_L2_RATIO 8
+#endif
+constexpr uint32_t L2_STAGE_RATIO = LH_L2_RATIO;  // stage at most this many probed keys per driver key
+
+// Membership of x[it] (it < nit) in the strictly increasing keys a[0, m),
+// m >= 1: a branchless bisection whose trip count depends on m only, so the
+// probes of a lane's values are issued together.  nit is wave-uniform.
+template <class Arr>
+__device__ __forceinline__ uint32_t count_members(Arr a, uint32_t m, const uint32_t* x, const bool* v, uint32_t nit) {
+  uint32_t lo[U_IT];
+#pragma unroll
+  for (int it = 0; it < U_IT; it++) lo[it] = 0;
+  uint32_t n = m;
+  while (n > 1) {
+    const uint32_t half = n >> 1;
+#pragma unroll
+    for (int it = 0; it < U_IT; it++)
+      if (it < (int)nit) lo[it] = (a[lo[it] + half] <= x[it]) ? lo[it] + half : lo[it];
+    n -= half;
+  }
+  uint32_t c = 0;
+#pragma unroll
+  for (int it = 0; it < U_IT; it++)
+    if (it < (int)nit) c += (v[it] && a[lo[it]] == x[it]) ? 1u : 0u;
+  return c;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  // LDS operations of one wave complete in order; this keeps the compiler
+  // from moving them across the point where lanes read what others wrote
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
+  __shared__ uint32_t s_stage[J_NW][L2_CAP];
   __shared__ unsigned long long s_cnt;
   const int tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
   if (tid == 0) s_cnt = 0;
+  uint32_t* stage = s_stage[w];
   uint64_t run = 0;
   for (uint64_t vb = blockIdx.x; vb < a.nvblk; vb += gridDim.x) {
     const uint64_t u = vb * J_NW + w;
     if (u >= a.units) continue;  // wave-uniform; no barrier inside the loop
     const UnitDesc t = a.desc[u];
+    const uint32_t next_lo = (u + 1 < a.units) ? a.desc[u + 1].plo : 0u;
     const uint32_t* dk = t.drv ? a.keys[1] : a.keys[0];
     const uint32_t* pk = t.drv ? a.keys[0] : a.keys[1];
     const uint64_t* pool = t.drv ? a.pool[0] : a.pool[1];
+    const uint32_t nit = (t.dcount + WAVE - 1) / WAVE;
     uint32_t x[U_IT];
     bool v[U_IT];
 #pragma unroll
@@ -631,19 +699,23 @@ __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
     }
     uint32_t c = 0;
     if (t.pword != UINT64_MAX) {
-      const uint32_t hi = pk[t.pe - 1];
 #pragma unroll
       for (int it = 0; it < U_IT; it++) {
-        if (!v[it] || x[it] < t.pbase || x[it] > hi) continue;
-        const uint32_t dd = x[it] - t.pbase;
+        if (!v[it] || x[it] < t.plo || x[it] > t.phi) continue;
+        const uint32_t dd = x[it] - t.plo;
         c += (uint32_t)((pool[t.pword + (dd >> 6)] >> (dd & 63u)) & 1ull);
       }
     } else {
-#pragma unroll
-      for (int it = 0; it < U_IT; it++) {
-        if (!v[it]) continue;
-        const uint32_t j = lower_bound_u32(pk, t.pb, t.pe, x[it]);
-        c += (j < t.pe && pk[j] == x[it]) ? 1u : 0u;
+      const uint32_t lo = t.plo;
+      const uint32_t hi = t.phi == UINT32_MAX ? next_lo : t.phi;
+      const uint32_t m = hi - lo;
+      if (m > 0 && m <= (uint32_t)L2_CAP && m <= L2_STAGE_RATIO * t.dcount) {
+        for (uint32_t k = lane; k < m; k += WAVE) stage[k] = pk[lo + k];
+        wave_lds_sync();
+        c = count_members(stage, m, x, v, nit);
+        wave_lds_sync();
+      } else if (m > 0) {
+        c = count_members(pk + lo, m, x, v, nit);
       }
     }
     if (a.gid) {
@@ -997,7 +1069,6 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
     if (total) {
       bool all_set = !is_sum;
       for (const auto& A : p->atoms) all_set = all_set && !A.bag;
-      ProfScope ps("leaf_aggregate", s, F.n, total);
       if (all_set && a.np == 2) {
         // two sets, set semantics: per-unit descriptors, one load per wave
         DBuf<UnitDesc> desc(dw.units, s);
@@ -1005,8 +1076,12 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         wa.np = 2;
         wa.set[0] = a.set[0];
         wa.set[1] = a.set[1];
-        k_unit_desc<<<grid_for(F.n), 256, 0, s>>>(wa, dw.U.p, dw.drv.p, F.n, desc.p);
+        {
+          ProfScope ps("leaf_units", s, dw.units, 0);
+          k_unit_desc<<<grid_for(dw.units), 256, 0, s>>>(wa, dw.U.p, dw.urow.p, dw.drv.p, dw.units, desc.p);
+        }
         LH_HIP(hipGetLastError());
+        ProfScope ps("leaf_aggregate", s, F.n, total);
         Leaf2Args l2{};
         l2.keys[0] = a.set[0].keys;
         l2.keys[1] = a.set[1].keys;
@@ -1019,8 +1094,11 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         l2.units = dw.units;
         l2.nvblk = nblk;
         k_leaf2_count<<<elem_grid(nblk), J_NT, 0, s>>>(l2);
-      } else if (all_set) k_elem<M_LEAF_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
-      else k_elem<M_LEAF_A><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+      } else {
+        ProfScope ps("leaf_aggregate", s, F.n, total);
+        if (all_set) k_elem<M_LEAF_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+        else k_elem<M_LEAF_A><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+      }
       LH_HIP(hipGetLastError());
     }
     FinA f{};

@@ -283,9 +283,26 @@ uint64_t select_flagged(const uint32_t* flags, uint64_t n, uint32_t* out, hipStr
   return m;
 }
 
+// Histogram of a column.  Runs of equal values inside a wave (the sorted
+// first column is long runs) are added with one atomic per run.
 __global__ void k_hist_u32(const uint32_t* col, uint64_t n, uint32_t* cnt) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    atomicAdd(&cnt[col[i]], 1u);
+  const int lane = lane_id();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;  // a multiple of the wave size
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(WAVE - 1)); base < n; base += stride) {
+    const uint64_t i = base + lane;
+    const bool valid = i < n;
+    const uint32_t v = valid ? col[i] : 0u;
+    const uint32_t prev = (uint32_t)__shfl_up((int)v, 1, WAVE);
+    const bool head = valid && (lane == 0 || prev != v);
+    const uint64_t heads = ballot(head);
+    if (head) {
+      // the run ends at the next head or at the last valid lane
+      const uint64_t above = lane == WAVE - 1 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+      const uint32_t nvalid = (uint32_t)min<uint64_t>(WAVE, n - base);
+      const uint32_t end = above ? (uint32_t)__builtin_ctzll(above) : nvalid;
+      atomicAdd(&cnt[v], end - (uint32_t)lane);
+    }
+  }
 }
 
 __global__ void k_hist_stats(const uint32_t* cnt, uint64_t m, unsigned long long* distinct, uint32_t* fmax) {
