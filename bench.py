@@ -47,6 +47,13 @@ ALG_BYTES = {
 }
 
 
+# profiling scope -> the kernel it times (the two-set COUNT leaf of the triangle)
+KERNEL_OF_SCOPE = {"leaf_aggregate": "k_leaf2_count"}
+# HBM bytes per launch of that kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# used only while the kernel's source matches the one the counters saw
+TRAFFIC_SUMMARY = "triangle_rmat22_leaf2_count_traffic.txt"
+
+
 def cpu_baseline(scale):
     import numpy as np
 
@@ -74,9 +81,11 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=15)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--layout", default="plain", choices=["plain", "uint", "bitset", "learned"])
-    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--card", type=int, default=1_000_000)
+    ap.add_argument("--pairs", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU layout is a design "
@@ -95,6 +104,8 @@ def main():
         return bench_learned(args, lh, torch, synth)
     if args.workload == "copy":
         return bench_copy(args, torch)
+    if args.workload == "intersect":
+        return bench_intersect(args, lh, torch, synth)
     log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
     t0 = time.perf_counter()
     lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
@@ -147,8 +158,14 @@ def main():
         per_launch_bytes = ALG_BYTES[dom](e["rows"], e["elements"]) / e["launches"]
         avg_ms = e["total_ms"] / e["launches"]
         achieved = per_launch_bytes / (avg_ms / 1000) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        kernel = KERNEL_OF_SCOPE.get(dom, dom)
+        traffic = None
+        if (args.scale, args.samples_log2, args.layout) == (22, 26, "plain"):
+            from paper_1708_07859_amd import profiling
+            traffic = profiling.read_traffic(os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY), kernel)
+        roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
                 "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(per_launch_bytes)}
     join_ms = sum(prof[k]["total_ms"] for k in prof if k.startswith(("join_", "leaf_"))) / args.steps
     out = {
@@ -245,6 +262,76 @@ def bench_learned(args, lh, torch, synth):
                    "regret_plain": t_plain / best - 1, "regret_learned": t_learn / best - 1,
                    "best_candidate_ms": best, "candidates_ms": cands},
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_intersect(args, lh, torch, synth):
+    """Set-pair intersections, the shape of the paper's intersection
+    micro-benchmark (Fig. 5a, section 6.3): `pairs` pairs of sets of `card`
+    elements drawn without replacement from [0, 2*card) (density 1/2),
+    intersected as R(p,x) |x| S(p,x) COUNT GROUP BY p in one launch, with the
+    sets as uint arrays or bitsets; plus a sparse variant (universe 64*card,
+    uint arrays).  Algorithmic bytes per pair: uint & uint 8c (both sets
+    streamed), uint & bitset 4c + U/8, bitset & bitset 2 U/8 (U = universe)."""
+    import numpy as np
+    c, npairs = args.card, args.pairs
+    variants = [("uint", "uint", 2), ("uint", "bitset", 2), ("bitset", "bitset", 2), ("uint", "uint", 64)]
+    results = {}
+    pairs_of = {}
+    for la, lb, mult in variants:
+        U = mult * c
+        if U not in pairs_of:
+            log(f"generating {npairs} pairs of {c} elements from [0, {U})")
+            t0 = time.perf_counter()
+            pairs = synth.set_pairs(c, U, npairs, seed=100 if mult == 2 else 101)
+            pr = np.repeat(np.arange(npairs, dtype=np.uint32), c)
+            xr = np.concatenate([a for a, _ in pairs])
+            xs = np.concatenate([b for _, b in pairs])
+            want = [len(np.intersect1d(pairs[i][0], pairs[i][1], assume_unique=True)) for i in range(0, npairs,
+                                                                                                  max(1, npairs // 8))]
+            pairs_of[U] = (lh.to_device(pr), lh.to_device(xr), lh.to_device(xs), want)
+            del pairs, pr, xr, xs
+            log(f"  {time.perf_counter() - t0:.1f} s")
+        pr_d, xr_d, xs_d, want = pairs_of[U]
+        ta = lh.trie_build([pr_d, xr_d], layout=la)
+        tb = lh.trie_build([pr_d, xs_d], layout=lb)
+        p = lh.plan(2, [(ta, [0, 1], -1), (tb, [0, 1], -1)], out=[0], agg="count", attr_order=[0, 1],
+                    policy="fixed")
+        for _ in range(max(1, args.warmup)):
+            r = lh.join_aggregate([p])[0]
+            res = r.to_host()
+            r.free()
+        got = res["counts"][::max(1, npairs // 8)].tolist()
+        assert got == want, (got, want)
+        torch.cuda.synchronize()
+        lh.profile_reset()
+        lh.profile_enable(True)
+        for _ in range(args.steps):
+            lh.join_aggregate([p])[0].free()
+        torch.cuda.synchronize()
+        lh.profile_enable(False)
+        prof = lh.profile_read()
+        leaf = prof["leaf_aggregate"]
+        ms = leaf["total_ms"] / leaf["launches"]
+        per_pair = {("uint", "uint"): 8 * c, ("uint", "bitset"): 4 * c + U / 8,
+                    ("bitset", "bitset"): 2 * U / 8}[(la, lb)]
+        alg = per_pair * npairs
+        gbs = alg / (ms / 1000) / 1e9
+        name = f"{la}&{lb} density 1/{mult}"
+        results[name] = {"leaf_ms": round(ms, 4), "alg_bytes": int(alg), "achieved_GBs": round(gbs, 1),
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "elements_per_s": 2 * c * npairs / (ms / 1000),
+                         "units_ms": round(prof.get("leaf_units", {"total_ms": 0, "launches": 1})["total_ms"]
+                                           / max(1, prof.get("leaf_units", {"launches": 1})["launches"]), 4)}
+        log(f"{name}: leaf {ms:.3f} ms, {gbs:.0f} GB/s algorithmic ({gbs / HBM_PEAK_GBS:.1%} of peak)")
+        p.free()
+        ta.free()
+        tb.free()
+    head = results["uint&uint density 1/2"]
+    out = {"metric": "set-pair intersection, algorithmic HBM GB/s of the leaf kernel", "value": head["achieved_GBs"],
+           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["leaf_ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"{npairs} set pairs of {c} elements, COUNT of each intersection",
+                      "variants": results}}
     print(json.dumps(out), flush=True)
 
 

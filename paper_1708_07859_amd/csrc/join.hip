@@ -32,6 +32,7 @@ struct DSet {
   const uint32_t* ppos;   // frontier positions at the previous level (null: root set)
   const uint32_t* poffs;  // child offsets of the previous level (null: root set)
   const uint32_t* keys;   // keys of this level
+  const uint32_t* samp;   // one key sample per line of keys
   uint32_t root_n;
   const uint64_t* bs_word;
   const uint32_t* bs_base;
@@ -139,7 +140,12 @@ struct WorkArgs {
   DSet set[MAXP];
 };
 
-__global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv, uint32_t* units) {
+// Driver value DRV_AND: the row's two sets are both bitsets and are
+// intersected word by word (AND + popcount over the overlap of their
+// windows); its work is counted in words instead of driver elements.
+constexpr uint8_t DRV_AND = 0xff;
+
+__global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv, uint32_t* units, uint32_t allow_and) {
   for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x) {
     // Driver: the set whose elements are cheapest to stream and probe into
     // the others; probing a bitset costs one word load, probing a sorted
@@ -181,8 +187,27 @@ __global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv,
       if (p < (int)a.np && card[p] == 0) empty = true;
     }
     if (empty) best = 0;
+    uint8_t dv = (uint8_t)bi;
+    if (allow_and && a.np == 2 && !empty) {
+      // both bitsets: AND the overlapping words when that moves fewer words
+      // than the probe path moves elements and probes
+      uint32_t b0, e0, b1, e1;
+      uint64_t s0, s1;
+      dset_range(a.set[0], r, b0, e0, s0);
+      dset_range(a.set[1], r, b1, e1, s1);
+      const uint64_t w0 = a.set[0].bs_word[s0], w1 = a.set[1].bs_word[s1];
+      if (w0 != UINT64_MAX && w1 != UINT64_MAX) {
+        const uint32_t v0 = max(a.set[0].bs_base[s0], a.set[1].bs_base[s1]);
+        const uint32_t v1 = min(a.set[0].keys[e0 - 1], a.set[1].keys[e1 - 1]);
+        const uint32_t words = v1 >= v0 ? ((v1 - v0) >> 6) + 1 : 0;
+        if (2.0f * (float)words < best_cost) {
+          dv = DRV_AND;
+          best = words;
+        }
+      }
+    }
     work[r] = best;
-    drv[r] = (uint8_t)bi;
+    drv[r] = dv;
     units[r] = (best + U_EL - 1) / U_EL;
   }
 }
@@ -553,10 +578,28 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
   }
 }
 
-// Row of every work unit.
-__global__ void k_unit_rows(const uint64_t* U, uint64_t nrows, uint32_t* urow) {
-  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x)
-    for (uint64_t u = U[r]; u < U[r + 1]; u++) urow[u] = (uint32_t)r;
+// Row of every work unit.  A thread writes up to UROW_SMALL units of its
+// row; rows with more are listed and finished by whole blocks.
+constexpr uint64_t UROW_SMALL = 16;
+
+__global__ void k_unit_rows(const uint64_t* U, uint64_t nrows, uint32_t* urow, uint32_t* big, uint32_t* nbig) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t u0 = U[r];
+    uint64_t u1 = U[r + 1];
+    if (u1 - u0 > UROW_SMALL) {
+      big[atomicAdd(nbig, 1u)] = (uint32_t)r;
+      u1 = u0 + UROW_SMALL;
+    }
+    for (uint64_t u = u0; u < u1; u++) urow[u] = (uint32_t)r;
+  }
+}
+
+__global__ void k_unit_rows_big(const uint64_t* U, const uint32_t* big, const uint32_t* nbig, uint32_t* urow) {
+  const uint32_t nb = *nbig;
+  for (uint32_t i = blockIdx.x; i < nb; i += gridDim.x) {
+    const uint32_t r = big[i];
+    for (uint64_t u = U[r] + UROW_SMALL + threadIdx.x; u < U[r + 1]; u += blockDim.x) urow[u] = r;
+  }
 }
 
 // ---- two-set COUNT leaf with per-unit descriptors ----------------------------
@@ -571,7 +614,8 @@ struct UnitDesc {
   uint32_t plo;      // uint: first probed key index; bitset: window base value
   uint32_t phi;      // uint: end of probed keys (UINT32_MAX: next unit's plo); bitset: largest value
   uint64_t pword;    // probed set's first bitset word, or UINT64_MAX (sorted keys)
-  uint32_t drv;      // driving participant (0 or 1)
+  uint32_t drv;      // driving participant (0 or 1), or DRV_AND: words [plo | phi << 32, +dcount) of
+                     // participant 0's pool AND words [pword, +dcount) of participant 1's
   uint32_t pad;
 };
 
@@ -598,6 +642,25 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
     dset_range(wa.set[0], r, b[0], e[0], sidx[0]);
     dset_range(wa.set[1], r, b[1], e[1], sidx[1]);
     const uint32_t d = drv[r];
+    UnitDesc t;
+    t.pad = 0;
+    if (d == DRV_AND) {
+      // word k of each window covers base + 64 k; both bases are multiples of 64
+      const uint32_t base0 = wa.set[0].bs_base[sidx[0]], base1 = wa.set[1].bs_base[sidx[1]];
+      const uint32_t v0 = max(base0, base1);
+      const uint32_t v1 = min(wa.set[0].keys[e[0] - 1], wa.set[1].keys[e[1] - 1]);
+      const uint32_t words = ((v1 - v0) >> 6) + 1;
+      const uint32_t k0 = (uint32_t)(u - u0) * U_EL;
+      const uint64_t w0 = wa.set[0].bs_word[sidx[0]] + ((v0 - base0) >> 6) + k0;
+      t.drv = DRV_AND;
+      t.dstart = 0;
+      t.dcount = min((uint32_t)U_EL, words - k0);
+      t.plo = (uint32_t)w0;
+      t.phi = (uint32_t)(w0 >> 32);
+      t.pword = wa.set[1].bs_word[sidx[1]] + ((v0 - base1) >> 6) + k0;
+      desc[u] = t;
+      continue;
+    }
     const uint32_t db = d ? b[1] : b[0], de = d ? e[1] : e[0];
     const uint32_t pb = d ? b[0] : b[1], pe = d ? e[0] : e[1];
     const uint64_t sq = d ? sidx[0] : sidx[1];
@@ -605,9 +668,7 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
     const uint32_t* pk = d ? wa.set[0].keys : wa.set[1].keys;
     const uint64_t* bsw = d ? wa.set[0].bs_word : wa.set[1].bs_word;
     const uint32_t* bsb = d ? wa.set[0].bs_base : wa.set[1].bs_base;
-    UnitDesc t;
     t.drv = d;
-    t.pad = 0;
     t.dstart = db + (uint32_t)(u - u0) * U_EL;
     t.dcount = min((uint32_t)U_EL, de - t.dstart);
     t.pword = (pe > pb) ? bsw[sq] : UINT64_MAX;
@@ -624,14 +685,31 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
 
 struct Leaf2Args {
   const uint32_t* keys[2];
+  const uint32_t* samp[2];
   const uint64_t* pool[2];
   const UnitDesc* desc;
-  const uint32_t* urow;   // grouped only
-  const uint32_t* gid;    // null: one group
+  uint64_t* ucnt;         // grouped: count of every unit; null: one group, summed into gcount[0]
   uint64_t* gcount;
   uint64_t units;
   uint64_t nvblk;
 };
+
+// Groups own contiguous runs of units (frontier rows are in group order):
+// a group's count is the difference of the scanned unit counts at the ends
+// of its run.
+__global__ void k_group_bounds(const uint32_t* urow, const uint32_t* gid, uint64_t units, const uint64_t* uex,
+                               uint64_t* gstart, uint64_t* gend) {
+  for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t g = gid[urow[u]];
+    if (u == 0 || gid[urow[u - 1]] != g) gstart[g] = uex[u];
+    if (u + 1 == units || gid[urow[u + 1]] != g) gend[g] = uex[u + 1];
+  }
+}
+
+__global__ void k_group_add(const uint64_t* gstart, const uint64_t* gend, uint64_t n, uint64_t* gcount) {
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (uint64_t)gridDim.x * blockDim.x)
+    gcount[g] += gend[g] - gstart[g];
+}
 
 #ifndef LH_L2_CAP
 #define LH_L2_CAP 1024
@@ -665,6 +743,42 @@ __device__ __forceinline__ uint32_t count_members(Arr a, uint32_t m, const uint3
   return c;
 }
 
+// Number of entries <= x[it] in the sorted a[0, n), n >= 1, for it < nit:
+// branchless, trip count set by n alone.
+template <class Arr>
+__device__ __forceinline__ void count_le(Arr a, uint32_t n0, const uint32_t* x, uint32_t nit, uint32_t* k) {
+#pragma unroll
+  for (int it = 0; it < U_IT; it++) k[it] = 0;
+  uint32_t n = n0;
+  while (n > 1) {
+    const uint32_t half = n >> 1;
+#pragma unroll
+    for (int it = 0; it < U_IT; it++)
+      if (it < (int)nit) k[it] = (a[k[it] + half - 1] <= x[it]) ? k[it] + half : k[it];
+    n -= half;
+  }
+#pragma unroll
+  for (int it = 0; it < U_IT; it++)
+    if (it < (int)nit) k[it] += (a[k[it]] <= x[it]) ? 1u : 0u;
+}
+
+// The wave copies src[0, m) to LDS, U_IT loads in flight per lane.
+__device__ __forceinline__ void wave_stage(uint32_t* dst, const uint32_t* src, uint32_t m, int lane) {
+  for (uint32_t k0 = 0; k0 < m; k0 += U_IT * WAVE) {
+    uint32_t t[U_IT];
+#pragma unroll
+    for (int j = 0; j < U_IT; j++) {
+      const uint32_t i = k0 + j * WAVE + lane;
+      t[j] = i < m ? src[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < U_IT; j++) {
+      const uint32_t i = k0 + j * WAVE + lane;
+      if (i < m) dst[i] = t[j];
+    }
+  }
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
   // LDS operations of one wave complete in order; this keeps the compiler
   // from moving them across the point where lanes read what others wrote
@@ -673,59 +787,118 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Probe path of a unit: the unit's driver keys against the probed set's
+// bitset, its LDS-staged keys, or its line samples.
+__device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDesc& t, uint64_t u, uint32_t* stage,
+                                               int lane) {
+  uint32_t c = 0;
+  const uint32_t next_lo = (u + 1 < a.units) ? a.desc[u + 1].plo : 0u;
+  const uint32_t* dk = t.drv ? a.keys[1] : a.keys[0];
+  const uint32_t* pk = t.drv ? a.keys[0] : a.keys[1];
+  const uint64_t* pool = t.drv ? a.pool[0] : a.pool[1];
+  const uint32_t nit = (t.dcount + WAVE - 1) / WAVE;
+  uint32_t x[U_IT];
+  bool v[U_IT];
+#pragma unroll
+  for (int it = 0; it < U_IT; it++) {
+    const uint32_t i = it * WAVE + lane;
+    v[it] = i < t.dcount;
+    x[it] = v[it] ? dk[t.dstart + i] : 0u;
+  }
+  if (t.pword != UINT64_MAX) {
+#pragma unroll
+    for (int it = 0; it < U_IT; it++) {
+      if (!v[it] || x[it] < t.plo || x[it] > t.phi) continue;
+      const uint32_t dd = x[it] - t.plo;
+      c += (uint32_t)((pool[t.pword + (dd >> 6)] >> (dd & 63u)) & 1ull);
+    }
+  } else {
+    const uint32_t lo = t.plo;
+    const uint32_t hi = t.phi == UINT32_MAX ? next_lo : t.phi;
+    const uint32_t m = hi - lo;
+    if (m > 0 && m <= (uint32_t)L2_CAP && m <= L2_STAGE_RATIO * t.dcount) {
+      wave_stage(stage, pk + lo, m, lane);
+      wave_lds_sync();
+      c = count_members(stage, m, x, v, nit);
+      wave_lds_sync();
+    } else if (m > 0) {
+      // A large range: bisect the line samples inside it (staged in LDS
+      // when they fit), then search the one line that can hold x.
+      // Samples j in [jf, jl] start lines inside [lo, hi); keys before
+      // the first of them belong to the range's first, partial line.
+      const uint32_t* sp = t.drv ? a.samp[0] : a.samp[1];
+      const uint32_t jf = (lo + (1u << LINE_SHIFT) - 1) >> LINE_SHIFT;
+      const uint32_t jl = (hi - 1) >> LINE_SHIFT;
+      uint32_t k[U_IT];
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) k[it] = 0;
+      if (jl >= jf) {
+        const uint32_t ns = jl - jf + 1;
+        if (ns <= (uint32_t)L2_CAP) {
+          wave_stage(stage, sp + jf, ns, lane);
+          wave_lds_sync();
+          count_le(stage, ns, x, nit, k);
+          wave_lds_sync();
+        } else {
+          count_le(sp + jf, ns, x, nit, k);
+        }
+      }
+      uint32_t pos[U_IT], len[U_IT];
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        const uint32_t sb = k[it] ? (jf + k[it] - 1) << LINE_SHIFT : lo;
+        const uint32_t se = (uint32_t)min<uint64_t>(hi, (uint64_t)(jf + k[it]) << LINE_SHIFT);
+        pos[it] = sb;
+        len[it] = se > sb ? se - sb : 0;
+      }
+#pragma unroll
+      for (int step = 0; step < (int)LINE_SHIFT; step++)
+#pragma unroll
+        for (int it = 0; it < U_IT; it++)
+          if (it < (int)nit && len[it] > 1) {
+            const uint32_t half = len[it] >> 1;
+            pos[it] = (pk[pos[it] + half] <= x[it]) ? pos[it] + half : pos[it];
+            len[it] -= half;
+          }
+#pragma unroll
+      for (int it = 0; it < U_IT; it++)
+        if (it < (int)nit) c += (v[it] && len[it] > 0 && pk[pos[it]] == x[it]) ? 1u : 0u;
+    }
+  }
+  return c;
+}
+
 __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
   __shared__ uint32_t s_stage[J_NW][L2_CAP];
   __shared__ unsigned long long s_cnt;
   const int tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
   if (tid == 0) s_cnt = 0;
   uint32_t* stage = s_stage[w];
-  uint64_t run = 0;
+  uint64_t run = 0;  // ungrouped: this lane's part of the block's count
   for (uint64_t vb = blockIdx.x; vb < a.nvblk; vb += gridDim.x) {
     const uint64_t u = vb * J_NW + w;
     if (u >= a.units) continue;  // wave-uniform; no barrier inside the loop
     const UnitDesc t = a.desc[u];
-    const uint32_t next_lo = (u + 1 < a.units) ? a.desc[u + 1].plo : 0u;
-    const uint32_t* dk = t.drv ? a.keys[1] : a.keys[0];
-    const uint32_t* pk = t.drv ? a.keys[0] : a.keys[1];
-    const uint64_t* pool = t.drv ? a.pool[0] : a.pool[1];
-    const uint32_t nit = (t.dcount + WAVE - 1) / WAVE;
-    uint32_t x[U_IT];
-    bool v[U_IT];
-#pragma unroll
-    for (int it = 0; it < U_IT; it++) {
-      const uint32_t i = it * WAVE + lane;
-      v[it] = i < t.dcount;
-      x[it] = v[it] ? dk[t.dstart + i] : 0u;
-    }
     uint32_t c = 0;
-    if (t.pword != UINT64_MAX) {
+    if (t.drv == DRV_AND) {
+      const uint64_t w0 = (uint64_t)t.plo | ((uint64_t)t.phi << 32);
 #pragma unroll
       for (int it = 0; it < U_IT; it++) {
-        if (!v[it] || x[it] < t.plo || x[it] > t.phi) continue;
-        const uint32_t dd = x[it] - t.plo;
-        c += (uint32_t)((pool[t.pword + (dd >> 6)] >> (dd & 63u)) & 1ull);
+        const uint32_t i = it * WAVE + lane;
+        if (i < t.dcount) c += (uint32_t)__popcll(a.pool[0][w0 + i] & a.pool[1][t.pword + i]);
       }
     } else {
-      const uint32_t lo = t.plo;
-      const uint32_t hi = t.phi == UINT32_MAX ? next_lo : t.phi;
-      const uint32_t m = hi - lo;
-      if (m > 0 && m <= (uint32_t)L2_CAP && m <= L2_STAGE_RATIO * t.dcount) {
-        for (uint32_t k = lane; k < m; k += WAVE) stage[k] = pk[lo + k];
-        wave_lds_sync();
-        c = count_members(stage, m, x, v, nit);
-        wave_lds_sync();
-      } else if (m > 0) {
-        c = count_members(pk + lo, m, x, v, nit);
-      }
+      c = probe_unit(a, t, u, stage, lane);
     }
-    if (a.gid) {
+    if (a.ucnt) {
+      // grouped: one count per unit; groups are summed by a scan afterwards
       const uint64_t s = wave_sum((uint64_t)c);
-      if (lane == 0 && s) atomicAdd((unsigned long long*)&a.gcount[a.gid[a.urow[u]]], (unsigned long long)s);
+      if (lane == 0) a.ucnt[u] = s;
     } else {
       run += c;
     }
   }
-  if (!a.gid) {
+  if (!a.ucnt) {
     __syncthreads();
     const uint64_t s = wave_sum(run);
     if (lane == 0 && s) atomicAdd(&s_cnt, (unsigned long long)s);
@@ -845,6 +1018,7 @@ DSet make_dset(const lh_plan_t* p, const Participant& pt, const Frontier& F) {
   const Level& L = t->lv[pt.level];
   DSet d{};
   d.keys = L.keys.p;
+  d.samp = L.samp.p;
   d.bs_word = L.bs_word.p;
   d.bs_base = L.bs_base.p;
   d.pool = L.pool.p;
@@ -866,7 +1040,8 @@ struct DepthWork {
   uint64_t total = 0, units = 0, nblk = 0;
 };
 
-void depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs& a, DepthWork& dw, hipStream_t s) {
+void depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs& a, DepthWork& dw, hipStream_t s,
+                bool allow_and = false) {
   const auto& parts = p->parts[d];
   WorkArgs wa{};
   wa.np = (uint32_t)parts.size();
@@ -881,7 +1056,7 @@ void depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs& a, 
   dw.U.alloc(F.n + 1, s);
   {
     ProfScope ps("join_work", s, F.n, 0);
-    k_work<<<grid_for(F.n), 256, 0, s>>>(wa, F.n, work.p, dw.drv.p, units.p);
+    k_work<<<grid_for(F.n), 256, 0, s>>>(wa, F.n, work.p, dw.drv.p, units.p, allow_and ? 1u : 0u);
   }
   LH_HIP(hipGetLastError());
   dw.total = scan_u32_to_u64(work.p, dw.W.p, F.n, s);
@@ -889,7 +1064,12 @@ void depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs& a, 
   if (dw.units >= (1ull << 32)) fail(LH_ERR_OVERFLOW, "join: more than 2^32 work units at one attribute");
   dw.urow.alloc(dw.units, s);
   if (dw.units) {
-    k_unit_rows<<<grid_for(F.n), 256, 0, s>>>(dw.U.p, F.n, dw.urow.p);
+    // rows with more than UROW_SMALL units number at most units / UROW_SMALL
+    DBuf<uint32_t> big(std::max<uint64_t>(1, std::min<uint64_t>(F.n, dw.units / UROW_SMALL)), s), nbig(1, s);
+    fill_u32(nbig.p, 0u, 1, s);
+    k_unit_rows<<<grid_for(F.n), 256, 0, s>>>(dw.U.p, F.n, dw.urow.p, big.p, nbig.p);
+    LH_HIP(hipGetLastError());
+    k_unit_rows_big<<<1024, 256, 0, s>>>(dw.U.p, big.p, nbig.p, dw.urow.p);
     LH_HIP(hipGetLastError());
   }
   dw.nblk = (dw.units + J_NW - 1) / J_NW;
@@ -1018,7 +1198,12 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
   // leaf attribute: intersect and aggregate
   ElemArgs a{};
   DepthWork dw;
-  if (F.n) depth_work(p, leaf, F, a, dw, s);
+  // two sets with set semantics and COUNT: the descriptor-driven leaf, which
+  // also intersects two bitsets word by word
+  bool all_set = !is_sum;
+  for (const auto& A : p->atoms) all_set = all_set && !A.bag;
+  const bool leaf2 = p->case_prefix && all_set && p->parts[leaf].size() == 2;
+  if (F.n) depth_work(p, leaf, F, a, dw, s, leaf2);
   const uint64_t total = dw.total;
   const uint64_t nblk = dw.nblk;
   if (nblk >= (1ull << 31)) fail(LH_ERR_OVERFLOW, "join: too much work at the last attribute");
@@ -1067,9 +1252,7 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
     L.gcount = gcount.p;
     L.gacc = gacc.p;
     if (total) {
-      bool all_set = !is_sum;
-      for (const auto& A : p->atoms) all_set = all_set && !A.bag;
-      if (all_set && a.np == 2) {
+      if (leaf2) {
         // two sets, set semantics: per-unit descriptors, one load per wave
         DBuf<UnitDesc> desc(dw.units, s);
         WorkArgs wa{};
@@ -1081,19 +1264,34 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
           k_unit_desc<<<grid_for(dw.units), 256, 0, s>>>(wa, dw.U.p, dw.urow.p, dw.drv.p, dw.units, desc.p);
         }
         LH_HIP(hipGetLastError());
-        ProfScope ps("leaf_aggregate", s, F.n, total);
         Leaf2Args l2{};
         l2.keys[0] = a.set[0].keys;
         l2.keys[1] = a.set[1].keys;
+        l2.samp[0] = a.set[0].samp;
+        l2.samp[1] = a.set[1].samp;
         l2.pool[0] = a.set[0].pool;
         l2.pool[1] = a.set[1].pool;
         l2.desc = desc.p;
-        l2.urow = dw.urow.p;
-        l2.gid = L.gid;
         l2.gcount = L.gcount;
         l2.units = dw.units;
         l2.nvblk = nblk;
-        k_leaf2_count<<<elem_grid(nblk), J_NT, 0, s>>>(l2);
+        DBuf<uint64_t> ucnt(L.gid ? dw.units : 0, s);
+        l2.ucnt = ucnt.p;
+        {
+          ProfScope ps("leaf_aggregate", s, F.n, total);
+          k_leaf2_count<<<elem_grid(nblk), J_NT, 0, s>>>(l2);
+        }
+        LH_HIP(hipGetLastError());
+        if (L.gid) {
+          ProfScope ps("leaf_groups", s, dw.units, 0);
+          DBuf<uint64_t> uex(dw.units + 1, s), gstart(n_groups, s), gend(n_groups, s);
+          scan_u64(ucnt.p, uex.p, dw.units, s);
+          fill_u64(gstart.p, 0, n_groups, s);
+          fill_u64(gend.p, 0, n_groups, s);
+          k_group_bounds<<<grid_for(dw.units), 256, 0, s>>>(dw.urow.p, L.gid, dw.units, uex.p, gstart.p, gend.p);
+          LH_HIP(hipGetLastError());
+          k_group_add<<<grid_for(n_groups), 256, 0, s>>>(gstart.p, gend.p, n_groups, L.gcount);
+        }
       } else {
         ProfScope ps("leaf_aggregate", s, F.n, total);
         if (all_set) k_elem<M_LEAF_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);

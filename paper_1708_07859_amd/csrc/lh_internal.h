@@ -122,9 +122,14 @@ AnnoStats anno_stats(const double* v, uint64_t n, hipStream_t s);
 // ---------------------------------------------------------------------------
 // Tries (trie.hip)
 // ---------------------------------------------------------------------------
+// A level's keys carry one sample per 2^LINE_SHIFT keys (one 128-byte
+// line): samp[j] = keys[j << LINE_SHIFT].
+constexpr uint32_t LINE_SHIFT = 5;
+
 struct Level {
   uint64_t n = 0;            // nodes
   DBuf<uint32_t> keys;       // n
+  DBuf<uint32_t> samp;       // ceil(n / 32): first key of every 32
   DBuf<uint32_t> offs;       // n+1: children in the next level; last level: run offsets
   uint64_t n_sets = 0;       // sets at this level (1 at level 0, else nodes of level-1)
   DBuf<uint64_t> bs_word;    // n_sets: first word in pool, UINT64_MAX = uint layout

@@ -93,6 +93,11 @@ __global__ __launch_bounds__(TB_NT) void k_emit_levels(EmitArgs a, uint64_t n) {
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
+__global__ void k_line_samples(const uint32_t* keys, uint64_t n_samp, uint32_t* samp) {
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_samp; j += (uint64_t)gridDim.x * blockDim.x)
+    samp[j] = keys[j << LINE_SHIFT];
+}
+
 // ---- layouts ---------------------------------------------------------------
 
 struct SetRange {
@@ -282,6 +287,16 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
   if (bag) {
     k_set_u32<<<1, 1, 0, s>>>(t->lv[n_keys - 1].offs.p + n_leaf, (uint32_t)n);
     LH_HIP(hipGetLastError());
+  }
+
+  for (uint32_t l = 0; l < n_keys; l++) {
+    Level& L = t->lv[l];
+    const uint64_t ns = (L.n + (1u << LINE_SHIFT) - 1) >> LINE_SHIFT;
+    L.samp.alloc(ns, s);
+    if (ns) {
+      k_line_samples<<<grid_for(ns), 256, 0, s>>>(L.keys.p, ns, L.samp.p);
+      LH_HIP(hipGetLastError());
+    }
   }
 
   // Rows in trie order: bag keeps every sorted row, set keeps leaf heads.

@@ -246,9 +246,16 @@ def set_pairs(card, universe, n_pairs, seed):
     """n_pairs pairs of sorted distinct uint32 sets, each of size ``card``
     drawn uniformly without replacement from [0, universe)."""
     rng = rng_for(seed)
+
+    def one():
+        # the sorted draw, read off a mask (no sort of the sample needed)
+        mask = np.zeros(universe, dtype=bool)
+        mask[rng.choice(universe, card, replace=False)] = True
+        return np.flatnonzero(mask).astype(np.uint32)
+
     out = []
     for _ in range(n_pairs):
-        a = np.sort(rng.choice(universe, card, replace=False)).astype(np.uint32)
-        b = np.sort(rng.choice(universe, card, replace=False)).astype(np.uint32)
+        a = one()
+        b = one()
         out.append((a, b))
     return out

@@ -33,6 +33,18 @@ def spmv(a, x):
                        "anno": 0, "bag": True}]}
 
 
+def set_pairs(pairs):
+    """R(p,x) |x| S(p,x), COUNT(*) GROUP BY p: row p of the result is
+    |A_p intersect B_p| for the p-th pair (A_p, B_p); attributes p=0, x=1."""
+    pr = np.concatenate([np.full(len(a), i, np.uint32) for i, (a, _) in enumerate(pairs)])
+    ps = np.concatenate([np.full(len(b), i, np.uint32) for i, (_, b) in enumerate(pairs)])
+    xr = np.concatenate([a for a, _ in pairs]).astype(np.uint32)
+    xs = np.concatenate([b for _, b in pairs]).astype(np.uint32)
+    return {"n_attrs": 2, "agg": "count", "out": [0],
+            "atoms": [{"keys": [pr, xr], "attrs": [0, 1], "bag": False},
+                      {"keys": [ps, xs], "attrs": [0, 1], "bag": False}]}
+
+
 def star(s, u_hi=0.20, m2=0, m3=0):
     """SUM(fact.ann) GROUP BY D1.g over fact |x| D0..D3 with D0.u < u_hi,
     D2.m == m2 and D3.m == m3.  Attributes k0..k3 = 0..3."""

@@ -241,3 +241,39 @@ def test_no_device_memory_leaks(lh):
     a = synth.sparse_matrix(100, 5, seed=1)
     lh.run_query(queries.spgemm(a, a))
     assert lh.live_allocations() == before
+
+
+def _mixed_pairs():
+    rng = synth.rng_for(7)
+    pairs = list(synth.set_pairs(30000, 60000, 6, seed=100))         # density 1/2
+    pairs += synth.set_pairs(5000, 64 * 5000, 3, seed=101)           # sparse
+    big = np.sort(rng.choice(1 << 20, 40000, replace=False)).astype(np.uint32)
+    small = np.sort(rng.choice(1 << 20, 400, replace=False)).astype(np.uint32)
+    pairs.append((big, small))                                       # size ratio 100
+    pairs.append((small, big))
+    pairs.append((np.arange(0, 1000, dtype=np.uint32), np.arange(5000, 7000, dtype=np.uint32)))  # disjoint
+    pairs.append((np.arange(1, 4000, 3, dtype=np.uint32), np.arange(2, 4000, 2, dtype=np.uint32)))
+    pairs.append((np.array([7], np.uint32), np.array([7], np.uint32)))
+    return pairs
+
+
+@pytest.mark.parametrize("la,lb", [("uint", "uint"), ("uint", "bitset"), ("bitset", "uint"),
+                                   ("bitset", "bitset"), ("plain", "plain")])
+def test_set_pair_intersections(lh, la, lb):
+    """Intersections of set pairs (the intersection micro-benchmark's shape)
+    in every layout combination, including the word-AND path of two
+    bitsets: equal to the oracle and to numpy's intersect1d."""
+    pairs = _mixed_pairs()
+    q = queries.set_pairs(pairs)
+    say(f"set pairs {la}/{lb}: {len(pairs)} pairs")
+    ta = lh.trie_build(q["atoms"][0]["keys"], layout=la)
+    tb = lh.trie_build(q["atoms"][1]["keys"], layout=lb)
+    p = lh.plan(2, [(ta, [0, 1], -1), (tb, [0, 1], -1)], out=[0], agg="count")
+    r = lh.join_aggregate([p])[0]
+    got = r.to_host()
+    r.free(); p.free(); ta.free(); tb.free()
+    want = oracle.join_aggregate(q)
+    assert_same(got, want)
+    sizes = np.array([len(np.intersect1d(a, b)) for a, b in pairs])
+    nz = np.nonzero(sizes)[0]
+    assert np.array_equal(got["keys"][:, 0], nz) and np.array_equal(got["counts"], sizes[nz])
