@@ -168,6 +168,8 @@ const char* lh_last_error(void) { return g_last_error.c_str(); }
 lh_status lh_trie_get_info(const lh_trie* t, lh_trie_info* info) {
   return guard([&] {
     if (!t || !info || !tracked(g_tries, t)) fail(LH_ERR_INVALID, "not a live lh_trie");
+    lh::ensure_column_stats(const_cast<lh_trie*>(t), nullptr);
+    LH_HIP(hipStreamSynchronize(nullptr));
     memset(info, 0, sizeof *info);
     info->n_levels = t->n_levels;
     info->n_rows = t->n_rows;

@@ -150,6 +150,8 @@ struct lh_trie {
   uint32_t level_order[LH_MAX_KEYS];   // input key column of each level
   uint32_t key_bits[LH_MAX_KEYS];      // significant bits per level
   uint32_t key_max[LH_MAX_KEYS];       // largest key per level
+  // column statistics (learned order features), computed on first use
+  bool col_stats = false;
   uint64_t col_distinct[LH_MAX_KEYS];  // distinct values of each level's column (kept rows)
   uint64_t col_freq_max[LH_MAX_KEYS];  // largest number of kept rows sharing one value
   lh::Level lv[LH_MAX_KEYS];
@@ -173,6 +175,9 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
                     uint32_t n_annos, const double* const* annos, uint32_t n_meta,
                     const uint32_t* const* meta, const uint32_t* level_order, uint32_t flags,
                     const uint32_t* sel, uint64_t n_sel, hipStream_t s);
+
+// Column statistics (col_distinct, col_freq_max), computed once per trie.
+void ensure_column_stats(lh_trie* t, hipStream_t s);
 
 // Per-set layout and bitset materialization for one level.
 void build_layouts(lh_trie* t, uint32_t level, uint32_t layout_flags, hipStream_t s);

@@ -180,8 +180,10 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
   // ---- attribute order --------------------------------------------------------
   Hypergraph h;
   h.n_attrs = q->n_attrs;
+  const bool learned_policy = !q->attr_order && (q->policy & LH_POLICY_MASK) == LH_POLICY_LEARNED;
   for (uint32_t e = 0; e < q->n_atoms; e++) {
     const lh_atom& A = q->atoms[e];
+    if (learned_policy) ensure_column_stats(const_cast<lh_trie*>(A.trie), s);
     Edge E;
     // attributes in the trie's level order (an order that breaks it re-sorts the relation)
     for (uint32_t l = 0; l < A.trie->n_levels; l++) {

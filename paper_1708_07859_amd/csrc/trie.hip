@@ -193,6 +193,19 @@ void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, hipStream_t s) {
   }
 }
 
+void ensure_column_stats(lh_trie* t, hipStream_t s) {
+  if (t->col_stats) return;
+  for (uint32_t l = 0; l < t->n_levels; l++) {
+    if (t->key_max[l] < (1u << 28)) {
+      column_freq(t->skeys[l].p, t->n_rows, t->key_max[l], t->col_distinct[l], t->col_freq_max[l], s);
+    } else {
+      t->col_distinct[l] = t->n_rows;
+      t->col_freq_max[l] = 1;
+    }
+  }
+  t->col_stats = true;
+}
+
 lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* keys, uint32_t n_annos,
                     const double* const* annos, uint32_t n_meta, const uint32_t* const* meta,
                     const uint32_t* level_order, uint32_t flags, const uint32_t* sel, uint64_t n_sel,
@@ -328,16 +341,6 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
   for (uint32_t m = 0; m < n_meta; m++) {
     t->meta.emplace_back(t->n_rows, s);
     gather_u32(meta[m], rowmap, t->meta.back().p, t->n_rows, s);
-  }
-
-  // column statistics for the learned cost model's order features
-  for (uint32_t l = 0; l < n_keys; l++) {
-    if (t->key_max[l] < (1u << 28)) {
-      column_freq(t->skeys[l].p, t->n_rows, t->key_max[l], t->col_distinct[l], t->col_freq_max[l], s);
-    } else {
-      t->col_distinct[l] = t->n_rows;
-      t->col_freq_max[l] = 1;
-    }
   }
 
   uint32_t mode = flags & LH_LAYOUT_MASK;
