@@ -247,7 +247,7 @@ def bench_learned(args, lh, torch, synth):
     cands = {}
     for layout in ("plain", "learned"):
         for order in itertools.permutations(range(3)):
-            t, c, _ = best_of(layout, "fixed", list(order), reps=1)
+            t, c, _ = best_of(layout, "fixed", list(order), reps=2)
             assert c == c_plain
             cands[f"{layout}:{list(order)}"] = t
             log(f"  candidate {layout} {list(order)}: {t:.1f} ms")

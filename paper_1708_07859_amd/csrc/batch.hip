@@ -9,8 +9,14 @@
 // section 5).  Every row i of every instance is a work item:
 //  * light rows (few products) are taken by one wave, which sums exactly
 //    into a private LDS hash keyed by k;
-//  * heavy rows are taken by a whole block, which sums into a dense LDS
-//    window of k values, window after window.
+//  * heavy rows are taken by a whole block in one pass over their products:
+//    each product marks its k in an LDS bitmap and adds its exact digits at
+//    k in the block's own global scratch; the row is then emitted in k order
+//    at each k's bitmap rank, clearing the scratch as it is read;
+//  * rows with many products relative to the size of E are taken by a
+//    block in inner-product form: A's row becomes an LDS bitmap over j and
+//    one thread per output k walks column k of E (a transposed copy of E
+//    built once per batch), summing exactly in registers, with no atomics.
 // Workers pull items from two device queues (heavy rows first, longest
 // first), so one launch balances thousands of instances.  The launch and
 // its queue resets are captured once in a hipGraph and replayed.  Sums are
@@ -38,7 +44,7 @@ namespace {
 
 constexpr int B_NT = 256;
 constexpr int B_NW = B_NT / WAVE;
-constexpr int HS = 256;                       // hash slots per wave
+constexpr uint32_t KW_MAX = 64 * 4 * B_NT;   // k values per heavy window (4 bitmap words per thread)
 constexpr uint32_t EMPTY_KEY = 0xffffffffu;
 
 struct BInst {
@@ -63,6 +69,15 @@ struct BInst {
   uint32_t sum;
   uint32_t n_k;              // matrix: largest k + 1
   uint64_t row_base;         // first batch row of this instance
+  // matrix, inner-product rows: E transposed (levels k, j) and A's j range
+  uint32_t n_j;              // largest j of A + 1
+  uint32_t bt_n0;            // k nodes of E transposed
+  const uint32_t* bt_k;      // their k values
+  const uint32_t* bt_off;    // child offsets into bt_j
+  const uint32_t* bt_j;      // j of each (k, j)
+  const uint32_t* bt_run;    // bag runs of (k, j) into bt_val rows (null: one row each)
+  const double* bt_val;      // E's annotation in transposed row order
+  uint64_t nnz_e;            // (k, j) pairs of E
 };
 
 __device__ __forceinline__ bool find_j(const BInst& I, uint32_t j, uint32_t& pos) {
@@ -93,8 +108,8 @@ __device__ __forceinline__ void rows_of(const uint32_t* run, uint32_t node, uint
 // ---- setup: per-row product bounds and classes ----------------------------
 
 __global__ void k_row_setup(const BInst* inst, const uint64_t* inst_row0, uint32_t n_inst, uint64_t R,
-                            uint32_t light_max, uint32_t* row_inst, uint64_t* prod, uint32_t* ub, uint32_t* is_heavy,
-                            uint32_t* is_light) {
+                            uint32_t light_max, uint32_t inner_ratio, uint32_t* row_inst, uint64_t* prod, uint32_t* ub,
+                            uint32_t* is_heavy, uint32_t* is_light, uint32_t* is_inner) {
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < R; t += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t ii = (uint32_t)upper_bound_minus1<uint64_t>(inst_row0, 0, n_inst, t);
     const BInst& I = inst[ii];
@@ -115,9 +130,13 @@ __global__ void k_row_setup(const BInst* inst, const uint64_t* inst_row0, uint32
     }
     prod[t] = u;
     const bool heavy = I.kind == 1 && u > light_max;
+    // inner-product form when walking all of E costs less than inner_ratio
+    // scattered updates per product
+    const bool inner = heavy && I.bt_k && I.n_j <= KW_MAX && u * inner_ratio >= I.nnz_e;
     ub[t] = I.kind == 0 ? 1u : (uint32_t)min<uint64_t>(u, I.n_k);
-    is_heavy[t] = heavy ? 1u : 0u;
+    is_heavy[t] = heavy && !inner ? 1u : 0u;
     is_light[t] = heavy ? 0u : 1u;
+    is_inner[t] = inner ? 1u : 0u;
   }
 }
 
@@ -136,12 +155,17 @@ struct BatchArgs {
   uint64_t n_heavy;
   const uint32_t* light;     // light rows
   uint64_t n_light;
-  uint32_t* qhead;           // [0] heavy queue, [1] light queue
+  const uint32_t* inner;     // inner-product rows, grouped by instance
+  uint64_t n_inner;
+  uint32_t* qhead;           // [0] heavy queue, [1] light queue, [2] inner queue
   uint32_t* row_nnz;         // outputs per row
   uint32_t* ub_k;
   uint64_t* ub_cnt;
   double* ub_sum;
   uint32_t* err;
+  unsigned long long* scratch_cnt;  // per block: kw counts, all zero between rows
+  long long* scratch_dig;           // per block: kw x EXACT_MAXD digit slots, zero between rows
+  uint32_t kw;                      // k values per heavy window (multiple of 64, <= KW_MAX)
 };
 
 // Exact sum held in slots (EXACT_MAXD stride) of one accumulator: add t.
@@ -166,99 +190,214 @@ __device__ __forceinline__ bool lds_add_term(long long* slots, double v, int32_t
   return ok;
 }
 
-template <int WIN>
-__global__ __launch_bounds__(B_NT) void k_batch(BatchArgs a) {
-  // LDS: heavy phase uses a dense window, light phase per-wave hashes
-  constexpr int HEAVY_BYTES = WIN * (8 + 8 * EXACT_MAXD);
-  constexpr int LIGHT_BYTES = B_NW * HS * (4 + 8 + 8 * EXACT_MAXD + 2);
-  constexpr int LDS_BYTES = HEAVY_BYTES > LIGHT_BYTES ? HEAVY_BYTES : LIGHT_BYTES;
-  __shared__ __align__(16) unsigned char lds[LDS_BYTES];
+// Heavy rows: one block per row, one pass over its products.
+__global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
+  __shared__ unsigned long long bm[KW_MAX / 64];   // touched k of the window
   __shared__ uint32_t s_item;
   __shared__ uint32_t s_wsum[B_NW];
-  const int tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+  const int tid = threadIdx.x;
   uint32_t bad = 0;
 
-  // ---- heavy rows: one block per row, dense windows of k ----
-  unsigned long long* wcnt = (unsigned long long*)lds;
-  long long* wdig = (long long*)(lds + WIN * 8);
+  unsigned long long* scnt = a.scratch_cnt + (uint64_t)blockIdx.x * a.kw;
+  long long* sdig = a.scratch_dig + (uint64_t)blockIdx.x * a.kw * EXACT_MAXD;
   for (;;) {
     if (tid == 0) s_item = atomicAdd(&a.qhead[0], 1u);
     __syncthreads();
-    const uint32_t item = s_item;
+    // uniform across the block: the row's descriptor goes to scalar registers
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (item >= a.n_heavy) break;
-    const uint32_t t = a.heavy[item];
+    const uint32_t t = __builtin_amdgcn_readfirstlane(a.heavy[item]);
     const BInst I = a.inst[a.row_inst[t]];
     const uint32_t p = t - (uint32_t)a.inst_row0[a.row_inst[t]];
     const uint32_t qb = I.a_off[p], qe = I.a_off[p + 1];
-    uint64_t out = a.ub_off[t];
+    const uint64_t out = a.ub_off[t];
     uint32_t nnz = 0;
-    for (uint32_t w0 = 0; w0 < I.n_k; w0 += WIN) {
-      for (int s = tid; s < WIN; s += B_NT) wcnt[s] = 0;
-      for (int s = tid; s < WIN * EXACT_MAXD; s += B_NT) wdig[s] = 0;
+    for (uint32_t w0 = 0; w0 < I.n_k; w0 += a.kw) {
+      const uint32_t wend = min(w0 + a.kw, I.n_k);
+      const uint32_t nwords = (wend - w0 + 63) / 64;
+      for (uint32_t s = tid; s < nwords; s += B_NT) bm[s] = 0;
       __syncthreads();
       for (uint32_t q = qb + tid; q < qe; q += B_NT) {
         uint32_t pe;
         if (!find_j(I, I.a_j[q], pe)) continue;
         uint32_t ab, ae;
         rows_of(I.a_run, q, ab, ae);
-        const uint32_t kb = lower_bound_u32(I.e_k, I.e_off[pe], I.e_off[pe + 1], w0);
-        const uint32_t kend = lower_bound_u32(I.e_k, kb, I.e_off[pe + 1], min(w0 + (uint32_t)WIN, I.n_k));
+        uint32_t kb = I.e_off[pe], kend = I.e_off[pe + 1];
+        if (I.n_k > a.kw) {
+          kb = lower_bound_u32(I.e_k, kb, kend, w0);
+          kend = lower_bound_u32(I.e_k, kb, kend, wend);
+        }
         for (uint32_t kp = kb; kp < kend; kp++) {
-          const uint32_t slot = I.e_k[kp] - w0;
+          const uint32_t k = I.e_k[kp] - w0;
+          atomicOr(&bm[k >> 6], 1ull << (k & 63u));
           uint32_t eb, ee;
           rows_of(I.e_run, kp, eb, ee);
-          atomicAdd(&wcnt[slot], (unsigned long long)(ae - ab) * (ee - eb));
+          atomicAdd(&scnt[k], (unsigned long long)(ae - ab) * (ee - eb));
           if (I.sum)
             for (uint32_t ra = ab; ra < ae; ra++)
               for (uint32_t re = eb; re < ee; re++) {
                 double hi, lo;
                 two_prod(I.a_val[ra], I.e_val[re], hi, lo);
-                bool ok = lds_add_term(wdig + slot * EXACT_MAXD, hi, I.lsb, I.D, 1);
-                ok = lds_add_term(wdig + slot * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
+                bool ok = lds_add_term(sdig + (uint64_t)k * EXACT_MAXD, hi, I.lsb, I.D, 1);
+                ok = lds_add_term(sdig + (uint64_t)k * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
                 if (!ok) bad = 1;
               }
         }
       }
+      __threadfence();
       __syncthreads();
-      // emit the window's non-empty slots in k order
-      constexpr int PER = WIN / B_NT;
-      uint32_t flags = 0, c = 0;
+      // emit in k order: thread tid owns bitmap words 4 tid .. 4 tid + 3
+      uint64_t wv[4];
+      uint32_t c = 0;
 #pragma unroll
-      for (int i = 0; i < PER; i++)
-        if (wcnt[tid * PER + i]) {
-          flags |= 1u << i;
-          c++;
-        }
+      for (int i = 0; i < 4; i++) {
+        const uint32_t wi = 4 * tid + i;
+        wv[i] = wi < nwords ? bm[wi] : 0ull;
+        c += (uint32_t)__popcll(wv[i]);
+      }
       uint32_t tot;
-      uint32_t pre = block_excl_scan<uint32_t, B_NT>(c, s_wsum, tot);
+      uint32_t r = block_excl_scan<uint32_t, B_NT>(c, s_wsum, tot);
 #pragma unroll
-      for (int i = 0; i < PER; i++) {
-        if (!((flags >> i) & 1u)) continue;
-        const int s = tid * PER + i;
-        const uint64_t o = out + nnz + pre;
-        a.ub_k[o] = w0 + (uint32_t)s;
-        a.ub_cnt[o] = wcnt[s];
-        if (I.sum) a.ub_sum[o] = exact_round((const int64_t*)(wdig + s * EXACT_MAXD), I.D, I.lsb, a.err);
-        pre++;
+      for (int i = 0; i < 4; i++) {
+        uint64_t word = wv[i];
+        while (word) {
+          const uint32_t k = (4 * tid + i) * 64 + (uint32_t)__builtin_ctzll(word);
+          word &= word - 1;
+          const uint64_t o = out + nnz + r++;
+          a.ub_k[o] = w0 + k;
+          a.ub_cnt[o] = atomicExch(&scnt[k], 0ull);
+          if (I.sum) {
+            int64_t dg[EXACT_MAXD];
+#pragma unroll
+            for (int d = 0; d < EXACT_MAXD; d++)
+              dg[d] = d < (int)I.D ? (int64_t)atomicExch((unsigned long long*)&sdig[(uint64_t)k * EXACT_MAXD + d], 0ull)
+                                   : 0;
+            a.ub_sum[o] = exact_round(dg, I.D, I.lsb, a.err);
+          }
+        }
       }
       nnz += tot;
       __syncthreads();
     }
     if (tid == 0) a.row_nnz[t] = nnz;
   }
+  if (bad) atomicOr(a.err, 1u);
+}
 
-  // ---- light rows: one wave per row, private LDS hash ----
-  uint32_t* hk = (uint32_t*)(lds + w * HS * (4 + 8 + 8 * EXACT_MAXD + 2));
+// Inner-product rows: one block per row.  A's row is marked in an LDS
+// bitmap over j with per-word rank prefixes (the position of j in the row);
+// thread by thread, the k nodes of E transposed are walked in k order, each
+// column's j probed in the bitmap and the matching products summed exactly
+// in registers; non-empty outputs are placed by a block scan.
+__global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
+  __shared__ unsigned long long bm[KW_MAX / 64];
+  __shared__ uint32_t pre[KW_MAX / 64];
+  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_wsum[B_NW];
+  const int tid = threadIdx.x;
+  uint32_t bad = 0;
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(&a.qhead[2], 1u);
+    __syncthreads();
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (item >= a.n_inner) break;
+    const uint32_t t = __builtin_amdgcn_readfirstlane(a.inner[item]);
+    const BInst I = a.inst[a.row_inst[t]];
+    const uint32_t p = t - (uint32_t)a.inst_row0[a.row_inst[t]];
+    const uint32_t qb = I.a_off[p], qe = I.a_off[p + 1];
+    const uint32_t nwords = (I.n_j + 63) / 64;
+    for (uint32_t s = tid; s < nwords; s += B_NT) bm[s] = 0;
+    __syncthreads();
+    for (uint32_t q = qb + tid; q < qe; q += B_NT) {
+      const uint32_t j = I.a_j[q];
+      atomicOr(&bm[j >> 6], 1ull << (j & 63u));
+    }
+    __syncthreads();
+    {
+      uint32_t c = 0;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const uint32_t wi = 4 * tid + i;
+        c += wi < nwords ? (uint32_t)__popcll(bm[wi]) : 0u;
+      }
+      uint32_t tot;
+      uint32_t r = block_excl_scan<uint32_t, B_NT>(c, s_wsum, tot);
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const uint32_t wi = 4 * tid + i;
+        if (wi < nwords) {
+          pre[wi] = r;
+          r += (uint32_t)__popcll(bm[wi]);
+        }
+      }
+    }
+    __syncthreads();
+    const uint64_t out = a.ub_off[t];
+    uint32_t nnz = 0;
+    for (uint32_t kb0 = 0; kb0 < I.bt_n0; kb0 += B_NT) {
+      const uint32_t kn = kb0 + tid;
+      uint64_t cnt = 0;
+      RegAcc acc;
+      acc.clear();
+      if (kn < I.bt_n0) {
+        for (uint32_t e = I.bt_off[kn]; e < I.bt_off[kn + 1]; e++) {
+          const uint32_t j = I.bt_j[e];
+          if (j >= I.n_j) break;                       // j ascending within the column
+          const uint64_t word = bm[j >> 6];
+          if (!((word >> (j & 63u)) & 1ull)) continue;
+          const uint32_t q = qb + pre[j >> 6] + (uint32_t)__popcll(word & ((1ull << (j & 63u)) - 1ull));
+          uint32_t ab, ae, eb, ee;
+          rows_of(I.a_run, q, ab, ae);
+          rows_of(I.bt_run, e, eb, ee);
+          cnt += (uint64_t)(ae - ab) * (ee - eb);
+          if (I.sum)
+            for (uint32_t ra = ab; ra < ae; ra++)
+              for (uint32_t re = eb; re < ee; re++) {
+                double hi, lo;
+                two_prod(I.a_val[ra], I.bt_val[re], hi, lo);
+                bool ok = acc.add(hi, I.lsb, I.D, 1);
+                ok = acc.add(lo, I.lsb, I.D, 1) && ok;
+                if (!ok) bad = 1;
+              }
+        }
+      }
+      uint32_t tot;
+      const uint32_t r = block_excl_scan<uint32_t, B_NT>(cnt ? 1u : 0u, s_wsum, tot);
+      if (cnt) {
+        const uint64_t o = out + nnz + r;
+        a.ub_k[o] = I.bt_k[kn];
+        a.ub_cnt[o] = cnt;
+        if (I.sum) a.ub_sum[o] = exact_round(acc.s, I.D, I.lsb, a.err);
+      }
+      nnz += tot;
+    }
+    if (tid == 0) a.row_nnz[t] = nnz;
+    __syncthreads();
+  }
+  if (bad) atomicOr(a.err, 1u);
+}
+
+// Light rows: one wave per row, private LDS hash of HS slots.
+template <int HS>
+__global__ __launch_bounds__(B_NT) void k_batch_light(BatchArgs a) {
+  constexpr int SLOT_BYTES = 4 + 8 + 8 * EXACT_MAXD + 2;
+  constexpr uint32_t HS_SHIFT = HS == 128 ? 25 : 24;  // top bits of the multiplicative hash
+  static_assert(HS == 128 || HS == 256, "hash size");
+  __shared__ __align__(16) unsigned char lds[B_NW * HS * SLOT_BYTES];
+  const int tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+  uint32_t bad = 0;
+  uint32_t* hk = (uint32_t*)(lds + w * HS * SLOT_BYTES);
   unsigned long long* hc = (unsigned long long*)(hk + HS);
   long long* hd = (long long*)(hc + HS);
   uint16_t* hl = (uint16_t*)(hd + HS * EXACT_MAXD);
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = atomicAdd(&a.qhead[1], 1u);
-    item = __shfl(item, 0, WAVE);
+    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, WAVE));
     if (item >= a.n_light) break;
-    const uint32_t t = a.light[item];
+    const uint32_t t = __builtin_amdgcn_readfirstlane(a.light[item]);
     const BInst I = a.inst[a.row_inst[t]];
     const uint32_t p = t - (uint32_t)a.inst_row0[a.row_inst[t]];
     const uint32_t qb = I.a_off[p], qe = I.a_off[p + 1];
@@ -316,7 +455,7 @@ __global__ __launch_bounds__(B_NT) void k_batch(BatchArgs a) {
       rows_of(I.a_run, q, ab, ae);
       for (uint32_t kp = I.e_off[pe]; kp < I.e_off[pe + 1]; kp++) {
         const uint32_t k = I.e_k[kp];
-        uint32_t slot = (k * 2654435761u) >> 24;  // HS = 256
+        uint32_t slot = (k * 2654435761u) >> HS_SHIFT;
         for (;;) {
           const uint32_t prev = atomicCAS(&hk[slot], EMPTY_KEY, k);
           if (prev == EMPTY_KEY || prev == k) break;
@@ -418,10 +557,21 @@ unsigned grid_for(uint64_t n) {
 // ---- host side ----------------------------------------------------------------
 
 struct Tuning {
-  uint32_t light_max = 128;   // products above which a matrix row is heavy
-  uint32_t win = 1024;        // dense window of the heavy path
+  uint32_t light_max = 128;   // products above which a matrix row is heavy (light hash: 2x slots)
   uint32_t blocks_per_cu = 2; // persistent grid
+  uint32_t inner_ratio = 64;  // heavy row in inner-product form when products * ratio >= nnz(E)
 };
+
+// E transposed (levels k, j) of every matrix instance, built once per batch
+// and shared by the autotuner's candidate setups; keyed by E's trie and
+// annotation column.
+struct Transposes {
+  std::map<std::pair<const lh_trie*, int32_t>, lh_trie*> by_e;
+  ~Transposes() {
+    for (auto& kv : by_e) free_trie(kv.second);
+  }
+};
+constexpr uint32_t MAX_BLOCKS_PER_CU = 4;
 
 // Everything one batch needs; kept across calls with the same plans so the
 // graph is replayed rather than rebuilt.
@@ -432,10 +582,14 @@ struct BatchState {
   hipStream_t s = nullptr;
   DBuf<BInst> inst;
   DBuf<uint64_t> inst_row0, prod, ub_off;
-  DBuf<uint32_t> row_inst, ub, heavy_f, light_f, heavy, light, qhead, row_nnz, ub_k, err;
+  DBuf<uint32_t> row_inst, ub, heavy_f, light_f, inner_f, heavy, light, inner, qhead, row_nnz, ub_k, err;
+  std::shared_ptr<Transposes> tr;
   DBuf<uint64_t> ub_cnt;
   DBuf<double> ub_sum;
-  uint64_t n_heavy = 0, n_light = 0;
+  DBuf<unsigned long long> scratch_cnt;   // heavy rows: per-block k-indexed exact sums
+  DBuf<long long> scratch_dig;
+  uint32_t kw = 64;
+  uint64_t n_heavy = 0, n_light = 0, n_inner = 0;
   std::vector<uint64_t> h_inst_row0;
   std::vector<BInst> h_inst;
   hipGraph_t graph = nullptr;
@@ -483,7 +637,33 @@ BInst describe(const lh_plan_t* p) {
   b.e_val = (b.sum && E.anno >= 0) ? te->annos[E.anno].p : nullptr;
   b.lsb = p->exact_lsb;
   b.D = p->exact_digits;
+  b.n_j = ta->key_max[1] + 1;
   return b;
+}
+
+// E transposed: the same rows keyed (k, j), bag semantics, sorted arrays.
+lh_trie* transpose_e(const lh_trie* te, int32_t anno, hipStream_t s) {
+  const uint32_t* keys[2] = {te->skeys[0].p, te->skeys[1].p};
+  const double* annos[1] = {anno >= 0 ? te->annos[anno].p : nullptr};
+  const uint32_t level_order[2] = {1, 0};
+  return build_trie(te->n_rows, 2, keys, anno >= 0 ? 1u : 0u, annos, 0, nullptr, level_order,
+                    LH_BAG | LH_LAYOUT_UINT, nullptr, 0, s);
+}
+
+void attach_transpose(BInst& b, const lh_plan_t* p, Transposes& tr, hipStream_t s) {
+  const PlanAtom& E = p->atoms[1];
+  const int32_t anno = b.sum ? E.anno : -1;
+  auto key = std::make_pair(E.trie, anno);
+  auto it = tr.by_e.find(key);
+  if (it == tr.by_e.end()) it = tr.by_e.emplace(key, transpose_e(E.trie, anno, s)).first;
+  const lh_trie* t = it->second;
+  b.bt_n0 = (uint32_t)t->lv[0].n;
+  b.bt_k = t->lv[0].keys.p;
+  b.bt_off = t->lv[0].offs.p;
+  b.bt_j = t->lv[1].keys.p;
+  b.bt_run = t->lv[1].offs.p;
+  b.bt_val = anno >= 0 ? t->annos[0].p : nullptr;
+  b.nnz_e = t->lv[1].n;
 }
 
 std::string cache_path() {
@@ -502,8 +682,8 @@ std::string signature(const BatchState& b) {
   uint64_t rows_log = 0, ub_log = 0;
   while ((1ull << rows_log) < b.R) rows_log++;
   while ((1ull << ub_log) < b.UB) ub_log++;
-  os << prop.gcnArchName << "_cu" << prop.multiProcessorCount << "_inst" << b.plans.size() << "_r" << rows_log << "_u"
-     << ub_log;
+  os << "v3_" << prop.gcnArchName << "_cu" << prop.multiProcessorCount << "_inst" << b.plans.size() << "_r" << rows_log
+     << "_u" << ub_log;
   return os.str();
 }
 
@@ -511,7 +691,7 @@ bool load_tuning(const std::string& sig, Tuning& t) {
   std::ifstream f(cache_path());
   std::string key;
   Tuning x;
-  while (f >> key >> x.light_max >> x.win >> x.blocks_per_cu) {
+  while (f >> key >> x.light_max >> x.blocks_per_cu >> x.inner_ratio) {
     if (key == sig) {
       t = x;
       return true;
@@ -525,7 +705,7 @@ void save_tuning(const std::string& sig, const Tuning& t) {
   std::string dir = path.substr(0, path.find_last_of('/'));
   (void)std::system(("mkdir -p '" + dir + "' 2>/dev/null").c_str());
   std::ofstream f(path, std::ios::app);
-  f << sig << " " << t.light_max << " " << t.win << " " << t.blocks_per_cu << "\n";
+  f << sig << " " << t.light_max << " " << t.blocks_per_cu << " " << t.inner_ratio << "\n";
 }
 
 void setup(BatchState& b, hipStream_t s) {
@@ -533,8 +713,10 @@ void setup(BatchState& b, hipStream_t s) {
   b.s = s;
   b.h_inst.resize(n);
   b.h_inst_row0.assign(n + 1, 0);
+  if (!b.tr) b.tr = std::make_shared<Transposes>();
   for (uint32_t i = 0; i < n; i++) {
     b.h_inst[i] = describe(b.plans[i]);
+    if (b.h_inst[i].kind == 1) attach_transpose(b.h_inst[i], b.plans[i], *b.tr, s);
     b.h_inst[i].row_base = b.h_inst_row0[i];
     b.h_inst_row0[i + 1] = b.h_inst_row0[i] + b.h_inst[i].n_rows;
   }
@@ -549,9 +731,10 @@ void setup(BatchState& b, hipStream_t s) {
   b.ub.alloc(b.R, s);
   b.heavy_f.alloc(b.R, s);
   b.light_f.alloc(b.R, s);
+  b.inner_f.alloc(b.R, s);
   if (b.R) {
-    k_row_setup<<<grid_for(b.R), 256, 0, s>>>(b.inst.p, b.inst_row0.p, n, b.R, b.tune.light_max, b.row_inst.p, b.prod.p,
-                                              b.ub.p, b.heavy_f.p, b.light_f.p);
+    k_row_setup<<<grid_for(b.R), 256, 0, s>>>(b.inst.p, b.inst_row0.p, n, b.R, b.tune.light_max, b.tune.inner_ratio,
+                                              b.row_inst.p, b.prod.p, b.ub.p, b.heavy_f.p, b.light_f.p, b.inner_f.p);
     LH_HIP(hipGetLastError());
   }
   b.ub_off.alloc(b.R + 1, s);
@@ -560,6 +743,8 @@ void setup(BatchState& b, hipStream_t s) {
   b.light.alloc(b.R, s);
   b.n_heavy = select_flagged(b.heavy_f.p, b.R, b.heavy.p, s);
   b.n_light = select_flagged(b.light_f.p, b.R, b.light.p, s);
+  b.inner.alloc(b.R, s);
+  b.n_inner = select_flagged(b.inner_f.p, b.R, b.inner.p, s);   // in row order: grouped by instance
   // heavy rows longest first (LPT): sort their ids by descending product count
   if (b.n_heavy > 1) {
     DBuf<uint64_t> key(b.n_heavy, s), tk(b.n_heavy, s);
@@ -572,12 +757,27 @@ void setup(BatchState& b, hipStream_t s) {
     std::stable_sort(hrows.begin(), hrows.end(), [&](uint32_t x, uint32_t y) { return hp[x] > hp[y]; });
     LH_HIP(hipMemcpyAsync(b.heavy.p, hrows.data(), b.n_heavy * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   }
-  b.qhead.alloc(2, s);
+  b.qhead.alloc(3, s);
   b.row_nnz.alloc(b.R, s);
   b.ub_k.alloc(b.UB, s);
   b.ub_cnt.alloc(b.UB, s);
   b.ub_sum.alloc(b.UB, s);
   b.err.alloc(1, s);
+  // heavy rows: one k window of scratch per possible persistent block
+  if (b.n_heavy) {
+    uint32_t nk = 0;
+    for (const BInst& I : b.h_inst)
+      if (I.kind == 1) nk = std::max(nk, I.n_k);
+    b.kw = std::min<uint32_t>(KW_MAX, (nk + 63) / 64 * 64);
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const uint64_t slots = (uint64_t)cus * MAX_BLOCKS_PER_CU * b.kw;
+    b.scratch_cnt.alloc(slots, s);
+    b.scratch_dig.alloc(slots * EXACT_MAXD, s);
+    fill_u64((uint64_t*)b.scratch_cnt.p, 0, slots, s);
+    fill_u64((uint64_t*)b.scratch_dig.p, 0, slots * EXACT_MAXD, s);
+  }
   LH_HIP(hipStreamSynchronize(s));
 }
 
@@ -585,7 +785,7 @@ void launch_compute(BatchState& b, hipStream_t s) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  k_fill_u32_dev<<<1, 64, 0, s>>>(b.qhead.p, 0u, 2);
+  k_fill_u32_dev<<<1, 64, 0, s>>>(b.qhead.p, 0u, 3);
   k_fill_u32_dev<<<1, 64, 0, s>>>(b.err.p, 0u, 1);
   BatchArgs a{};
   a.inst = b.inst.p;
@@ -596,15 +796,22 @@ void launch_compute(BatchState& b, hipStream_t s) {
   a.n_heavy = b.n_heavy;
   a.light = b.light.p;
   a.n_light = b.n_light;
+  a.inner = b.inner.p;
+  a.n_inner = b.n_inner;
   a.qhead = b.qhead.p;
   a.row_nnz = b.row_nnz.p;
   a.ub_k = b.ub_k.p;
   a.ub_cnt = b.ub_cnt.p;
   a.ub_sum = b.ub_sum.p;
   a.err = b.err.p;
-  const unsigned grid = (unsigned)(cus * b.tune.blocks_per_cu);
-  if (b.tune.win == 512) k_batch<512><<<grid, B_NT, 0, s>>>(a);
-  else k_batch<1024><<<grid, B_NT, 0, s>>>(a);
+  a.scratch_cnt = b.scratch_cnt.p;
+  a.scratch_dig = b.scratch_dig.p;
+  a.kw = b.kw;
+  const unsigned grid = (unsigned)(cus * std::min(b.tune.blocks_per_cu, MAX_BLOCKS_PER_CU));
+  if (b.n_inner) k_batch_inner<<<grid, B_NT, 0, s>>>(a);
+  if (b.n_heavy) k_batch_heavy<<<grid, B_NT, 0, s>>>(a);
+  if (b.tune.light_max <= 64) k_batch_light<128><<<grid, B_NT, 0, s>>>(a);
+  else k_batch_light<256><<<grid, B_NT, 0, s>>>(a);
 }
 
 void build_graph(BatchState& b) {
@@ -631,66 +838,77 @@ float time_replay(BatchState& b, hipStream_t s) {
   return ms;
 }
 
-// The project's autotuner: time each candidate's graph twice, keep the
-// fastest, remember it per device and batch signature.
+// The project's autotuner: time each candidate's graph, keep the fastest,
+// remember it per device and batch signature.  The light/heavy split and
+// the inner-product ratio change the setup (row classes and queues); the
+// grid only changes the captured launch, so it is tried on each setup.
+// Only the best setup so far is kept alive (each holds the output bounds).
 void autotune(std::unique_ptr<BatchState>& cur, lh_plan_t* const* plans, uint32_t n, hipStream_t s) {
   const std::string sig = signature(*cur);
   Tuning t;
   if (load_tuning(sig, t)) {
-    if (t.light_max != cur->tune.light_max || t.win != cur->tune.win || t.blocks_per_cu != cur->tune.blocks_per_cu) {
+    if (t.light_max != cur->tune.light_max || t.blocks_per_cu != cur->tune.blocks_per_cu ||
+        t.inner_ratio != cur->tune.inner_ratio) {
       auto nb = std::make_unique<BatchState>();
       nb->plans = cur->plans;
+      nb->tr = cur->tr;
       nb->tune = t;
+      cur.reset();
       setup(*nb, s);
       build_graph(*nb);
       cur = std::move(nb);
     }
     return;
   }
-  // The light/heavy split changes the setup; window and grid only change
-  // the captured launch, so they are tried on one setup each.
   const uint32_t lights[] = {64, 128};
-  const uint32_t wins[] = {512, 1024};
-  const uint32_t bpcs[] = {1, 2};
+  const uint32_t ratios[] = {64, 512, 4096};
+  const uint32_t bpcs[] = {1, 2, 4};
+  const std::vector<const lh_plan_t*> pv(plans, plans + n);
+  std::shared_ptr<Transposes> tr = cur->tr;
   float best = 3.0e38f;
   std::unique_ptr<BatchState> winner;
-  Tuning best_t = cur->tune;
-  for (uint32_t lm : lights) {
-    std::unique_ptr<BatchState> cand;
-    if (lm == cur->tune.light_max) {
-      cand = std::move(cur);
-    } else {
-      cand = std::make_unique<BatchState>();
-      cand->plans = winner ? winner->plans : std::vector<const lh_plan_t*>(plans, plans + n);
-      cand->tune.light_max = lm;
-      setup(*cand, s);
-    }
-    for (uint32_t wn : wins)
+  for (uint32_t lm : lights)
+    for (uint32_t ir : ratios) {
+      std::unique_ptr<BatchState> cand;
+      if (cur && lm == cur->tune.light_max && ir == cur->tune.inner_ratio) {
+        cand = std::move(cur);
+      } else {
+        cand = std::make_unique<BatchState>();
+        cand->plans = pv;
+        cand->tr = tr;
+        cand->tune.light_max = lm;
+        cand->tune.inner_ratio = ir;
+        setup(*cand, s);
+      }
+      float cand_best = 3.0e38f;
+      uint32_t cand_bp = cand->tune.blocks_per_cu;
       for (uint32_t bp : bpcs) {
         if (cand->exec) (void)hipGraphExecDestroy(cand->exec);
         if (cand->graph) (void)hipGraphDestroy(cand->graph);
         cand->exec = nullptr;
         cand->graph = nullptr;
-        cand->tune.win = wn;
         cand->tune.blocks_per_cu = bp;
         build_graph(*cand);
-        float ms = time_replay(*cand, s);
-        if (ms < best) {
-          best = ms;
-          best_t = cand->tune;
+        const float ms = time_replay(*cand, s);
+        if (ms < cand_best) {
+          cand_best = ms;
+          cand_bp = bp;
         }
       }
-    if (!winner || best_t.light_max == lm) winner = std::move(cand);
-  }
-  if (winner->tune.win != best_t.win || winner->tune.blocks_per_cu != best_t.blocks_per_cu) {
-    (void)hipGraphExecDestroy(winner->exec);
-    (void)hipGraphDestroy(winner->graph);
-    winner->exec = nullptr;
-    winner->graph = nullptr;
-    winner->tune = best_t;
-    build_graph(*winner);
-  }
-  save_tuning(sig, best_t);
+      if (cand->tune.blocks_per_cu != cand_bp) {
+        (void)hipGraphExecDestroy(cand->exec);
+        (void)hipGraphDestroy(cand->graph);
+        cand->exec = nullptr;
+        cand->graph = nullptr;
+        cand->tune.blocks_per_cu = cand_bp;
+        build_graph(*cand);
+      }
+      if (cand_best < best) {
+        best = cand_best;
+        winner = std::move(cand);
+      }
+    }
+  save_tuning(sig, winner->tune);
   cur = std::move(winner);
 }
 

@@ -111,48 +111,59 @@ struct RegAcc {
   }
 };
 
-// Round the exact value held in D slots (any carry state) to a double.
-// Sets *overflow if the value does not fit the D-digit window.
+// Round the exact value held in D slots (any carry state) to a double,
+// nearest with ties to even.  Sets *overflow if the value does not fit the
+// D-digit window.  The digits are carried into 32-bit words, the leading
+// word and the two below it give a 96-bit window holding the 53 result
+// bits, the rounding bit and the first sticky bits; words further down
+// only feed the sticky bit.  Every index is resolved with unrolled selects.
 __device__ inline double exact_round(const int64_t* slot, uint32_t D, int32_t lsb, uint32_t* overflow) {
-  // carry-propagate into D+1 unsigned digits (two's complement, top = sign)
-  uint32_t dg[EXACT_MAXD + 1];
+  uint32_t dg[EXACT_MAXD];
   int64_t c = 0;
-  for (uint32_t i = 0; i < D; i++) {
-    int64_t v = slot[i] + c;
-    c = v >> 32;
-    dg[i] = (uint32_t)(v - (c << 32));
-  }
-  // c is the value above the top digit: must be a sign extension
-  if (c != 0 && c != -1) {
-    if (overflow) *overflow = 1;
-  }
-  bool neg = c < 0;
-  if (neg) {  // magnitude of the two's complement value
-    uint64_t carry = 1;
-    for (uint32_t i = 0; i < D; i++) {
-      uint64_t v = (uint64_t)(uint32_t)~dg[i] + carry;
+#pragma unroll
+  for (int i = 0; i < EXACT_MAXD; i++) {
+    dg[i] = 0;
+    if (i < (int)D) {
+      const int64_t v = slot[i] + c;
+      c = v >> 32;
       dg[i] = (uint32_t)v;
-      carry = v >> 32;
     }
   }
-  int top = -1;
-  for (int i = (int)D - 1; i >= 0; i--)
-    if (dg[i]) { top = i * 32 + 31 - __builtin_clz(dg[i]); break; }
-  if (top < 0) return 0.0;
-  // 64-bit window of the top bits, top bit at position 63
-  uint64_t win = 0;
-  bool sticky = false;
-  for (int b = 0; b < 64; b++) {
-    int p = top - b;
-    if (p < 0) break;
-    if ((dg[p >> 5] >> (p & 31)) & 1u) win |= 1ull << (63 - b);
+  // c is the value above the top digit: it must be a sign extension
+  if (c != 0 && c != -1 && overflow) *overflow = 1;
+  const bool neg = c < 0;
+  if (neg) {  // magnitude of the two's complement value
+    uint64_t carry = 1;
+#pragma unroll
+    for (int i = 0; i < EXACT_MAXD; i++)
+      if (i < (int)D) {
+        const uint64_t v = (uint64_t)(uint32_t)~dg[i] + carry;
+        dg[i] = (uint32_t)v;
+        carry = v >> 32;
+      }
   }
-  for (int i = 0; i <= top - 64 && !sticky; i++)
-    if (i < top - 63 && ((dg[i >> 5] >> (i & 31)) & 1u)) sticky = true;
-  uint64_t m = win >> 11;               // 53 bits
-  bool rbit = (win >> 10) & 1ull;
-  sticky = sticky || (win & 0x3ffull) != 0;
-  int e = top - 52 + lsb;
+  int ti = -1;
+#pragma unroll
+  for (int i = 0; i < EXACT_MAXD; i++)
+    if (dg[i]) ti = i;
+  if (ti < 0) return 0.0;
+  uint32_t d2 = 0, d1 = 0, d0 = 0;
+  bool below = false;
+#pragma unroll
+  for (int i = 0; i < EXACT_MAXD; i++) {
+    if (i == ti) d2 = dg[i];
+    if (i == ti - 1) d1 = dg[i];
+    if (i == ti - 2) d0 = dg[i];
+    if (i < ti - 2 && dg[i]) below = true;
+  }
+  const int lz = __builtin_clz(d2);
+  const uint64_t hi = ((uint64_t)d2 << 32) | d1;
+  const uint64_t win = lz ? (hi << lz) | (d0 >> (32 - lz)) : hi;   // leading one at bit 63
+  const uint32_t rest = lz ? d0 << lz : d0;
+  uint64_t m = win >> 11;                                          // 53 bits
+  const bool rbit = (win >> 10) & 1ull;
+  const bool sticky = below || rest != 0 || (win & 0x3ffull) != 0;
+  int e = ti * 32 + 31 - lz - 52 + lsb;
   if (rbit && (sticky || (m & 1ull))) {
     m++;
     if (m == (1ull << 53)) {
@@ -160,7 +171,7 @@ __device__ inline double exact_round(const int64_t* slot, uint32_t D, int32_t ls
       e++;
     }
   }
-  double r = ldexp((double)m, e);
+  const double r = ldexp((double)m, e);
   return neg ? -r : r;
 }
 

@@ -55,7 +55,9 @@ def _probe_time(R, P, n_probes):
     lh.profile_enable(False)
     prof = lh.profile_read()
     p.free()
-    ms = prof["leaf_aggregate"]["total_ms"] / 3
+    # the leaf kernel and its per-unit descriptor pass (whose work also
+    # depends on the probed set's layout)
+    ms = sum(prof[k]["total_ms"] for k in ("leaf_aggregate", "leaf_units") if k in prof) / 3
     return ms * 1e6 / n_probes
 
 
@@ -72,7 +74,6 @@ def calibrate_layouts(seed=7, total=1 << 23, cards=None, densities=None):
             if span > max_span or span < card:
                 continue
             n_sets = max(1, total // card)
-            m = max(8, card // 2)
 
             def stratified(count):
                 # one uniform value in each of `count` equal slices of [0, span):
@@ -83,21 +84,29 @@ def calibrate_layouts(seed=7, total=1 << 23, cards=None, densities=None):
 
             a_r = np.repeat(np.arange(n_sets, dtype=np.uint32), card)
             c_r = stratified(card)
-            a_p = np.repeat(np.arange(n_sets, dtype=np.uint32), m)
-            c_p = stratified(m)
-            P = lh.trie_build([a_p, c_p], layout="uint")
+            Rs = {}
             for choice, layout in ((0, "uint"), (1, "bitset")):
                 R = lh.trie_build([a_r, c_r], layout=layout)
-                inf = R.info()
-                if choice == 1 and inf["level_bitsets"][1] < n_sets:
+                if choice == 1 and R.info()["level_bitsets"][1] < n_sets:
                     R.free()
                     continue                     # the window was too large to store
-                ns = _probe_time(R, P, n_sets * m)
-                R.free()
-                X.append(layout_features(card, span, choice))
+                Rs[choice] = R
+            # a set is probed by driver sets of many sizes: the target is
+            # the mean probe time over drivers of card/2, card/32 and 8 keys
+            t_sum = {c: 0.0 for c in Rs}
+            drivers = sorted({max(8, card // 2), max(8, card // 32), 8})
+            for m in drivers:
+                a_p = np.repeat(np.arange(n_sets, dtype=np.uint32), m)
+                P = lh.trie_build([a_p, stratified(m)], layout="uint")
+                for c, R in Rs.items():
+                    t_sum[c] += _probe_time(R, P, n_sets * m)
+                P.free()
+            for c, R in Rs.items():
+                ns = t_sum[c] / len(drivers)
+                X.append(layout_features(card, span, c))
                 y.append(np.log2(ns))
-                rows.append({"card": card, "span": span, "layout": layout, "ns_per_probe": ns})
-            P.free()
+                rows.append({"card": card, "span": span, "layout": "bitset" if c else "uint", "ns_per_probe": ns})
+                R.free()
         log(f"  layout calibration card={card}: {len(rows)} samples")
     return np.array(X, np.float32), np.array(y, np.float32), rows
 

@@ -100,3 +100,35 @@ def test_fullsize_triangles_sampled(graph):
         want = int(oracle.join_aggregate(q)["counts"][0])
         say("vertex", a0, "wedges", int(wedge[a0]), "triangles", want)
         assert per_a.get(a0, 0) == want
+
+
+def test_fullsize_star_group_by():
+    """The star-schema query at full size (60M fact rows, dimensions of
+    2M / 500k / 100k / 10k rows, filters of 20% / 10% / 1%): GROUP BY a
+    dimension attribute of SUM(price * (1 - discount)), checked against a
+    direct denormalized scan (each fact row looks up its dimension rows by
+    dense id) whose per-group sums are exact (math.fsum rounds once)."""
+    import math
+
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_07859_amd import lh
+    say("generating the star schema (60M fact rows)")
+    s = synth.star_schema(seed=3)
+    q = queries.star(s, u_hi=0.20, m2=0, m3=0)
+    got = lh.run_query(q)
+    k0, k1, k2, k3 = s["fact"]["k"]
+    d = s["dims"]
+    keep = (d[0]["u"][k0] < 0.20) & (d[2]["m"][k2] == 0) & (d[3]["m"][k3] == 0)
+    g = d[1]["g"][k1][keep]
+    ann = s["fact"]["ann"][keep]
+    groups = np.unique(g)
+    say("surviving fact rows", int(keep.sum()), "groups", len(groups))
+    assert got["keys"][:, 0].tolist() == groups.tolist()
+    order = np.argsort(g, kind="stable")
+    bounds = np.searchsorted(g[order], groups, side="left").tolist() + [len(g)]
+    for i, gv in enumerate(groups):
+        sel = ann[order[bounds[i]:bounds[i + 1]]]
+        assert got["counts"][i] == len(sel)
+        assert got["sums"][i] == math.fsum(sel.tolist()), (int(gv), got["sums"][i], math.fsum(sel.tolist()))
