@@ -220,6 +220,8 @@ def bench_learned(args, lh, torch, synth):
 
     def run(layout, policy, order=None):
         torch.cuda.synchronize()
+        lh.profile_reset()
+        lh.profile_enable(True)
         t0 = time.perf_counter()
         t = lh.trie_build([lo_d, hi_d], layout=layout)
         p = lh.plan(3, [(t, [0, 1], -1), (t, [1, 2], -1), (t, [0, 2], -1)], agg="count", attr_order=order,
@@ -228,7 +230,14 @@ def bench_learned(args, lh, torch, synth):
         c = int(r.to_host()["counts"][0])
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) * 1000
+        lh.profile_enable(False)
+        prof = lh.profile_read()
+        build = sum(v["total_ms"] for k, v in prof.items() if k.startswith(("trie_", "sort_", "layout")))
+        join = sum(v["total_ms"] for k, v in prof.items() if k.startswith(("join_", "leaf_")))
         chosen = p.info()["attr_order"]
+        words = sum(t.info()["level_words"])
+        log(f"    {layout:7s} {policy:7s} {str(chosen):9s} {dt:8.1f} ms (build kernels {build:.1f}, join kernels "
+            f"{join:.1f}, bitset words {words})")
         r.free()
         p.free()
         t.free()

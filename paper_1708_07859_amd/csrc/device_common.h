@@ -10,6 +10,16 @@ constexpr int WAVE = 64;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) in turn:
+// block b runs on XCD b % 8.  This renumbers blocks so that each XCD owns
+// one contiguous range of logical block ids (when the grid is a multiple of
+// 8), keeping neighbouring work, which reads neighbouring data, on one L2.
+constexpr uint32_t N_XCD = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t grid) {
+  if (grid % N_XCD) return b;
+  return (b % N_XCD) * (grid / N_XCD) + b / N_XCD;
+}
+
 // Number of set bits of `mask` in lanes below this lane (mbcnt).
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

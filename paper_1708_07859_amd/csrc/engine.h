@@ -54,9 +54,11 @@ struct lh_plan_s {
   uint32_t exact_digits = 0;
   double cost = 0.0;
   uint32_t level_alg[lh::MAXV];
+  std::vector<lh_trie*> reordered;          // re-sorted tries, shared by atoms over the same relation
   ~lh_plan_s() {
     for (auto& a : atoms)
       if (a.owned) delete a.owned;
+    for (lh_trie* t : reordered) delete t;
   }
 };
 

@@ -875,7 +875,7 @@ __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
   if (tid == 0) s_cnt = 0;
   uint32_t* stage = s_stage[w];
   uint64_t run = 0;  // ungrouped: this lane's part of the block's count
-  for (uint64_t vb = blockIdx.x; vb < a.nvblk; vb += gridDim.x) {
+  for (uint64_t vb = xcd_block(blockIdx.x, gridDim.x); vb < a.nvblk; vb += gridDim.x) {
     const uint64_t u = vb * J_NW + w;
     if (u >= a.units) continue;  // wave-uniform; no barrier inside the loop
     const UnitDesc t = a.desc[u];

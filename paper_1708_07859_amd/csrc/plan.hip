@@ -221,6 +221,8 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
 
   // ---- atoms: filtered / re-ordered tries ---------------------------------------
   p->parts.assign(q->n_attrs, {});
+  std::vector<const lh_trie*> reorder_src;
+  std::vector<std::vector<uint32_t>> reorder_cols;
   for (uint32_t e = 0; e < q->n_atoms; e++) {
     const lh_atom& A = q->atoms[e];
     const lh_trie* t = A.trie;
@@ -235,9 +237,21 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
     std::iota(cols.begin(), cols.end(), 0u);
     std::sort(cols.begin(), cols.end(),
               [&](uint32_t a, uint32_t b) { return p->depth_of[A.attr_of_key[a]] < p->depth_of[A.attr_of_key[b]]; });
-    if (!filt[e].empty() || !same_order(t, cols.data())) {
+    if (!filt[e].empty()) {
       pa.owned = filtered_or_reordered(t, cols.data(), filt[e], s);
       pa.trie = pa.owned;
+    } else if (!same_order(t, cols.data())) {
+      // one re-sorted copy per (relation, level order), shared by its atoms
+      lh_trie* shared = nullptr;
+      for (size_t i = 0; i < reorder_src.size() && !shared; i++)
+        if (reorder_src[i] == t && reorder_cols[i] == cols) shared = p->reordered[i];
+      if (!shared) {
+        shared = filtered_or_reordered(t, cols.data(), filt[e], s);
+        p->reordered.push_back(shared);
+        reorder_src.push_back(t);
+        reorder_cols.push_back(cols);
+      }
+      pa.trie = shared;
     } else {
       pa.trie = t;
     }

@@ -187,6 +187,7 @@ void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, hipStream_t s) {
   L.n_bitsets = 0;
   if (L.pool_words) {
     L.pool.alloc(L.pool_words, s);
+    ProfScope ps("layout_fill", s, L.n_sets, L.pool_words);
     k_layout_fill<<<grid_for(L.pool_words), 256, 0, s>>>(sr, L.keys.p, L.n_sets, woff.p, L.bs_base.p, L.pool.p,
                                                         L.pool_words);
     LH_HIP(hipGetLastError());

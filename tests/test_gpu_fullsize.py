@@ -132,3 +132,46 @@ def test_fullsize_star_group_by():
         sel = ann[order[bounds[i]:bounds[i + 1]]]
         assert got["counts"][i] == len(sel)
         assert got["sums"][i] == math.fsum(sel.tolist()), (int(gv), got["sums"][i], math.fsum(sel.tolist()))
+
+
+def test_fullsize_batch(tmp_path, monkeypatch):
+    """The 512 SpMV / SpGEMM instances of the batched benchmark (n
+    log-uniform in [1k, 64k], Zipf(1.1) degrees with mean 16): the batched,
+    graph-captured run gives every instance bit for bit the result of its
+    own single-plan run, on two replays; the smallest instances also match
+    the oracle."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_07859_amd import lh
+    from tests.test_gpu_batch import make_plans, same
+    monkeypatch.setenv("LH_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    insts = synth.batched_instances(count=512)
+    keep, plans, qs = make_plans(lh, insts)
+    say("instances", len(plans), "rows", sum(i["n"] for i in insts))
+    import hashlib
+    digests = []
+    for rnd in range(2):                       # the second round replays the captured graph
+        rs = lh.join_aggregate(plans)
+        say("batched round", rnd, "output rows", sum(r.n_rows for r in rs))
+        for i, (p, r) in enumerate(zip(plans, rs)):
+            got = r.to_host()
+            r.free()
+            d = hashlib.sha256(got["keys"].tobytes() + got["counts"].tobytes() + got["sums"].tobytes()).hexdigest()
+            if rnd == 0:
+                alone = lh.join_aggregate([p])[0]
+                same(got, alone.to_host())
+                alone.free()
+                digests.append(d)
+            else:
+                assert d == digests[i]
+    smallest = np.argsort([i["n"] for i in insts])[:3]
+    for i in smallest:
+        got = lh.join_aggregate([plans[i]])[0]
+        same(got.to_host(), oracle.join_aggregate(qs[i]))
+        got.free()
+    for p in plans:
+        p.free()
+    for ts in keep:
+        for t in ts:
+            t.free()
