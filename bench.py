@@ -10,6 +10,12 @@ lh_trie_build (sort, dedup, levels, layouts) + lh_plan (order, policies)
 value = join-aggregate input tuples per second = 3 * |E'| / step time (the
 three atoms each hold the |E'| deduplicated edges).
 
+The same steps are timed twice on the same graph: under the plain rules of
+section 4 (plain layout, plain order), then under the learned cost model
+(learned layouts and order, committed weights); the learned run is the
+reported value, the plain run and the ratio sit in the config.  Results of
+both must be identical.
+
 Prints one JSON line.
 """
 import argparse
@@ -51,7 +57,8 @@ ALG_BYTES = {
 KERNEL_OF_SCOPE = {"leaf_aggregate": "k_leaf2_count"}
 # HBM bytes per launch of that kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # used only while the kernel's source matches the one the counters saw
-TRAFFIC_SUMMARY = "triangle_rmat22_leaf2_count_traffic.txt"
+TRAFFIC_SUMMARY = {"plain": "triangle_rmat22_leaf2_count_traffic.txt",
+                   "learned": "triangle_rmat22_learned_leaf2_count_traffic.txt"}
 
 
 def cpu_baseline(scale):
@@ -80,7 +87,10 @@ def main():
     ap.add_argument("--samples-log2", type=int, default=26)
     ap.add_argument("--cpu-scale", type=int, default=15)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--layout", default="plain", choices=["plain", "uint", "bitset", "learned"])
+    ap.add_argument("--layout", default="plain", choices=["plain", "uint", "bitset", "learned"],
+                    help="layout of the plain-policy run")
+    ap.add_argument("--policy", default="both", choices=["both", "plain", "learned"],
+                    help="both: time the plain rule, then the learned cost model (reported)")
     ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
@@ -112,13 +122,84 @@ def main():
     log(f"  {len(lo)} oriented samples in {time.perf_counter() - t0:.1f} s")
     lo_d = lh.to_device(lo)
     hi_d = lh.to_device(hi)
+    del lo, hi
     torch.cuda.synchronize()
 
+    runs = {}
+    policies = ["plain", "learned"] if args.policy == "both" else [args.policy]
+    for policy in policies:
+        layout = args.layout if policy == "plain" else "learned"
+        if policy == "learned":
+            from paper_1708_07859_amd import learned as L
+            lm, om, _ = L.load(args.weights or L.DEFAULT_WEIGHTS)
+            L.register(lm, om)
+        runs[policy] = measure_triangle(args, lh, torch, lo_d, hi_d, layout, policy)
+        if policy == "learned":
+            lh.use_model(lh.LH_MODEL_LAYOUT, None)
+            lh.use_model(lh.LH_MODEL_ORDER, None)
+    head_policy = policies[-1]
+    head = runs[head_policy]
+    if len(runs) == 2:
+        assert runs["plain"]["count"] == runs["learned"]["count"], "policies disagree on the count"
+    prof = head["prof"]
+    # roofline of the dominant kernel with a known byte formula
+    dom = max((k for k in prof if k in ALG_BYTES), key=lambda k: prof[k]["total_ms"], default=None)
+    roof = None
+    if dom:
+        e = prof[dom]
+        per_launch_bytes = ALG_BYTES[dom](e["rows"], e["elements"]) / e["launches"]
+        avg_ms = e["total_ms"] / e["launches"]
+        achieved = per_launch_bytes / (avg_ms / 1000) / 1e9
+        kernel = KERNEL_OF_SCOPE.get(dom, dom)
+        traffic = None
+        summary = TRAFFIC_SUMMARY.get(head_policy)
+        if summary and (args.scale, args.samples_log2) == (22, 26) and (head_policy != "plain" or args.layout == "plain"):
+            from paper_1708_07859_amd import profiling
+            traffic = profiling.read_traffic(os.path.join(ROOT, "profiles", summary), kernel)
+        roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
+                "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(per_launch_bytes)}
+    config = {"workload": f"triangle COUNT on R-MAT scale {args.scale}, 2^{args.samples_log2} samples "
+                          f"(a=0.57,b=0.19,c=0.19), oriented low->high, set-mode dedup",
+              "edges": head["edges"], "triangles": head["count"], "step": "trie_build + plan + join_aggregate",
+              "policy": head_policy, "layout": head["layout"], "attr_order": head["order"],
+              "join_kernels_ms_per_step": head["join_ms"]}
+    if len(runs) == 2:
+        pl = runs["plain"]
+        config["plain"] = {"ms_per_step": pl["ms"], "tuples_per_s": pl["value"], "attr_order": pl["order"],
+                           "layout": pl["layout"]}
+        config["learned_over_plain"] = pl["ms"] / head["ms"]
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": config,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log(f"cpu baseline: oracle on R-MAT scale {args.cpu_scale}")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_scale)
+    print(json.dumps(out), flush=True)
+
+
+def measure_triangle(args, lh, torch, lo_d, hi_d, layout, policy):
+    """Warm-up, then `steps` timed steps of trie build + plan + join + count
+    readback under one layout and policy; kernels timed with HIP events."""
     state = {}
 
     def step():
-        t = lh.trie_build([lo_d, hi_d], layout=args.layout)
-        p = lh.plan(3, [(t, [0, 1], -1), (t, [1, 2], -1), (t, [0, 2], -1)], agg="count")
+        t = lh.trie_build([lo_d, hi_d], layout=layout)
+        p = lh.plan(3, [(t, [0, 1], -1), (t, [1, 2], -1), (t, [0, 2], -1)], agg="count", policy=policy)
         r = lh.join_aggregate([p])[0]
         res = r.to_host()
         if "edges" not in state:
@@ -131,7 +212,7 @@ def main():
 
     for i in range(args.warmup):
         step()
-        log(f"warmup {i}: triangles={state['count']} edges={state['edges']}")
+        log(f"[{policy}] warmup {i}: triangles={state['count']} edges={state['edges']} order={state['order']}")
     torch.cuda.synchronize()
     lh.profile_reset()
     lh.profile_enable(True)
@@ -144,54 +225,13 @@ def main():
     lh.profile_enable(False)
     prof = lh.profile_read()
     ms = dt * 1000 / args.steps
-    tuples = 3 * state["edges"]
-    value = tuples / (ms / 1000)
-    log(f"{args.steps} steps: {ms:.2f} ms/step, triangles={state['count']}")
+    log(f"[{policy}] {args.steps} steps: {ms:.2f} ms/step, triangles={state['count']}")
     for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
         log(f"  {k:22s} launches={v['launches']:6d} total={v['total_ms']:9.3f} ms "
             f"rows={v['rows']} elems={v['elements']}")
-    # roofline of the dominant kernel with a known byte formula
-    dom = max((k for k in prof if k in ALG_BYTES), key=lambda k: prof[k]["total_ms"], default=None)
-    roof = None
-    if dom:
-        e = prof[dom]
-        per_launch_bytes = ALG_BYTES[dom](e["rows"], e["elements"]) / e["launches"]
-        avg_ms = e["total_ms"] / e["launches"]
-        achieved = per_launch_bytes / (avg_ms / 1000) / 1e9
-        kernel = KERNEL_OF_SCOPE.get(dom, dom)
-        traffic = None
-        if (args.scale, args.samples_log2, args.layout) == (22, 26, "plain"):
-            from paper_1708_07859_amd import profiling
-            traffic = profiling.read_traffic(os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY), kernel)
-        roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else int(traffic),
-                "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(per_launch_bytes)}
     join_ms = sum(prof[k]["total_ms"] for k in prof if k.startswith(("join_", "leaf_"))) / args.steps
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "tuples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": f"triangle COUNT on R-MAT scale {args.scale}, 2^{args.samples_log2} samples "
-                               f"(a=0.57,b=0.19,c=0.19), oriented low->high, set-mode dedup",
-                   "edges": state["edges"], "triangles": state["count"], "attr_order": state["order"],
-                   "step": "trie_build + plan + join_aggregate", "layout": args.layout,
-                   "join_kernels_ms_per_step": round(join_ms, 3)},
-        "roofline": roof,
-    }
-    if not args.no_cpu:
-        log(f"cpu baseline: oracle on R-MAT scale {args.cpu_scale}")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_scale)
-    print(json.dumps(out), flush=True)
+    return {"ms": ms, "value": 3 * state["edges"] / (ms / 1000), "prof": prof, "edges": state["edges"],
+            "count": state["count"], "order": state["order"], "layout": layout, "join_ms": round(join_ms, 3)}
 
 
 def bench_learned(args, lh, torch, synth):
