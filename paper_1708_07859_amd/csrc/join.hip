@@ -789,10 +789,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Probe path of a unit: the unit's driver keys against the probed set's
 // bitset, its LDS-staged keys, or its line samples.
-__device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDesc& t, uint64_t u, uint32_t* stage,
+__device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDesc& t, uint32_t next_lo, uint32_t* stage,
                                                int lane) {
   uint32_t c = 0;
-  const uint32_t next_lo = (u + 1 < a.units) ? a.desc[u + 1].plo : 0u;
   const uint32_t* dk = t.drv ? a.keys[1] : a.keys[0];
   const uint32_t* pk = t.drv ? a.keys[0] : a.keys[1];
   const uint64_t* pool = t.drv ? a.pool[0] : a.pool[1];
@@ -868,17 +867,52 @@ __device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDes
   return c;
 }
 
+typedef const UnitDesc __attribute__((address_space(4)))* CDesc;
+
+__device__ __forceinline__ UnitDesc load_desc(CDesc d, uint64_t u) {
+  UnitDesc t;
+  t.dstart = d[u].dstart;
+  t.dcount = d[u].dcount;
+  t.plo = d[u].plo;
+  t.phi = d[u].phi;
+  t.pword = d[u].pword;
+  t.drv = d[u].drv;
+  t.pad = 0;
+  return t;
+}
+
 __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
   __shared__ uint32_t s_stage[J_NW][L2_CAP];
   __shared__ unsigned long long s_cnt;
-  const int tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+  // w is uniform across the wave: unit indices and descriptors then live in
+  // scalar registers and descriptors come through the scalar cache, whose
+  // loads are counted apart from the vector loads of the keys
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid / WAVE), lane = lane_id();
   if (tid == 0) s_cnt = 0;
   uint32_t* stage = s_stage[w];
   uint64_t run = 0;  // ungrouped: this lane's part of the block's count
-  for (uint64_t vb = xcd_block(blockIdx.x, gridDim.x); vb < a.nvblk; vb += gridDim.x) {
+  // The next unit's descriptor is loaded while the current unit is worked
+  // on, so its latency overlaps the current unit's key loads.
+  // descriptors are read-only here: read through the constant address space
+  const CDesc desc = (CDesc)a.desc;
+  UnitDesc nt{};
+  uint32_t nlo = 0;
+  const uint64_t vb0 = xcd_block(blockIdx.x, gridDim.x);
+  if (vb0 < a.nvblk && vb0 * J_NW + w < a.units) {
+    const uint64_t u0 = vb0 * J_NW + w;
+    nt = load_desc(desc, u0);
+    nlo = (u0 + 1 < a.units) ? desc[u0 + 1].plo : 0u;
+  }
+  for (uint64_t vb = vb0; vb < a.nvblk; vb += gridDim.x) {
     const uint64_t u = vb * J_NW + w;
+    const UnitDesc t = nt;
+    const uint32_t next_lo = nlo;
+    const uint64_t un = (vb + gridDim.x) * J_NW + w;
+    if (vb + gridDim.x < a.nvblk && un < a.units) {
+      nt = load_desc(desc, un);
+      nlo = (un + 1 < a.units) ? desc[un + 1].plo : 0u;
+    }
     if (u >= a.units) continue;  // wave-uniform; no barrier inside the loop
-    const UnitDesc t = a.desc[u];
     uint32_t c = 0;
     if (t.drv == DRV_AND) {
       const uint64_t w0 = (uint64_t)t.plo | ((uint64_t)t.phi << 32);
@@ -888,7 +922,7 @@ __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
         if (i < t.dcount) c += (uint32_t)__popcll(a.pool[0][w0 + i] & a.pool[1][t.pword + i]);
       }
     } else {
-      c = probe_unit(a, t, u, stage, lane);
+      c = probe_unit(a, t, next_lo, stage, lane);
     }
     if (a.ucnt) {
       // grouped: one count per unit; groups are summed by a scan afterwards
