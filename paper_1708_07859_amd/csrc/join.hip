@@ -52,6 +52,37 @@ __device__ __forceinline__ void dset_range(const DSet& st, uint64_t row, uint32_
   }
 }
 
+// Position of x in the sorted keys [b, e) (b < e) through the level's line
+// samples: bisect the samples of the lines that start inside the range
+// (a 32x smaller, cache-resident array), then the one line that can hold x.
+__device__ __forceinline__ bool sampled_find(const uint32_t* keys, const uint32_t* samp, uint32_t b, uint32_t e,
+                                             uint32_t x, uint32_t& pos) {
+  const uint32_t jf = (b + (1u << LINE_SHIFT) - 1) >> LINE_SHIFT;
+  const uint32_t jl = (e - 1) >> LINE_SHIFT;
+  uint32_t k = 0;
+  if (jl >= jf) {
+    const uint32_t* sp = samp + jf;
+    uint32_t n = jl - jf + 1;
+    while (n > 1) {
+      const uint32_t half = n >> 1;
+      k = (sp[k + half - 1] <= x) ? k + half : k;
+      n -= half;
+    }
+    k += (sp[k] <= x) ? 1u : 0u;
+  }
+  uint32_t lo = k ? (jf + k - 1) << LINE_SHIFT : b;
+  const uint32_t hi = (uint32_t)min<uint64_t>(e, (uint64_t)(jf + k) << LINE_SHIFT);
+  if (hi <= lo) return false;
+  uint32_t len = hi - lo;
+  while (len > 1) {
+    const uint32_t half = len >> 1;
+    lo = (keys[lo + half] <= x) ? lo + half : lo;
+    len -= half;
+  }
+  pos = lo;
+  return keys[lo] == x;
+}
+
 // Membership of x in set [b, e) (descriptor sidx); its position if asked.
 __device__ __forceinline__ bool dset_find(const DSet& st, uint32_t b, uint32_t e, uint64_t sidx, uint32_t x,
                                           bool need_pos, uint32_t& pos) {
@@ -63,15 +94,10 @@ __device__ __forceinline__ bool dset_find(const DSet& st, uint32_t b, uint32_t e
     uint32_t d = x - base;
     uint64_t word = st.pool[w + (d >> 6)];
     if (!((word >> (d & 63u)) & 1ull)) return false;
-    if (need_pos) pos = lower_bound_u32(st.keys, b, e, x);
+    if (need_pos) (void)sampled_find(st.keys, st.samp, b, e, x, pos);
     return true;
   }
-  uint32_t j = lower_bound_u32(st.keys, b, e, x);
-  if (j < e && st.keys[j] == x) {
-    pos = j;
-    return true;
-  }
-  return false;
+  return sampled_find(st.keys, st.samp, b, e, x, pos);
 }
 
 struct LeafAtom {

@@ -97,13 +97,22 @@ TO scan_impl(const TI* in, TO* out, uint64_t n, hipStream_t s) {
   return read_scalar(out + n, s);
 }
 
-__global__ void k_reduce_max_u32(const uint32_t* in, uint64_t n, uint32_t* out) {
+// Maximum of a column: a block reduction, then one atomic per block (the
+// grid is capped, so the atomics on the single result stay few).
+__global__ __launch_bounds__(256) void k_reduce_max_u32(const uint32_t* in, uint64_t n, uint32_t* out) {
+  __shared__ uint32_t s_m[256 / WAVE];
   uint32_t m = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     m = max(m, in[i]);
 #pragma unroll
   for (int d = WAVE / 2; d > 0; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, WAVE));
-  if (lane_id() == 0) atomicMax(out, m);
+  if (lane_id() == 0) s_m[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t b = 0;
+    for (int w = 0; w < 256 / WAVE; w++) b = max(b, s_m[w]);
+    atomicMax(out, b);
+  }
 }
 
 __global__ void k_iota(uint32_t* out, uint64_t n) {
@@ -159,46 +168,68 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, uint64_
   hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Stable scatter of one tile: elements are ranked by digit (ballots inside
+// a wave, LDS counts across waves), placed in LDS in digit order, then
+// written out in that order, so each digit's run of the tile goes to
+// consecutive global slots (coalesced writes).
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                                                       uint32_t* vout, uint64_t n, uint32_t shift,
-                                                      const uint32_t* offs, uint32_t ntiles) {
-  __shared__ uint32_t run[256];
+                                                      const uint32_t* offs, const uint32_t* hist, uint32_t ntiles) {
+  __shared__ uint64_t sk[RS_TILE];
+  __shared__ uint32_t sv[RS_TILE];
+  __shared__ uint32_t lstart[256];   // first slot of each digit in the tile
+  __shared__ uint32_t run[256];      // next slot of each digit in the tile
   __shared__ uint32_t wcnt[RS_NW][256];
+  __shared__ uint32_t s_red[RS_NW];
   const int tid = threadIdx.x, w = tid / WAVE;
-  run[tid] = offs[(uint64_t)tid * ntiles + blockIdx.x];
-  uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+  const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+  const uint32_t ntile = (uint32_t)min<uint64_t>(RS_TILE, n - base);
+  {
+    const uint32_t c = hist[(uint64_t)tid * ntiles + blockIdx.x];
+    uint32_t tot;
+    const uint32_t st = block_excl_scan<uint32_t, RS_NT>(c, s_red, tot);
+    lstart[tid] = st;
+    run[tid] = st;
+  }
   for (int i = 0; i < RS_ITEMS; i++) {
 #pragma unroll
     for (int j = 0; j < RS_NW; j++) wcnt[j][tid] = 0;
     __syncthreads();
-    uint64_t idx = base + (uint64_t)i * RS_NT + tid;
-    bool valid = idx < n;
-    uint64_t k = valid ? kin[idx] : 0;
-    uint32_t v = valid ? vin[idx] : 0;
-    uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t li = (uint32_t)i * RS_NT + tid;
+    const bool valid = li < ntile;
+    const uint64_t k = valid ? kin[base + li] : 0;
+    const uint32_t v = valid ? vin[base + li] : 0;
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
     uint64_t peers = ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; b++) {
-      bool bit = (d >> b) & 1u;
-      uint64_t m = ballot(valid && bit);
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = ballot(valid && bit);
       peers &= bit ? m : ~m;
     }
-    uint32_t rank = lanes_below(peers);
+    const uint32_t rank = lanes_below(peers);
     if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
       uint32_t pre = 0;
       for (int j = 0; j < w; j++) pre += wcnt[j][d];
-      uint32_t pos = run[d] + pre + rank;
-      kout[pos] = k;
-      vout[pos] = v;
+      const uint32_t lp = run[d] + pre + rank;
+      sk[lp] = k;
+      sv[lp] = v;
     }
     __syncthreads();
     uint32_t add = 0;
 #pragma unroll
     for (int j = 0; j < RS_NW; j++) add += wcnt[j][tid];
     run[tid] += add;
-    __syncthreads();
+  }
+  __syncthreads();
+  for (uint32_t t = tid; t < ntile; t += RS_NT) {
+    const uint64_t k = sk[t];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t pos = offs[(uint64_t)d * ntiles + blockIdx.x] + (t - lstart[d]);
+    kout[pos] = k;
+    vout[pos] = sv[t];
   }
 }
 
@@ -267,7 +298,7 @@ uint32_t reduce_max_u32(const uint32_t* in, uint64_t n, hipStream_t s) {
   DBuf<uint32_t> r(1, s);
   LH_HIP(hipMemsetAsync(r.p, 0, sizeof(uint32_t), s));
   if (n) {
-    k_reduce_max_u32<<<grid_for(n), 256, 0, s>>>(in, n, r.p);
+    k_reduce_max_u32<<<std::min(grid_for(n), 1024u), 256, 0, s>>>(in, n, r.p);
     LH_HIP(hipGetLastError());
   }
   return read_scalar(r.p, s);
@@ -386,7 +417,7 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t*
     scan_u32(hist.p, offs.p, hn, s);
     {
       ProfScope ps("sort_scatter", s, n, 0);
-      k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, offs.p, ntiles);
+      k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, offs.p, hist.p, ntiles);
     }
     LH_HIP(hipGetLastError());
     std::swap(ki, ko);

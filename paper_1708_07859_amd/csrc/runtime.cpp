@@ -2,7 +2,10 @@
 #include <atomic>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <sstream>
+#include <unordered_map>
 
 #include "lh_internal.h"
 
@@ -45,19 +48,74 @@ void configure_pool() {
 }
 }  // namespace
 
+// Freed blocks are kept and handed out again (a stream-ordered free and a
+// fresh allocation each cost host time, milliseconds for large blocks).
+// A cached block is reused only on the stream that freed it, so work still
+// queued on that stream is ordered before the block's next use; every call
+// of the library synchronizes its stream before it returns.  Sizes are
+// rounded to 512 B below 1 MiB and to 2 MiB above; a block serves requests
+// down to 4/5 of its size.  On an allocation failure the cache is released
+// and the allocation retried.
+namespace {
+struct CachedBlock {
+  void* p;
+  hipStream_t s;
+};
+std::mutex g_cache_mu;
+std::multimap<size_t, CachedBlock> g_free;      // cached blocks by capacity
+std::unordered_map<void*, size_t> g_cap;        // capacity of every block held (live or cached)
+
+size_t round_size(size_t b) {
+  if (b <= (size_t(1) << 20)) return (b + 511) & ~size_t(511);
+  const size_t g = size_t(2) << 20;
+  return (b + g - 1) & ~(g - 1);
+}
+
+void release_cache(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& kv : g_free) {
+    (void)hipFreeAsync(kv.second.p, s);
+    g_cap.erase(kv.second.p);
+  }
+  g_free.clear();
+}
+}  // namespace
+
 void* dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) return nullptr;
   configure_pool();
   long fa = fail_after();
   long k = g_allocs.fetch_add(1);
   if (fa >= 0 && k >= fa) fail(LH_ERR_OOM, "injected allocation failure (LH_FAULT_ALLOC_AFTER)");
+  const size_t want = round_size(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto it = g_free.lower_bound(want); it != g_free.end() && it->first <= want + want / 4; ++it) {
+      if (it->second.s != s) continue;
+      void* p = it->second.p;
+      g_free.erase(it);
+      g_live.fetch_add(1);
+      return p;
+    }
+  }
   void* p = nullptr;
-  hipError_t e = hipMallocAsync(&p, bytes, s);
+  hipError_t e = hipMallocAsync(&p, want, s);
+  if (e == hipErrorOutOfMemory || (e == hipSuccess && !p)) {
+    (void)hipGetLastError();
+    release_cache(s);
+    LH_HIP(hipStreamSynchronize(s));
+    p = nullptr;
+    e = hipMallocAsync(&p, want, s);
+  }
   if (e != hipSuccess || !p) {
     (void)hipGetLastError();
     std::ostringstream os;
     os << "device allocation of " << bytes << " bytes failed: " << hipGetErrorString(e);
     fail(e == hipErrorOutOfMemory ? LH_ERR_OOM : LH_ERR_DEVICE, os.str());
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cap[p] = want;
   }
   g_live.fetch_add(1);
   return p;
@@ -65,7 +123,13 @@ void* dalloc(size_t bytes, hipStream_t s) {
 
 void dfree(void* p, hipStream_t s) {
   if (!p) return;
-  (void)hipFreeAsync(p, s);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cap.find(p);
+  if (it == g_cap.end()) {
+    (void)hipFreeAsync(p, s);
+  } else {
+    g_free.emplace(it->second, CachedBlock{p, s});
+  }
   g_live.fetch_sub(1);
 }
 

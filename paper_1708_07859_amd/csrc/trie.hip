@@ -194,9 +194,52 @@ void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, hipStream_t s) {
   }
 }
 
+namespace {
+
+struct LevelOffs {
+  const uint32_t* offs[LH_MAX_KEYS];  // child offsets of levels 0 .. n_levels-2
+  const uint32_t* run;                // bag: run offsets of the last level
+  uint32_t n_levels;
+};
+
+// Rows under each level-0 node: its child range composed down to the last
+// level (and through the runs of a bag trie).
+__global__ void k_level0_rows(LevelOffs lo, uint64_t n0, uint32_t* rows) {
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n0; p += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t b = (uint32_t)p, e = (uint32_t)p + 1;
+    for (uint32_t l = 0; l + 1 < lo.n_levels; l++) {
+      b = lo.offs[l][b];
+      e = lo.offs[l][e];
+    }
+    if (lo.run) {
+      b = lo.run[b];
+      e = lo.run[e];
+    }
+    rows[p] = e - b;
+  }
+}
+
+}  // namespace
+
 void ensure_column_stats(lh_trie* t, hipStream_t s) {
   if (t->col_stats) return;
-  for (uint32_t l = 0; l < t->n_levels; l++) {
+  // the first column: its values are the level-0 keys, each shared by the
+  // rows under its node
+  if (t->n_levels && t->lv[0].n) {
+    LevelOffs lo{};
+    lo.n_levels = t->n_levels;
+    for (uint32_t l = 0; l + 1 < t->n_levels; l++) lo.offs[l] = t->lv[l].offs.p;
+    lo.run = (t->flags & LH_BAG) ? t->lv[t->n_levels - 1].offs.p : nullptr;
+    DBuf<uint32_t> rows(t->lv[0].n, s);
+    k_level0_rows<<<grid_for(t->lv[0].n), 256, 0, s>>>(lo, t->lv[0].n, rows.p);
+    LH_HIP(hipGetLastError());
+    t->col_distinct[0] = t->lv[0].n;
+    t->col_freq_max[0] = reduce_max_u32(rows.p, t->lv[0].n, s);
+  } else if (t->n_levels) {
+    t->col_distinct[0] = 0;
+    t->col_freq_max[0] = 0;
+  }
+  for (uint32_t l = 1; l < t->n_levels; l++) {
     if (t->key_max[l] < (1u << 28)) {
       column_freq(t->skeys[l].p, t->n_rows, t->key_max[l], t->col_distinct[l], t->col_freq_max[l], s);
     } else {
@@ -314,17 +357,23 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
   }
 
   // Rows in trie order: bag keeps every sorted row, set keeps leaf heads.
+  // Their keys are the sorted columns themselves (bag), or the sorted
+  // columns at the leaf heads, an increasing, nearly sequential gather (set).
   t->n_rows = bag ? n : n_leaf;
   const uint32_t* rowsel = perm.p;  // sorted position -> input row
   DBuf<uint32_t> keptrows;
-  if (!bag) {
+  if (!bag && (n_annos || n_meta)) {  // (a set relation carries neither; kept for safety)
     keptrows.alloc(n_leaf, s);
     gather_u32(perm.p, kept.p, keptrows.p, n_leaf, s);
     rowsel = keptrows.p;
   }
   for (uint32_t l = 0; l < n_keys; l++) {
-    t->skeys[l].alloc(t->n_rows, s);
-    gather_u32(col[l], rowsel, t->skeys[l].p, t->n_rows, s);
+    if (bag) {
+      t->skeys[l] = std::move(sorted[l]);
+    } else {
+      t->skeys[l].alloc(t->n_rows, s);
+      gather_u32(lc.k[l], kept.p, t->skeys[l].p, t->n_rows, s);
+    }
   }
   // annotation / meta columns (bag relations only); `sel` maps rows first
   DBuf<uint32_t> srcrow;

@@ -277,3 +277,24 @@ def test_set_pair_intersections(lh, la, lb):
     sizes = np.array([len(np.intersect1d(a, b)) for a, b in pairs])
     nz = np.nonzero(sizes)[0]
     assert np.array_equal(got["keys"][:, 0], nz) and np.array_equal(got["counts"], sizes[nz])
+
+
+@pytest.mark.parametrize("bag,nk", [(False, 2), (True, 2), (False, 3), (True, 3)])
+def test_column_stats(lh, bag, nk):
+    """Per-column statistics behind the learned order features: distinct
+    values and the largest number of the trie's rows sharing one value,
+    against numpy on the rows the trie keeps (all rows for a bag, distinct
+    key tuples for a set)."""
+    rng = synth.rng_for(60 + nk + 10 * bag)
+    n = 50_000
+    cols = [rng.integers(0, d, n).astype(np.uint32) for d in (300, 2000, 70)[:nk]]
+    t = lh.trie_build(cols, bag=bag)
+    inf = t.info()
+    t.free()
+    rows = np.stack(cols, 1)
+    if not bag:
+        rows = np.unique(rows, axis=0)
+    for l in range(nk):
+        vals, cnt = np.unique(rows[:, l], return_counts=True)
+        assert inf["col_distinct"][l] == len(vals)
+        assert inf["col_freq_max"][l] == cnt.max()
