@@ -9,10 +9,11 @@
 // section 5).  Every row i of every instance is a work item:
 //  * light rows (few products) are taken by one wave, which sums exactly
 //    into a private LDS hash keyed by k;
-//  * heavy rows are taken by a whole block in one pass over their products:
-//    each product marks its k in an LDS bitmap and adds its exact digits at
-//    k in the block's own global scratch; the row is then emitted in k order
-//    at each k's bitmap rank, clearing the scratch as it is read;
+//  * heavy rows are taken by a whole block: a symbolic pass marks the k the
+//    row produces in an LDS bitmap, whose popcount prefixes rank them; the
+//    products are then summed exactly in LDS accumulators indexed by rank,
+//    512 ranks at a time, each window's products cut out of the B rows by
+//    binary search, and emitted in k order;
 //  * rows with many products relative to the size of E are taken by a
 //    block in inner-product form: A's row becomes an LDS bitmap over j and
 //    one thread per output k walks column k of E (a transposed copy of E
@@ -57,6 +58,7 @@ struct BInst {
   const double* a_val;       // A annotation in trie order (null for COUNT)
   const uint32_t* e_j;       // E level 0 keys
   uint32_t e_n0;
+  uint32_t e_dense;          // E's first-level keys are exactly 0 .. e_n0 - 1
   uint64_t e_bsw;            // E root set bitset word (UINT64_MAX: uint layout)
   uint32_t e_bsb;
   const uint64_t* e_pool;
@@ -81,6 +83,10 @@ struct BInst {
 };
 
 __device__ __forceinline__ bool find_j(const BInst& I, uint32_t j, uint32_t& pos) {
+  if (I.e_dense) {  // E's first level holds every key 0 .. e_n0 - 1: j is its own position
+    pos = j;
+    return j < I.e_n0;
+  }
   if (I.e_n0 == 0) return false;
   if (I.e_bsw != UINT64_MAX) {
     if (j < I.e_bsb || j > I.e_j[I.e_n0 - 1]) return false;
@@ -163,8 +169,6 @@ struct BatchArgs {
   uint64_t* ub_cnt;
   double* ub_sum;
   uint32_t* err;
-  unsigned long long* scratch_cnt;  // per block: kw counts, all zero between rows
-  long long* scratch_dig;           // per block: kw x EXACT_MAXD digit slots, zero between rows
   uint32_t kw;                      // k values per heavy window (multiple of 64, <= KW_MAX)
 };
 
@@ -190,16 +194,45 @@ __device__ __forceinline__ bool lds_add_term(long long* slots, double v, int32_t
   return ok;
 }
 
-// Heavy rows: one block per row, one pass over its products.
+// Heavy rows: one block per row.  A symbolic pass marks every k the row
+// produces in an LDS bitmap (per window of kw values of k); per-word
+// popcount prefixes give each k its rank, which is also its place in the
+// row's sorted output.  The ranks are then taken HC at a time: the k range
+// of the rank window is found from the bitmap, every B row is cut to that
+// range by two binary searches, and the products in it add their exact
+// digits to LDS accumulators indexed by rank - r0, which are emitted in
+// order and cleared.  No global atomics.
+constexpr uint32_t HC = 512;
+
+__device__ __forceinline__ uint32_t rank_select(const unsigned long long* bm, const uint32_t* pre, uint32_t nwords,
+                                                uint32_t r) {
+  // the k whose rank is r: the word holding the r-th set bit, then the bit
+  uint32_t w = 0, n = nwords;
+  while (n > 1) {
+    const uint32_t half = n >> 1;
+    w = (pre[w + half] <= r) ? w + half : w;
+    n -= half;
+  }
+  uint64_t word = bm[w];
+  for (uint32_t i = pre[w]; i < r; i++) word &= word - 1;
+  return w * 64 + (uint32_t)__builtin_ctzll(word);
+}
+
 __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
-  __shared__ unsigned long long bm[KW_MAX / 64];   // touched k of the window
-  __shared__ uint32_t s_item;
+  __shared__ unsigned long long bm[KW_MAX / 64];   // k the row touches in the window
+  __shared__ uint32_t pre[KW_MAX / 64];            // set bits before each word
+  __shared__ uint32_t sk[HC];
+  __shared__ unsigned long long scnt[HC];
+  __shared__ long long sdig[HC * EXACT_MAXD];
+  __shared__ uint32_t s_item, s_klo, s_khi;
   __shared__ uint32_t s_wsum[B_NW];
   const int tid = threadIdx.x;
   uint32_t bad = 0;
-
-  unsigned long long* scnt = a.scratch_cnt + (uint64_t)blockIdx.x * a.kw;
-  long long* sdig = a.scratch_dig + (uint64_t)blockIdx.x * a.kw * EXACT_MAXD;
+  for (uint32_t sl = tid; sl < HC; sl += B_NT) {
+    scnt[sl] = 0;
+#pragma unroll
+    for (int d = 0; d < EXACT_MAXD; d++) sdig[sl * EXACT_MAXD + d] = 0;
+  }
   for (;;) {
     if (tid == 0) s_item = atomicAdd(&a.qhead[0], 1u);
     __syncthreads();
@@ -216,13 +249,11 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
     for (uint32_t w0 = 0; w0 < I.n_k; w0 += a.kw) {
       const uint32_t wend = min(w0 + a.kw, I.n_k);
       const uint32_t nwords = (wend - w0 + 63) / 64;
-      for (uint32_t s = tid; s < nwords; s += B_NT) bm[s] = 0;
+      for (uint32_t sl = tid; sl < nwords; sl += B_NT) bm[sl] = 0;
       __syncthreads();
       for (uint32_t q = qb + tid; q < qe; q += B_NT) {
         uint32_t pe;
         if (!find_j(I, I.a_j[q], pe)) continue;
-        uint32_t ab, ae;
-        rows_of(I.a_run, q, ab, ae);
         uint32_t kb = I.e_off[pe], kend = I.e_off[pe + 1];
         if (I.n_k > a.kw) {
           kb = lower_bound_u32(I.e_k, kb, kend, w0);
@@ -231,54 +262,78 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
         for (uint32_t kp = kb; kp < kend; kp++) {
           const uint32_t k = I.e_k[kp] - w0;
           atomicOr(&bm[k >> 6], 1ull << (k & 63u));
-          uint32_t eb, ee;
-          rows_of(I.e_run, kp, eb, ee);
-          atomicAdd(&scnt[k], (unsigned long long)(ae - ab) * (ee - eb));
-          if (I.sum)
-            for (uint32_t ra = ab; ra < ae; ra++)
-              for (uint32_t re = eb; re < ee; re++) {
-                double hi, lo;
-                two_prod(I.a_val[ra], I.e_val[re], hi, lo);
-                bool ok = lds_add_term(sdig + (uint64_t)k * EXACT_MAXD, hi, I.lsb, I.D, 1);
-                ok = lds_add_term(sdig + (uint64_t)k * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
-                if (!ok) bad = 1;
-              }
         }
       }
-      __threadfence();
       __syncthreads();
-      // emit in k order: thread tid owns bitmap words 4 tid .. 4 tid + 3
-      uint64_t wv[4];
-      uint32_t c = 0;
+      uint32_t m;
+      {
+        uint32_t c = 0;
 #pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const uint32_t wi = 4 * tid + i;
-        wv[i] = wi < nwords ? bm[wi] : 0ull;
-        c += (uint32_t)__popcll(wv[i]);
-      }
-      uint32_t tot;
-      uint32_t r = block_excl_scan<uint32_t, B_NT>(c, s_wsum, tot);
+        for (int i = 0; i < 4; i++) {
+          const uint32_t wi = 4 * tid + i;
+          c += wi < nwords ? (uint32_t)__popcll(bm[wi]) : 0u;
+        }
+        uint32_t r = block_excl_scan<uint32_t, B_NT>(c, s_wsum, m);
 #pragma unroll
-      for (int i = 0; i < 4; i++) {
-        uint64_t word = wv[i];
-        while (word) {
-          const uint32_t k = (4 * tid + i) * 64 + (uint32_t)__builtin_ctzll(word);
-          word &= word - 1;
-          const uint64_t o = out + nnz + r++;
-          a.ub_k[o] = w0 + k;
-          a.ub_cnt[o] = atomicExch(&scnt[k], 0ull);
-          if (I.sum) {
-            int64_t dg[EXACT_MAXD];
-#pragma unroll
-            for (int d = 0; d < EXACT_MAXD; d++)
-              dg[d] = d < (int)I.D ? (int64_t)atomicExch((unsigned long long*)&sdig[(uint64_t)k * EXACT_MAXD + d], 0ull)
-                                   : 0;
-            a.ub_sum[o] = exact_round(dg, I.D, I.lsb, a.err);
+        for (int i = 0; i < 4; i++) {
+          const uint32_t wi = 4 * tid + i;
+          if (wi < nwords) {
+            pre[wi] = r;
+            r += (uint32_t)__popcll(bm[wi]);
           }
         }
       }
-      nnz += tot;
       __syncthreads();
+      for (uint32_t r0 = 0; r0 < m; r0 += HC) {
+        if (tid == 0) {
+          s_klo = rank_select(bm, pre, nwords, r0);
+          s_khi = r0 + HC < m ? rank_select(bm, pre, nwords, r0 + HC) : wend - w0;
+        }
+        __syncthreads();
+        const uint32_t klo = s_klo + w0, khi = s_khi + w0;
+        for (uint32_t q = qb + tid; q < qe; q += B_NT) {
+          uint32_t pe;
+          if (!find_j(I, I.a_j[q], pe)) continue;
+          uint32_t ab, ae;
+          rows_of(I.a_run, q, ab, ae);
+          uint32_t kb = I.e_off[pe], kend = I.e_off[pe + 1];
+          if (m > HC || I.n_k > a.kw) {
+            kb = lower_bound_u32(I.e_k, kb, kend, klo);
+            kend = lower_bound_u32(I.e_k, kb, kend, khi);
+          }
+          for (uint32_t kp = kb; kp < kend; kp++) {
+            const uint32_t k = I.e_k[kp] - w0;
+            const uint64_t word = bm[k >> 6];
+            const uint32_t sl = pre[k >> 6] + (uint32_t)__popcll(word & ((1ull << (k & 63u)) - 1ull)) - r0;
+            sk[sl] = k + w0;
+            uint32_t eb, ee;
+            rows_of(I.e_run, kp, eb, ee);
+            atomicAdd(&scnt[sl], (unsigned long long)(ae - ab) * (ee - eb));
+            if (I.sum)
+              for (uint32_t ra = ab; ra < ae; ra++)
+                for (uint32_t re = eb; re < ee; re++) {
+                  double hi, lo;
+                  two_prod(I.a_val[ra], I.e_val[re], hi, lo);
+                  bool ok = lds_add_term(sdig + sl * EXACT_MAXD, hi, I.lsb, I.D, 1);
+                  ok = lds_add_term(sdig + sl * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
+                  if (!ok) bad = 1;
+                }
+          }
+        }
+        __syncthreads();
+        const uint32_t nw = min(HC, m - r0);
+        for (uint32_t sl = tid; sl < nw; sl += B_NT) {
+          const uint64_t o = out + nnz + r0 + sl;
+          a.ub_k[o] = sk[sl];
+          a.ub_cnt[o] = scnt[sl];
+          if (I.sum) a.ub_sum[o] = exact_round((const int64_t*)(sdig + sl * EXACT_MAXD), I.D, I.lsb, a.err);
+          scnt[sl] = 0;
+#pragma unroll
+          for (int d = 0; d < EXACT_MAXD; d++) sdig[sl * EXACT_MAXD + d] = 0;
+        }
+        __syncthreads();
+      }
+      nnz += m;
     }
     if (tid == 0) a.row_nnz[t] = nnz;
   }
@@ -290,13 +345,27 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
 // thread by thread, the k nodes of E transposed are walked in k order, each
 // column's j probed in the bitmap and the matching products summed exactly
 // in registers; non-empty outputs are placed by a block scan.
+// Inner-product rows: one block per row.  A's row is marked in an LDS
+// bitmap over j with per-word rank prefixes (the position of j in the row).
+// E transposed is then streamed chunk by chunk (256 columns k at a time):
+// the block's threads take the chunk's (k, j) entries in order, coalesced
+// and independent, probe j in the bitmap, and add each matching product's
+// exact digits to its column's LDS accumulator (the column found by
+// bisecting the chunk's offsets); the columns are then emitted in k order
+// and their accumulators cleared.
 __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
   __shared__ unsigned long long bm[KW_MAX / 64];
   __shared__ uint32_t pre[KW_MAX / 64];
+  __shared__ uint32_t soff[B_NT + 1];                 // the chunk's column offsets
+  __shared__ unsigned long long ccnt[B_NT];           // per column of the chunk
+  __shared__ long long cdig[B_NT * EXACT_MAXD];
   __shared__ uint32_t s_item;
   __shared__ uint32_t s_wsum[B_NW];
   const int tid = threadIdx.x;
   uint32_t bad = 0;
+  ccnt[tid] = 0;
+#pragma unroll
+  for (int d = 0; d < EXACT_MAXD; d++) cdig[tid * EXACT_MAXD + d] = 0;
   for (;;) {
     if (tid == 0) s_item = atomicAdd(&a.qhead[2], 1u);
     __syncthreads();
@@ -333,51 +402,64 @@ __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
         }
       }
     }
-    __syncthreads();
     const uint64_t out = a.ub_off[t];
     uint32_t nnz = 0;
     for (uint32_t kb0 = 0; kb0 < I.bt_n0; kb0 += B_NT) {
-      const uint32_t kn = kb0 + tid;
-      uint64_t cnt = 0;
-      RegAcc acc;
-      acc.clear();
-      if (kn < I.bt_n0) {
-        for (uint32_t e = I.bt_off[kn]; e < I.bt_off[kn + 1]; e++) {
-          const uint32_t j = I.bt_j[e];
-          if (j >= I.n_j) break;                       // j ascending within the column
-          const uint64_t word = bm[j >> 6];
-          if (!((word >> (j & 63u)) & 1ull)) continue;
-          const uint32_t q = qb + pre[j >> 6] + (uint32_t)__popcll(word & ((1ull << (j & 63u)) - 1ull));
-          uint32_t ab, ae, eb, ee;
-          rows_of(I.a_run, q, ab, ae);
-          rows_of(I.bt_run, e, eb, ee);
-          cnt += (uint64_t)(ae - ab) * (ee - eb);
-          if (I.sum)
-            for (uint32_t ra = ab; ra < ae; ra++)
-              for (uint32_t re = eb; re < ee; re++) {
-                double hi, lo;
-                two_prod(I.a_val[ra], I.bt_val[re], hi, lo);
-                bool ok = acc.add(hi, I.lsb, I.D, 1);
-                ok = acc.add(lo, I.lsb, I.D, 1) && ok;
-                if (!ok) bad = 1;
-              }
+      const uint32_t nk = min((uint32_t)B_NT, I.bt_n0 - kb0);
+      soff[tid] = I.bt_off[kb0 + min((uint32_t)tid, nk)];
+      if (tid == 0) soff[B_NT] = I.bt_off[kb0 + nk];
+      __syncthreads();
+      const uint32_t e0 = soff[0], e1 = soff[nk];
+      for (uint32_t e = e0 + tid; e < e1; e += B_NT) {
+        const uint32_t j = I.bt_j[e];
+        if (j >= I.n_j) continue;
+        const uint64_t word = bm[j >> 6];
+        if (!((word >> (j & 63u)) & 1ull)) continue;
+        // column of entry e: the last c with soff[c] <= e
+        uint32_t c = 0, n = nk;
+        while (n > 1) {
+          const uint32_t half = n >> 1;
+          c = (soff[c + half] <= e) ? c + half : c;
+          n -= half;
         }
+        const uint32_t q = qb + pre[j >> 6] + (uint32_t)__popcll(word & ((1ull << (j & 63u)) - 1ull));
+        uint32_t ab, ae, eb, ee;
+        rows_of(I.a_run, q, ab, ae);
+        rows_of(I.bt_run, e, eb, ee);
+        atomicAdd(&ccnt[c], (unsigned long long)(ae - ab) * (ee - eb));
+        if (I.sum)
+          for (uint32_t ra = ab; ra < ae; ra++)
+            for (uint32_t re = eb; re < ee; re++) {
+              double hi, lo;
+              two_prod(I.a_val[ra], I.bt_val[re], hi, lo);
+              bool ok = lds_add_term(cdig + c * EXACT_MAXD, hi, I.lsb, I.D, 1);
+              ok = lds_add_term(cdig + c * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
+              if (!ok) bad = 1;
+            }
       }
+      __syncthreads();
+      const uint64_t cnt = (uint32_t)tid < nk ? ccnt[tid] : 0ull;
       uint32_t tot;
       const uint32_t r = block_excl_scan<uint32_t, B_NT>(cnt ? 1u : 0u, s_wsum, tot);
       if (cnt) {
         const uint64_t o = out + nnz + r;
-        a.ub_k[o] = I.bt_k[kn];
+        a.ub_k[o] = I.bt_k[kb0 + tid];
         a.ub_cnt[o] = cnt;
-        if (I.sum) a.ub_sum[o] = exact_round(acc.s, I.D, I.lsb, a.err);
+        if (I.sum) a.ub_sum[o] = exact_round((const int64_t*)(cdig + tid * EXACT_MAXD), I.D, I.lsb, a.err);
       }
+      ccnt[tid] = 0;
+#pragma unroll
+      for (int d = 0; d < EXACT_MAXD; d++) cdig[tid * EXACT_MAXD + d] = 0;
       nnz += tot;
+      __syncthreads();
     }
     if (tid == 0) a.row_nnz[t] = nnz;
     __syncthreads();
   }
   if (bad) atomicOr(a.err, 1u);
 }
+
+constexpr uint32_t LIGHT_GRAB = 32;
 
 // Light rows: one wave per row, private LDS hash of HS slots.
 template <int HS>
@@ -392,12 +474,19 @@ __global__ __launch_bounds__(B_NT) void k_batch_light(BatchArgs a) {
   unsigned long long* hc = (unsigned long long*)(hk + HS);
   long long* hd = (long long*)(hc + HS);
   uint16_t* hl = (uint16_t*)(hd + HS * EXACT_MAXD);
+  // Light rows are claimed LIGHT_GRAB at a time: one atomic on the queue
+  // head per claim (a head taken once per row serializes millions of rows).
+  uint32_t item = 0, item_end = 0;
   for (;;) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(&a.qhead[1], 1u);
-    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, WAVE));
+    if (item == item_end) {
+      uint32_t g = 0;
+      if (lane == 0) g = atomicAdd(&a.qhead[1], LIGHT_GRAB);
+      item = __builtin_amdgcn_readfirstlane(__shfl(g, 0, WAVE));
+      item_end = (uint32_t)min<uint64_t>((uint64_t)item + LIGHT_GRAB, a.n_light);
+    }
     if (item >= a.n_light) break;
     const uint32_t t = __builtin_amdgcn_readfirstlane(a.light[item]);
+    item++;
     const BInst I = a.inst[a.row_inst[t]];
     const uint32_t p = t - (uint32_t)a.inst_row0[a.row_inst[t]];
     const uint32_t qb = I.a_off[p], qe = I.a_off[p + 1];
@@ -448,12 +537,38 @@ __global__ __launch_bounds__(B_NT) void k_batch_light(BatchArgs a) {
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t q = qb + lane; q < qe; q += WAVE) {
-      uint32_t pe;
-      if (!find_j(I, I.a_j[q], pe)) continue;
-      uint32_t ab, ae;
-      rows_of(I.a_run, q, ab, ae);
-      for (uint32_t kp = I.e_off[pe]; kp < I.e_off[pe + 1]; kp++) {
+    // The row's products are spread over the lanes: per chunk of 64 A
+    // entries, a scan of their B-row lengths numbers the products, and
+    // each lane takes products f, f + 64, ... (finding its A entry by
+    // bisecting the scan across lanes), so all loads are independent.
+    for (uint32_t c0 = qb; c0 < qe; c0 += WAVE) {
+      const uint32_t q = c0 + lane;
+      uint32_t pe = 0, len = 0, kb = 0;
+      if (q < qe && find_j(I, I.a_j[q], pe)) {
+        kb = I.e_off[pe];
+        len = I.e_off[pe + 1] - kb;
+      }
+      const uint32_t incl = wave_incl_scan(len);
+      const uint32_t start = incl - len;
+      const uint32_t total = (uint32_t)__shfl((int)incl, WAVE - 1, WAVE);
+      for (uint32_t f0 = 0; f0 < total; f0 += WAVE) {   // uniform: every lane takes part in the shuffles
+        const uint32_t f = f0 + lane;
+        // owner: the last lane whose start <= f (lanes with len 0 share a start)
+        uint32_t src = 0, n = WAVE;
+#pragma unroll
+        for (int step = 0; step < 6; step++) {
+          const uint32_t half = n >> 1;
+          const uint32_t st = (uint32_t)__shfl((int)start, (int)(src + half), WAVE);
+          src = st <= f ? src + half : src;
+          n -= half;
+        }
+        const uint32_t kbs = (uint32_t)__shfl((int)kb, (int)src, WAVE);
+        const uint32_t sts = (uint32_t)__shfl((int)start, (int)src, WAVE);
+        if (f >= total) continue;
+        const uint32_t qq = c0 + src;
+        const uint32_t kp = kbs + (f - sts);
+        uint32_t ab, ae;
+        rows_of(I.a_run, qq, ab, ae);
         const uint32_t k = I.e_k[kp];
         uint32_t slot = (k * 2654435761u) >> HS_SHIFT;
         for (;;) {
@@ -487,13 +602,33 @@ __global__ __launch_bounds__(B_NT) void k_batch_light(BatchArgs a) {
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t e = lane; e < m; e += WAVE) {
-      const uint32_t s = hl[e];
-      const uint32_t k = hk[s];
-      uint32_t rank = 0;
-      for (uint32_t f = 0; f < m; f++) rank += hk[hl[f]] < k ? 1u : 0u;
-      const uint64_t o = out + rank;
-      a.ub_k[o] = k;
+    // rank of each listed key among the listed keys: lane holds entries
+    // lane + 64 c in registers; every key is broadcast once by a shuffle
+    constexpr int NC = HS / WAVE;
+    uint32_t kk[NC], ss[NC], rk[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      const uint32_t f = c * WAVE + lane;
+      ss[c] = f < m ? hl[f] : 0u;
+      kk[c] = f < m ? hk[ss[c]] : EMPTY_KEY;
+      rk[c] = 0;
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < NC; c2++) {
+      if ((uint32_t)c2 * WAVE >= m) break;
+      const uint32_t n2 = min((uint32_t)WAVE, m - (uint32_t)c2 * WAVE);
+      for (uint32_t j = 0; j < n2; j++) {
+        const uint32_t kf = (uint32_t)__shfl((int)kk[c2], (int)j, WAVE);
+#pragma unroll
+        for (int c = 0; c < NC; c++) rk[c] += kf < kk[c] ? 1u : 0u;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      if ((uint32_t)c * WAVE + lane >= m) continue;
+      const uint32_t s = ss[c];
+      const uint64_t o = out + rk[c];
+      a.ub_k[o] = kk[c];
       a.ub_cnt[o] = hc[s];
       if (I.sum) a.ub_sum[o] = exact_round((const int64_t*)(hd + s * EXACT_MAXD), I.D, I.lsb, a.err);
     }
@@ -559,7 +694,7 @@ unsigned grid_for(uint64_t n) {
 struct Tuning {
   uint32_t light_max = 128;   // products above which a matrix row is heavy (light hash: 2x slots)
   uint32_t blocks_per_cu = 2; // persistent grid
-  uint32_t inner_ratio = 64;  // heavy row in inner-product form when products * ratio >= nnz(E)
+  uint32_t inner_ratio = 512; // heavy row in inner-product form when products * ratio >= nnz(E)
 };
 
 // E transposed (levels k, j) of every matrix instance, built once per batch
@@ -586,8 +721,6 @@ struct BatchState {
   std::shared_ptr<Transposes> tr;
   DBuf<uint64_t> ub_cnt;
   DBuf<double> ub_sum;
-  DBuf<unsigned long long> scratch_cnt;   // heavy rows: per-block k-indexed exact sums
-  DBuf<long long> scratch_dig;
   uint32_t kw = 64;
   uint64_t n_heavy = 0, n_light = 0, n_inner = 0;
   std::vector<uint64_t> h_inst_row0;
@@ -621,6 +754,8 @@ BInst describe(const lh_plan_t* p) {
   b.a_val = (b.sum && A.anno >= 0) ? ta->annos[A.anno].p : nullptr;
   b.e_j = te->lv[0].keys.p;
   b.e_n0 = (uint32_t)te->lv[0].n;
+  // distinct sorted keys, as many as the largest key + 1: exactly 0 .. n - 1
+  b.e_dense = (b.e_n0 > 0 && (uint64_t)te->key_max[0] + 1 == te->lv[0].n) ? 1u : 0u;
   b.e_pool = te->lv[0].pool.p;
   b.e_bsw = UINT64_MAX;
   b.e_bsb = 0;
@@ -763,20 +898,12 @@ void setup(BatchState& b, hipStream_t s) {
   b.ub_cnt.alloc(b.UB, s);
   b.ub_sum.alloc(b.UB, s);
   b.err.alloc(1, s);
-  // heavy rows: one k window of scratch per possible persistent block
-  if (b.n_heavy) {
+  // heavy rows: the window of k values their bitmap covers
+  {
     uint32_t nk = 0;
     for (const BInst& I : b.h_inst)
       if (I.kind == 1) nk = std::max(nk, I.n_k);
-    b.kw = std::min<uint32_t>(KW_MAX, (nk + 63) / 64 * 64);
-    int dev = 0, cus = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const uint64_t slots = (uint64_t)cus * MAX_BLOCKS_PER_CU * b.kw;
-    b.scratch_cnt.alloc(slots, s);
-    b.scratch_dig.alloc(slots * EXACT_MAXD, s);
-    fill_u64((uint64_t*)b.scratch_cnt.p, 0, slots, s);
-    fill_u64((uint64_t*)b.scratch_dig.p, 0, slots * EXACT_MAXD, s);
+    b.kw = std::max<uint32_t>(64, std::min<uint32_t>(KW_MAX, (nk + 63) / 64 * 64));
   }
   LH_HIP(hipStreamSynchronize(s));
 }
@@ -804,8 +931,6 @@ void launch_compute(BatchState& b, hipStream_t s) {
   a.ub_cnt = b.ub_cnt.p;
   a.ub_sum = b.ub_sum.p;
   a.err = b.err.p;
-  a.scratch_cnt = b.scratch_cnt.p;
-  a.scratch_dig = b.scratch_dig.p;
   a.kw = b.kw;
   const unsigned grid = (unsigned)(cus * std::min(b.tune.blocks_per_cu, MAX_BLOCKS_PER_CU));
   if (b.n_inner) k_batch_inner<<<grid, B_NT, 0, s>>>(a);

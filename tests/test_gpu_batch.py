@@ -100,3 +100,23 @@ def test_mixed_batch_falls_back(lh):
     r = lh.join_aggregate([p1, p2])
     assert int(r[0].to_host()["counts"][0]) == 220
     same(r[1].to_host(), lh.join_aggregate([p2])[0].to_host())
+
+
+def test_batch_wide_k_range(lh, tmp_path, monkeypatch):
+    """SpGEMM instances whose k range exceeds one bitmap window of the heavy
+    path (n = 100,000 > 65,536), with heavy and dense rows, next to small
+    instances: the batched result equals each plan run alone, and the
+    oracle on the small ones."""
+    monkeypatch.setenv("LH_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    rng = synth.rng_for(31)
+    insts = synth.batched_instances(count=6, n_lo=64, n_hi=500, seed=12)
+    r, c, v = synth.zipf_degree_matrix(100_000, 1.1, 4, rng)
+    insts.append({"kind": "spgemm", "n": 100_000, "rows": r, "cols": c, "vals": v})
+    keep, plans, qs = make_plans(lh, insts)
+    batched = [x.to_host() for x in lh.join_aggregate(plans)]
+    for i, p in enumerate(plans):
+        same(batched[i], lh.join_aggregate([p])[0].to_host())
+    for i in range(6):
+        want = oracle.join_aggregate(qs[i])
+        assert np.array_equal(batched[i]["keys"], want["keys"])
+        assert np.array_equal(batched[i]["sums"].view(np.uint64), want["sums"].view(np.uint64))
