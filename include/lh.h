@@ -259,6 +259,67 @@ lh_status lh_order_cost(const lh_hypergraph* h, const uint32_t* order, uint32_t*
 lh_status lh_choose_order(const lh_hypergraph* h, uint32_t n_out, const uint32_t* out_attrs, uint32_t* order,
                           double* cost);
 
+/* ---- multi-node plans: generalized hypertree decompositions ------------- */
+#define LH_GHD_MAX_NODES 16
+
+/* A GHD (section 2.3, "Generalized Hypertree Decompositions"): a tree of
+ * nodes, each joining its hyperedges (the query's atoms) and the results of
+ * its children, and handing its parent, per tuple of the attributes they
+ * share, the aggregate over everything below (the annotation semiring of
+ * section 2.3).  Every edge belongs to exactly one ordinary node; a node's
+ * attributes chi are its edges' attributes.  A selection node (pushed = 1,
+ * section 3.2) holds one filtered edge of its parent and evaluates the
+ * selection before the parent joins it.  Node 0 is the root and
+ * parent[t] < t for t > 0. */
+typedef struct {
+  uint32_t n_nodes;
+  int32_t parent[LH_GHD_MAX_NODES];   /* -1 for the root */
+  uint32_t edges[LH_GHD_MAX_NODES];   /* bit e: hyperedge e */
+  uint32_t attrs[LH_GHD_MAX_NODES];   /* chi(t), bit v: attribute v (output) */
+  uint32_t pushed[LH_GHD_MAX_NODES];  /* 1: a selection node */
+  double node_fhw[LH_GHD_MAX_NODES];  /* fractional edge cover number of chi(t) by t's edges (output) */
+  double fhw;                         /* width: the largest node_fhw over ordinary nodes (output) */
+  uint32_t depth;                     /* longest root-to-leaf path in tree edges, ordinary nodes (output) */
+  uint32_t shared;                    /* sum over tree edges of |chi(t) & chi(parent)| (output) */
+  uint32_t sel_depth;                 /* sum of the depths of the nodes holding filtered edges (output) */
+} lh_ghd;
+
+/* Fractional edge cover number of the attributes of the edges in edge_mask
+ * by those edges (the width of one GHD node, section 2.3).  Host only; the
+ * hypergraph's edge_card may be NULL here. */
+lh_status lh_ghd_fhw(const lh_hypergraph* h, uint32_t edge_mask, double* fhw);
+
+/* Choose a GHD (section 3.2): least width, then fewest nodes, least depth,
+ * fewest vertices shared between adjacent nodes, deepest selections; a
+ * decomposition of width 1 becomes a single node (section 2.3); then every
+ * filtered edge in a node of two or more edges gets a selection node.  The
+ * root holds every attribute in out_attrs and every edge flagged in
+ * edge_root (GROUP BY meta columns live in root relations).  edge_sel and
+ * edge_root (n_edges entries) may be NULL.  Host only; edge_card may be
+ * NULL.  Errors: LH_ERR_INVALID for 0 or more than 8 edges or ids out of
+ * range. */
+lh_status lh_ghd_choose(const lh_hypergraph* h, const uint32_t* edge_sel, const uint32_t* edge_root,
+                        uint32_t n_out, const uint32_t* out_attrs, lh_ghd* out);
+
+/* The decomposition lh_ghd_join_aggregate would choose for q (its atoms'
+ * attributes, filtered atoms, GROUP BY atoms and outputs).  Host only. */
+lh_status lh_ghd_for_query(const lh_query* q, lh_ghd* out);
+
+/* Run q under the decomposition g (NULL: the one lh_ghd_for_query gives).
+ * Nodes run bottom-up, each as lh_plan + lh_join_aggregate over its edges
+ * (with their filters) and its children's results, which become annotated
+ * relations keyed by the attributes shared with the parent; the root groups
+ * by the query's outputs.  The result has the single-plan layout: keys and
+ * counts identical to lh_plan + lh_join_aggregate of q; for SUM, the sum is
+ * rounded once per node instead of once overall, so exact = 0 when the
+ * root has children.  Errors: those of lh_plan and lh_join_aggregate;
+ * LH_ERR_INVALID for a g that is not a GHD of q (edge in no or two
+ * ordinary nodes, running intersection broken, a child sharing no
+ * attribute with its parent, outputs or GROUP BY atoms outside the root, a
+ * selection node that does not hold one filtered edge of its parent);
+ * LH_ERR_OVERFLOW when a count reaches 2^53. */
+lh_status lh_ghd_join_aggregate(const lh_query* q, const lh_ghd* g, void* hip_stream, lh_result** out);
+
 /* Device allocations currently held by the library (leak checks). */
 long lh_live_allocations(void);
 

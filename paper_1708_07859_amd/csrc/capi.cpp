@@ -6,6 +6,7 @@
 
 #include "costmodel.h"
 #include "engine.h"
+#include "ghd.h"
 
 namespace lh {
 
@@ -68,6 +69,72 @@ Hypergraph hypergraph_from(const lh_hypergraph* h) {
     g.edges.push_back(E);
   }
   return g;
+}
+
+std::vector<uint32_t> edge_masks(const lh_hypergraph* h) {
+  if (!h || !h->edge_attr_count || !h->edge_attrs) fail(LH_ERR_INVALID, "hypergraph is incomplete");
+  if (h->n_attrs == 0 || h->n_attrs > MAXV) fail(LH_ERR_INVALID, "n_attrs must be 1..16");
+  if (h->n_edges == 0 || h->n_edges > MAXA) fail(LH_ERR_INVALID, "n_edges must be 1..8");
+  std::vector<uint32_t> m(h->n_edges, 0);
+  uint32_t k = 0;
+  for (uint32_t e = 0; e < h->n_edges; e++)
+    for (uint32_t i = 0; i < h->edge_attr_count[e]; i++) {
+      const uint32_t v = h->edge_attrs[k++];
+      if (v >= h->n_attrs) fail(LH_ERR_INVALID, "edge attribute out of range");
+      m[e] |= 1u << v;
+    }
+  return m;
+}
+
+void ghd_to_public(const Ghd& g, lh_ghd* out) {
+  memset(out, 0, sizeof(*out));
+  out->n_nodes = (uint32_t)g.nodes.size();
+  for (size_t t = 0; t < g.nodes.size(); t++) {
+    out->parent[t] = g.nodes[t].parent;
+    out->edges[t] = g.nodes[t].edges;
+    out->attrs[t] = g.nodes[t].attrs;
+    out->pushed[t] = g.nodes[t].pushed ? 1u : 0u;
+    out->node_fhw[t] = g.nodes[t].fhw;
+  }
+  out->fhw = g.fhw;
+  out->depth = g.depth;
+  out->shared = g.shared;
+  out->sel_depth = g.sel_depth;
+}
+
+// The hypergraph of a query: edge attribute masks, filtered edges, GROUP BY
+// edges and the output attribute mask.
+void query_hypergraph(const lh_query* q, std::vector<uint32_t>& masks, uint32_t& sel, uint32_t& root,
+                      uint32_t& outm) {
+  if (!q || !q->atoms) fail(LH_ERR_INVALID, "NULL argument");
+  if (q->n_attrs == 0 || q->n_attrs > MAXV) fail(LH_ERR_INVALID, "n_attrs must be 1..16");
+  if (q->n_atoms == 0 || q->n_atoms > MAXA) fail(LH_ERR_INVALID, "n_atoms must be 1..8");
+  masks.assign(q->n_atoms, 0);
+  for (uint32_t e = 0; e < q->n_atoms; e++) {
+    const lh_atom& A = q->atoms[e];
+    if (!tracked(g_tries, A.trie)) fail(LH_ERR_INVALID, "atom trie is not a live lh_trie");
+    if (!A.attr_of_key) fail(LH_ERR_INVALID, "attr_of_key is NULL");
+    for (uint32_t k = 0; k < A.trie->n_levels; k++) {
+      if (A.attr_of_key[k] >= q->n_attrs) fail(LH_ERR_INVALID, "attribute out of range");
+      masks[e] |= 1u << A.attr_of_key[k];
+    }
+  }
+  sel = root = outm = 0;
+  if (q->n_filters && !q->filters) fail(LH_ERR_INVALID, "filters is NULL");
+  for (uint32_t f = 0; f < q->n_filters; f++) {
+    if (q->filters[f].atom >= q->n_atoms) fail(LH_ERR_INVALID, "filter atom out of range");
+    sel |= 1u << q->filters[f].atom;
+  }
+  if (q->n_group && !q->group_cols) fail(LH_ERR_INVALID, "group_cols is NULL");
+  for (uint32_t g = 0; g < q->n_group; g++) {
+    if (q->group_cols[g].atom >= q->n_atoms) fail(LH_ERR_INVALID, "group column out of range");
+    root |= 1u << q->group_cols[g].atom;
+  }
+  if (q->n_out && !q->out_attrs) fail(LH_ERR_INVALID, "out_attrs is NULL");
+  for (uint32_t i = 0; i < q->n_out; i++) {
+    if (q->out_attrs[i] >= q->n_attrs) fail(LH_ERR_INVALID, "output attribute out of range");
+    outm |= 1u << q->out_attrs[i];
+  }
 }
 
 }  // namespace
@@ -263,6 +330,68 @@ lh_status lh_choose_order(const lh_hypergraph* h, uint32_t n_out, const uint32_t
     double c = choose_order(g, out, o);
     std::copy(o.begin(), o.end(), order);
     if (cost) *cost = c;
+  });
+}
+
+lh_status lh_ghd_fhw(const lh_hypergraph* h, uint32_t edge_mask, double* fhw) {
+  return guard([&] {
+    std::vector<uint32_t> m = edge_masks(h);
+    if (!fhw) fail(LH_ERR_INVALID, "NULL argument");
+    if (edge_mask >> m.size()) fail(LH_ERR_INVALID, "edge mask out of range");
+    *fhw = fractional_cover(m, edge_mask);
+  });
+}
+
+lh_status lh_ghd_choose(const lh_hypergraph* h, const uint32_t* edge_sel, const uint32_t* edge_root,
+                        uint32_t n_out, const uint32_t* out_attrs, lh_ghd* out) {
+  return guard([&] {
+    std::vector<uint32_t> m = edge_masks(h);
+    if (!out || (n_out && !out_attrs)) fail(LH_ERR_INVALID, "NULL argument");
+    uint32_t sel = 0, root = 0, outm = 0;
+    for (uint32_t e = 0; e < m.size(); e++) {
+      if (edge_sel && edge_sel[e]) sel |= 1u << e;
+      if (edge_root && edge_root[e]) root |= 1u << e;
+    }
+    for (uint32_t i = 0; i < n_out; i++) {
+      if (out_attrs[i] >= h->n_attrs) fail(LH_ERR_INVALID, "output attribute out of range");
+      outm |= 1u << out_attrs[i];
+    }
+    ghd_to_public(choose_ghd(m, sel, root, outm), out);
+  });
+}
+
+lh_status lh_ghd_for_query(const lh_query* q, lh_ghd* out) {
+  return guard([&] {
+    if (!out) fail(LH_ERR_INVALID, "NULL argument");
+    std::vector<uint32_t> m;
+    uint32_t sel, root, outm;
+    query_hypergraph(q, m, sel, root, outm);
+    ghd_to_public(choose_ghd(m, sel, root, outm), out);
+  });
+}
+
+lh_status lh_ghd_join_aggregate(const lh_query* q, const lh_ghd* g, void* hip_stream, lh_result** out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    if (!out) fail(LH_ERR_INVALID, "NULL argument");
+    std::vector<uint32_t> m;
+    uint32_t sel, root, outm;
+    query_hypergraph(q, m, sel, root, outm);
+    Ghd d;
+    if (g) {
+      if (g->n_nodes == 0 || g->n_nodes > LH_GHD_MAX_NODES) fail(LH_ERR_INVALID, "ghd: 1..16 nodes");
+      for (uint32_t t = 0; t < g->n_nodes; t++) {
+        GhdNode n;
+        n.edges = g->edges[t];
+        n.parent = g->parent[t];
+        n.pushed = g->pushed[t] != 0;
+        d.nodes.push_back(n);
+      }
+      check_ghd(m, sel, root, outm, d);
+    } else {
+      d = choose_ghd(m, sel, root, outm);
+    }
+    *out = run_ghd(q, d, (hipStream_t)hip_stream);
   });
 }
 

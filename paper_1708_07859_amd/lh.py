@@ -119,6 +119,24 @@ class Hypergraph(C.Structure):
     ]
 
 
+LH_GHD_MAX_NODES = 16
+
+
+class Ghd(C.Structure):
+    _fields_ = [
+        ("n_nodes", C.c_uint32),
+        ("parent", C.c_int32 * LH_GHD_MAX_NODES),
+        ("edges", C.c_uint32 * LH_GHD_MAX_NODES),
+        ("attrs", C.c_uint32 * LH_GHD_MAX_NODES),
+        ("pushed", C.c_uint32 * LH_GHD_MAX_NODES),
+        ("node_fhw", C.c_double * LH_GHD_MAX_NODES),
+        ("fhw", C.c_double),
+        ("depth", C.c_uint32),
+        ("shared", C.c_uint32),
+        ("sel_depth", C.c_uint32),
+    ]
+
+
 # Every entry point declared in include/lh.h, with its ctypes signature.
 SIGNATURES = {
     "lh_trie_build": ([C.POINTER(RelationDesc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
@@ -150,6 +168,12 @@ SIGNATURES = {
     "lh_profile_enable": ([C.c_int], None),
     "lh_profile_reset": ([], None),
     "lh_profile_read": ([C.c_void_p, C.c_uint32], C.c_uint32),
+    "lh_ghd_fhw": ([C.POINTER(Hypergraph), C.c_uint32, C.POINTER(C.c_double)], C.c_int),
+    "lh_ghd_choose": ([C.POINTER(Hypergraph), C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32),
+                       C.POINTER(Ghd)], C.c_int),
+    "lh_ghd_for_query": ([C.POINTER(Query), C.POINTER(Ghd)], C.c_int),
+    "lh_ghd_join_aggregate": ([C.POINTER(Query), C.POINTER(Ghd), C.c_void_p, C.POINTER(C.POINTER(Result))],
+                              C.c_int),
 }
 
 
@@ -302,11 +326,10 @@ class Plan:
             pass
 
 
-def plan(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None, policy="plain",
-         stream=None):
-    """lh_plan.  atoms: [(Trie, attr_of_key list, anno index or -1)]."""
+def _query(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None, policy="plain"):
+    """An lh_query and the ctypes arrays it points into (keep them alive)."""
     catoms = (Atom * len(atoms))()
-    keep = []
+    keep = [catoms]
     for i, (t, attrs, anno) in enumerate(atoms):
         am = (C.c_uint32 * len(attrs))(*attrs)
         keep.append(am)
@@ -318,15 +341,18 @@ def plan(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=N
     q.n_atoms = len(atoms)
     q.atoms = catoms
     oa = (C.c_uint32 * max(1, len(out)))(*out)
+    keep.append(oa)
     q.n_out = len(out)
     q.out_attrs = C.cast(oa, C.POINTER(C.c_uint32))
     ga = (GroupCol * max(1, len(group)))()
+    keep.append(ga)
     for i, (a, c) in enumerate(group):
         ga[i].atom, ga[i].meta_col = a, c
     q.n_group = len(group)
     q.group_cols = ga
     q.agg = LH_AGG_SUM if agg == "sum" else LH_AGG_COUNT
     fa = (Filter * max(1, len(filters)))()
+    keep.append(fa)
     for i, f in enumerate(filters):
         fa[i].atom = f["atom"]
         fa[i].kind = FILTER_KIND[f["kind"]]
@@ -336,11 +362,18 @@ def plan(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=N
         fa[i].hi = f.get("hi", 0.0)
     q.n_filters = len(filters)
     q.filters = fa
-    ao = None
     if attr_order is not None:
         ao = (C.c_uint32 * len(attr_order))(*attr_order)
+        keep.append(ao)
         q.attr_order = C.cast(ao, C.POINTER(C.c_uint32))
     q.policy = POLICY[policy]
+    return q, keep
+
+
+def plan(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None, policy="plain",
+         stream=None):
+    """lh_plan.  atoms: [(Trie, attr_of_key list, anno index or -1)]."""
+    q, keep = _query(n_attrs, atoms, out, group, agg, filters, attr_order, policy)
     out_h = C.c_void_p()
     _check(lib.lh_plan(C.byref(q), stream if stream is not None else current_stream(), C.byref(out_h)))
     return Plan(out_h.value, [a[0] for a in atoms])
@@ -528,12 +561,77 @@ def choose_order(n_attrs, edges, out=()):
 
 
 # --------------------------------------------------------------------------
+# multi-node plans (generalized hypertree decompositions)
+# --------------------------------------------------------------------------
+
+def _ghd_dict(g):
+    n = g.n_nodes
+    return {"n_nodes": n, "parent": list(g.parent[:n]), "edges": list(g.edges[:n]), "attrs": list(g.attrs[:n]),
+            "pushed": list(g.pushed[:n]), "node_fhw": list(g.node_fhw[:n]), "fhw": g.fhw, "depth": g.depth,
+            "shared": g.shared, "sel_depth": g.sel_depth}
+
+
+def _ghd_struct(d):
+    g = Ghd()
+    g.n_nodes = len(d["edges"])
+    for t in range(g.n_nodes):
+        g.parent[t] = d["parent"][t]
+        g.edges[t] = d["edges"][t]
+        g.pushed[t] = 1 if d.get("pushed", [0] * g.n_nodes)[t] else 0
+    return g
+
+
+def _edges_only(n_attrs, edges):
+    return _hypergraph(n_attrs, [dict(e, card=e.get("card", 1)) for e in edges])
+
+
+def ghd_fhw(n_attrs, edges, edge_mask):
+    """lh_ghd_fhw: edges [{"attrs": [...]}]."""
+    h, keep = _edges_only(n_attrs, edges)
+    f = C.c_double()
+    _check(lib.lh_ghd_fhw(C.byref(h), edge_mask, C.byref(f)))
+    return f.value
+
+
+def ghd_choose(n_attrs, edges, out=()):
+    """lh_ghd_choose: edges [{"attrs": [...], "sel": bool, "root": bool}]."""
+    h, keep = _edges_only(n_attrs, edges)
+    sel = (C.c_uint32 * len(edges))(*[1 if e.get("sel") else 0 for e in edges])
+    root = (C.c_uint32 * len(edges))(*[1 if e.get("root") else 0 for e in edges])
+    oa = (C.c_uint32 * max(1, len(out)))(*out)
+    g = Ghd()
+    _check(lib.lh_ghd_choose(C.byref(h), sel, root, len(out), oa, C.byref(g)))
+    return _ghd_dict(g)
+
+
+def ghd_for_query(n_attrs, atoms, out=(), group=(), agg="count", filters=()):
+    q, keep = _query(n_attrs, atoms, out, group, agg, filters)
+    g = Ghd()
+    _check(lib.lh_ghd_for_query(C.byref(q), C.byref(g)))
+    return _ghd_dict(g)
+
+
+def ghd_join_aggregate(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None,
+                       policy="plain", ghd=None, stream=None):
+    """lh_ghd_join_aggregate; ghd: a dict with parent/edges/pushed lists, or
+    None for the library's choice."""
+    q, keep = _query(n_attrs, atoms, out, group, agg, filters, attr_order, policy)
+    gp = C.byref(_ghd_struct(ghd)) if ghd is not None else None
+    res = C.POINTER(Result)()
+    _check(lib.lh_ghd_join_aggregate(C.byref(q), gp, stream if stream is not None else current_stream(),
+                                     C.byref(res)))
+    return JoinResult(res)
+
+
+# --------------------------------------------------------------------------
 # query dictionaries (the format documented in tests/queries.py)
 # --------------------------------------------------------------------------
 
-def run_query(query, attr_order=None, policy="plain", layout="plain", return_plan_info=False):
+def run_query(query, attr_order=None, policy="plain", layout="plain", return_plan_info=False, ghd=False):
     """Build one trie per distinct relation of the query, plan, run, and
-    copy the result to host in the format {keys, counts, sums, n_join}."""
+    copy the result to host in the format {keys, counts, sums, n_join}.
+    ghd=False runs one plan; ghd=None runs the library's decomposition, a
+    dict (parent/edges/pushed lists) runs that one."""
     tries = {}
     atoms = []
     for a in query["atoms"]:
@@ -543,16 +641,22 @@ def run_query(query, attr_order=None, policy="plain", layout="plain", return_pla
             tries[ident] = trie_build(a["keys"], a.get("annos", []), a.get("meta", []), bag=a.get("bag", False),
                                       layout=layout)
         atoms.append((tries[ident], list(a["attrs"]), int(a.get("anno", -1))))
-    p = plan(query["n_attrs"], atoms, out=query.get("out", []), group=query.get("group", []),
-             agg=query.get("agg", "count"), filters=query.get("filters", []), attr_order=attr_order,
-             policy=policy)
-    r = join_aggregate([p])[0]
-    out = r.to_host()
-    info = p.info() if return_plan_info else None
-    r.free()
-    p.free()
-    for t in tries.values():
-        t.free()
-    if return_plan_info:
-        out["plan"] = info
+    args = dict(out=query.get("out", []), group=query.get("group", []), agg=query.get("agg", "count"),
+                filters=query.get("filters", []), attr_order=attr_order, policy=policy)
+    p = None
+    try:
+        if ghd is False:
+            p = plan(query["n_attrs"], atoms, **args)
+            r = join_aggregate([p])[0]
+        else:
+            r = ghd_join_aggregate(query["n_attrs"], atoms, ghd=ghd, **args)
+        out = r.to_host()
+        r.free()
+        if return_plan_info and p is not None:
+            out["plan"] = p.info()
+    finally:
+        if p is not None:
+            p.free()
+        for t in tries.values():
+            t.free()
     return out

@@ -238,6 +238,39 @@ def star_schema(n_fact=60_000_000, dims=(2_000_000, 500_000, 100_000, 10_000), s
     return {"fact": {"k": fk, "ann": ann}, "dims": [d0, d1, d2, d3]}
 
 
+def q5_schema(sf=1.0, seed=5):
+    """Six relations with the join shape of a five-way TPC-H-style query
+    around a cycle (customer, orders, lineitem, supplier sharing the nation
+    key) with a nation/region tail, at TPC-H-like sizes per scale factor:
+      region(r)          5 rows,   meta name = r
+      nation(n, r)       25 rows,  r = n // 5
+      supplier(s, n)     10,000 sf rows, n uniform
+      customer(c, n)     150,000 sf rows, n uniform
+      orders(o, c)       1,500,000 sf rows, c uniform, meta date in [0, 2557) days
+      lineitem(o, s)     1..7 rows per order (mean 4), s uniform, bag,
+                         annotation price * (1 - discount)
+    Keys are dense ids; an expression over one relation inside the
+    aggregate is that relation's annotation."""
+    rng = rng_for(seed)
+    n_s = max(1, int(10_000 * sf))
+    n_c = max(1, int(150_000 * sf))
+    n_o = max(1, int(1_500_000 * sf))
+    region = {"r": np.arange(5, dtype=np.uint32), "name": np.arange(5, dtype=np.uint32)}
+    nation = {"n": np.arange(25, dtype=np.uint32), "r": (np.arange(25) // 5).astype(np.uint32)}
+    supplier = {"s": np.arange(n_s, dtype=np.uint32), "n": rng.integers(0, 25, n_s).astype(np.uint32)}
+    customer = {"c": np.arange(n_c, dtype=np.uint32), "n": rng.integers(0, 25, n_c).astype(np.uint32)}
+    orders = {"o": np.arange(n_o, dtype=np.uint32), "c": rng.integers(0, n_c, n_o).astype(np.uint32),
+              "date": rng.integers(0, 2557, n_o).astype(np.uint32)}
+    per = rng.integers(1, 8, n_o)
+    lo = np.repeat(np.arange(n_o, dtype=np.uint32), per)
+    n_l = len(lo)
+    price = rng.random(n_l)
+    discount = rng.integers(0, 11, n_l) / 100.0
+    lineitem = {"o": lo, "s": rng.integers(0, n_s, n_l).astype(np.uint32), "ann": price * (1.0 - discount)}
+    return {"region": region, "nation": nation, "supplier": supplier, "customer": customer,
+            "orders": orders, "lineitem": lineitem}
+
+
 # --------------------------------------------------------------------------
 # Intersection micro-benchmark sets
 # --------------------------------------------------------------------------

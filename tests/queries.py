@@ -65,6 +65,26 @@ def star(s, u_hi=0.20, m2=0, m3=0):
     return {"n_attrs": 4, "agg": "sum", "out": [], "group": [(2, 0)], "atoms": atoms, "filters": filters}
 
 
+def q5(s, region=2, date_lo=730, date_hi=1095, agg="sum"):
+    """SUM(lineitem.ann) (or COUNT) GROUP BY n over customer(c,n),
+    orders(o,c), lineitem(o,s), supplier(s,n), nation(n,r), region(r) with
+    region.name == region and date_lo <= orders.date < date_hi.
+    Attributes c=0, o=1, s=2, n=3, r=4."""
+    atoms = [
+        {"keys": [s["customer"]["c"], s["customer"]["n"]], "attrs": [0, 3], "bag": False},
+        {"keys": [s["orders"]["o"], s["orders"]["c"]], "attrs": [1, 0], "meta": [s["orders"]["date"]],
+         "bag": True},
+        {"keys": [s["lineitem"]["o"], s["lineitem"]["s"]], "attrs": [1, 2], "annos": [s["lineitem"]["ann"]],
+         "anno": 0 if agg == "sum" else -1, "bag": True},
+        {"keys": [s["supplier"]["s"], s["supplier"]["n"]], "attrs": [2, 3], "bag": False},
+        {"keys": [s["nation"]["n"], s["nation"]["r"]], "attrs": [3, 4], "bag": False},
+        {"keys": [s["region"]["r"]], "attrs": [4], "meta": [s["region"]["name"]], "bag": True},
+    ]
+    filters = [{"atom": 5, "kind": "eq_meta", "col": 0, "eq": region},
+               {"atom": 1, "kind": "range_meta", "col": 0, "lo": float(date_lo), "hi": float(date_hi)}]
+    return {"n_attrs": 5, "agg": agg, "out": [3], "atoms": atoms, "filters": filters}
+
+
 def random_query(seed, max_atoms=4, max_attrs=4, domain=6, max_rows=7):
     """A tiny random hypergraph query with filters, group columns, bag or
     set relations, COUNT or SUM.  Values are small multiples of 2^-3 and
