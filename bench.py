@@ -91,11 +91,12 @@ def main():
                     help="layout of the plain-policy run")
     ap.add_argument("--policy", default="both", choices=["both", "plain", "learned"],
                     help="both: time the plain rule, then the learned cost model (reported)")
-    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--card", type=int, default=1_000_000)
     ap.add_argument("--pairs", type=int, default=256)
+    ap.add_argument("--sf", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU layout is a design "
@@ -116,6 +117,8 @@ def main():
         return bench_copy(args, torch)
     if args.workload == "intersect":
         return bench_intersect(args, lh, torch, synth)
+    if args.workload == "q5":
+        return bench_q5(args, lh, torch, synth)
     log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
     t0 = time.perf_counter()
     lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
@@ -381,6 +384,93 @@ def bench_intersect(args, lh, torch, synth):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
            "config": {"workload": f"{npairs} set pairs of {c} elements, COUNT of each intersection",
                       "variants": results}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_q5(args, lh, torch, synth):
+    """Multi-node plans (sections 2.3, 3.2) on the Q5-shaped schema at scale
+    factor `sf`: SUM(lineitem.ann) GROUP BY nation over the customer /
+    orders / lineitem / supplier cycle and the nation / region tail, with an
+    equality selection on region and a one-year range on orders.  One step
+    builds the six tries from resident columns, then runs the query; the
+    decompositions timed are the library's choice, one generic-join node
+    (width 3), the same two nodes with the tail as root (the last tie-break
+    reversed) and the tail split into a chain (more nodes and depth, same
+    width).  value = input rows / step time of the chosen plan."""
+    import numpy as np
+
+    from tests import queries
+    log(f"generating the Q5-shaped schema at sf {args.sf}")
+    sch = synth.q5_schema(args.sf, seed=5)
+    q = queries.q5(sch)
+    dev = [{"keys": [lh.to_device(k) for k in a["keys"]], "annos": [lh.to_device(x) for x in a.get("annos", [])],
+            "meta": [lh.to_device(m) for m in a.get("meta", [])], "bag": a.get("bag", False)} for a in q["atoms"]]
+    n_rows = sum(len(a["keys"][0]) for a in q["atoms"])
+    del sch
+    args_q = dict(out=q["out"], agg="sum", filters=q["filters"])
+    variants = {
+        "chosen": None,
+        "one node": "single",
+        "tail as root": {"edges": [0b110000, 0b001111], "parent": [-1, 0], "pushed": [0, 0]},
+        "chain tail": {"edges": [0b001111, 0b010000, 0b100000], "parent": [-1, 0, 1], "pushed": [0, 0, 0]},
+    }
+
+    def step(g):
+        tries = [lh.trie_build(a["keys"], a["annos"], a["meta"], bag=a["bag"]) for a in dev]
+        atoms = [(t, a["attrs"], a.get("anno", -1)) for t, a in zip(tries, q["atoms"])]
+        if g == "single":
+            p = lh.plan(q["n_attrs"], atoms, **args_q)
+            r = lh.join_aggregate([p])[0]
+            out = r.to_host()
+            r.free()
+            p.free()
+        else:
+            r = lh.ghd_join_aggregate(q["n_attrs"], atoms, ghd=g, **args_q)
+            out = r.to_host()
+            r.free()
+        chosen = lh.ghd_for_query(q["n_attrs"], atoms, **args_q) if g is None else None
+        for t in tries:
+            t.free()
+        return out, chosen
+
+    results, ref, chosen = {}, None, None
+    for name, g in variants.items():
+        for _ in range(max(1, args.warmup)):
+            out, ch = step(g)
+            chosen = ch or chosen
+        if ref is None:
+            ref = out
+        assert np.array_equal(out["keys"], ref["keys"]) and np.array_equal(out["counts"], ref["counts"])
+        assert np.all(np.abs(out["sums"] - ref["sums"]) <= 1e-9 * np.abs(ref["sums"]))
+        torch.cuda.synchronize()
+        if name == "chosen":
+            lh.profile_reset()
+            lh.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(g)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000 / args.steps
+        if name == "chosen":
+            lh.profile_enable(False)
+            prof = lh.profile_read()
+            top = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]
+            for k, v in top:
+                log(f"  {k:22s} {v['total_ms'] / args.steps:8.2f} ms/step  launches {v['launches'] // args.steps}")
+        results[name] = {"ms_per_step": round(ms, 3), "rows_per_s": n_rows / (ms / 1000)}
+        log(f"{name}: {ms:.2f} ms/step")
+    head = results["chosen"]
+    out = {"metric": "join-aggregate input tuples/s, multi-node plan", "value": head["rows_per_s"],
+           "unit": "tuples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32+f64", "data": "synthetic",
+           "config": {"workload": f"Q5-shaped SUM GROUP BY nation, sf {args.sf}, {n_rows} input rows",
+                      "step": "6 x trie_build + GHD plan + join_aggregate per node + readback",
+                      "groups": len(ref["counts"]), "join_tuples": ref["n_join"],
+                      "ghd": {"edges": chosen["edges"], "parent": chosen["parent"], "pushed": chosen["pushed"],
+                              "fhw": chosen["fhw"]},
+                      "variants": results,
+                      "chosen_over_one_node": results["one node"]["ms_per_step"] / head["ms_per_step"]}}
     print(json.dumps(out), flush=True)
 
 

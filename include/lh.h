@@ -290,7 +290,10 @@ typedef struct {
 lh_status lh_ghd_fhw(const lh_hypergraph* h, uint32_t edge_mask, double* fhw);
 
 /* Choose a GHD (section 3.2): least width, then fewest nodes, least depth,
- * fewest vertices shared between adjacent nodes, deepest selections; a
+ * fewest vertices shared between adjacent nodes, deepest selections, and
+ * last (this library's addition) the least sum of node width x depth, so
+ * that narrow nodes sit below wide ones and their results restrict the
+ * wide joins, as nodes run bottom-up; a
  * decomposition of width 1 becomes a single node (section 2.3); then every
  * filtered edge in a node of two or more edges gets a selection node.  The
  * root holds every attribute in out_attrs and every edge flagged in

@@ -13,8 +13,9 @@
 //    keeps the running-intersection property;
 //  - among the decompositions of least width, section 3.2's tie-breaks
 //    pick: fewest nodes, least depth, fewest vertices shared between
-//    adjacent nodes, deepest selections; a chosen decomposition of width 1
-//    is compressed into one node (section 2.3);
+//    adjacent nodes, deepest selections; a last tie-break of this library
+//    puts wide nodes nearer the root (least sum of width x depth); a chosen
+//    decomposition of width 1 is compressed into one node (section 2.3);
 //  - selections are pushed down (section 3.2): a filtered edge in a node of
 //    several edges gets a child node holding it alone.
 //
@@ -113,6 +114,7 @@ namespace {
 struct Sub {                       // a decomposition of one subproblem, rooted
   double fhw = 0.0;
   uint32_t nodes = 0, depth = 0, shared = 0, sel = 0;
+  double wsum = 0.0, wdepth = 0.0;  // sum of node widths; sum of width x depth
   std::vector<uint32_t> bag;       // node edge masks, node 0 = this root
   std::vector<int32_t> parent;     // local parent index, -1 for node 0
 };
@@ -120,18 +122,22 @@ struct Sub {                       // a decomposition of one subproblem, rooted
 // a is at least as good as b in every tie-break quantity
 bool covers(const Sub& a, const Sub& b) {
   return a.fhw <= b.fhw + FHW_EPS && a.nodes <= b.nodes && a.depth <= b.depth && a.shared <= b.shared &&
-         a.sel >= b.sel;
+         a.sel >= b.sel && a.wsum <= b.wsum + FHW_EPS && a.wdepth <= b.wdepth + FHW_EPS;
 }
 
 // Lexicographic order of section 3.2: width, nodes, depth, shared vertices,
-// then the deeper selections.
+// the deeper selections; then wide nodes nearer the root (least sum of
+// width x depth): nodes run bottom-up, so a child's result restricts its
+// parent's join, and a narrow node below a wide one filters the expensive
+// join instead of the reverse.
 bool better(const Sub& a, const Sub& b) {
   if (a.fhw < b.fhw - FHW_EPS) return true;
   if (a.fhw > b.fhw + FHW_EPS) return false;
   if (a.nodes != b.nodes) return a.nodes < b.nodes;
   if (a.depth != b.depth) return a.depth < b.depth;
   if (a.shared != b.shared) return a.shared < b.shared;
-  return a.sel > b.sel;
+  if (a.sel != b.sel) return a.sel > b.sel;
+  return a.wdepth < b.wdepth - FHW_EPS;
 }
 
 struct Enumerator {
@@ -221,6 +227,7 @@ struct Enumerator {
           for (;;) {
             Sub sb;
             sb.fhw = fb;
+            sb.wsum = fb;
             sb.nodes = 1;
             sb.bag.push_back(B);
             sb.parent.push_back(-1);
@@ -231,6 +238,8 @@ struct Enumerator {
               sb.depth = std::max(sb.depth, kd.depth + 1);
               sb.shared += kd.shared + popcount(iface[k]);
               sb.sel += kd.sel + popcount(gm[k] & sel_edges);
+              sb.wsum += kd.wsum;
+              sb.wdepth += kd.wdepth + kd.wsum;
               const int32_t base = (int32_t)sb.bag.size();
               for (size_t j = 0; j < kd.bag.size(); j++) {
                 sb.bag.push_back(kd.bag[j]);

@@ -130,8 +130,9 @@ def rooted_trees(k):
 
 
 def brute_best(edges, sel, root_edges, out_mask):
-    """Lexicographically best (width, nodes, depth, shared, -selection depth)
-    over every GHD assigning each edge to exactly one node."""
+    """Lexicographically best (width, nodes, depth, shared, -selection depth,
+    sum of width x depth) over every GHD assigning each edge to exactly one
+    node."""
     m = masks_of(edges)
     cover = {}
     best = None
@@ -168,7 +169,8 @@ def brute_best(edges, sel, root_edges, out_mask):
             width = max(cover[b] for b in bags)
             shared = sum(bin(chis[t] & chis[parent[t]]).count("1") for t in range(k) if parent[t] >= 0)
             seld = sum(depth[t] * bin(bags[t] & sel).count("1") for t in range(k))
-            key = (round(width, 9), k, max(depth), shared, -seld)
+            wdepth = sum(cover[bags[t]] * depth[t] for t in range(k))
+            key = (round(width, 9), k, max(depth), shared, -seld, round(wdepth, 9))
             if best is None or key < best:
                 best = key
     return best
@@ -192,7 +194,11 @@ def test_choice_is_the_brute_force_optimum(seed):
         assert ordinary == [0]
         assert g["edges"][0] == (1 << n_edges) - 1
     else:
-        got = (round(g["fhw"], 9), len(ordinary), g["depth"], g["shared"], -g["sel_depth"])
+        dep = [0] * g["n_nodes"]
+        for t in range(1, g["n_nodes"]):
+            dep[t] = dep[g["parent"][t]] + 1
+        wdepth = sum(g["node_fhw"][t] * dep[t] for t in ordinary)
+        got = (round(g["fhw"], 9), len(ordinary), g["depth"], g["shared"], -g["sel_depth"], round(wdepth, 9))
         assert got == want
     check_structure(g, edges, sel_mask, out_mask)
 
@@ -257,6 +263,9 @@ def q5_edges():
 
 def test_q5_shape_two_nodes_and_pushed_selections():
     g = lh.ghd_choose(5, q5_edges(), out=[3])
+    # both two-node trees tie on the four rules; the cycle (width 2) is the
+    # root so that the tail's result restricts it
+    assert g["edges"][0] == 0b001111
     ordinary = [t for t in range(g["n_nodes"]) if not g["pushed"][t]]
     bags = sorted(g["edges"][t] for t in ordinary)
     # the 4-cycle of customer, orders, lineitem, supplier (width 2) and the
