@@ -103,6 +103,19 @@ lh_status lh_trie_build(const lh_relation_desc* rel, void* hip_stream, lh_trie**
 #define LH_POLICY_LEARNED 0x1u  /* learned cost model picks; the plain rule is its fallback */
 #define LH_POLICY_FIXED   0x2u  /* caller's attr_order, plain per-level algorithms */
 #define LH_POLICY_MASK    0x3u
+/* GROUP BY whose keys are not a prefix of the attribute order (section 5),
+ * or'ed into lh_query.policy: the key union and the GROUP BY on meta
+ * columns.  AUTO takes DENSE when the key space (the product of each output
+ * column's largest value + 1) is at most 4x the leaf's work or 2^16, and
+ * fits 2^27 entries; else HASH.  SORT materializes every tuple and sorts;
+ * HASH upserts into a device-wide open-addressing table (grown and rerun
+ * when the estimate of its size was short); DENSE adds into an array over
+ * the key space.  Results are identical whichever runs. */
+#define LH_GROUP_AUTO     0x00u
+#define LH_GROUP_SORT     0x10u
+#define LH_GROUP_HASH     0x20u
+#define LH_GROUP_DENSE    0x30u
+#define LH_GROUP_MASK     0x30u
 
 /* A hyperedge: one relation's trie and the query attribute of each of its
  * key columns (columns mapping to one attribute are equi-joined, Rule 1 of
@@ -168,6 +181,8 @@ typedef struct lh_result {
   const double* sums;
   uint32_t exact;                   /* 1: sums are correctly rounded exact sums */
   uint64_t n_join_tuples;           /* full-join tuples aggregated */
+  uint32_t group_impl;              /* how rows were grouped: 0 streamed (prefix or one group), 1 sort,
+                                       2 hash, 3 dense */
 } lh_result;
 
 /* Run plans (Algorithm 1 per plan).  n_plans > 1 runs them as one batch:

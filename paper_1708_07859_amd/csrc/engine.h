@@ -50,6 +50,7 @@ struct lh_plan_s {
   uint32_t agg = LH_AGG_COUNT;
   uint32_t policy = LH_POLICY_PLAIN;
   bool case_prefix = false;                 // outputs = first n_out attributes of the order
+  uint32_t group_impl = 0;                  // GROUP BY outside the prefix: 0 auto, 1 sort, 2 hash, 3 dense
   int32_t exact_lsb = 0;
   uint32_t exact_digits = 0;
   double cost = 0.0;

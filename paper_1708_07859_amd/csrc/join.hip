@@ -105,8 +105,7 @@ struct LeafAtom {
   int32_t part;           // participant index at the leaf attribute, or -1
   const uint32_t* run;    // bag: run offsets of the last level; null: one row per node
   const double* anno;     // SUM factor column (trie order), or null
-  const uint32_t* gmeta;  // GROUP BY meta column (trie order), or null
-  int32_t gcol;           // output column of gmeta
+  const uint32_t* gmeta;  // a GROUP BY meta column of this atom (trie order), or null
   uint32_t expand;        // iterate the node's rows (anno or gmeta present)
 };
 
@@ -124,10 +123,20 @@ struct LeafArgs {
   uint32_t n_cols;
   uint32_t* col_out[MAXV + MAXA];
   int32_t col_src[MAXV + MAXA];  // >= 0: frontier out column; -1: leaf value; -2: group meta
+  const uint32_t* gm_col[MAXV + MAXA];  // group meta column of output column c (trie order)
+  int32_t gm_atom[MAXV + MAXA];         // its atom
   uint64_t* mult_out;
   double* hi_out;
   double* lo_out;
   uint32_t* err;
+  // tuples aggregated in place (GROUP BY outside the order's prefix):
+  // gmode 1 = dense array indexed by the mixed-radix key, 2 = hash table
+  // (col_out = its key columns, gtag = slot states); counts in gcount and
+  // exact digits in gacc at stride D
+  uint32_t gmode;
+  uint32_t* gtag;
+  uint64_t gmask;
+  uint64_t radix[MAXV + MAXA];
 };
 
 struct ElemArgs {
@@ -159,7 +168,23 @@ struct ElemArgs {
   LeafArgs leaf;
 };
 
-enum { M_COUNT = 0, M_FILL = 1, M_LEAF_A = 2, M_LEAF_B_COUNT = 3, M_LEAF_B_FILL = 4, M_LEAF_COUNT = 5 };
+enum { M_COUNT = 0, M_FILL = 1, M_LEAF_A = 2, M_LEAF_B_COUNT = 3, M_LEAF_B_FILL = 4, M_LEAF_COUNT = 5,
+       M_LEAF_B_AGG = 6 };
+
+// Hash-table slot states (GROUP BY upserts)
+constexpr uint32_t SLOT_EMPTY = 0, SLOT_BUSY = 1, SLOT_READY = 2;
+// A slot being written is re-read at most this many times before the
+// upsert gives up and flags an error (the writer publishes right after
+// its claim, so the bound is never reached in a correct run)
+constexpr uint32_t SLOT_SPIN_MAX = 1u << 22;
+constexpr uint32_t ERR_TABLE_FULL = 2u, ERR_SLOT_SPIN = 4u;
+
+__device__ __forceinline__ uint64_t key_mix(uint64_t h, uint32_t v) {
+  h ^= v;
+  h *= 0xff51afd7ed558ccdull;
+  h ^= h >> 33;
+  return h;
+}
 
 struct WorkArgs {
   uint32_t np;
@@ -554,9 +579,10 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
               else if (src == -1) v = x[it];
               else {
                 v = 0;
+                const int32_t ga = L.gm_atom[c];
 #pragma unroll
                 for (int at = 0; at < MAXA; at++)
-                  if (at < (int)L.n_atoms && L.at[at].gmeta && L.at[at].gcol == (int32_t)c) v = L.at[at].gmeta[cur[at]];
+                  if (at == ga) v = L.gm_col[c][cur[at]];
               }
               L.col_out[c][o] = v;
             }
@@ -573,9 +599,93 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
         off += tot;
       }
       __syncthreads();
+    } else if (MODE == M_LEAF_B_AGG) {
+      // once the hash table is known to be too small the pass is wasted:
+      // skip the remaining units (the host sizes the table and reruns)
+      const bool table_full = L.gmode == 2 &&
+          (__hip_atomic_load(L.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_TABLE_FULL);
+#pragma unroll
+      for (int it = 0; it < U_IT; it++) {
+        if (!hit[it] || table_full) continue;
+        HitRows h;
+        leaf_rows(L, r, ppos[it], h);
+        if (!combos(L, h)) continue;
+        uint32_t cur[MAXA];
+#pragma unroll
+        for (int at = 0; at < MAXA; at++) cur[at] = h.rb[at];
+        do {
+          auto val = [&](uint32_t c) -> uint32_t {
+            const int32_t src = L.col_src[c];
+            if (src >= 0) return a.outv_in[src][r];
+            if (src == -1) return x[it];
+            uint32_t v = 0;
+            const int32_t ga = L.gm_atom[c];
+#pragma unroll
+            for (int at = 0; at < MAXA; at++)
+              if (at == ga) v = L.gm_col[c][cur[at]];
+            return v;
+          };
+          uint64_t slot = 0;
+          bool ok = true;
+          if (L.gmode == 1) {
+            for (uint32_t c = 0; c < L.n_cols; c++) slot = slot * L.radix[c] + val(c);
+          } else {
+            uint64_t hs = 0x9e3779b97f4a7c15ull;
+            for (uint32_t c = 0; c < L.n_cols; c++) hs = key_mix(hs, val(c));
+            slot = hs & L.gmask;
+            ok = false;
+            // a probe run longer than this means the table is too full: the
+            // host grows it and runs the pass again
+            const uint64_t max_probes = L.gmask < 256 ? L.gmask + 1 : 256;
+            uint64_t probes = 0;
+            uint32_t spins = 0;
+            while (probes < max_probes) {
+              const uint32_t t = __hip_atomic_load(&L.gtag[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+              if (t == SLOT_READY) {
+                bool same = true;
+                for (uint32_t c = 0; c < L.n_cols && same; c++) same = L.col_out[c][slot] == val(c);
+                if (same) {
+                  ok = true;
+                  break;
+                }
+                slot = (slot + 1) & L.gmask;
+                probes++;
+                continue;
+              }
+              if (t == SLOT_EMPTY && atomicCAS(&L.gtag[slot], SLOT_EMPTY, SLOT_BUSY) == SLOT_EMPTY) {
+                for (uint32_t c = 0; c < L.n_cols; c++) L.col_out[c][slot] = val(c);
+                __hip_atomic_store(&L.gtag[slot], SLOT_READY, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                ok = true;
+                break;
+              }
+              // claimed by another upsert that is writing its key: read again
+              if (++spins > SLOT_SPIN_MAX) break;
+            }
+            if (!ok) {
+              atomicOr(L.err, spins > SLOT_SPIN_MAX ? ERR_SLOT_SPIN : ERR_TABLE_FULL);
+              break;  // this lane's remaining tuples wait for the rerun
+            }
+          }
+          if (ok) {
+            atomicAdd((unsigned long long*)&L.gcount[slot], (unsigned long long)h.mult);
+            if (L.sum) {
+              double hi, lo;
+              term_of(L, cur, hi, lo);
+              RegAcc t;
+              t.clear();
+              bool fits = t.add(hi, L.lsb, L.D, (int64_t)h.mult);
+              fits = t.add(lo, L.lsb, L.D, (int64_t)h.mult) && fits;
+              if (!fits) bad = 1;
+              for (uint32_t q = 0; q < L.D; q++)
+                if (t.s[q]) atomicAdd((unsigned long long*)&L.gacc[slot * L.D + q], (unsigned long long)t.s[q]);
+            }
+          }
+        } while (next_combo(L, h, cur));
+      }
     }
   }
 
+  if (MODE == M_LEAF_B_AGG && bad) atomicOr(L.err, 1u);
   if (LEAF_AGG) {
     if (bad) atomicOr(L.err, 1u);
     if (one_group) {
@@ -974,6 +1084,56 @@ __global__ void k_nonzero_flags(const uint64_t* cnt, uint64_t n, uint32_t* flags
     flags[i] = cnt[i] != 0 ? 1u : 0u;
 }
 
+__global__ void k_tag_flags(const uint32_t* tag, uint64_t n, uint32_t* flags) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    flags[i] = tag[i] == SLOT_READY ? 1u : 0u;
+}
+
+struct GroupFin {
+  const uint64_t* cnt;
+  const int64_t* acc;       // stride D
+  const uint64_t* off;      // dense: exclusive scan of the non-empty flags
+  const uint32_t* sid;      // hash: table slot of each group
+  const uint32_t* perm;     // hash: groups in key order
+  uint32_t n_cols;
+  const uint32_t* key_in[MAXV + MAXA];  // hash: keys of each group (sid order)
+  uint64_t radix[MAXV + MAXA];          // dense: mixed radix of the index
+  uint32_t* key_out[MAXV + MAXA];
+  uint64_t* count_out;
+  double* sum_out;
+  uint32_t sum;
+  int32_t lsb;
+  uint32_t D;
+  uint32_t* err;
+};
+
+// Dense GROUP BY: a non-empty index becomes the next output row; its keys
+// are the digits of the index, so rows come out in key order.
+__global__ void k_dense_finalize(GroupFin f, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    if (f.off[i + 1] == f.off[i]) continue;
+    const uint64_t o = f.off[i];
+    uint64_t idx = i;
+    for (int c = (int)f.n_cols - 1; c >= 0; c--) {
+      f.key_out[c][o] = (uint32_t)(idx % f.radix[c]);
+      idx /= f.radix[c];
+    }
+    f.count_out[o] = f.cnt[i];
+    if (f.sum) f.sum_out[o] = exact_round(f.acc + i * f.D, f.D, f.lsb, f.err);
+  }
+}
+
+// Hash GROUP BY: output row i is the i-th group in key order.
+__global__ void k_hash_finalize(GroupFin f, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = f.perm[i];
+    const uint64_t slot = f.sid[j];
+    for (uint32_t c = 0; c < f.n_cols; c++) f.key_out[c][i] = f.key_in[c][j];
+    f.count_out[i] = f.cnt[slot];
+    if (f.sum) f.sum_out[i] = exact_round(f.acc + slot * f.D, f.D, f.lsb, f.err);
+  }
+}
+
 struct FinA {
   const uint64_t* gcount;
   const int64_t* gacc;
@@ -1221,6 +1381,183 @@ void step(const lh_plan_t* p, uint32_t d, Frontier& F, hipStream_t s) {
 
 }  // namespace
 
+// GROUP BY outside the order's prefix, aggregated where the leaf finds the
+// tuples (section 5): a dense array over the key space when the expected
+// output is dense, else a device-wide hash table (open addressing, linear
+// probing); either way no tuple is materialized.  Returns false when the
+// sort-based path should run instead (asked for, or the table would not
+// fit).
+bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t nblk, uint64_t total,
+                    uint32_t no, uint32_t n_cols, bool is_sum, uint32_t D, DBuf<uint32_t>& err,
+                    lh_result_impl* res, hipStream_t s) {
+  uint32_t impl = p->group_impl;
+  if (impl == LH_GROUP_SORT >> 4) return false;
+  const uint32_t leaf = p->n_attrs - 1;
+  LeafArgs& L = a.leaf;
+  // key space: the largest value of every output column
+  std::vector<uint32_t> bits(n_cols);
+  uint64_t space = 1;
+  for (uint32_t c = 0; c < n_cols; c++) {
+    uint32_t mx = 0;
+    if (c < no) {
+      const uint32_t attr = p->out_attrs[c];
+      if (p->depth_of[attr] == leaf) {
+        L.col_src[c] = -1;
+        const Participant& P = p->parts[leaf][0];
+        const Level& lv = p->atoms[P.atom].trie->lv[P.level];
+        mx = lv.n ? reduce_max_u32(lv.keys.p, lv.n, s) : 0;
+      } else {
+        L.col_src[c] = (int32_t)c;
+        mx = F.n ? reduce_max_u32(F.outv[c].p, F.n, s) : 0;
+      }
+    } else {
+      L.col_src[c] = -2;
+      const lh_group_col& G = p->groups[c - no];
+      const lh_trie* T = p->atoms[G.atom].trie;
+      mx = T->n_rows ? reduce_max_u32(T->meta[G.meta_col].p, T->n_rows, s) : 0;
+    }
+    L.radix[c] = (uint64_t)mx + 1;
+    bits[c] = bitlen(mx);
+    space = (space > (1ull << 62) / L.radix[c]) ? (1ull << 62) : space * L.radix[c];
+  }
+  const uint64_t dense_bytes = 8 + (is_sum ? 8ull * D : 0);
+  const bool dense_fits = space <= (1ull << 27) && space * dense_bytes <= (2ull << 30);
+  if (impl == 0) impl = (dense_fits && space <= std::max<uint64_t>(4 * total, 1u << 16)) ? 3 : 2;
+  if (impl == 3 && !dense_fits) fail(LH_ERR_UNSUPPORTED, "join: the GROUP BY key space is too large for a dense array");
+  const uint64_t hash_bytes = 4 + 4ull * n_cols + 8 + (is_sum ? 8ull * D : 0);
+  uint64_t cap = 1024;
+  if (impl == 2) {
+    const uint64_t want = 2 * std::min<uint64_t>(space, std::max<uint64_t>(total, 512));
+    while (cap < want) cap <<= 1;
+    if (cap > (1ull << 31) || cap * hash_bytes > (16ull << 30)) return false;
+  }
+  const uint64_t slots = impl == 3 ? space : cap;
+  L.n_cols = n_cols;
+  L.gmode = impl == 3 ? 1u : 2u;
+  DBuf<uint64_t> cnt;
+  DBuf<int64_t> acc;
+  DBuf<uint32_t> tag;
+  std::vector<DBuf<uint32_t>> tkeys;
+  bool counted = false;
+  for (;;) {
+    const uint64_t n = impl == 3 ? space : cap;
+    cnt.alloc(n, s);
+    acc.alloc(is_sum ? n * D : 0, s);
+    LH_HIP(hipMemsetAsync(cnt.p, 0, n * sizeof(uint64_t), s));
+    if (is_sum) LH_HIP(hipMemsetAsync(acc.p, 0, n * D * sizeof(int64_t), s));
+    L.gcount = cnt.p;
+    L.gacc = acc.p;
+    if (impl == 2) {
+      tag.alloc(n, s);
+      LH_HIP(hipMemsetAsync(tag.p, 0, n * sizeof(uint32_t), s));
+      tkeys.clear();
+      for (uint32_t c = 0; c < n_cols; c++) {
+        tkeys.emplace_back(n, s);
+        L.col_out[c] = tkeys.back().p;
+      }
+      L.gtag = tag.p;
+      L.gmask = n - 1;
+    }
+    if (total) {
+      ProfScope ps(impl == 3 ? "leaf_group_dense" : "leaf_group_hash", s, F.n, total);
+      k_elem<M_LEAF_B_AGG><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+      LH_HIP(hipGetLastError());
+    }
+    const uint32_t e = read_scalar(err.p, s);
+    if (e & ERR_SLOT_SPIN) fail(LH_ERR_DEVICE, "join: a GROUP BY hash slot was never published");
+    if (impl == 2 && (e & ERR_TABLE_FULL)) {
+      // more groups than the estimate: count the tuples exactly once and
+      // size the table for them (later overflows double it), from scratch
+      fill_u32(err.p, 0, 1, s);
+      uint64_t want = 2 * cap;
+      if (!counted) {
+        counted = true;
+        DBuf<uint32_t> bcnt(nblk, s);
+        DBuf<uint64_t> boff(nblk + 1, s);
+        a.blk_cnt = bcnt.p;
+        {
+          ProfScope ps("leaf_emit_count", s, F.n, total);
+          k_elem<M_LEAF_B_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+        }
+        LH_HIP(hipGetLastError());
+        const uint64_t n_emit = scan_u32_to_u64(bcnt.p, boff.p, nblk, s);
+        want = std::max(want, 2 * std::min<uint64_t>(space, n_emit));
+      }
+      while (cap < want) cap <<= 1;
+      if (cap > (1ull << 31) || cap * hash_bytes > (16ull << 30)) return false;
+      continue;
+    }
+    break;
+  }
+  (void)slots;
+  GroupFin f{};
+  f.cnt = cnt.p;
+  f.acc = acc.p;
+  f.n_cols = n_cols;
+  f.sum = is_sum ? 1u : 0u;
+  f.lsb = L.lsb;
+  f.D = D;
+  f.err = err.p;
+  uint64_t n_groups = 0;
+  lh_result& R = res->pub;
+  if (impl == 3) {
+    DBuf<uint32_t> flags(space, s);
+    DBuf<uint64_t> off(space + 1, s);
+    k_nonzero_flags<<<grid_for(space), 256, 0, s>>>(cnt.p, space, flags.p);
+    LH_HIP(hipGetLastError());
+    n_groups = scan_u32_to_u64(flags.p, off.p, space, s);
+    res->cols.resize(n_cols);
+    for (uint32_t c = 0; c < n_cols; c++) {
+      res->cols[c].alloc(n_groups, s);
+      f.key_out[c] = res->cols[c].p;
+      f.radix[c] = L.radix[c];
+    }
+    res->counts.alloc(n_groups, s);
+    if (is_sum) res->sums.alloc(n_groups, s);
+    f.count_out = res->counts.p;
+    f.sum_out = res->sums.p;
+    f.off = off.p;
+    if (n_groups) {
+      k_dense_finalize<<<grid_for(space), 256, 0, s>>>(f, space);
+      LH_HIP(hipGetLastError());
+    }
+    R.group_impl = 3;
+  } else {
+    DBuf<uint32_t> flags(cap, s), sid(cap, s);
+    k_tag_flags<<<grid_for(cap), 256, 0, s>>>(tag.p, cap, flags.p);
+    LH_HIP(hipGetLastError());
+    n_groups = select_flagged(flags.p, cap, sid.p, s);
+    std::vector<DBuf<uint32_t>> gk(n_cols);
+    std::vector<const uint32_t*> gp(n_cols);
+    for (uint32_t c = 0; c < n_cols; c++) {
+      gk[c].alloc(n_groups, s);
+      if (n_groups) gather_u32(tkeys[c].p, sid.p, gk[c].p, n_groups, s);
+      gp[c] = gk[c].p;
+      f.key_in[c] = gk[c].p;
+    }
+    DBuf<uint32_t> perm(n_groups, s);
+    if (n_groups) lex_sort_perm(gp.data(), bits.data(), n_cols, n_groups, perm.p, s);
+    res->cols.resize(n_cols);
+    for (uint32_t c = 0; c < n_cols; c++) {
+      res->cols[c].alloc(n_groups, s);
+      f.key_out[c] = res->cols[c].p;
+    }
+    res->counts.alloc(n_groups, s);
+    if (is_sum) res->sums.alloc(n_groups, s);
+    f.count_out = res->counts.p;
+    f.sum_out = res->sums.p;
+    f.sid = sid.p;
+    f.perm = perm.p;
+    if (n_groups) {
+      k_hash_finalize<<<grid_for(n_groups), 256, 0, s>>>(f, n_groups);
+      LH_HIP(hipGetLastError());
+    }
+    R.group_impl = 2;
+  }
+  R.n_rows = n_groups;
+  return true;
+}
+
 lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
   std::unique_ptr<lh_result_impl> res(new lh_result_impl());
   memset(&res->pub, 0, sizeof(res->pub));
@@ -1287,11 +1624,13 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
     LA.run = A.bag ? A.trie->lv[A.n_levels - 1].offs.p : nullptr;
     LA.anno = (is_sum && A.anno >= 0) ? A.trie->annos[A.anno].p : nullptr;
     LA.gmeta = nullptr;
-    LA.gcol = -1;
     for (uint32_t g = 0; g < ngc; g++)
       if (p->groups[g].atom == e) {
+        // every meta column of the atom that is grouped on has its own
+        // output column
         LA.gmeta = A.trie->meta[p->groups[g].meta_col].p;
-        LA.gcol = (int32_t)(no + g);
+        L.gm_col[no + g] = LA.gmeta;
+        L.gm_atom[no + g] = (int32_t)e;
       }
     LA.expand = (LA.anno || LA.gmeta) ? 1u : 0u;
     if (LA.part >= 0 && (A.bag || LA.expand)) need |= 1u << LA.part;
@@ -1397,8 +1736,9 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
       LH_HIP(hipGetLastError());
     }
     R.n_rows = n_out_rows;
-  } else {
+  } else if (!group_in_place(p, F, a, nblk, total, no, n_cols, is_sum, D, err, res.get(), s)) {
     // materialize leaf tuples keyed by the output columns, sort, reduce
+    R.group_impl = 1;
     uint64_t n_emit = 0;
     DBuf<uint64_t> boff;
     if (total) {

@@ -110,6 +110,7 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
   p->n_attrs = q->n_attrs;
   p->agg = q->agg;
   p->policy = q->policy & LH_POLICY_MASK;
+  p->group_impl = (q->policy & LH_GROUP_MASK) >> 4;
   uint32_t covered = 0;
   int annotated = 0;
   for (uint32_t e = 0; e < q->n_atoms; e++) {

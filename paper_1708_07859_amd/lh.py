@@ -20,6 +20,8 @@ LAYOUT = {"plain": 0x00, "uint": 0x10, "bitset": 0x20, "learned": 0x30}
 LH_AGG_COUNT, LH_AGG_SUM = 0, 1
 FILTER_KIND = {"eq_key": 0, "eq_meta": 1, "range_anno": 2, "range_meta": 3}
 POLICY = {"plain": 0, "learned": 1, "fixed": 2}
+GROUP_IMPL = {"auto": 0x00, "sort": 0x10, "hash": 0x20, "dense": 0x30}
+GROUP_IMPL_NAME = {0: "streamed", 1: "sort", 2: "hash", 3: "dense"}
 LH_MAX_KEYS = 8
 
 
@@ -76,6 +78,7 @@ class Result(C.Structure):
         ("sums", C.c_void_p),
         ("exact", C.c_uint32),
         ("n_join_tuples", C.c_uint64),
+        ("group_impl", C.c_uint32),
     ]
 
 
@@ -326,7 +329,8 @@ class Plan:
             pass
 
 
-def _query(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None, policy="plain"):
+def _query(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None, policy="plain",
+           group_impl="auto"):
     """An lh_query and the ctypes arrays it points into (keep them alive)."""
     catoms = (Atom * len(atoms))()
     keep = [catoms]
@@ -366,14 +370,14 @@ def _query(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order
         ao = (C.c_uint32 * len(attr_order))(*attr_order)
         keep.append(ao)
         q.attr_order = C.cast(ao, C.POINTER(C.c_uint32))
-    q.policy = POLICY[policy]
+    q.policy = POLICY[policy] | GROUP_IMPL[group_impl]
     return q, keep
 
 
 def plan(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None, policy="plain",
-         stream=None):
+         stream=None, group_impl="auto"):
     """lh_plan.  atoms: [(Trie, attr_of_key list, anno index or -1)]."""
-    q, keep = _query(n_attrs, atoms, out, group, agg, filters, attr_order, policy)
+    q, keep = _query(n_attrs, atoms, out, group, agg, filters, attr_order, policy, group_impl)
     out_h = C.c_void_p()
     _check(lib.lh_plan(C.byref(q), stream if stream is not None else current_stream(), C.byref(out_h)))
     return Plan(out_h.value, [a[0] for a in atoms])
@@ -398,7 +402,8 @@ class JoinResult:
         _check(lib.lh_result_read(self.ptr, kp, counts.ctypes.data,
                                   sums.ctypes.data if (sums is not None and n) else None))
         keys = np.stack(cols, axis=1) if w else np.zeros((n, 0), np.uint32)
-        return {"keys": keys, "counts": counts, "sums": sums, "n_join": int(r.n_join_tuples), "exact": r.exact}
+        return {"keys": keys, "counts": counts, "sums": sums, "n_join": int(r.n_join_tuples), "exact": r.exact,
+                "group_impl": GROUP_IMPL_NAME.get(r.group_impl, r.group_impl)}
 
     def free(self):
         if self.ptr:
@@ -612,10 +617,10 @@ def ghd_for_query(n_attrs, atoms, out=(), group=(), agg="count", filters=()):
 
 
 def ghd_join_aggregate(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None,
-                       policy="plain", ghd=None, stream=None):
+                       policy="plain", ghd=None, stream=None, group_impl="auto"):
     """lh_ghd_join_aggregate; ghd: a dict with parent/edges/pushed lists, or
     None for the library's choice."""
-    q, keep = _query(n_attrs, atoms, out, group, agg, filters, attr_order, policy)
+    q, keep = _query(n_attrs, atoms, out, group, agg, filters, attr_order, policy, group_impl)
     gp = C.byref(_ghd_struct(ghd)) if ghd is not None else None
     res = C.POINTER(Result)()
     _check(lib.lh_ghd_join_aggregate(C.byref(q), gp, stream if stream is not None else current_stream(),
@@ -627,7 +632,8 @@ def ghd_join_aggregate(n_attrs, atoms, out=(), group=(), agg="count", filters=()
 # query dictionaries (the format documented in tests/queries.py)
 # --------------------------------------------------------------------------
 
-def run_query(query, attr_order=None, policy="plain", layout="plain", return_plan_info=False, ghd=False):
+def run_query(query, attr_order=None, policy="plain", layout="plain", return_plan_info=False, ghd=False,
+              group_impl="auto"):
     """Build one trie per distinct relation of the query, plan, run, and
     copy the result to host in the format {keys, counts, sums, n_join}.
     ghd=False runs one plan; ghd=None runs the library's decomposition, a
@@ -642,7 +648,7 @@ def run_query(query, attr_order=None, policy="plain", layout="plain", return_pla
                                       layout=layout)
         atoms.append((tries[ident], list(a["attrs"]), int(a.get("anno", -1))))
     args = dict(out=query.get("out", []), group=query.get("group", []), agg=query.get("agg", "count"),
-                filters=query.get("filters", []), attr_order=attr_order, policy=policy)
+                filters=query.get("filters", []), attr_order=attr_order, policy=policy, group_impl=group_impl)
     p = None
     try:
         if ghd is False:
