@@ -91,7 +91,7 @@ def main():
                     help="layout of the plain-policy run")
     ap.add_argument("--policy", default="both", choices=["both", "plain", "learned"],
                     help="both: time the plain rule, then the learned cost model (reported)")
-    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--card", type=int, default=1_000_000)
@@ -119,6 +119,8 @@ def main():
         return bench_intersect(args, lh, torch, synth)
     if args.workload == "q5":
         return bench_q5(args, lh, torch, synth)
+    if args.workload == "groupby":
+        return bench_groupby(args, lh, torch, synth)
     log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
     t0 = time.perf_counter()
     lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
@@ -471,6 +473,97 @@ def bench_q5(args, lh, torch, synth):
                               "fhw": chosen["fhw"]},
                       "variants": results,
                       "chosen_over_one_node": results["one node"]["ms_per_step"] / head["ms_per_step"]}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_groupby(args, lh, torch, synth):
+    """GROUP BY implementations (section 5, Fig. 6 shapes).
+
+    Key union: R(x,y) |x| S(y,z), SUM(R.v * S.w) GROUP BY z under the order
+    x,y,z, so the leaf's z values are unioned by a GROUP BY; about 10^7 join
+    tuples; z drawn from a random subset of [0, 10^6) whose size sets the
+    output density (Fig. 6a).  Wide key: the same join grouped by x, z and
+    three meta columns (a five-value key, Fig. 6c) with about 10^6 groups.
+    Each implementation runs the same plan; only lh_join_aggregate is
+    timed."""
+    import numpy as np
+
+    rng = synth.rng_for(31)
+    n_r, n_s, dom_x, dom_y, zr = 10_000, 1_000_000, 1000, 1000, 1_000_000
+    rx = rng.integers(0, dom_x, n_r).astype(np.uint32)
+    ry = rng.integers(0, dom_y, n_r).astype(np.uint32)
+    rv = rng.integers(-8, 9, n_r) / 8.0
+    sy = rng.integers(0, dom_y, n_s).astype(np.uint32)
+    sw = synth.uniform_pm1(rng, n_s)
+    rm = [rng.integers(0, 16, n_r).astype(np.uint32), rng.integers(0, 64, n_r).astype(np.uint32)]
+    sm = [rng.integers(0, 8, n_s).astype(np.uint32)]
+    tr = lh.trie_build([lh.to_device(rx), lh.to_device(ry)], [lh.to_device(rv)], [lh.to_device(m) for m in rm],
+                       bag=True)
+    impls = ["sort", "hash", "dense", "auto"]
+
+    def time_plan(p):
+        for _ in range(max(1, args.warmup)):
+            r = lh.join_aggregate([p])[0]
+            out = r.to_host()
+            r.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lh.join_aggregate([p])[0].free()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1000 / args.steps, out
+
+    sweep = {}
+    for density in [1e-4, 1e-3, 1e-2, 1e-1, 1.0]:
+        values = rng.choice(zr, max(1, int(density * zr)), replace=False).astype(np.uint32)
+        sz = values[rng.integers(0, len(values), n_s)]
+        ts = lh.trie_build([lh.to_device(sy), lh.to_device(sz)], [lh.to_device(sw)], bag=True)
+        row, ref = {}, None
+        for impl in impls:
+            p = lh.plan(3, [(tr, [0, 1], 0), (ts, [1, 2], 0)], out=[2], agg="sum", attr_order=[0, 1, 2],
+                        policy="fixed", group_impl=impl)
+            ms, out = time_plan(p)
+            p.free()
+            if ref is None:
+                ref = out
+            assert np.array_equal(out["keys"], ref["keys"]) and np.array_equal(out["counts"], ref["counts"])
+            assert np.array_equal(out["sums"].view(np.uint64), ref["sums"].view(np.uint64))
+            row[impl] = round(ms, 3)
+            if impl == "auto":
+                row["auto_chose"] = out["group_impl"]
+        row["groups"] = len(ref["counts"])
+        row["join_tuples"] = int(ref["counts"].sum())
+        sweep[f"density {density:g}"] = row
+        log(f"key union, output density {density:g}: {row}")
+        ts.free()
+    # wide key
+    sz = rng.integers(0, 4096, n_s).astype(np.uint32)
+    ts = lh.trie_build([lh.to_device(sy), lh.to_device(sz)], [lh.to_device(sw)], [lh.to_device(sm[0])], bag=True)
+    wide, ref = {}, None
+    for impl in ["sort", "hash", "auto"]:
+        p = lh.plan(3, [(tr, [0, 1], 0), (ts, [1, 2], 0)], out=[0, 2], group=[(0, 0), (0, 1), (1, 0)], agg="sum",
+                    attr_order=[0, 1, 2], policy="fixed", group_impl=impl)
+        ms, out = time_plan(p)
+        p.free()
+        if ref is None:
+            ref = out
+        assert np.array_equal(out["keys"], ref["keys"]) and np.array_equal(out["counts"], ref["counts"])
+        wide[impl] = round(ms, 3)
+        if impl == "auto":
+            wide["auto_chose"] = out["group_impl"]
+    wide["groups"] = len(ref["counts"])
+    wide["join_tuples"] = int(ref["counts"].sum())
+    log(f"wide key (5 values): {wide}")
+    ts.free()
+    tr.free()
+    head = sweep["density 0.01"]
+    out = {"metric": "join-aggregate tuples/s, GROUP BY outside the order's prefix", "unit": "tuples/s",
+           "value": head["join_tuples"] / (head["auto"] / 1000), "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["auto"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32+f64", "data": "synthetic",
+           "config": {"workload": "R(x,y) join S(y,z), SUM GROUP BY z under order x,y,z; 10^4 x 10^6 rows, "
+                                  "about 10^7 join tuples; z from a subset of [0, 10^6)",
+                      "key_union_ms": sweep, "wide_key_ms": wide}}
     print(json.dumps(out), flush=True)
 
 

@@ -137,7 +137,13 @@ struct LeafArgs {
   uint32_t* gtag;
   uint64_t gmask;
   uint64_t radix[MAXV + MAXA];
+  // keys of at most 63 bits are packed into one word (column 0 highest),
+  // claimed with one compare-and-swap; gkey64 is then the table
+  uint64_t* gkey64;
+  uint32_t gshift[MAXV + MAXA];
 };
+
+constexpr uint64_t KEY64_EMPTY = ~0ull;
 
 struct ElemArgs {
   uint32_t np;
@@ -629,6 +635,33 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
           bool ok = true;
           if (L.gmode == 1) {
             for (uint32_t c = 0; c < L.n_cols; c++) slot = slot * L.radix[c] + val(c);
+          } else if (L.gkey64) {
+            uint64_t k = 0;
+            for (uint32_t c = 0; c < L.n_cols; c++) k |= (uint64_t)val(c) << L.gshift[c];
+            uint64_t hs = k * 0x9e3779b97f4a7c15ull;
+            hs ^= hs >> 31;
+            slot = hs & L.gmask;
+            ok = false;
+            const uint64_t max_probes = L.gmask < 256 ? L.gmask + 1 : 256;
+            for (uint64_t probes = 0; probes < max_probes; probes++) {
+              uint64_t cur = L.gkey64[slot];
+              if (cur == KEY64_EMPTY) {
+                // the swap returns the word's true value, whatever a cached
+                // read said
+                cur = atomicCAS((unsigned long long*)&L.gkey64[slot], (unsigned long long)KEY64_EMPTY,
+                                (unsigned long long)k);
+                if (cur == KEY64_EMPTY) cur = k;
+              }
+              if (cur == k) {
+                ok = true;
+                break;
+              }
+              slot = (slot + 1) & L.gmask;
+            }
+            if (!ok) {
+              atomicOr(L.err, ERR_TABLE_FULL);
+              break;
+            }
           } else {
             uint64_t hs = 0x9e3779b97f4a7c15ull;
             for (uint32_t c = 0; c < L.n_cols; c++) hs = key_mix(hs, val(c));
@@ -1089,6 +1122,28 @@ __global__ void k_tag_flags(const uint32_t* tag, uint64_t n, uint32_t* flags) {
     flags[i] = tag[i] == SLOT_READY ? 1u : 0u;
 }
 
+__global__ void k_key64_flags(const uint64_t* key, uint64_t n, uint32_t* flags) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    flags[i] = key[i] != KEY64_EMPTY ? 1u : 0u;
+}
+
+struct UnpackArgs {
+  const uint64_t* key;
+  const uint32_t* sid;
+  uint32_t n_cols;
+  uint32_t shift[MAXV + MAXA];
+  uint32_t bits[MAXV + MAXA];
+  uint32_t* out[MAXV + MAXA];
+};
+
+__global__ void k_unpack_keys(UnpackArgs a, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = a.key[a.sid[i]];
+    for (uint32_t c = 0; c < a.n_cols; c++)
+      a.out[c][i] = a.bits[c] ? (uint32_t)((k >> a.shift[c]) & ((1ull << a.bits[c]) - 1)) : 0u;
+  }
+}
+
 struct GroupFin {
   const uint64_t* cnt;
   const int64_t* acc;       // stride D
@@ -1424,7 +1479,7 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
   const bool dense_fits = space <= (1ull << 27) && space * dense_bytes <= (2ull << 30);
   if (impl == 0) impl = (dense_fits && space <= std::max<uint64_t>(4 * total, 1u << 16)) ? 3 : 2;
   if (impl == 3 && !dense_fits) fail(LH_ERR_UNSUPPORTED, "join: the GROUP BY key space is too large for a dense array");
-  const uint64_t hash_bytes = 4 + 4ull * n_cols + 8 + (is_sum ? 8ull * D : 0);
+  const uint64_t hash_bytes = 4 + 4ull * n_cols + 8 + (is_sum ? 8ull * D : 0);  // an upper bound
   uint64_t cap = 1024;
   if (impl == 2) {
     const uint64_t want = 2 * std::min<uint64_t>(space, std::max<uint64_t>(total, 512));
@@ -1438,7 +1493,20 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
   DBuf<int64_t> acc;
   DBuf<uint32_t> tag;
   std::vector<DBuf<uint32_t>> tkeys;
+  DBuf<uint64_t> key64;
   bool counted = false;
+  // keys of at most 63 bits: one word per slot, column 0 most significant
+  uint32_t key_bits = 0;
+  for (uint32_t c = 0; c < n_cols; c++) key_bits += bits[c];
+  const bool packed = key_bits <= 63;
+  L.gkey64 = nullptr;
+  if (packed) {
+    uint32_t sh = key_bits;
+    for (uint32_t c = 0; c < n_cols; c++) {
+      sh -= bits[c];
+      L.gshift[c] = sh;
+    }
+  }
   for (;;) {
     const uint64_t n = impl == 3 ? space : cap;
     cnt.alloc(n, s);
@@ -1447,7 +1515,12 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
     if (is_sum) LH_HIP(hipMemsetAsync(acc.p, 0, n * D * sizeof(int64_t), s));
     L.gcount = cnt.p;
     L.gacc = acc.p;
-    if (impl == 2) {
+    if (impl == 2 && packed) {
+      key64.alloc(n, s);
+      LH_HIP(hipMemsetAsync(key64.p, 0xff, n * sizeof(uint64_t), s));
+      L.gkey64 = key64.p;
+      L.gmask = n - 1;
+    } else if (impl == 2) {
       tag.alloc(n, s);
       LH_HIP(hipMemsetAsync(tag.p, 0, n * sizeof(uint32_t), s));
       tkeys.clear();
@@ -1524,16 +1597,28 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
     R.group_impl = 3;
   } else {
     DBuf<uint32_t> flags(cap, s), sid(cap, s);
-    k_tag_flags<<<grid_for(cap), 256, 0, s>>>(tag.p, cap, flags.p);
+    if (packed) k_key64_flags<<<grid_for(cap), 256, 0, s>>>(key64.p, cap, flags.p);
+    else k_tag_flags<<<grid_for(cap), 256, 0, s>>>(tag.p, cap, flags.p);
     LH_HIP(hipGetLastError());
     n_groups = select_flagged(flags.p, cap, sid.p, s);
     std::vector<DBuf<uint32_t>> gk(n_cols);
     std::vector<const uint32_t*> gp(n_cols);
+    UnpackArgs ua{};
+    ua.key = key64.p;
+    ua.sid = sid.p;
+    ua.n_cols = n_cols;
     for (uint32_t c = 0; c < n_cols; c++) {
       gk[c].alloc(n_groups, s);
-      if (n_groups) gather_u32(tkeys[c].p, sid.p, gk[c].p, n_groups, s);
+      if (n_groups && !packed) gather_u32(tkeys[c].p, sid.p, gk[c].p, n_groups, s);
       gp[c] = gk[c].p;
       f.key_in[c] = gk[c].p;
+      ua.shift[c] = L.gshift[c];
+      ua.bits[c] = bits[c];
+      ua.out[c] = gk[c].p;
+    }
+    if (n_groups && packed) {
+      k_unpack_keys<<<grid_for(n_groups), 256, 0, s>>>(ua, n_groups);
+      LH_HIP(hipGetLastError());
     }
     DBuf<uint32_t> perm(n_groups, s);
     if (n_groups) lex_sort_perm(gp.data(), bits.data(), n_cols, n_groups, perm.p, s);

@@ -154,3 +154,26 @@ def test_no_device_memory_leaks(lh):
     for impl in IMPLS:
         lh.run_query(q, attr_order=[0, 1, 2], policy="fixed", group_impl=impl)
     assert lh.live_allocations() == before
+
+
+@pytest.mark.parametrize("impl", ["hash", "auto", "sort"])
+def test_group_key_wider_than_64_bits(lh, impl):
+    # x and z take values up to 2^30 and a meta column up to 2^20: an 80-bit
+    # key, kept column by column in the table (claim, write, publish)
+    rng = synth.rng_for(44)
+    n = 20_000
+    xs = rng.integers(0, 1 << 30, 300).astype(np.uint32)
+    zs = rng.integers(0, 1 << 30, 500).astype(np.uint32)
+    a = [xs[rng.integers(0, 300, n)], rng.integers(0, 200, n).astype(np.uint32)]
+    b = [rng.integers(0, 200, n).astype(np.uint32), zs[rng.integers(0, 500, n)]]
+    q = {"n_attrs": 3, "agg": "sum", "out": [0, 2],
+         "atoms": [{"keys": a, "attrs": [0, 1], "annos": [synth.uniform_pm1(rng, n)], "anno": 0, "bag": True},
+                   {"keys": b, "attrs": [1, 2], "annos": [rng.integers(-4, 5, n) / 4.0], "anno": 0, "bag": True,
+                    "meta": [rng.integers(0, 1 << 20, n).astype(np.uint32)]}],
+         "group": [(1, 0)]}
+    want = oracle.join_aggregate(q)
+    assert len(want["counts"]) > 100_000
+    got = lh.run_query(q, attr_order=[0, 1, 2], policy="fixed", group_impl=impl)
+    if impl != "sort":
+        assert got["group_impl"] == "hash"
+    assert_same(got, want)
