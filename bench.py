@@ -91,7 +91,7 @@ def main():
                     help="layout of the plain-policy run")
     ap.add_argument("--policy", default="both", choices=["both", "plain", "learned"],
                     help="both: time the plain rule, then the learned cost model (reported)")
-    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby", "dense"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--card", type=int, default=1_000_000)
@@ -121,6 +121,8 @@ def main():
         return bench_q5(args, lh, torch, synth)
     if args.workload == "groupby":
         return bench_groupby(args, lh, torch, synth)
+    if args.workload == "dense":
+        return bench_dense(args, lh, torch, synth)
     log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
     t0 = time.perf_counter()
     lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
@@ -564,6 +566,84 @@ def bench_groupby(args, lh, torch, synth):
            "config": {"workload": "R(x,y) join S(y,z), SUM GROUP BY z under order x,y,z; 10^4 x 10^6 rows, "
                                   "about 10^7 join tuples; z from a subset of [0, 10^6)",
                       "key_union_ms": sweep, "wide_key_ms": wide}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_dense(args, lh, torch, synth):
+    """Dense LA by attribute elimination (Table 3's DMV and DMM, n = 16384):
+    completely dense relations A(i,j), B(j,k) / x(j) with U(-1,1) values.
+    Times lh_join_aggregate of the planned query with LH_DENSE_BLAS (rocBLAS
+    DGEMV / DGEMM over the annotation buffers, plus the output key columns)
+    and, where it finishes in seconds, the exact generic join of the same
+    query.  Roofline: DGEMM against the 78.6 TFLOP/s FP64 matrix peak
+    (2 n^3 flops), DGEMV against 8 TB/s (8 n^2 bytes of matrix)."""
+    import numpy as np
+
+    def dense_trie(rows, cols, seed):
+        rng = synth.rng_for(seed)
+        r = torch.arange(rows, dtype=torch.int64, device="cuda").repeat_interleave(cols).to(torch.int32)
+        c = torch.arange(cols, dtype=torch.int64, device="cuda").repeat(rows).to(torch.int32)
+        v = torch.from_numpy(synth.uniform_pm1(rng, rows * cols)).cuda()
+        t = lh.trie_build([r, c], [v], bag=True)
+        del r, c, v
+        return t
+
+    def timed(p, steps):
+        r = lh.join_aggregate([p])[0]
+        r.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lh.join_aggregate([p])[0].free()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1000 / steps
+
+    res = {}
+    for n, exact_too in [(1024, True), (4096, False), (16384, False)]:
+        log(f"DMM n={n}")
+        ta = dense_trie(n, n, 1)
+        tb = dense_trie(n, n, 2)
+        atoms = [(ta, [0, 1], 0), (tb, [1, 2], 0)]
+        p = lh.plan(3, atoms, out=[0, 2], agg="sum", dense_blas=True)
+        assert p.info()["blas"] == 2
+        ms = timed(p, max(1, args.steps))
+        p.free()
+        row = {"blas_ms": round(ms, 3), "tflops": round(2 * n ** 3 / (ms / 1000) / 1e12, 2)}
+        if exact_too:
+            p = lh.plan(3, atoms, out=[0, 2], agg="sum")
+            row["exact_join_ms"] = round(timed(p, 1), 3)
+            p.free()
+        res[f"DMM {n}"] = row
+        log(f"  {row}")
+        ta.free()
+        tb.free()
+    for n, exact_too in [(16384, True)]:
+        log(f"DMV n={n}")
+        tm = dense_trie(n, n, 3)
+        x = torch.from_numpy(synth.uniform_pm1(synth.rng_for(4), n)).cuda()
+        tx = lh.trie_build([torch.arange(n, dtype=torch.int32, device="cuda")], [x], bag=True)
+        atoms = [(tm, [0, 1], 0), (tx, [1], 0)]
+        p = lh.plan(2, atoms, out=[0], agg="sum", dense_blas=True)
+        assert p.info()["blas"] == 1
+        ms = timed(p, max(1, args.steps))
+        p.free()
+        row = {"blas_ms": round(ms, 3), "GBs": round(8 * n * n / (ms / 1000) / 1e9, 1)}
+        if exact_too:
+            p = lh.plan(2, atoms, out=[0], agg="sum")
+            row["exact_join_ms"] = round(timed(p, 2), 3)
+            p.free()
+        res[f"DMV {n}"] = row
+        log(f"  {row}")
+        tm.free()
+        tx.free()
+    head = res["DMM 16384"]
+    out = {"metric": "dense LA via attribute elimination, FP64 TFLOP/s of DMM n=16384", "value": head["tflops"],
+           "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": head["blas_ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "completely dense A(i,j), B(j,k), x(j), U(-1,1) values",
+                      "results": res,
+                      "roofline": {"bound": "mfma", "achieved": head["tflops"], "peak": 78.6, "unit": "TFLOP/s",
+                                   "frac": round(head["tflops"] / 78.6, 4)}}}
     print(json.dumps(out), flush=True)
 
 

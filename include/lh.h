@@ -116,6 +116,15 @@ lh_status lh_trie_build(const lh_relation_desc* rel, void* hip_stream, lh_trie**
 #define LH_GROUP_HASH     0x20u
 #define LH_GROUP_DENSE    0x30u
 #define LH_GROUP_MASK     0x30u
+/* Dense LA by attribute elimination (sections 3.1, 6.2.2), or'ed into
+ * lh_query.policy: a SUM over two annotated, completely dense relations
+ * (every key tuple of [0,R) x [0,K) present once) sharing one attribute,
+ * grouped by the other attributes (matrix-vector: outputs r of M(r,j),
+ * x(j); matrix-matrix: outputs r, c of P(r,j), Q(j,c), either key order in
+ * storage), is computed by rocBLAS DGEMV / DGEMM over the annotation
+ * buffers in trie order.  Keys and counts are those of the join; sums are
+ * BLAS sums (exact = 0).  Other queries ignore the bit. */
+#define LH_DENSE_BLAS     0x40u
 
 /* A hyperedge: one relation's trie and the query attribute of each of its
  * key columns (columns mapping to one attribute are equi-joined, Rule 1 of
@@ -233,6 +242,7 @@ typedef struct {
   uint32_t exact_digits;            /* 32-bit digits of the exact accumulator (0: COUNT) */
   int32_t exact_lsb;                /* exponent of the accumulator's least significant bit */
   uint32_t level_alg[16];           /* intersection algorithm per attribute position */
+  uint32_t blas;                    /* 1: run as BLAS DGEMV, 2: as DGEMM (LH_DENSE_BLAS), else 0 */
 } lh_plan_info;
 
 lh_status lh_plan_get_info(const lh_plan_t* p, lh_plan_info* info);

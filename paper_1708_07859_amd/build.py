@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblh.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["runtime.cpp", "prims.hip", "trie.hip", "join.hip", "batch.hip", "mlp.hip", "learned.hip", "plan.hip", "ghd.hip", "costmodel.cpp", "capi.cpp"]
+SOURCES = ["runtime.cpp", "prims.hip", "trie.hip", "join.hip", "batch.hip", "mlp.hip", "learned.hip", "plan.hip", "ghd.hip", "dense.hip", "costmodel.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -41,7 +41,7 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-L/opt/rocm/lib", "-lrocblas"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")

@@ -299,6 +299,7 @@ lh_status lh_plan_get_info(const lh_plan_t* p, lh_plan_info* info) {
     info->case_prefix = p->case_prefix ? 1u : 0u;
     info->exact_digits = p->exact_digits;
     info->exact_lsb = p->exact_lsb;
+    info->blas = p->blas;
   });
 }
 

@@ -31,6 +31,16 @@ struct PlanAtom {
   bool has_eq_filter = false;
 };
 
+// A product handed to BLAS (completely dense relations, LH_DENSE_BLAS):
+// output (rows x cols) = a (rows x inner) . b (inner x cols), both row-major
+// in trie order unless marked as stored transposed.
+struct DensePlan {
+  const double* a = nullptr;
+  const double* b = nullptr;
+  uint32_t rows = 0, cols = 0, inner = 0;
+  bool a_trans = false, b_trans = false;
+};
+
 struct Participant {
   uint32_t atom;
   uint32_t level;  // trie level holding this attribute
@@ -51,6 +61,8 @@ struct lh_plan_s {
   uint32_t policy = LH_POLICY_PLAIN;
   bool case_prefix = false;                 // outputs = first n_out attributes of the order
   uint32_t group_impl = 0;                  // GROUP BY outside the prefix: 0 auto, 1 sort, 2 hash, 3 dense
+  uint32_t blas = 0;                        // 1: BLAS matrix-vector, 2: matrix-matrix (dense relations)
+  lh::DensePlan dense;
   int32_t exact_lsb = 0;
   uint32_t exact_digits = 0;
   double cost = 0.0;
@@ -77,6 +89,9 @@ namespace lh {
 
 lh_plan_t* make_plan(const lh_query* q, hipStream_t s);
 lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s);
+// Dense relations under LH_DENSE_BLAS: mark the plan for a BLAS product.
+void plan_dense(const lh_query* q, lh_plan_t* p, hipStream_t s);
+lh_result_impl* run_dense(const lh_plan_t* p, hipStream_t s);
 // Batched execution of many plans; returns false (and does nothing) when
 // the plans are not all of a shape the batched executor handles.
 bool run_batch(lh_plan_t* const* plans, uint32_t n, hipStream_t s, std::vector<lh_result_impl*>& out);

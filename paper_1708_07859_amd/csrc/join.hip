@@ -1644,6 +1644,7 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
 }
 
 lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
+  if (p->blas) return run_dense(p, s);
   std::unique_ptr<lh_result_impl> res(new lh_result_impl());
   memset(&res->pub, 0, sizeof(res->pub));
   const uint32_t na = (uint32_t)p->atoms.size();

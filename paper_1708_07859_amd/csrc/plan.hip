@@ -295,6 +295,7 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
     p->exact_lsb = lsb;
     p->exact_digits = D;
   }
+  plan_dense(q, p.get(), s);
   return p.release();
 }
 

@@ -105,6 +105,7 @@ class PlanInfo(C.Structure):
         ("exact_digits", C.c_uint32),
         ("exact_lsb", C.c_int32),
         ("level_alg", C.c_uint32 * 16),
+        ("blas", C.c_uint32),
     ]
 
 
@@ -315,7 +316,7 @@ class Plan:
         n = inf.n_attrs
         return {"attr_order": list(inf.attr_order[:n]), "cost": inf.cost, "case_prefix": inf.case_prefix,
                 "exact_digits": inf.exact_digits, "exact_lsb": inf.exact_lsb,
-                "level_alg": list(inf.level_alg[:n])}
+                "level_alg": list(inf.level_alg[:n]), "blas": inf.blas}
 
     def free(self):
         if self.handle:
@@ -329,8 +330,11 @@ class Plan:
             pass
 
 
+LH_DENSE_BLAS = 0x40
+
+
 def _query(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None, policy="plain",
-           group_impl="auto"):
+           group_impl="auto", dense_blas=False):
     """An lh_query and the ctypes arrays it points into (keep them alive)."""
     catoms = (Atom * len(atoms))()
     keep = [catoms]
@@ -370,14 +374,14 @@ def _query(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order
         ao = (C.c_uint32 * len(attr_order))(*attr_order)
         keep.append(ao)
         q.attr_order = C.cast(ao, C.POINTER(C.c_uint32))
-    q.policy = POLICY[policy] | GROUP_IMPL[group_impl]
+    q.policy = POLICY[policy] | GROUP_IMPL[group_impl] | (LH_DENSE_BLAS if dense_blas else 0)
     return q, keep
 
 
 def plan(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=None, policy="plain",
-         stream=None, group_impl="auto"):
+         stream=None, group_impl="auto", dense_blas=False):
     """lh_plan.  atoms: [(Trie, attr_of_key list, anno index or -1)]."""
-    q, keep = _query(n_attrs, atoms, out, group, agg, filters, attr_order, policy, group_impl)
+    q, keep = _query(n_attrs, atoms, out, group, agg, filters, attr_order, policy, group_impl, dense_blas)
     out_h = C.c_void_p()
     _check(lib.lh_plan(C.byref(q), stream if stream is not None else current_stream(), C.byref(out_h)))
     return Plan(out_h.value, [a[0] for a in atoms])
@@ -633,7 +637,7 @@ def ghd_join_aggregate(n_attrs, atoms, out=(), group=(), agg="count", filters=()
 # --------------------------------------------------------------------------
 
 def run_query(query, attr_order=None, policy="plain", layout="plain", return_plan_info=False, ghd=False,
-              group_impl="auto"):
+              group_impl="auto", dense_blas=False):
     """Build one trie per distinct relation of the query, plan, run, and
     copy the result to host in the format {keys, counts, sums, n_join}.
     ghd=False runs one plan; ghd=None runs the library's decomposition, a
@@ -652,7 +656,7 @@ def run_query(query, attr_order=None, policy="plain", layout="plain", return_pla
     p = None
     try:
         if ghd is False:
-            p = plan(query["n_attrs"], atoms, **args)
+            p = plan(query["n_attrs"], atoms, dense_blas=dense_blas, **args)
             r = join_aggregate([p])[0]
         else:
             r = ghd_join_aggregate(query["n_attrs"], atoms, ghd=ghd, **args)
