@@ -102,8 +102,17 @@ void gather_f64(const double* src, const uint32_t* idx, double* dst, uint64_t n,
 
 // Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
 // Sorted pairs end in (keys, vals); tmp buffers must hold n entries each.
+// vals (and tvals) may be null: keys only.
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals,
                       uint64_t n, uint32_t bits, hipStream_t s);
+
+// Sort rows lexicographically by cols[0], cols[1], ... when their bits add
+// up to at most 64: one packed key per row, radix-sorted, then unpacked into
+// the sorted columns (ncols buffers of n).  perm (n entries, may be null)
+// receives the input row of each sorted position.  Returns false, doing
+// nothing, when the keys do not fit one word.
+bool sort_packed(const uint32_t* const* cols, const uint32_t* bits, uint32_t ncols, uint64_t n, uint32_t* perm,
+                 uint32_t* const* sorted, hipStream_t s);
 
 // Permutation that sorts rows lexicographically by cols[0], cols[1], ...
 // (stable); bits[c] = significant bits of column c.  perm receives n ids.

@@ -172,11 +172,13 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, uint64_
 // a wave, LDS counts across waves), placed in LDS in digit order, then
 // written out in that order, so each digit's run of the tile goes to
 // consecutive global slots (coalesced writes).
+// HAS_V: a 32-bit value travels with each key (else keys only)
+template <bool HAS_V>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                                                       uint32_t* vout, uint64_t n, uint32_t shift,
                                                       const uint32_t* offs, const uint32_t* hist, uint32_t ntiles) {
   __shared__ uint64_t sk[RS_TILE];
-  __shared__ uint32_t sv[RS_TILE];
+  __shared__ uint32_t sv[HAS_V ? RS_TILE : 1];
   __shared__ uint32_t lstart[256];   // first slot of each digit in the tile
   __shared__ uint32_t run[256];      // next slot of each digit in the tile
   __shared__ uint32_t wcnt[RS_NW][256];
@@ -198,7 +200,8 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const
     const uint32_t li = (uint32_t)i * RS_NT + tid;
     const bool valid = li < ntile;
     const uint64_t k = valid ? kin[base + li] : 0;
-    const uint32_t v = valid ? vin[base + li] : 0;
+    uint32_t v = 0;
+    if constexpr (HAS_V) v = valid ? vin[base + li] : 0u;
     const uint32_t d = (uint32_t)(k >> shift) & 255u;
     uint64_t peers = ballot(valid);
 #pragma unroll
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const
       for (int j = 0; j < w; j++) pre += wcnt[j][d];
       const uint32_t lp = run[d] + pre + rank;
       sk[lp] = k;
-      sv[lp] = v;
+      if constexpr (HAS_V) sv[lp] = v;
     }
     __syncthreads();
     uint32_t add = 0;
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const
     const uint32_t d = (uint32_t)(k >> shift) & 255u;
     const uint32_t pos = offs[(uint64_t)d * ntiles + blockIdx.x] + (t - lstart[d]);
     kout[pos] = k;
-    vout[pos] = sv[t];
+    if constexpr (HAS_V) vout[pos] = sv[t];
   }
 }
 
@@ -239,9 +242,24 @@ struct PackArgs {
   uint32_t ncols;
 };
 
+struct UnpackCols {
+  uint32_t* col[LH_MAX_KEYS];
+  uint32_t shift[LH_MAX_KEYS];
+  uint32_t bits[LH_MAX_KEYS];
+  uint32_t ncols;
+};
+
+__global__ void k_unpack_cols(UnpackCols a, const uint64_t* keys, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    for (uint32_t c = 0; c < a.ncols; c++)
+      a.col[c][i] = a.bits[c] ? (uint32_t)((k >> a.shift[c]) & ((1ull << a.bits[c]) - 1)) : 0u;
+  }
+}
+
 __global__ void k_pack(PackArgs a, const uint32_t* perm, uint64_t* out, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t r = perm[i];
+    const uint32_t r = perm ? perm[i] : (uint32_t)i;
     uint64_t k = 0;
     for (uint32_t c = 0; c < a.ncols; c++) k |= (uint64_t)a.col[c][r] << a.shift[c];
     out[i] = k;
@@ -397,6 +415,7 @@ void gather_f64(const double* src, const uint32_t* idx, double* dst, uint64_t n,
 
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, uint64_t n,
                       uint32_t bits, hipStream_t s) {
+  // vals == nullptr: keys only
   if (n <= 1 || bits == 0) return;
   if (n >= (1ull << 32)) fail(LH_ERR_OVERFLOW, "radix sort: more than 2^32 - 1 keys");
   uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
@@ -417,7 +436,8 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t*
     scan_u32(hist.p, offs.p, hn, s);
     {
       ProfScope ps("sort_scatter", s, n, 0);
-      k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, offs.p, hist.p, ntiles);
+      if (vals) k_rs_scatter<true><<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, offs.p, hist.p, ntiles);
+      else k_rs_scatter<false><<<ntiles, RS_NT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, offs.p, hist.p, ntiles);
     }
     LH_HIP(hipGetLastError());
     std::swap(ki, ko);
@@ -425,7 +445,7 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t*
   }
   if (ki != keys) {
     LH_HIP(hipMemcpyAsync(keys, ki, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    LH_HIP(hipMemcpyAsync(vals, vi, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (vals) LH_HIP(hipMemcpyAsync(vals, vi, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   }
 }
 
@@ -458,6 +478,35 @@ void lex_sort_perm(const uint32_t* const* cols, const uint32_t* bits, uint32_t n
     }
     end = start;
   }
+}
+
+bool sort_packed(const uint32_t* const* cols, const uint32_t* bits, uint32_t ncols, uint64_t n, uint32_t* perm,
+                 uint32_t* const* sorted, hipStream_t s) {
+  uint32_t tot = 0;
+  for (uint32_t c = 0; c < ncols; c++) tot += bits[c];
+  if (tot > 64 || ncols > LH_MAX_KEYS) return false;
+  DBuf<uint64_t> k(n, s), tk(n, s);
+  DBuf<uint32_t> tv(perm ? n : 0, s);
+  PackArgs a{};
+  UnpackCols u{};
+  a.ncols = u.ncols = ncols;
+  uint32_t sh = 0;
+  for (int c = (int)ncols - 1; c >= 0; c--) {  // the last column lowest
+    a.col[c] = cols[c];
+    a.shift[c] = u.shift[c] = sh;
+    u.bits[c] = bits[c];
+    u.col[c] = sorted[c];
+    sh += bits[c];
+  }
+  if (perm) iota_u32(perm, n, s);
+  if (n) {
+    k_pack<<<grid_for(n), 256, 0, s>>>(a, nullptr, k.p, n);
+    LH_HIP(hipGetLastError());
+    radix_sort_pairs(k.p, perm, tk.p, tv.p, n, tot, s);
+    k_unpack_cols<<<grid_for(n), 256, 0, s>>>(u, k.p, n);
+    LH_HIP(hipGetLastError());
+  }
+  return true;
 }
 
 AnnoStats anno_stats(const double* v, uint64_t n, hipStream_t s) {

@@ -279,16 +279,24 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
     t->key_bits[l] = bitlen(t->key_max[l]);
   }
 
-  DBuf<uint32_t> perm(n, s);
-  lex_sort_perm(col, t->key_bits, n_keys, n, perm.p, s);
-
+  // The permutation is needed only to carry annotation and meta columns.
+  // Keys that pack into one word are sorted as such and unpacked into the
+  // sorted columns (no gathers); wider keys take the multi-pass sort.
+  const bool need_perm = n_annos || n_meta;
+  DBuf<uint32_t> perm(need_perm ? n : 0, s);
   LevelCols lc{};
   lc.n_levels = n_keys;
   std::vector<DBuf<uint32_t>> sorted;
+  uint32_t* sorted_p[LH_MAX_KEYS];
   for (uint32_t l = 0; l < n_keys; l++) {
     sorted.emplace_back(n, s);
-    gather_u32(col[l], perm.p, sorted.back().p, n, s);
+    sorted_p[l] = sorted.back().p;
     lc.k[l] = sorted.back().p;
+  }
+  if (!sort_packed(col, t->key_bits, n_keys, n, need_perm ? perm.p : nullptr, sorted_p, s)) {
+    if (!need_perm) perm.alloc(n, s);
+    lex_sort_perm(col, t->key_bits, n_keys, n, perm.p, s);
+    for (uint32_t l = 0; l < n_keys; l++) gather_u32(col[l], perm.p, sorted_p[l], n, s);
   }
 
   uint32_t ntiles = (uint32_t)((n + TB_NT - 1) / TB_NT);
