@@ -37,6 +37,11 @@ struct DSet {
   const uint64_t* bs_word;
   const uint32_t* bs_base;
   const uint64_t* pool;
+  const uint32_t* bs_rank;   // rank directory of the bitset sets, or null
+  const uint32_t* bs_delta;
+  const uint64_t* root_bits; // root sets: level-0 bitmap with a rank per word, or null
+  const uint32_t* root_rank;
+  uint64_t root_span;
 };
 
 __device__ __forceinline__ void dset_range(const DSet& st, uint64_t row, uint32_t& b, uint32_t& e, uint64_t& sidx) {
@@ -87,6 +92,13 @@ __device__ __forceinline__ bool sampled_find(const uint32_t* keys, const uint32_
 __device__ __forceinline__ bool dset_find(const DSet& st, uint32_t b, uint32_t e, uint64_t sidx, uint32_t x,
                                           bool need_pos, uint32_t& pos) {
   if (b >= e) return false;
+  if (st.root_bits) {
+    if (x >= st.root_span) return false;
+    const uint64_t word = st.root_bits[x >> 6];
+    if (!((word >> (x & 63u)) & 1ull)) return false;
+    if (need_pos) pos = st.root_rank[x >> 6] + (uint32_t)__popcll(word & ((1ull << (x & 63u)) - 1ull));
+    return true;
+  }
   uint64_t w = st.bs_word[sidx];
   if (w != UINT64_MAX) {
     uint32_t base = st.bs_base[sidx];
@@ -94,7 +106,12 @@ __device__ __forceinline__ bool dset_find(const DSet& st, uint32_t b, uint32_t e
     uint32_t d = x - base;
     uint64_t word = st.pool[w + (d >> 6)];
     if (!((word >> (d & 63u)) & 1ull)) return false;
-    if (need_pos) (void)sampled_find(st.keys, st.samp, b, e, x, pos);
+    if (need_pos) {
+      if (st.bs_rank)
+        pos = st.bs_rank[w + (d >> 6)] + (uint32_t)__popcll(word & ((1ull << (d & 63u)) - 1ull)) + st.bs_delta[sidx];
+      else
+        (void)sampled_find(st.keys, st.samp, b, e, x, pos);
+    }
     return true;
   }
   return sampled_find(st.keys, st.samp, b, e, x, pos);
@@ -1297,8 +1314,13 @@ DSet make_dset(const lh_plan_t* p, const Participant& pt, const Frontier& F) {
   d.bs_word = L.bs_word.p;
   d.bs_base = L.bs_base.p;
   d.pool = L.pool.p;
+  d.bs_rank = L.bs_rank.p;
+  d.bs_delta = L.bs_delta.p;
   if (pt.level == 0) {
     d.root_n = (uint32_t)t->lv[0].n;
+    d.root_bits = t->root_bits.p;
+    d.root_rank = t->root_rank.p;
+    d.root_span = t->root_span;
   } else {
     d.ppos = F.pos[pt.atom].p;
     d.poffs = t->lv[pt.level - 1].offs.p;

@@ -145,6 +145,11 @@ struct Level {
   DBuf<uint32_t> bs_base;    // n_sets: value of bit 0 (multiple of 64)
   DBuf<uint64_t> pool;       // bitset words
   uint64_t pool_words = 0;
+  // rank directory of the bitset sets (levels whose positions are used):
+  // bs_rank[w] = set bits in the pool before word w, bs_delta[s] = first
+  // position of set s minus bs_rank of its first word (mod 2^32)
+  DBuf<uint32_t> bs_rank;    // pool_words + 1, or empty
+  DBuf<uint32_t> bs_delta;   // n_sets, or empty
   uint64_t n_bitsets = 0;
 };
 
@@ -164,6 +169,12 @@ struct lh_trie {
   uint64_t col_distinct[LH_MAX_KEYS];  // distinct values of each level's column (kept rows)
   uint64_t col_freq_max[LH_MAX_KEYS];  // largest number of kept rows sharing one value
   lh::Level lv[LH_MAX_KEYS];
+  // root index: level 0's keys as a bitmap over [0, root_span) with a rank
+  // per 64-bit word, when the span is small next to the keys (membership
+  // and position in one load each, whatever level 0's layout)
+  uint64_t root_span = 0;
+  lh::DBuf<uint64_t> root_bits;
+  lh::DBuf<uint32_t> root_rank;
   // rows in trie order (bag: every row; set: one per distinct tuple)
   lh::DBuf<uint32_t> skeys[LH_MAX_KEYS];   // per level
   std::vector<lh::DBuf<double>> annos;      // per annotation column

@@ -159,6 +159,28 @@ __global__ void k_layout_fill(SetRange sr, const uint32_t* keys, uint64_t n_sets
   }
 }
 
+__global__ void k_word_popc(const uint64_t* pool, uint64_t n, uint32_t* cnt) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    cnt[i] = (uint32_t)__popcll(pool[i]);
+}
+
+__global__ void k_rank_delta(SetRange sr, uint64_t n_sets, const uint64_t* bs_word, const uint32_t* rank,
+                             uint32_t* delta) {
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_sets; s += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t b, e;
+    set_range(sr, s, b, e);
+    const uint64_t w = bs_word[s];
+    delta[s] = w != UINT64_MAX ? b - rank[w] : 0u;
+  }
+}
+
+__global__ void k_root_bits(const uint32_t* keys, uint64_t n, uint64_t* bits) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    atomicOr((unsigned long long*)&bits[k >> 6], 1ull << (k & 63u));
+  }
+}
+
 unsigned grid_for(uint64_t n) {
   uint64_t b = (n + 255) / 256;
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(b, 256 * 64));
@@ -190,6 +212,19 @@ void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, hipStream_t s) {
     ProfScope ps("layout_fill", s, L.n_sets, L.pool_words);
     k_layout_fill<<<grid_for(L.pool_words), 256, 0, s>>>(sr, L.keys.p, L.n_sets, woff.p, L.bs_base.p, L.pool.p,
                                                         L.pool_words);
+    LH_HIP(hipGetLastError());
+  }
+  // positions inside bitset sets are needed when a deeper level hangs below
+  // or the rows of a bag are reached through them: a rank directory turns
+  // them into one load and a popcount
+  if (L.pool_words && (l + 1 < t->n_levels || (t->flags & LH_BAG))) {
+    DBuf<uint32_t> pc(L.pool_words, s);
+    k_word_popc<<<grid_for(L.pool_words), 256, 0, s>>>(L.pool.p, L.pool_words, pc.p);
+    LH_HIP(hipGetLastError());
+    L.bs_rank.alloc(L.pool_words + 1, s);
+    scan_u32(pc.p, L.bs_rank.p, L.pool_words, s);
+    L.bs_delta.alloc(L.n_sets, s);
+    k_rank_delta<<<grid_for(L.n_sets), 256, 0, s>>>(sr, L.n_sets, L.bs_word.p, L.bs_rank.p, L.bs_delta.p);
     LH_HIP(hipGetLastError());
   }
 }
@@ -403,6 +438,24 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
 
   uint32_t mode = flags & LH_LAYOUT_MASK;
   for (uint32_t l = 0; l < n_keys; l++) build_layouts(t.get(), l, mode, s);
+  // root index, when level 0 holds at least one key per 64 of its span
+  const uint64_t n0 = t->lv[0].n;
+  if (n0) {
+    const uint64_t span = (uint64_t)t->key_max[0] + 1;
+    if (span <= 64 * n0 && span <= (1ull << 32)) {
+      const uint64_t words = (span + 63) / 64;
+      t->root_span = span;
+      t->root_bits.alloc(words, s);
+      t->root_rank.alloc(words + 1, s);
+      LH_HIP(hipMemsetAsync(t->root_bits.p, 0, words * sizeof(uint64_t), s));
+      k_root_bits<<<grid_for(n0), 256, 0, s>>>(t->lv[0].keys.p, n0, t->root_bits.p);
+      LH_HIP(hipGetLastError());
+      DBuf<uint32_t> pc(words, s);
+      k_word_popc<<<grid_for(words), 256, 0, s>>>(t->root_bits.p, words, pc.p);
+      LH_HIP(hipGetLastError());
+      scan_u32(pc.p, t->root_rank.p, words, s);
+    }
+  }
   LH_HIP(hipStreamSynchronize(s));
   return t.release();
 }
