@@ -334,57 +334,37 @@ uint64_t select_flagged(const uint32_t* flags, uint64_t n, uint32_t* out, hipStr
 
 // Histogram of a column.  Runs of equal values inside a wave (the sorted
 // first column is long runs) are added with one atomic per run.
-__global__ void k_hist_u32(const uint32_t* col, uint64_t n, uint32_t* cnt) {
-  const int lane = lane_id();
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;  // a multiple of the wave size
-  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(WAVE - 1)); base < n; base += stride) {
-    const uint64_t i = base + lane;
-    const bool valid = i < n;
-    const uint32_t v = valid ? col[i] : 0u;
-    const uint32_t prev = (uint32_t)__shfl_up((int)v, 1, WAVE);
-    const bool head = valid && (lane == 0 || prev != v);
-    const uint64_t heads = ballot(head);
-    if (head) {
-      // the run ends at the next head or at the last valid lane
-      const uint64_t above = lane == WAVE - 1 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
-      const uint32_t nvalid = (uint32_t)min<uint64_t>(WAVE, n - base);
-      const uint32_t end = above ? (uint32_t)__builtin_ctzll(above) : nvalid;
-      atomicAdd(&cnt[v], end - (uint32_t)lane);
-    }
-  }
+__global__ void k_run_heads(const uint32_t* v, uint64_t n, uint32_t* head) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    head[i] = (i == 0 || v[i] != v[i - 1]) ? 1u : 0u;
 }
 
-__global__ void k_hist_stats(const uint32_t* cnt, uint64_t m, unsigned long long* distinct, uint32_t* fmax) {
-  uint64_t d = 0;
-  uint32_t f = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
-    d += cnt[i] != 0;
-    f = max(f, cnt[i]);
-  }
-  d = wave_sum(d);
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) f = max(f, (uint32_t)__shfl_xor((int)f, o, WAVE));
-  if (lane_id() == 0) {
-    atomicAdd(distinct, (unsigned long long)d);
-    atomicMax(fmax, f);
-  }
+// run k spans [pos[k], pos[k+1]) (the last ends at n)
+__global__ void k_run_lengths(const uint32_t* pos, uint64_t d, uint64_t n, uint32_t* len) {
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < d; k += (uint64_t)gridDim.x * blockDim.x)
+    len[k] = (uint32_t)((k + 1 < d ? (uint64_t)pos[k + 1] : n) - pos[k]);
 }
 
 void column_freq(const uint32_t* col, uint64_t n, uint32_t range, uint64_t& distinct, uint64_t& freq_max,
                  hipStream_t s) {
+  // sort the values (no atomics: hub values would serialize them), then
+  // the distinct values are the runs and the largest frequency the longest
+  // run
   distinct = 0;
   freq_max = 0;
   if (!n) return;
-  DBuf<uint32_t> cnt((uint64_t)range + 1, s), fm(1, s);
-  DBuf<unsigned long long> d(1, s);
-  k_fill<uint32_t><<<grid_for(range + 1ull), 256, 0, s>>>(cnt.p, 0u, range + 1ull);
-  k_fill<uint32_t><<<1, 64, 0, s>>>(fm.p, 0u, 1);
-  k_fill<unsigned long long><<<1, 64, 0, s>>>(d.p, 0ull, 1);
-  k_hist_u32<<<grid_for(n), 256, 0, s>>>(col, n, cnt.p);
-  k_hist_stats<<<grid_for(range + 1ull), 256, 0, s>>>(cnt.p, range + 1ull, d.p, fm.p);
+  const uint32_t bits = range ? 32 - __builtin_clz(range) : 0;
+  DBuf<uint32_t> sorted(n, s);
+  uint32_t* out = sorted.p;
+  if (!sort_packed(&col, &bits, 1, n, nullptr, &out, s)) fail(LH_ERR_DEVICE, "column statistics: sort failed");
+  DBuf<uint32_t> heads(n, s), pos(n, s);
+  k_run_heads<<<grid_for(n), 256, 0, s>>>(sorted.p, n, heads.p);
   LH_HIP(hipGetLastError());
-  distinct = read_scalar(d.p, s);
-  freq_max = read_scalar(fm.p, s);
+  const uint64_t d = select_flagged(heads.p, n, pos.p, s);
+  k_run_lengths<<<grid_for(d), 256, 0, s>>>(pos.p, d, n, heads.p);
+  LH_HIP(hipGetLastError());
+  distinct = d;
+  freq_max = reduce_max_u32(heads.p, d, s);
 }
 
 void iota_u32(uint32_t* out, uint64_t n, hipStream_t s) {
