@@ -200,7 +200,7 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
 void ensure_column_stats(lh_trie* t, hipStream_t s);
 
 // Per-set layout and bitset materialization for one level.
-void build_layouts(lh_trie* t, uint32_t level, uint32_t layout_flags, hipStream_t s);
+void build_layouts(lh_trie* t, uint32_t level, uint32_t layout_flags, const uint32_t* parent, hipStream_t s);
 
 // Per-set layout choices from the registered learned layout model (0 plain
 // rule, 1 uint, 2 bitset); false when no model is registered.

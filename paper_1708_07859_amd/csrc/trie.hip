@@ -56,6 +56,7 @@ struct EmitArgs {
   uint32_t* offs_out[LH_MAX_KEYS];   // level child offsets (levels 0..L-2)
   uint32_t* run_out;                 // bag: leaf run starts (sorted-row index); may be null
   uint32_t* kept_out;                // set: sorted-row index of each kept row; may be null
+  uint32_t* parent_out[LH_MAX_KEYS]; // level l >= 1: the level l-1 node above each node; may be null
   const uint32_t* tile_off;          // [l * ntiles + tile]
   uint32_t ntiles;
 };
@@ -81,6 +82,13 @@ __global__ __launch_bounds__(TB_NT) void k_emit_levels(EmitArgs a, uint64_t n) {
     for (int j = 0; j < w; j++) pre += w_cnt[j][l];
     uint32_t pos = a.tile_off[(uint64_t)l * a.ntiles + blockIdx.x] + pre + rank[l];
     a.keys_out[l][pos] = a.c.k[l][r];
+    if (l > 0 && a.parent_out[l]) {
+      // the parent is the last level l-1 node starting at or before row r
+      uint32_t pp = 0;
+      for (int j = 0; j < w; j++) pp += w_cnt[j][l - 1];
+      a.parent_out[l][pos] = a.tile_off[(uint64_t)(l - 1) * a.ntiles + blockIdx.x] + pp + rank[l - 1] +
+                             ((m >> (l - 1)) & 1u) - 1u;
+    }
     // a head at level l-1 is also a head at l: its first child is pos
     if (l > 0 && ((m >> (l - 1)) & 1u)) a.offs_out[l - 1][pos_prev] = pos;
     if (l + 1 == L) {
@@ -142,20 +150,25 @@ __global__ void k_layout_desc(SetRange sr, const uint32_t* keys, uint64_t n_sets
   }
 }
 
-__global__ void k_layout_fill(SetRange sr, const uint32_t* keys, uint64_t n_sets, const uint64_t* woff,
-                              const uint32_t* bs_base, uint64_t* pool, uint64_t n_words) {
-  for (uint64_t wi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < n_words; wi += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t s = upper_bound_minus1<uint64_t>(woff, 0, n_sets, wi);
-    uint32_t b, e;
-    set_range(sr, s, b, e);
-    uint32_t lo = bs_base[s] + (uint32_t)((wi - woff[s]) << 6);
-    uint32_t j = lower_bound_u32(keys, b, e, lo);
+// Bitset words from the keys: the first key of each (set, word) pair ORs in
+// the bits of the keys that follow it in the same word (at most 64) and
+// writes the word; words without keys stay zero.
+__global__ void k_layout_fill(const uint32_t* keys, const uint32_t* parent, uint64_t n, const uint64_t* bs_word,
+                              const uint32_t* bs_base, uint64_t* pool) {
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t st = parent ? parent[j] : 0u;
+    const uint64_t w0 = bs_word[st];
+    if (w0 == UINT64_MAX) continue;
+    const uint32_t base = bs_base[st];
+    const uint32_t word = (keys[j] - base) >> 6;
+    if (j > 0 && (!parent || parent[j - 1] == st) && ((keys[j - 1] - base) >> 6) == word) continue;
     uint64_t bits = 0;
-    while (j < e && keys[j] - lo < 64u && keys[j] >= lo) {
-      bits |= 1ull << (keys[j] - lo);
-      j++;
+    for (uint64_t t = j; t < n && (!parent || parent[t] == st); t++) {
+      const uint32_t d = keys[t] - base;
+      if ((d >> 6) != word) break;
+      bits |= 1ull << (d & 63u);
     }
-    pool[wi] = bits;
+    pool[w0 + word] = bits;
   }
 }
 
@@ -190,7 +203,7 @@ uint32_t bitlen(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
 
 }  // namespace
 
-void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, hipStream_t s) {
+void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, const uint32_t* parent, hipStream_t s) {
   Level& L = t->lv[l];
   L.n_sets = (l == 0) ? 1 : t->lv[l - 1].n;
   SetRange sr{l == 0 ? nullptr : t->lv[l - 1].offs.p, t->lv[0].n};
@@ -210,8 +223,8 @@ void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, hipStream_t s) {
   if (L.pool_words) {
     L.pool.alloc(L.pool_words, s);
     ProfScope ps("layout_fill", s, L.n_sets, L.pool_words);
-    k_layout_fill<<<grid_for(L.pool_words), 256, 0, s>>>(sr, L.keys.p, L.n_sets, woff.p, L.bs_base.p, L.pool.p,
-                                                        L.pool_words);
+    LH_HIP(hipMemsetAsync(L.pool.p, 0, L.pool_words * sizeof(uint64_t), s));
+    k_layout_fill<<<grid_for(L.n), 256, 0, s>>>(L.keys.p, parent, L.n, L.bs_word.p, L.bs_base.p, L.pool.p);
     LH_HIP(hipGetLastError());
   }
   // positions inside bitset sets are needed when a deeper level hangs below
@@ -374,6 +387,12 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
     kept.alloc(n_leaf, s);
     ea.kept_out = kept.p;
   }
+  // parents of each level's nodes, for the bitset fill of levels below 0
+  std::vector<DBuf<uint32_t>> parent(n_keys);
+  for (uint32_t l = 1; l < n_keys; l++) {
+    parent[l].alloc(level_n[l], s);
+    ea.parent_out[l] = parent[l].p;
+  }
   if (n) {
     ProfScope ps("trie_emit_levels", s, n, 0);
     k_emit_levels<<<ntiles, TB_NT, 0, s>>>(ea, n);
@@ -437,7 +456,7 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
   }
 
   uint32_t mode = flags & LH_LAYOUT_MASK;
-  for (uint32_t l = 0; l < n_keys; l++) build_layouts(t.get(), l, mode, s);
+  for (uint32_t l = 0; l < n_keys; l++) build_layouts(t.get(), l, mode, l ? parent[l].p : nullptr, s);
   // root index, when level 0 holds at least one key per 64 of its span
   const uint64_t n0 = t->lv[0].n;
   if (n0) {
