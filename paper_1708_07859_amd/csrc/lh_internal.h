@@ -100,19 +100,21 @@ void fill_u64(uint64_t* out, uint64_t v, uint64_t n, hipStream_t s);
 void gather_u32(const uint32_t* src, const uint32_t* idx, uint32_t* dst, uint64_t n, hipStream_t s);
 void gather_f64(const double* src, const uint32_t* idx, double* dst, uint64_t n, hipStream_t s);
 
-// Stable LSD radix sort of (key, val) pairs on the low `bits` bits of key.
+// Stable LSD radix sort of (key, val) pairs on bits [lo_bit, bits) of key
+// (pairs already ordered by the bits below lo_bit keep that order).
 // Sorted pairs end in (keys, vals); tmp buffers must hold n entries each.
 // vals (and tvals) may be null: keys only.
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals,
-                      uint64_t n, uint32_t bits, hipStream_t s);
+                      uint64_t n, uint32_t bits, hipStream_t s, uint32_t lo_bit = 0);
 
 // Sort rows lexicographically by cols[0], cols[1], ... when their bits add
 // up to at most 64: one packed key per row, radix-sorted, then unpacked into
 // the sorted columns (ncols buffers of n).  perm (n entries, may be null)
-// receives the input row of each sorted position.  Returns false, doing
+// receives the input row of each sorted position.  Rows already sorted by
+// the last sorted_tail columns are sorted by the others only (stably).  Returns false, doing
 // nothing, when the keys do not fit one word.
 bool sort_packed(const uint32_t* const* cols, const uint32_t* bits, uint32_t ncols, uint64_t n, uint32_t* perm,
-                 uint32_t* const* sorted, hipStream_t s);
+                 uint32_t* const* sorted, hipStream_t s, uint32_t sorted_tail = 0);
 
 // Permutation that sorts rows lexicographically by cols[0], cols[1], ...
 // (stable); bits[c] = significant bits of column c.  perm receives n ids.
@@ -191,10 +193,12 @@ constexpr uint32_t RESULT_MAGIC = 0x52534c54u;
 // Build from device columns, optionally restricted to the rows listed in
 // `sel` (n_sel entries).  Columns are in the relation's own column order;
 // level_order maps levels to key columns.
+// sorted_tail: the input rows (after `sel`) are already in lexicographic
+// order of the last sorted_tail levels, which then need no sort passes.
 lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* keys,
                     uint32_t n_annos, const double* const* annos, uint32_t n_meta,
                     const uint32_t* const* meta, const uint32_t* level_order, uint32_t flags,
-                    const uint32_t* sel, uint64_t n_sel, hipStream_t s);
+                    const uint32_t* sel, uint64_t n_sel, hipStream_t s, uint32_t sorted_tail = 0);
 
 // Column statistics (col_distinct, col_freq_max), computed once per trie.
 void ensure_column_stats(lh_trie* t, hipStream_t s);

@@ -85,9 +85,19 @@ lh_trie* filtered_or_reordered(const lh_trie* t, const uint32_t* level_order, co
     sel.alloc(n, s);
     n_sel = select_flagged(flags.p, n, sel.p, s);
   }
+  // The rows are in the trie's order: if the new order ends with a prefix
+  // of the old one, those levels are already sorted (a filtered copy in the
+  // same order needs no sort at all).
+  const uint32_t k = t->n_levels;
+  uint32_t tail = 0;
+  for (uint32_t m = k; m > 0 && !tail; m--) {
+    bool ok = true;
+    for (uint32_t i = 0; i < m && ok; i++) ok = level_order[k - m + i] == t->level_order[i];
+    if (ok) tail = m;
+  }
   // a set relation keeps its set semantics; its rows are already distinct
   return build_trie(n, t->n_levels, keys, (uint32_t)annos.size(), annos.data(), (uint32_t)meta.size(), meta.data(),
-                    level_order, t->flags, filt.empty() ? nullptr : sel.p, n_sel, s);
+                    level_order, t->flags, filt.empty() ? nullptr : sel.p, n_sel, s, tail);
 }
 
 bool same_order(const lh_trie* t, const uint32_t* lo) {

@@ -394,9 +394,9 @@ void gather_f64(const double* src, const uint32_t* idx, double* dst, uint64_t n,
 }
 
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, uint64_t n,
-                      uint32_t bits, hipStream_t s) {
+                      uint32_t bits, hipStream_t s, uint32_t lo_bit) {
   // vals == nullptr: keys only
-  if (n <= 1 || bits == 0) return;
+  if (n <= 1 || bits <= lo_bit) return;
   if (n >= (1ull << 32)) fail(LH_ERR_OVERFLOW, "radix sort: more than 2^32 - 1 keys");
   uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
   uint64_t hn = (uint64_t)ntiles * 256;
@@ -405,9 +405,9 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t*
   uint32_t* vi = vals;
   uint64_t* ko = tkeys;
   uint32_t* vo = tvals;
-  uint32_t passes = (bits + 7) / 8;
+  uint32_t passes = (bits - lo_bit + 7) / 8;
   for (uint32_t p = 0; p < passes; p++) {
-    uint32_t shift = p * 8;
+    uint32_t shift = lo_bit + p * 8;
     {
       ProfScope ps("sort_hist", s, n, 0);
       k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ki, n, shift, hist.p, ntiles);
@@ -461,7 +461,7 @@ void lex_sort_perm(const uint32_t* const* cols, const uint32_t* bits, uint32_t n
 }
 
 bool sort_packed(const uint32_t* const* cols, const uint32_t* bits, uint32_t ncols, uint64_t n, uint32_t* perm,
-                 uint32_t* const* sorted, hipStream_t s) {
+                 uint32_t* const* sorted, hipStream_t s, uint32_t sorted_tail) {
   uint32_t tot = 0;
   for (uint32_t c = 0; c < ncols; c++) tot += bits[c];
   if (tot > 64 || ncols > LH_MAX_KEYS) return false;
@@ -482,7 +482,9 @@ bool sort_packed(const uint32_t* const* cols, const uint32_t* bits, uint32_t nco
   if (n) {
     k_pack<<<grid_for(n), 256, 0, s>>>(a, nullptr, k.p, n);
     LH_HIP(hipGetLastError());
-    radix_sort_pairs(k.p, perm, tk.p, tv.p, n, tot, s);
+    uint32_t tail_bits = 0;
+    for (uint32_t c = ncols - std::min(sorted_tail, ncols); c < ncols; c++) tail_bits += bits[c];
+    radix_sort_pairs(k.p, perm, tk.p, tv.p, n, tot, s, tail_bits);
     k_unpack_cols<<<grid_for(n), 256, 0, s>>>(u, k.p, n);
     LH_HIP(hipGetLastError());
   }

@@ -301,8 +301,9 @@ void ensure_column_stats(lh_trie* t, hipStream_t s) {
 lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* keys, uint32_t n_annos,
                     const double* const* annos, uint32_t n_meta, const uint32_t* const* meta,
                     const uint32_t* level_order, uint32_t flags, const uint32_t* sel, uint64_t n_sel,
-                    hipStream_t s) {
+                    hipStream_t s, uint32_t sorted_tail) {
   const uint64_t n = sel ? n_sel : n_rows;
+  sorted_tail = std::min(sorted_tail, n_keys);
   if (n >= (1ull << 32) - 1) fail(LH_ERR_OVERFLOW, "trie build: 2^32 - 1 rows or more");
   const bool bag = (flags & LH_BAG) != 0;
   std::unique_ptr<lh_trie> t(new lh_trie());
@@ -341,9 +342,10 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
     sorted_p[l] = sorted.back().p;
     lc.k[l] = sorted.back().p;
   }
-  if (!sort_packed(col, t->key_bits, n_keys, n, need_perm ? perm.p : nullptr, sorted_p, s)) {
+  if (!sort_packed(col, t->key_bits, n_keys, n, need_perm ? perm.p : nullptr, sorted_p, s, sorted_tail)) {
     if (!need_perm) perm.alloc(n, s);
-    lex_sort_perm(col, t->key_bits, n_keys, n, perm.p, s);
+    // a stable sort by the leading levels keeps the presorted tail's order
+    lex_sort_perm(col, t->key_bits, n_keys - sorted_tail, n, perm.p, s);
     for (uint32_t l = 0; l < n_keys; l++) gather_u32(col[l], perm.p, sorted_p[l], n, s);
   }
 
