@@ -45,8 +45,6 @@ def leaf_alg_bytes(rows, elements):
 
 ALG_BYTES = {
     "leaf_aggregate": leaf_alg_bytes,
-    "join_count": leaf_alg_bytes,
-    "join_fill": lambda rows, el: 33 * rows + 8 * el,
     # (u64 key + u32 value) read and written per sorted element
     "sort_scatter": lambda rows, el: 24 * rows,
     "sort_hist": lambda rows, el: 8 * rows,
@@ -458,7 +456,7 @@ def bench_q5(args, lh, torch, synth):
         if name == "chosen":
             lh.profile_enable(False)
             prof = lh.profile_read()
-            top = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]
+            top = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:12]
             for k, v in top:
                 log(f"  {k:22s} {v['total_ms'] / args.steps:8.2f} ms/step  launches {v['launches'] // args.steps}")
         results[name] = {"ms_per_step": round(ms, 3), "rows_per_s": n_rows / (ms / 1000)}

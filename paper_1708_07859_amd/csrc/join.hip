@@ -1402,7 +1402,11 @@ void step(const lh_plan_t* p, uint32_t d, Frontier& F, hipStream_t s) {
   a.blk_cnt = bcnt.p;
   a.need_pos_mask = 0;
   {
-    ProfScope ps("join_count", s, F.n, total);
+    static const char* names[MAXV] = {"join_count_d0", "join_count_d1", "join_count_d2", "join_count_d3",
+                                      "join_count_d4", "join_count_d5", "join_count_d6", "join_count_d7",
+                                      "join_count_d8", "join_count_d9", "join_count_d10", "join_count_d11",
+                                      "join_count_d12", "join_count_d13", "join_count_d14", "join_count_d15"};
+    ProfScope ps(names[d], s, F.n, total);
     k_elem<M_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
   }
   LH_HIP(hipGetLastError());
@@ -1449,7 +1453,11 @@ void step(const lh_plan_t* p, uint32_t d, Frontier& F, hipStream_t s) {
   a.blk_off = boff.p;
   a.need_pos_mask = 0xffu;
   {
-    ProfScope ps("join_fill", s, F.n, total);
+    static const char* names[MAXV] = {"join_fill_d0", "join_fill_d1", "join_fill_d2", "join_fill_d3",
+                                      "join_fill_d4", "join_fill_d5", "join_fill_d6", "join_fill_d7",
+                                      "join_fill_d8", "join_fill_d9", "join_fill_d10", "join_fill_d11",
+                                      "join_fill_d12", "join_fill_d13", "join_fill_d14", "join_fill_d15"};
+    ProfScope ps(names[d], s, F.n, total);
     k_elem<M_FILL><<<elem_grid(nblk), J_NT, 0, s>>>(a);
   }
   LH_HIP(hipGetLastError());
