@@ -88,6 +88,16 @@ __device__ __forceinline__ bool sampled_find(const uint32_t* keys, const uint32_
   return keys[lo] == x;
 }
 
+// First position in the sorted keys [b, e) holding a key >= x (e if none),
+// through the line samples.
+__device__ __forceinline__ uint32_t sampled_lower_bound(const uint32_t* keys, const uint32_t* samp, uint32_t b,
+                                                        uint32_t e, uint32_t x) {
+  if (b >= e) return b;
+  uint32_t pos = b;
+  if (sampled_find(keys, samp, b, e, x, pos)) return pos;
+  return keys[pos] < x ? pos + 1 : pos;
+}
+
 // Membership of x in set [b, e) (descriptor sidx); its position if asked.
 __device__ __forceinline__ bool dset_find(const DSet& st, uint32_t b, uint32_t e, uint64_t sidx, uint32_t x,
                                           bool need_pos, uint32_t& pos) {
@@ -852,6 +862,7 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
     const uint64_t sq = d ? sidx[0] : sidx[1];
     const uint32_t* dk = d ? wa.set[1].keys : wa.set[0].keys;
     const uint32_t* pk = d ? wa.set[0].keys : wa.set[1].keys;
+    const uint32_t* ps = d ? wa.set[0].samp : wa.set[1].samp;
     const uint64_t* bsw = d ? wa.set[0].bs_word : wa.set[1].bs_word;
     const uint32_t* bsb = d ? wa.set[0].bs_base : wa.set[1].bs_base;
     t.drv = d;
@@ -862,8 +873,13 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
       t.plo = bsb[sq];
       t.phi = pk[pe - 1];
     } else {
-      t.plo = lower_bound_u32(pk, pb, pe, dk[t.dstart]);
-      t.phi = (u + 1 == u1) ? upper_bound_u32(pk, t.plo, pe, dk[t.dstart + t.dcount - 1]) : UINT32_MAX;
+      t.plo = sampled_lower_bound(pk, ps, pb, pe, dk[t.dstart]);
+      if (u + 1 == u1) {
+        const uint32_t last = dk[t.dstart + t.dcount - 1];
+        t.phi = last == UINT32_MAX ? pe : sampled_lower_bound(pk, ps, t.plo, pe, last + 1);
+      } else {
+        t.phi = UINT32_MAX;
+      }
     }
     desc[u] = t;
   }
