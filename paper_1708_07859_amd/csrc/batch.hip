@@ -410,8 +410,20 @@ __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
       if (tid == 0) soff[B_NT] = I.bt_off[kb0 + nk];
       __syncthreads();
       const uint32_t e0 = soff[0], e1 = soff[nk];
-      for (uint32_t e = e0 + tid; e < e1; e += B_NT) {
-        const uint32_t j = I.bt_j[e];
+      // four entries per thread per round: their loads are independent and
+      // in flight together (few entries match, so the loop is load latency)
+      constexpr uint32_t UNR = 4;
+      for (uint32_t eb = e0 + tid; eb < e1; eb += UNR * B_NT) {
+        uint32_t jv[UNR];
+#pragma unroll
+        for (uint32_t u = 0; u < UNR; u++) {
+          const uint32_t e = eb + u * B_NT;
+          jv[u] = e < e1 ? I.bt_j[e] : UINT32_MAX;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < UNR; u++) {
+        const uint32_t e = eb + u * B_NT;
+        const uint32_t j = jv[u];
         if (j >= I.n_j) continue;
         const uint64_t word = bm[j >> 6];
         if (!((word >> (j & 63u)) & 1ull)) continue;
@@ -436,6 +448,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
               ok = lds_add_term(cdig + c * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
               if (!ok) bad = 1;
             }
+        }
       }
       __syncthreads();
       const uint64_t cnt = (uint32_t)tid < nk ? ccnt[tid] : 0ull;
