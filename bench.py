@@ -398,7 +398,10 @@ def bench_q5(args, lh, torch, synth):
     decompositions timed are the library's choice, one generic-join node
     (width 3), the same two nodes with the tail as root (the last tie-break
     reversed) and the tail split into a chain (more nodes and depth, same
-    width).  value = input rows / step time of the chosen plan."""
+    width); the chosen plan runs once with the plain rule's attribute orders
+    in every node and once with the learned model's.  value = input rows /
+    step time of the chosen plan under the learned orders (the plain
+    rule's time sits in the config)."""
     import numpy as np
 
     from tests import queries
@@ -410,24 +413,29 @@ def bench_q5(args, lh, torch, synth):
     n_rows = sum(len(a["keys"][0]) for a in q["atoms"])
     del sch
     args_q = dict(out=q["out"], agg="sum", filters=q["filters"])
+    from paper_1708_07859_amd import learned as L
+    weights = args.weights or L.DEFAULT_WEIGHTS
+    lm, om, _ = L.load(weights)
+    L.register(lm, om)
     variants = {
-        "chosen": None,
-        "one node": "single",
-        "tail as root": {"edges": [0b110000, 0b001111], "parent": [-1, 0], "pushed": [0, 0]},
-        "chain tail": {"edges": [0b001111, 0b010000, 0b100000], "parent": [-1, 0, 1], "pushed": [0, 0, 0]},
+        "chosen": (None, "plain"),
+        "chosen, learned orders": (None, "learned"),
+        "one node": ("single", "plain"),
+        "tail as root": ({"edges": [0b110000, 0b001111], "parent": [-1, 0], "pushed": [0, 0]}, "plain"),
+        "chain tail": ({"edges": [0b001111, 0b010000, 0b100000], "parent": [-1, 0, 1], "pushed": [0, 0, 0]}, "plain"),
     }
 
-    def step(g):
+    def step(g, policy):
         tries = [lh.trie_build(a["keys"], a["annos"], a["meta"], bag=a["bag"]) for a in dev]
         atoms = [(t, a["attrs"], a.get("anno", -1)) for t, a in zip(tries, q["atoms"])]
         if g == "single":
-            p = lh.plan(q["n_attrs"], atoms, **args_q)
+            p = lh.plan(q["n_attrs"], atoms, policy=policy, **args_q)
             r = lh.join_aggregate([p])[0]
             out = r.to_host()
             r.free()
             p.free()
         else:
-            r = lh.ghd_join_aggregate(q["n_attrs"], atoms, ghd=g, **args_q)
+            r = lh.ghd_join_aggregate(q["n_attrs"], atoms, ghd=g, policy=policy, **args_q)
             out = r.to_host()
             r.free()
         chosen = lh.ghd_for_query(q["n_attrs"], atoms, **args_q) if g is None else None
@@ -436,9 +444,9 @@ def bench_q5(args, lh, torch, synth):
         return out, chosen
 
     results, ref, chosen = {}, None, None
-    for name, g in variants.items():
+    for name, (g, policy) in variants.items():
         for _ in range(max(1, args.warmup)):
-            out, ch = step(g)
+            out, ch = step(g, policy)
             chosen = ch or chosen
         if ref is None:
             ref = out
@@ -450,7 +458,7 @@ def bench_q5(args, lh, torch, synth):
             lh.profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(g)
+            step(g, policy)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1000 / args.steps
         if name == "chosen":
@@ -461,7 +469,7 @@ def bench_q5(args, lh, torch, synth):
                 log(f"  {k:22s} {v['total_ms'] / args.steps:8.2f} ms/step  launches {v['launches'] // args.steps}")
         results[name] = {"ms_per_step": round(ms, 3), "rows_per_s": n_rows / (ms / 1000)}
         log(f"{name}: {ms:.2f} ms/step")
-    head = results["chosen"]
+    head = results["chosen, learned orders"]
     out = {"metric": "join-aggregate input tuples/s, multi-node plan", "value": head["rows_per_s"],
            "unit": "tuples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

@@ -108,6 +108,23 @@ bool same_order(const lh_trie* t, const uint32_t* lo) {
 
 }  // namespace
 
+// The learned order model sees each filtered relation at its size after the
+// selection (the relation its GHD node joins), where the plain rule of
+// section 4 scores the base cardinality.
+Hypergraph learned_view(const lh_query* q, const Hypergraph& h, const std::vector<std::vector<FilterDev>>& filt,
+                        hipStream_t s) {
+  Hypergraph hl = h;
+  for (uint32_t e = 0; e < q->n_atoms; e++) {
+    if (filt[e].empty()) continue;
+    const uint64_t n = q->atoms[e].trie->n_rows;
+    DBuf<uint32_t> flags(n, s);
+    DBuf<uint64_t> off(n + 1, s);
+    eval_filters(filt[e].data(), (uint32_t)filt[e].size(), n, flags.p, s);
+    hl.edges[e].card = n ? scan_u32_to_u64(flags.p, off.p, n, s) : 0;
+  }
+  return hl;
+}
+
 lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
   if (!q) fail(LH_ERR_INVALID, "query is NULL");
   if (q->agg != LH_AGG_COUNT && q->agg != LH_AGG_SUM) fail(LH_ERR_UNSUPPORTED, "aggregate must be COUNT or SUM");
@@ -219,7 +236,8 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
       order[i] = v;
     }
     p->cost = order_cost(h, order, nullptr, nullptr);
-  } else if ((q->policy & LH_POLICY_MASK) == LH_POLICY_LEARNED && learned_order(h, p->out_attrs, order, s)) {
+  } else if ((q->policy & LH_POLICY_MASK) == LH_POLICY_LEARNED && learned_order(learned_view(q, h, filt, s),
+                                                                                 p->out_attrs, order, s)) {
     p->cost = order_cost(h, order, nullptr, nullptr);
   } else {
     p->cost = choose_order(h, p->out_attrs, order);

@@ -130,8 +130,25 @@ def calibrate_layouts(seed=7, total=1 << 23, cards=None, densities=None):
 # order samples
 # --------------------------------------------------------------------------
 
+def _selected_rows(atom, filters):
+    """Rows of a bag relation that pass its filters (the size the learned
+    order model sees for a filtered relation)."""
+    keep = np.ones(len(atom["keys"][0]), dtype=bool)
+    for f in filters:
+        if f["kind"] == "eq_key":
+            keep &= np.asarray(atom["keys"][f.get("col", 0)]) == f["eq"]
+        elif f["kind"] == "eq_meta":
+            keep &= np.asarray(atom["meta"][f.get("col", 0)]) == f["eq"]
+        else:
+            col = atom["annos"] if f["kind"] == "range_anno" else atom["meta"]
+            v = np.asarray(col[f.get("col", 0)], dtype=np.float64)
+            keep &= (v >= f["lo"]) & (v < f["hi"])
+    return int(keep.sum())
+
+
 def _edges_of(query, tries):
-    """Hypergraph edges (attrs, base cardinality, eq flag) of a query dict."""
+    """Hypergraph edges (attrs, cardinality, eq flag) of a query dict; a
+    filtered relation counts the rows its filters keep."""
     eq_atoms = {f["atom"] for f in query.get("filters", []) if f["kind"] in ("eq_key", "eq_meta")}
     out = []
     for i, (a, t) in enumerate(zip(query["atoms"], tries)):
@@ -139,7 +156,9 @@ def _edges_of(query, tries):
         n = max(1, inf["n_rows"])
         lf_mean = [float(np.log2(1 + n / max(1, d))) for d in inf["col_distinct"]]
         lf_max = [float(np.log2(1 + f)) for f in inf["col_freq_max"]]
-        out.append({"attrs": list(a["attrs"]), "card": len(a["keys"][0]), "eq": i in eq_atoms,
+        mine = [f for f in query.get("filters", []) if f["atom"] == i]
+        card = _selected_rows(a, mine) if mine else len(a["keys"][0])
+        out.append({"attrs": list(a["attrs"]), "card": card, "eq": i in eq_atoms,
                     "lf_mean": lf_mean, "lf_max": lf_max})
     return out
 
@@ -220,7 +239,28 @@ def training_queries():
         qs.append(("spmv %d" % n, queries.spmv(synth.zipf_degree_matrix(n, 1.1, 16, rng), x)))
     s = synth.star_schema(n_fact=400_000, dims=(40_000, 10_000, 2000, 200), seed=31)
     qs.append(("star", queries.star(s, u_hi=0.2, m2=0, m3=0)))
+    # the cycle node of a Q5-shaped multi-node plan (customer, orders with a
+    # date window, lineitem, supplier, and the selected nations), at scale
+    # factors 1 and 2; the sf 10 schema (seed 5) is held out
+    for sf, seed in ((1.0, 51), (2.0, 52)):
+        qs.append(("q5 cycle sf%g" % sf, q5_cycle(synth.q5_schema(sf, seed=seed))))
     return qs
+
+
+def q5_cycle(s, region=2, date_lo=730, date_hi=1095):
+    """SUM(lineitem.ann) GROUP BY n over customer(c,n), orders(o,c),
+    lineitem(o,s), supplier(s,n) and the nations of one region (c=0, o=1,
+    s=2, n=3): the expensive node of the Q5-shaped plan."""
+    nat = s["nation"]["n"][s["nation"]["r"] == region].astype(np.uint32)
+    return {"n_attrs": 4, "agg": "sum", "out": [3],
+            "atoms": [{"keys": [s["customer"]["c"], s["customer"]["n"]], "attrs": [0, 3], "bag": False},
+                      {"keys": [s["orders"]["o"], s["orders"]["c"]], "attrs": [1, 0], "meta": [s["orders"]["date"]],
+                       "bag": True},
+                      {"keys": [s["lineitem"]["o"], s["lineitem"]["s"]], "attrs": [1, 2],
+                       "annos": [s["lineitem"]["ann"]], "anno": 0, "bag": True},
+                      {"keys": [s["supplier"]["s"], s["supplier"]["n"]], "attrs": [2, 3], "bag": False},
+                      {"keys": [nat], "attrs": [3], "annos": [np.ones(len(nat))], "anno": 0, "bag": True}],
+            "filters": [{"atom": 1, "kind": "range_meta", "col": 0, "lo": float(date_lo), "hi": float(date_hi)}]}
 
 
 def order_samples(queries_list):
@@ -290,17 +330,26 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train"])
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--keep-layout", default=None, help="take the layout model from these weights")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
-    log("layout calibration")
-    Xl, yl, rl = calibrate_layouts()
+    if args.keep_layout:
+        lm, _, old = load(args.keep_layout)
+        yl, rl, l0, l1 = old.get("layout_samples", 0), old.get("layout_rows", []), *old.get("layout_loss", [0, 0])
+        n_layout = yl
+        log(f"layout model kept from {args.keep_layout}")
+    else:
+        log("layout calibration")
+        Xl, yl, rl = calibrate_layouts()
+        n_layout = len(yl)
     log("order samples")
     Xo, yo, ro = order_samples(training_queries())
     log("training")
-    lm, l0, l1 = train_model(Xl, yl, lh.LH_LAYOUT_FEATURES)
+    if not args.keep_layout:
+        lm, l0, l1 = train_model(Xl, yl, lh.LH_LAYOUT_FEATURES)
     om, o0, o1 = train_model(Xo, yo, lh.LH_ORDER_FEATURES)
-    meta = {"layout_samples": len(yl), "order_samples": len(yo), "layout_loss": [l0, l1], "order_loss": [o0, o1],
+    meta = {"layout_samples": n_layout, "order_samples": len(yo), "layout_loss": [l0, l1], "order_loss": [o0, o1],
             "layout_rows": rl, "order_rows": ro}
     save(args.out, lm, om, meta)
     log(f"saved {args.out}")
