@@ -168,9 +168,14 @@ struct LeafArgs {
   // claimed with one compare-and-swap; gkey64 is then the table
   uint64_t* gkey64;
   uint32_t gshift[MAXV + MAXA];
+  // dense key spaces of at most GLDS_MAX entries are accumulated per block
+  // in LDS and flushed once (few groups would serialize global atomics)
+  uint32_t glds;
+  uint32_t gspace;
 };
 
 constexpr uint64_t KEY64_EMPTY = ~0ull;
+constexpr uint32_t GLDS_MAX = 256;
 
 struct ElemArgs {
   uint32_t np;
@@ -388,6 +393,10 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
   __shared__ unsigned long long s_cnt;
   __shared__ long long s_acc[EXACT_MAXD];
 
+  constexpr bool GAGG = MODE == M_LEAF_B_AGG;
+  __shared__ unsigned long long s_gcnt[GAGG ? GLDS_MAX : 1];
+  __shared__ long long s_gdig[GAGG ? GLDS_MAX * EXACT_MAXD : 1];
+
   const int tid = threadIdx.x;
   const int w = tid / WAVE;
   const int lane = lane_id();
@@ -395,6 +404,13 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
   constexpr bool NEED_POS = !(MODE == M_COUNT || MODE == M_LEAF_COUNT);
   constexpr bool LEAF_AGG = (MODE == M_LEAF_A || MODE == M_LEAF_COUNT);
   const bool one_group = LEAF_AGG && L.gid == nullptr;
+  if constexpr (GAGG) {
+    if (L.glds) {
+      for (uint32_t i = tid; i < GLDS_MAX; i += J_NT) s_gcnt[i] = 0;
+      for (uint32_t i = tid; i < GLDS_MAX * EXACT_MAXD; i += J_NT) s_gdig[i] = 0;
+      __syncthreads();
+    }
+  }
 
   if (LEAF_AGG && tid == 0) {
     s_cnt = 0;
@@ -727,7 +743,8 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
             }
           }
           if (ok) {
-            atomicAdd((unsigned long long*)&L.gcount[slot], (unsigned long long)h.mult);
+            if (GAGG && L.glds) atomicAdd(&s_gcnt[slot], (unsigned long long)h.mult);
+            else atomicAdd((unsigned long long*)&L.gcount[slot], (unsigned long long)h.mult);
             if (L.sum) {
               double hi, lo;
               term_of(L, cur, hi, lo);
@@ -736,8 +753,11 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
               bool fits = t.add(hi, L.lsb, L.D, (int64_t)h.mult);
               fits = t.add(lo, L.lsb, L.D, (int64_t)h.mult) && fits;
               if (!fits) bad = 1;
-              for (uint32_t q = 0; q < L.D; q++)
-                if (t.s[q]) atomicAdd((unsigned long long*)&L.gacc[slot * L.D + q], (unsigned long long)t.s[q]);
+              for (uint32_t q = 0; q < L.D; q++) {
+                if (!t.s[q]) continue;
+                if (GAGG && L.glds) atomicAdd((unsigned long long*)&s_gdig[slot * EXACT_MAXD + q], (unsigned long long)t.s[q]);
+                else atomicAdd((unsigned long long*)&L.gacc[slot * L.D + q], (unsigned long long)t.s[q]);
+              }
             }
           }
         } while (next_combo(L, h, cur));
@@ -746,6 +766,27 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
   }
 
   if (MODE == M_LEAF_B_AGG && bad) atomicOr(L.err, 1u);
+  if constexpr (GAGG) {
+    if (L.glds) {
+      // flush the block's groups; digits carried first, so every flushed
+      // digit is below 2^32 but the top one
+      __syncthreads();
+      for (uint32_t i = tid; i < L.gspace; i += J_NT) {
+        const unsigned long long c = s_gcnt[i];
+        if (!c) continue;
+        atomicAdd((unsigned long long*)&L.gcount[i], c);
+        if (L.sum) {
+          RegAcc t;
+          t.clear();
+#pragma unroll
+          for (int q = 0; q < EXACT_MAXD; q++) t.s[q] = s_gdig[i * EXACT_MAXD + q];
+          t.normalize(L.D);
+          for (uint32_t q = 0; q < L.D; q++)
+            if (t.s[q]) atomicAdd((unsigned long long*)&L.gacc[i * L.D + q], (unsigned long long)t.s[q]);
+        }
+      }
+    }
+  }
   if (LEAF_AGG) {
     if (bad) atomicOr(L.err, 1u);
     if (one_group) {
@@ -1535,6 +1576,8 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
   const uint64_t slots = impl == 3 ? space : cap;
   L.n_cols = n_cols;
   L.gmode = impl == 3 ? 1u : 2u;
+  L.glds = (impl == 3 && space <= GLDS_MAX) ? 1u : 0u;
+  L.gspace = (uint32_t)std::min<uint64_t>(space, GLDS_MAX);
   DBuf<uint64_t> cnt;
   DBuf<int64_t> acc;
   DBuf<uint32_t> tag;
