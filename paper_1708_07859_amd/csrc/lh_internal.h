@@ -92,6 +92,8 @@ uint32_t reduce_max_u32(const uint32_t* in, uint64_t n, hipStream_t s);
 // are below `range` (a histogram pass).
 void column_freq(const uint32_t* col, uint64_t n, uint32_t range, uint64_t& distinct, uint64_t& freq_max,
                  hipStream_t s);
+// Distinct values and the longest run of a sorted column.
+void sorted_run_stats(const uint32_t* sorted, uint64_t n, uint64_t& distinct, uint64_t& freq_max, hipStream_t s);
 // Indices i < n with flags[i] != 0, in order, into out (n entries); returns count.
 uint64_t select_flagged(const uint32_t* flags, uint64_t n, uint32_t* out, hipStream_t s);
 void iota_u32(uint32_t* out, uint64_t n, hipStream_t s);
@@ -177,6 +179,9 @@ struct lh_trie {
   uint64_t root_span = 0;
   lh::DBuf<uint64_t> root_bits;
   lh::DBuf<uint32_t> root_rank;
+  // two-level tries whose column statistics were taken: the rows sorted by
+  // (level 1, level 0), as level-1 and level-0 keys
+  lh::DBuf<uint32_t> tsorted[2];
   // rows in trie order (bag: every row; set: one per distinct tuple)
   lh::DBuf<uint32_t> skeys[LH_MAX_KEYS];   // per level
   std::vector<lh::DBuf<double>> annos;      // per annotation column

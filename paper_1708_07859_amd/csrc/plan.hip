@@ -72,6 +72,14 @@ lh_trie* filtered_or_reordered(const lh_trie* t, const uint32_t* level_order, co
   // columns of the trie's rows in the relation's own column order
   const uint32_t* keys[LH_MAX_KEYS];
   for (uint32_t l = 0; l < t->n_levels; l++) keys[t->level_order[l]] = t->skeys[l].p;
+  // the swapped order of a two-level trie whose rows were already sorted
+  // that way (by the column statistics): no sort at all
+  if (filt.empty() && t->n_levels == 2 && t->tsorted[0].p && level_order[0] == t->level_order[1] &&
+      level_order[1] == t->level_order[0]) {
+    keys[t->level_order[1]] = t->tsorted[0].p;
+    keys[t->level_order[0]] = t->tsorted[1].p;
+    return build_trie(t->n_rows, 2, keys, 0, nullptr, 0, nullptr, level_order, t->flags, nullptr, 0, s, 2);
+  }
   std::vector<const double*> annos;
   for (auto& a : t->annos) annos.push_back(a.p);
   std::vector<const uint32_t*> meta;

@@ -357,8 +357,15 @@ void column_freq(const uint32_t* col, uint64_t n, uint32_t range, uint64_t& dist
   DBuf<uint32_t> sorted(n, s);
   uint32_t* out = sorted.p;
   if (!sort_packed(&col, &bits, 1, n, nullptr, &out, s)) fail(LH_ERR_DEVICE, "column statistics: sort failed");
+  sorted_run_stats(sorted.p, n, distinct, freq_max, s);
+}
+
+void sorted_run_stats(const uint32_t* sorted, uint64_t n, uint64_t& distinct, uint64_t& freq_max, hipStream_t s) {
+  distinct = 0;
+  freq_max = 0;
+  if (!n) return;
   DBuf<uint32_t> heads(n, s), pos(n, s);
-  k_run_heads<<<grid_for(n), 256, 0, s>>>(sorted.p, n, heads.p);
+  k_run_heads<<<grid_for(n), 256, 0, s>>>(sorted, n, heads.p);
   LH_HIP(hipGetLastError());
   const uint64_t d = select_flagged(heads.p, n, pos.p, s);
   k_run_lengths<<<grid_for(d), 256, 0, s>>>(pos.p, d, n, heads.p);

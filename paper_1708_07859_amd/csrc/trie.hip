@@ -287,6 +287,22 @@ void ensure_column_stats(lh_trie* t, hipStream_t s) {
     t->col_distinct[0] = 0;
     t->col_freq_max[0] = 0;
   }
+  // A two-level trie without row columns: sort its rows by (level 1,
+  // level 0) (level 0 is in order already, so only level 1's bits are
+  // sorted) and keep them; the statistics come from the sorted runs and a
+  // copy of the trie in the swapped level order takes the rows unsorted.
+  if (t->n_levels == 2 && t->annos.empty() && t->meta.empty() && t->key_bits[0] + t->key_bits[1] <= 64 &&
+      t->n_rows) {
+    const uint32_t* cols[2] = {t->skeys[1].p, t->skeys[0].p};
+    const uint32_t bits[2] = {t->key_bits[1], t->key_bits[0]};
+    t->tsorted[0].alloc(t->n_rows, s);
+    t->tsorted[1].alloc(t->n_rows, s);
+    uint32_t* out[2] = {t->tsorted[0].p, t->tsorted[1].p};
+    sort_packed(cols, bits, 2, t->n_rows, nullptr, out, s, 1);
+    sorted_run_stats(t->tsorted[0].p, t->n_rows, t->col_distinct[1], t->col_freq_max[1], s);
+    t->col_stats = true;
+    return;
+  }
   for (uint32_t l = 1; l < t->n_levels; l++) {
     if (t->key_max[l] < (1u << 28)) {
       column_freq(t->skeys[l].p, t->n_rows, t->key_max[l], t->col_distinct[l], t->col_freq_max[l], s);
@@ -337,12 +353,22 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
   lc.n_levels = n_keys;
   std::vector<DBuf<uint32_t>> sorted;
   uint32_t* sorted_p[LH_MAX_KEYS];
+  // rows already in order: a set trie reads the input columns as they are
+  const bool in_order = sorted_tail >= n_keys && !need_perm && !bag && !sel;
   for (uint32_t l = 0; l < n_keys; l++) {
-    sorted.emplace_back(n, s);
-    sorted_p[l] = sorted.back().p;
-    lc.k[l] = sorted.back().p;
+    if (in_order) {
+      sorted.emplace_back();
+      sorted_p[l] = nullptr;
+      lc.k[l] = col[l];
+    } else {
+      sorted.emplace_back(n, s);
+      sorted_p[l] = sorted.back().p;
+      lc.k[l] = sorted.back().p;
+    }
   }
-  if (!sort_packed(col, t->key_bits, n_keys, n, need_perm ? perm.p : nullptr, sorted_p, s, sorted_tail)) {
+  if (in_order) {
+    // nothing to sort
+  } else if (!sort_packed(col, t->key_bits, n_keys, n, need_perm ? perm.p : nullptr, sorted_p, s, sorted_tail)) {
     if (!need_perm) perm.alloc(n, s);
     // a stable sort by the leading levels keeps the presorted tail's order
     lex_sort_perm(col, t->key_bits, n_keys - sorted_tail, n, perm.p, s);
