@@ -89,7 +89,7 @@ def main():
                     help="layout of the plain-policy run")
     ap.add_argument("--policy", default="both", choices=["both", "plain", "learned"],
                     help="both: time the plain rule, then the learned cost model (reported)")
-    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby", "dense"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby", "dense", "configs"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--card", type=int, default=1_000_000)
@@ -121,6 +121,8 @@ def main():
         return bench_groupby(args, lh, torch, synth)
     if args.workload == "dense":
         return bench_dense(args, lh, torch, synth)
+    if args.workload == "configs":
+        return bench_configs(args, lh, torch, synth)
     log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
     t0 = time.perf_counter()
     lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
@@ -650,6 +652,76 @@ def bench_dense(args, lh, torch, synth):
                       "results": res,
                       "roofline": {"bound": "mfma", "achieved": head["tflops"], "peak": 78.6, "unit": "TFLOP/s",
                                    "frac": round(head["tflops"] / 78.6, 4)}}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_configs(args, lh, torch, synth):
+    """The two other single-GPU workloads, timed as full steps (trie builds
+    from resident columns + plan + join + readback):
+    SpGEMM C(i,k) = SUM_j A(i,j) * A'(j,k), n = 4096, 10 distinct uniform
+    columns per row, U(-1,1) values, attribute order i,j,k; and the star
+    join with GROUP BY on 60M fact rows (Zipf 1.0 keys, dims of 2M / 500k /
+    100k / 10k rows, filters of 20% / 10% / 1%), under the plain rule and
+    the learned model."""
+    from paper_1708_07859_amd import learned as L
+    from tests import queries
+    lm, om, _ = L.load(args.weights or L.DEFAULT_WEIGHTS)
+    L.register(lm, om)
+
+    def devq(q):
+        return [{"keys": [lh.to_device(k) for k in a["keys"]],
+                 "annos": [lh.to_device(x) for x in a.get("annos", [])],
+                 "meta": [lh.to_device(m) for m in a.get("meta", [])], "bag": a.get("bag", False)}
+                for a in q["atoms"]]
+
+    def timed(q, dev, **kw):
+        def step():
+            tries = [lh.trie_build(a["keys"], a["annos"], a["meta"], bag=a["bag"]) for a in dev]
+            atoms = [(t, a["attrs"], a.get("anno", -1)) for t, a in zip(tries, q["atoms"])]
+            p = lh.plan(q["n_attrs"], atoms, out=q.get("out", []), group=q.get("group", []), agg=q["agg"],
+                        filters=q.get("filters", []), **kw)
+            r = lh.join_aggregate([p])[0]
+            out = r.to_host()
+            r.free()
+            p.free()
+            for t in tries:
+                t.free()
+            return out
+        for _ in range(max(1, args.warmup)):
+            out = step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1000 / args.steps, out
+
+    res = {}
+    a = synth.sparse_matrix(4096, 10, seed=1)
+    b = synth.sparse_matrix(4096, 10, seed=11)
+    q = queries.spgemm(a, b)
+    ms, out = timed(q, devq(q), attr_order=[0, 1, 2], policy="fixed")
+    res["spgemm 4096, order i,j,k"] = {"ms_per_step": round(ms, 3), "output_rows": len(out["counts"]),
+                                       "products": int(out["counts"].sum()),
+                                       "products_per_s": int(out["counts"].sum()) / (ms / 1000)}
+    log(f"spgemm: {res['spgemm 4096, order i,j,k']}")
+    sch = synth.star_schema()
+    q = queries.star(sch)
+    dev = devq(q)
+    del sch
+    rows = sum(len(x["keys"][0]) for x in q["atoms"])
+    for policy in ("plain", "learned"):
+        ms, out = timed(q, dev, policy=policy)
+        res[f"star 60M, {policy}"] = {"ms_per_step": round(ms, 3), "groups": len(out["counts"]),
+                                      "join_tuples": int(out["counts"].sum()), "input_rows": rows,
+                                      "rows_per_s": rows / (ms / 1000)}
+        log(f"star {policy}: {res[f'star 60M, {policy}']}")
+    head = res["star 60M, learned"]
+    out = {"metric": "join-aggregate input tuples/s, star GROUP BY and SpGEMM", "value": head["rows_per_s"],
+           "unit": "tuples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32+f64", "data": "synthetic",
+           "config": {"workload": "star join GROUP BY on 60M fact rows; SpGEMM n = 4096", "results": res}}
     print(json.dumps(out), flush=True)
 
 
