@@ -89,7 +89,7 @@ def main():
                     help="layout of the plain-policy run")
     ap.add_argument("--policy", default="both", choices=["both", "plain", "learned"],
                     help="both: time the plain rule, then the learned cost model (reported)")
-    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby", "dense", "configs"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby", "dense", "spgemm-star"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--card", type=int, default=1_000_000)
@@ -121,8 +121,8 @@ def main():
         return bench_groupby(args, lh, torch, synth)
     if args.workload == "dense":
         return bench_dense(args, lh, torch, synth)
-    if args.workload == "configs":
-        return bench_configs(args, lh, torch, synth)
+    if args.workload == "spgemm-star":
+        return bench_spgemm_star(args, lh, torch, synth)
     log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
     t0 = time.perf_counter()
     lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
@@ -655,7 +655,7 @@ def bench_dense(args, lh, torch, synth):
     print(json.dumps(out), flush=True)
 
 
-def bench_configs(args, lh, torch, synth):
+def bench_spgemm_star(args, lh, torch, synth):
     """The two other single-GPU workloads, timed as full steps (trie builds
     from resident columns + plan + join + readback):
     SpGEMM C(i,k) = SUM_j A(i,j) * A'(j,k), n = 4096, 10 distinct uniform

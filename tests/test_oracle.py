@@ -148,7 +148,7 @@ def test_spgemm_exact_small():
         assert s == float(Fraction(want[k], 2 ** 106))
 
 
-def test_spgemm_dense_product_cfg1_shape():
+def test_spgemm_dense_product_full_size_shape():
     """n = 4096, 10 nonzeros per row: structure equals the boolean product,
     values equal numpy's dense A @ B within a scale-aware bound, and the
     checksum 1'C1 = (1'A)(B1) holds exactly."""
