@@ -226,8 +226,22 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
   __shared__ long long sdig[HC * EXACT_MAXD];
   __shared__ uint32_t s_item, s_klo, s_khi;
   __shared__ uint32_t s_wsum[B_NW];
+  // products of a batch of B_NT entries of A's row, numbered by a block
+  // scan so that every thread takes an equal share (E's rows have skewed
+  // lengths, and one thread per entry would wait on the longest)
+  __shared__ uint32_t s_off[B_NT], s_kb[B_NT], s_ab[B_NT], s_ae[B_NT];
   const int tid = threadIdx.x;
   uint32_t bad = 0;
+  // owner of product idx: the last entry whose first product is <= idx
+  auto owner = [&](uint32_t idx) {
+    uint32_t lo = 0, n = B_NT;
+    while (n > 1) {
+      const uint32_t half = n >> 1;
+      lo = (s_off[lo + half] <= idx) ? lo + half : lo;
+      n -= half;
+    }
+    return lo;
+  };
   for (uint32_t sl = tid; sl < HC; sl += B_NT) {
     scnt[sl] = 0;
 #pragma unroll
@@ -251,20 +265,31 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
       const uint32_t nwords = (wend - w0 + 63) / 64;
       for (uint32_t sl = tid; sl < nwords; sl += B_NT) bm[sl] = 0;
       __syncthreads();
-      for (uint32_t q = qb + tid; q < qe; q += B_NT) {
+      for (uint32_t qs = qb; qs < qe; qs += B_NT) {
+        const uint32_t q = qs + tid;
+        uint32_t cnt = 0, kb = 0;
         uint32_t pe;
-        if (!find_j(I, I.a_j[q], pe)) continue;
-        uint32_t kb = I.e_off[pe], kend = I.e_off[pe + 1];
-        if (I.n_k > a.kw) {
-          kb = lower_bound_u32(I.e_k, kb, kend, w0);
-          kend = lower_bound_u32(I.e_k, kb, kend, wend);
+        if (q < qe && find_j(I, I.a_j[q], pe)) {
+          kb = I.e_off[pe];
+          uint32_t kend = I.e_off[pe + 1];
+          if (I.n_k > a.kw) {
+            kb = lower_bound_u32(I.e_k, kb, kend, w0);
+            kend = lower_bound_u32(I.e_k, kb, kend, wend);
+          }
+          cnt = kend - kb;
         }
-        for (uint32_t kp = kb; kp < kend; kp++) {
-          const uint32_t k = I.e_k[kp] - w0;
+        uint32_t tot;
+        const uint32_t off = block_excl_scan<uint32_t, B_NT>(cnt, s_wsum, tot);
+        s_off[tid] = off;
+        s_kb[tid] = kb;
+        __syncthreads();
+        for (uint32_t idx = tid; idx < tot; idx += B_NT) {
+          const uint32_t o = owner(idx);
+          const uint32_t k = I.e_k[s_kb[o] + (idx - s_off[o])] - w0;
           atomicOr(&bm[k >> 6], 1ull << (k & 63u));
         }
+        __syncthreads();
       }
-      __syncthreads();
       uint32_t m;
       {
         uint32_t c = 0;
@@ -291,17 +316,31 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
         }
         __syncthreads();
         const uint32_t klo = s_klo + w0, khi = s_khi + w0;
-        for (uint32_t q = qb + tid; q < qe; q += B_NT) {
+        for (uint32_t qs = qb; qs < qe; qs += B_NT) {
+          const uint32_t q = qs + tid;
+          uint32_t cnt = 0, kb = 0, ab = 0, ae = 0;
           uint32_t pe;
-          if (!find_j(I, I.a_j[q], pe)) continue;
-          uint32_t ab, ae;
-          rows_of(I.a_run, q, ab, ae);
-          uint32_t kb = I.e_off[pe], kend = I.e_off[pe + 1];
-          if (m > HC || I.n_k > a.kw) {
-            kb = lower_bound_u32(I.e_k, kb, kend, klo);
-            kend = lower_bound_u32(I.e_k, kb, kend, khi);
+          if (q < qe && find_j(I, I.a_j[q], pe)) {
+            rows_of(I.a_run, q, ab, ae);
+            kb = I.e_off[pe];
+            uint32_t kend = I.e_off[pe + 1];
+            if (m > HC || I.n_k > a.kw) {
+              kb = lower_bound_u32(I.e_k, kb, kend, klo);
+              kend = lower_bound_u32(I.e_k, kb, kend, khi);
+            }
+            cnt = kend - kb;
           }
-          for (uint32_t kp = kb; kp < kend; kp++) {
+          uint32_t tot;
+          const uint32_t off = block_excl_scan<uint32_t, B_NT>(cnt, s_wsum, tot);
+          s_off[tid] = off;
+          s_kb[tid] = kb;
+          s_ab[tid] = ab;
+          s_ae[tid] = ae;
+          __syncthreads();
+          for (uint32_t idx = tid; idx < tot; idx += B_NT) {
+            const uint32_t own = owner(idx);
+            const uint32_t kp = s_kb[own] + (idx - s_off[own]);
+            const uint32_t ab = s_ab[own], ae = s_ae[own];
             const uint32_t k = I.e_k[kp] - w0;
             const uint64_t word = bm[k >> 6];
             const uint32_t sl = pre[k >> 6] + (uint32_t)__popcll(word & ((1ull << (k & 63u)) - 1ull)) - r0;
@@ -319,6 +358,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
                   if (!ok) bad = 1;
                 }
           }
+          __syncthreads();
         }
         __syncthreads();
         const uint32_t nw = min(HC, m - r0);
@@ -340,11 +380,6 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
   if (bad) atomicOr(a.err, 1u);
 }
 
-// Inner-product rows: one block per row.  A's row is marked in an LDS
-// bitmap over j with per-word rank prefixes (the position of j in the row);
-// thread by thread, the k nodes of E transposed are walked in k order, each
-// column's j probed in the bitmap and the matching products summed exactly
-// in registers; non-empty outputs are placed by a block scan.
 // Inner-product rows: one block per row.  A's row is marked in an LDS
 // bitmap over j with per-word rank prefixes (the position of j in the row).
 // E transposed is then streamed chunk by chunk (256 columns k at a time):
