@@ -742,7 +742,7 @@ unsigned grid_for(uint64_t n) {
 struct Tuning {
   uint32_t light_max = 128;   // products above which a matrix row is heavy (light hash: 2x slots)
   uint32_t blocks_per_cu = 2; // persistent grid
-  uint32_t inner_ratio = 512; // heavy row in inner-product form when products * ratio >= nnz(E)
+  uint32_t inner_ratio = 16;  // heavy row in inner-product form when products * ratio >= nnz(E)
 };
 
 // E transposed (levels k, j) of every matrix instance, built once per batch
@@ -865,7 +865,7 @@ std::string signature(const BatchState& b) {
   uint64_t rows_log = 0, ub_log = 0;
   while ((1ull << rows_log) < b.R) rows_log++;
   while ((1ull << ub_log) < b.UB) ub_log++;
-  os << "v3_" << prop.gcnArchName << "_cu" << prop.multiProcessorCount << "_inst" << b.plans.size() << "_r" << rows_log
+  os << "v4_" << prop.gcnArchName << "_cu" << prop.multiProcessorCount << "_inst" << b.plans.size() << "_r" << rows_log
      << "_u" << ub_log;
   return os.str();
 }
@@ -1034,7 +1034,7 @@ void autotune(std::unique_ptr<BatchState>& cur, lh_plan_t* const* plans, uint32_
     return;
   }
   const uint32_t lights[] = {64, 128};
-  const uint32_t ratios[] = {64, 512, 4096};
+  const uint32_t ratios[] = {4, 16, 64};
   const uint32_t bpcs[] = {1, 2, 4};
   const std::vector<const lh_plan_t*> pv(plans, plans + n);
   std::shared_ptr<Transposes> tr = cur->tr;
