@@ -13,11 +13,11 @@
 //    row produces in an LDS bitmap, whose popcount prefixes rank them; the
 //    products are then summed exactly in LDS accumulators indexed by rank,
 //    512 ranks at a time, each window's products cut out of the B rows by
-//    binary search, and emitted in k order;
+//    binary search and spread evenly over the block, and emitted in k order;
 //  * rows with many products relative to the size of E are taken by a
 //    block in inner-product form: A's row becomes an LDS bitmap over j and
-//    one thread per output k walks column k of E (a transposed copy of E
-//    built once per batch), summing exactly in registers, with no atomics.
+//    the entries of E transposed (built once per batch) are streamed
+//    through it, matches adding to per-column LDS accumulators.
 // Workers pull items from two device queues (heavy rows first, longest
 // first), so one launch balances thousands of instances.  The launch and
 // its queue resets are captured once in a hipGraph and replayed.  Sums are
@@ -201,7 +201,9 @@ __device__ __forceinline__ bool lds_add_term(long long* slots, double v, int32_t
 // of the rank window is found from the bitmap, every B row is cut to that
 // range by two binary searches, and the products in it add their exact
 // digits to LDS accumulators indexed by rank - r0, which are emitted in
-// order and cleared.  No global atomics.
+// order and cleared.  No global atomics.  In both passes the products of
+// B_NT entries of A's row at a time are numbered by a block scan and dealt
+// out evenly to the threads.
 constexpr uint32_t HC = 512;
 
 __device__ __forceinline__ uint32_t rank_select(const unsigned long long* bm, const uint32_t* pre, uint32_t nwords,
