@@ -455,7 +455,7 @@ def bench_q5(args, lh, torch, synth):
         assert np.array_equal(out["keys"], ref["keys"]) and np.array_equal(out["counts"], ref["counts"])
         assert np.all(np.abs(out["sums"] - ref["sums"]) <= 1e-9 * np.abs(ref["sums"]))
         torch.cuda.synchronize()
-        if name == "chosen":
+        if name.startswith("chosen"):
             lh.profile_reset()
             lh.profile_enable(True)
         t0 = time.perf_counter()
@@ -463,9 +463,10 @@ def bench_q5(args, lh, torch, synth):
             step(g, policy)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1000 / args.steps
-        if name == "chosen":
+        if name.startswith("chosen"):
             lh.profile_enable(False)
             prof = lh.profile_read()
+            log(f"{name}, top scopes:")
             top = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:12]
             for k, v in top:
                 log(f"  {k:22s} {v['total_ms'] / args.steps:8.2f} ms/step  launches {v['launches'] // args.steps}")
