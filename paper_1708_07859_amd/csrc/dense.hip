@@ -23,11 +23,13 @@ namespace {
 std::mutex g_blas_mu;
 rocblas_handle g_blas[64] = {};
 
+// The handle of the current device, bound to stream s.  The caller holds
+// g_blas_mu for as long as it uses the handle (one handle per device is
+// shared by every thread).
 rocblas_handle blas_handle(hipStream_t s) {
   int dev = 0;
   LH_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) fail(LH_ERR_DEVICE, "dense: device id out of range");
-  std::lock_guard<std::mutex> lk(g_blas_mu);
   if (!g_blas[dev] && rocblas_create_handle(&g_blas[dev]) != rocblas_status_success)
     fail(LH_ERR_DEVICE, "dense: rocblas_create_handle failed");
   if (rocblas_set_stream(g_blas[dev], s) != rocblas_status_success) fail(LH_ERR_DEVICE, "dense: rocblas_set_stream failed");
@@ -131,6 +133,7 @@ lh_result_impl* run_dense(const lh_plan_t* p, hipStream_t s) {
   for (uint32_t c = 0; c < n_cols; c++) res->cols[c].alloc(n, s);
   res->counts.alloc(n, s);
   res->sums.alloc(n, s);
+  std::unique_lock<std::mutex> lk(g_blas_mu);
   rocblas_handle h = blas_handle(s);
   const double one = 1.0, zero = 0.0;
   rocblas_status st;
@@ -155,6 +158,7 @@ lh_result_impl* run_dense(const lh_plan_t* p, hipStream_t s) {
                          d.a, ldp, &zero, res->sums.p, (rocblas_int)d.cols);
     }
   }
+  lk.unlock();
   if (st != rocblas_status_success) fail(LH_ERR_DEVICE, "dense: rocBLAS call failed");
   if (n) {
     const uint64_t b = std::min<uint64_t>((n + 255) / 256, 16384);
