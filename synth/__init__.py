@@ -272,6 +272,65 @@ def q5_schema(sf=1.0, seed=5):
 
 
 # --------------------------------------------------------------------------
+# Voter classification (section 7)
+# --------------------------------------------------------------------------
+
+def voter_schema(n_voters=7_503_555, n_precincts=2_751, seed=7):
+    """Two tables shaped like the voter classification application of
+    section 7 (its dataset is not available): voters keyed by a dense id,
+    each registered in a precinct (Zipf s = 0.6 over precincts), and the
+    precincts keyed by a dense id.
+      voters:    precinct, sex (3 codes), race (7), age in [18, 100),
+                 age_group = (age - 18) // 10 (9 codes), party (4),
+                 age_std = (age - 50) / 20 (a numeric feature),
+                 voted (label 0/1)
+      precincts: county (100 codes), district (13), urban (2)
+    The label is a Bernoulli draw whose probability adds per-code offsets
+    of age group, party and the precinct's urban flag (clipped to
+    [0.02, 0.98]), so the classes depend on the features."""
+    rng = rng_for(seed)
+    n = n_voters
+    precinct = zipf_keys(rng, n_precincts, 0.6, n)
+    sex = rng.choice(3, n, p=[0.52, 0.46, 0.02]).astype(np.uint32)
+    race = rng.choice(7, n, p=[0.62, 0.17, 0.09, 0.06, 0.03, 0.02, 0.01]).astype(np.uint32)
+    age = rng.integers(18, 100, n).astype(np.uint32)
+    age_group = ((age - 18) // 10).astype(np.uint32)
+    party = rng.choice(4, n, p=[0.38, 0.33, 0.25, 0.04]).astype(np.uint32)
+    age_std = (age.astype(np.float64) - 50.0) / 20.0
+    county = rng.integers(0, 100, n_precincts).astype(np.uint32)
+    district = rng.integers(0, 13, n_precincts).astype(np.uint32)
+    urban = rng.integers(0, 2, n_precincts).astype(np.uint32)
+    t_age = rng.random(9) * 0.4
+    t_party = rng.random(4) * 0.3
+    t_urban = np.array([0.0, 0.15])
+    prob = np.clip(0.1 + t_age[age_group] + t_party[party] + t_urban[urban[precinct]], 0.02, 0.98)
+    voted = (rng.random(n) < prob).astype(np.float64)
+    voters = {"id": np.arange(n, dtype=np.uint32), "precinct": precinct, "sex": sex, "race": race, "age": age,
+              "age_group": age_group, "party": party, "age_std": age_std, "voted": voted}
+    precincts = {"id": np.arange(n_precincts, dtype=np.uint32), "county": county, "district": district,
+                 "urban": urban}
+    return {"voters": voters, "precincts": precincts}
+
+
+# The voter pipeline's selections and encoded columns: id column 0 is the
+# voter id, 1 the precinct id of a result row.
+VOTER_FILTER = {"age_lo": 21, "age_hi": 200, "district_lo": 0, "district_hi": 10}
+
+
+def voter_features(schema):
+    """The source columns of the encoding, in feature order."""
+    v, p = schema["voters"], schema["precincts"]
+    return [{"codes": v["sex"], "card": 3, "by": 0},
+            {"codes": v["race"], "card": 7, "by": 0},
+            {"codes": v["age_group"], "card": 9, "by": 0},
+            {"codes": v["party"], "card": 4, "by": 0},
+            {"codes": p["county"], "card": 100, "by": 1},
+            {"codes": p["district"], "card": 13, "by": 1},
+            {"codes": p["urban"], "card": 2, "by": 1},
+            {"values": v["age_std"], "by": 0}]
+
+
+# --------------------------------------------------------------------------
 # Intersection micro-benchmark sets
 # --------------------------------------------------------------------------
 
