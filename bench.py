@@ -89,12 +89,13 @@ def main():
                     help="layout of the plain-policy run")
     ap.add_argument("--policy", default="both", choices=["both", "plain", "learned"],
                     help="both: time the plain rule, then the learned cost model (reported)")
-    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby", "dense", "spgemm-star"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby", "dense", "spgemm-star", "voter"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--card", type=int, default=1_000_000)
     ap.add_argument("--pairs", type=int, default=256)
     ap.add_argument("--sf", type=float, default=10.0)
+    ap.add_argument("--voters", type=int, default=7_503_555)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU layout is a design "
@@ -123,6 +124,8 @@ def main():
         return bench_dense(args, lh, torch, synth)
     if args.workload == "spgemm-star":
         return bench_spgemm_star(args, lh, torch, synth)
+    if args.workload == "voter":
+        return bench_voter(args, lh, torch, synth)
     log(f"generating R-MAT scale {args.scale}, 2^{args.samples_log2} samples")
     t0 = time.perf_counter()
     lo, hi = synth.rmat_edges(args.scale, 1 << args.samples_log2, seed=2)
@@ -724,6 +727,115 @@ def bench_spgemm_star(args, lh, torch, synth):
            "dtype": "u32+f64", "data": "synthetic",
            "config": {"workload": "star join GROUP BY on 60M fact rows; SpGEMM n = 4096", "results": res}}
     print(json.dumps(out), flush=True)
+
+
+def bench_voter(args, lh, torch, synth):
+    """The voter classification application of section 7 on synthetic
+    tables of its sizes (7,503,555 voters, 2,751 precincts): the filtered
+    join, the categorical encoding of its result, the design matrix's two
+    tries and five iterations of logistic regression on them.  The base
+    tables' tries are resident before the timed region (loaded data); every
+    step runs the whole application.  Roofline: the two training kernels
+    against HBM, with algorithmic bytes per launch
+      lr_rows: nnz * (4 B feature + 8 B value) + n * (4 B row + 4 B offset + 8 B label + 8 B residual)
+      lr_cols: nnz * (4 B row + 8 B value + 8 B residual) + chunks * 8 B."""
+    import numpy as np
+
+    from paper_1708_07859_amd import pipeline
+
+    log(f"voter tables: {args.voters} voters, 2751 precincts")
+    d = synth.voter_schema(args.voters, 2751, seed=7)
+    feats = synth.voter_features(d)
+    t = pipeline.VoterTables(d, feats)
+    torch.cuda.synchronize()
+    f = synth.VOTER_FILTER
+    for _ in range(max(1, args.warmup)):
+        out = pipeline.run(t, iters=5, step=0.5, **f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = pipeline.run(t, iters=5, step=0.5, **f)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000 / args.steps
+    n_rows, nf = out["n_rows"], out["n_feat"]
+    loss = out["loss"].cpu().numpy().tolist()
+    log(f"  {ms:.2f} ms per pipeline; {n_rows} rows x {nf} features; loss {loss}")
+
+    # phase split (one extra run, synchronised between phases)
+    phases = {}
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    res = pipeline.sql_phase(t, **f)
+    torch.cuda.synchronize()
+    c1 = time.perf_counter()
+    rows, fe, vals, _ = lh.encode(res.key_columns(), 0, t.features)
+    torch.cuda.synchronize()
+    c2 = time.perf_counter()
+    res.free()
+    xr, xc = pipeline.design_tries(rows, fe, vals)
+    torch.cuda.synchronize()
+    c3 = time.perf_counter()
+    del rows, fe, vals
+    w = torch.zeros(nf, dtype=torch.float64, device="cuda")
+    lh.logreg_fit(xr, xc, t.y, w, 5, 0.5)
+    torch.cuda.synchronize()
+    c4 = time.perf_counter()
+    phases = {"sql_ms": round((c1 - c0) * 1000, 3), "encode_ms": round((c2 - c1) * 1000, 3),
+              "design_tries_ms": round((c3 - c2) * 1000, 3), "logreg_5_iters_ms": round((c4 - c3) * 1000, 3)}
+    log(f"  phases {phases}")
+    nnz = xr.info()["level_size"][1]
+    n0 = xr.info()["level_size"][0]
+    # kernel times of the training loop, on the stream the kernels run on
+    lh.profile_reset()
+    lh.profile_enable(True)
+    w = torch.zeros(nf, dtype=torch.float64, device="cuda")
+    lh.logreg_fit(xr, xc, t.y, w, 5, 0.5)
+    torch.cuda.synchronize()
+    lh.profile_enable(False)
+    prof = lh.profile_read()
+    _, foffs = xc.read_level(0)
+    chunks = int(np.sum((np.diff(foffs.astype(np.int64)) + 2047) // 2048))
+    xr.free()
+    xc.free()
+    t.free()
+    alg = {"lr_rows": nnz * 12 + n0 * 24, "lr_cols": nnz * 20 + chunks * 8}
+    kern = {}
+    for k, b in alg.items():
+        e = prof.get(k)
+        if e and e["launches"]:
+            avg = e["total_ms"] / e["launches"]
+            kern[k] = {"avg_ms": round(avg, 4), "alg_bytes": int(b), "GBs": round(b / (avg / 1000) / 1e9, 1)}
+    log(f"  kernels {kern}")
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"]) if kern else None
+    roof = None
+    if dom:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": kern[dom]["GBs"], "peak": 8000.0, "unit": "GB/s",
+                "frac": round(kern[dom]["GBs"] / 8000.0, 4), "traffic": None}
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import ml
+        m = 300_000
+        ds = synth.voter_schema(m, 2751, seed=7)
+        c0 = time.perf_counter()
+        vid, pid = ml.sql_phase(ds["voters"], ds["precincts"], **f)
+        r_, f_, v_, nf_ = ml.encode([vid, pid], 0, synth.voter_features(ds))
+        row_ids, X = ml.design_matrix(r_, f_, v_, nf_)
+        ml.logreg(X, ds["voters"]["voted"][row_ids], np.zeros(nf_), 5, 0.5)
+        sec = time.perf_counter() - c0
+        cpu = {"value": round(m / sec, 1), "unit": "voters/s", "cores": torch.get_num_threads(), "kind": "oracle",
+               "sample": f"{m} voters, the same pipeline (dense design matrix), {sec:.2f} s"}
+        log(f"  cpu oracle {cpu}")
+    value = args.voters / (ms / 1000)
+    outj = {"metric": "voter classification pipeline (SQL + encoding + 5 logistic regression iterations), voters/s",
+            "value": round(value, 1), "unit": "voters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"voter classification, {args.voters} voters x 2751 precincts, "
+                                   f"{n_rows} selected rows, {nf} features, {nnz} design-matrix entries",
+                       "phases": phases, "kernels": kern},
+            "roofline": roof, "cpu_baseline": cpu}
+    print(json.dumps(outj), flush=True)
 
 
 def bench_copy(args, torch):

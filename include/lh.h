@@ -348,6 +348,64 @@ lh_status lh_ghd_for_query(const lh_query* q, lh_ghd* out);
  * LH_ERR_OVERFLOW when a count reaches 2^53. */
 lh_status lh_ghd_join_aggregate(const lh_query* q, const lh_ghd* g, void* hip_stream, lh_result** out);
 
+/* ---- a mixed SQL + ML pipeline (section 7) --------------------------------
+ * The SQL phase is an ordinary query (lh_plan + lh_join_aggregate) whose
+ * output columns identify, per result row, the rows of the tables it
+ * joined.  lh_encode turns that result into the design matrix as (row,
+ * feature, value) triples; lh_trie_build over them gives the matrix's tries,
+ * and lh_logreg_fit trains on those tries directly. */
+#define LH_ENC_MAX_IDS  8u
+#define LH_ENC_MAX_COLS 32u
+
+/* One source column of the encoding, read at ids[by][r] for result row r.
+ * Exactly one of codes (categorical: one indicator feature per code) and
+ * values (numeric: one feature carrying the value) is set. */
+typedef struct {
+  const uint32_t* codes;    /* DEVICE, n_ids codes, each < card; or NULL */
+  const double* values;     /* DEVICE, n_ids values; or NULL */
+  uint32_t card;            /* categorical: number of codes (>= 1) */
+  uint32_t by;              /* which id column indexes this column (< n_id_cols) */
+  uint64_t n_ids;           /* entries of codes / values */
+} lh_feature_col;
+
+/* Categorical feature encoding (section 7, the feature engineering phase).
+ * Features are numbered in column order: the bias feature 0 (bias = 1),
+ * then each column's block (card ids for a categorical column, one for a
+ * numeric one).  Result row r (0 <= r < n) yields slots = bias + n_cols
+ * triples, written at r * slots + k of the DEVICE outputs (n * slots
+ * entries each): out_row = ids[row_col][r]; slot k = 0 of a biased
+ * encoding is (feature 0, value 1); the slot of a categorical column is
+ * (its base + code, 1), that of a numeric column (its base, value).
+ * ids is a HOST array of n_id_cols DEVICE columns of n entries (e.g. an
+ * lh_result's out_keys); cols is a HOST array.  *n_feat (host) receives
+ * the number of features.  Errors: LH_ERR_INVALID for NULL arguments,
+ * n_id_cols outside 1..8, more than 32 columns, row_col or by out of
+ * range, a column with both or neither of codes and values, card 0, or,
+ * found on the device, an id >= n_ids or a code >= card (the outputs are
+ * then unspecified); LH_ERR_OVERFLOW for 2^32 features or more. */
+lh_status lh_encode(uint64_t n, uint32_t n_id_cols, const uint32_t* const* ids, uint32_t row_col, uint32_t n_cols,
+                    const lh_feature_col* cols, uint32_t bias, uint32_t* out_row, uint32_t* out_feat,
+                    double* out_val, uint32_t* n_feat, void* hip_stream);
+
+/* Logistic regression by full-batch gradient descent over a design matrix X
+ * held as tries (section 7, the machine-learning phase): x_rows is the
+ * two-level bag trie of (row, feature) with X's entries in annotation
+ * column anno, x_cols the trie of the same relation with its levels
+ * swapped (both from lh_trie_build; duplicate (row, feature) pairs add
+ * up).  The n training rows are x_rows' level-0 keys.  y (DEVICE) holds
+ * the label of row id r at y[r] (n_y entries); w (DEVICE, n_feat entries)
+ * holds the initial weights and receives the final ones.  Each of iters
+ * iterations computes z = X w, p = 1 / (1 + exp(-z)), g = X^T (p - y) / n
+ * and w = w - step * g.  loss (DEVICE, iters entries, may be NULL)
+ * receives the mean log-loss, log(1 + exp(z)) - y z, at the start of each
+ * iteration.  Sums run in a fixed order, so results repeat exactly.  No
+ * training rows: w is unchanged and each loss is 0.  Errors: LH_ERR_INVALID
+ * for NULL arguments, tries that are not two-level bag tries with column
+ * anno, level orders that are not swapped, different row counts, a row id
+ * >= n_y or a feature id >= n_feat. */
+lh_status lh_logreg_fit(const lh_trie* x_rows, const lh_trie* x_cols, uint32_t anno, const double* y, uint64_t n_y,
+                        uint32_t n_feat, uint32_t iters, double step, double* w, double* loss, void* hip_stream);
+
 /* Device allocations currently held by the library (leak checks). */
 long lh_live_allocations(void);
 

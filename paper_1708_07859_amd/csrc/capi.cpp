@@ -174,7 +174,7 @@ lh_status lh_trie_build(const lh_relation_desc* rel, void* hip_stream, lh_trie**
     }
     hipStream_t s = (hipStream_t)hip_stream;
     lh_trie* t = build_trie(rel->n_rows, rel->n_keys, rel->keys, rel->n_annos, rel->annos, rel->n_meta, rel->meta, lo,
-                            rel->flags, nullptr, 0, s);
+                            rel->flags, nullptr, 0, s, 0, true);
     track(g_tries, t);
     *out = t;
   });
@@ -397,5 +397,23 @@ lh_status lh_ghd_join_aggregate(const lh_query* q, const lh_ghd* g, void* hip_st
 }
 
 long lh_live_allocations(void) { return live_allocations(); }
+
+lh_status lh_encode(uint64_t n, uint32_t n_id_cols, const uint32_t* const* ids, uint32_t row_col, uint32_t n_cols,
+                    const lh_feature_col* cols, uint32_t bias, uint32_t* out_row, uint32_t* out_feat,
+                    double* out_val, uint32_t* n_feat, void* hip_stream) {
+  return guard([&] {
+    if (!ids || !n_feat || (n_cols && !cols)) fail(LH_ERR_INVALID, "NULL argument");
+    *n_feat = encode_features(n, n_id_cols, ids, row_col, n_cols, cols, bias, out_row, out_feat, out_val,
+                              (hipStream_t)hip_stream);
+  });
+}
+
+lh_status lh_logreg_fit(const lh_trie* x_rows, const lh_trie* x_cols, uint32_t anno, const double* y, uint64_t n_y,
+                        uint32_t n_feat, uint32_t iters, double step, double* w, double* loss, void* hip_stream) {
+  return guard([&] {
+    if (!tracked(g_tries, x_rows) || !tracked(g_tries, x_cols)) fail(LH_ERR_INVALID, "X is not a live lh_trie");
+    logreg_fit(x_rows, x_cols, anno, y, n_y, n_feat, iters, step, w, loss, (hipStream_t)hip_stream);
+  });
+}
 
 }  // extern "C"

@@ -92,6 +92,14 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s);
 // Dense relations under LH_DENSE_BLAS: mark the plan for a BLAS product.
 void plan_dense(const lh_query* q, lh_plan_t* p, hipStream_t s);
 lh_result_impl* run_dense(const lh_plan_t* p, hipStream_t s);
+
+// Feature encoding of a join result and logistic regression on tries
+// (ml.hip); the C ABI's lh_encode and lh_logreg_fit after validation.
+uint32_t encode_features(uint64_t n, uint32_t n_id_cols, const uint32_t* const* ids, uint32_t row_col,
+                         uint32_t n_cols, const lh_feature_col* cols, uint32_t bias, uint32_t* out_row,
+                         uint32_t* out_feat, double* out_val, hipStream_t s);
+void logreg_fit(const lh_trie* x_rows, const lh_trie* x_cols, uint32_t anno, const double* y, uint64_t n_y,
+                uint32_t n_feat, uint32_t iters, double step, double* w, double* loss, hipStream_t s);
 // Batched execution of many plans; returns false (and does nothing) when
 // the plans are not all of a shape the batched executor handles.
 bool run_batch(lh_plan_t* const* plans, uint32_t n, hipStream_t s, std::vector<lh_result_impl*>& out);

@@ -200,10 +200,13 @@ constexpr uint32_t RESULT_MAGIC = 0x52534c54u;
 // level_order maps levels to key columns.
 // sorted_tail: the input rows (after `sel`) are already in lexicographic
 // order of the last sorted_tail levels, which then need no sort passes.
+// detect_sorted (with sorted_tail 0): find that tail with one pass over the
+// key columns first.
 lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* keys,
                     uint32_t n_annos, const double* const* annos, uint32_t n_meta,
                     const uint32_t* const* meta, const uint32_t* level_order, uint32_t flags,
-                    const uint32_t* sel, uint64_t n_sel, hipStream_t s, uint32_t sorted_tail = 0);
+                    const uint32_t* sel, uint64_t n_sel, hipStream_t s, uint32_t sorted_tail = 0,
+                    bool detect_sorted = false);
 
 // Column statistics (col_distinct, col_freq_max), computed once per trie.
 void ensure_column_stats(lh_trie* t, hipStream_t s);

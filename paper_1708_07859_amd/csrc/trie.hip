@@ -101,6 +101,24 @@ __global__ __launch_bounds__(TB_NT) void k_emit_levels(EmitArgs a, uint64_t n) {
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
+// Bit t-1 of *mask stays set while rows i-1, i are in lexicographic order
+// of the last t levels (equal tuples are in order), for every i.
+__global__ void k_sorted_tails(LevelCols c, uint64_t n, uint32_t* mask) {
+  const int K = (int)c.n_levels;
+  const uint32_t full = (1u << K) - 1;
+  uint32_t m = full;
+  for (uint64_t i = 1 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    bool ord = true;  // order of the suffix from level l on
+    for (int l = K - 1; l >= 0; l--) {
+      const uint32_t a = c.k[l][i - 1], b = c.k[l][i];
+      ord = a < b || (a == b && ord);
+      if (!ord) m &= ~(1u << (K - 1 - l));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) m &= (uint32_t)__shfl_xor((int)m, o, 64);
+  if ((threadIdx.x & 63) == 0 && m != full) atomicAnd(mask, m);
+}
+
 __global__ void k_line_samples(const uint32_t* keys, uint64_t n_samp, uint32_t* samp) {
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_samp; j += (uint64_t)gridDim.x * blockDim.x)
     samp[j] = keys[j << LINE_SHIFT];
@@ -314,10 +332,29 @@ void ensure_column_stats(lh_trie* t, hipStream_t s) {
   t->col_stats = true;
 }
 
+// The most trailing levels whose lexicographic order the rows already
+// follow (0: not even the last level's).
+static uint32_t presorted_tail(const uint32_t* const* col, uint32_t n_keys, uint64_t n, hipStream_t s) {
+  LevelCols c{};
+  c.n_levels = n_keys;
+  for (uint32_t l = 0; l < n_keys; l++) c.k[l] = col[l];
+  DBuf<uint32_t> m(1, s);
+  fill_u32(m.p, (1u << n_keys) - 1, 1, s);
+  {
+    ProfScope ps("trie_presorted", s, n, 0);
+    k_sorted_tails<<<grid_for(n), 256, 0, s>>>(c, n, m.p);
+    LH_HIP(hipGetLastError());
+  }
+  const uint32_t mask = read_scalar(m.p, s);
+  for (uint32_t t = n_keys; t >= 1; t--)
+    if (mask >> (t - 1) & 1u) return t;
+  return 0;
+}
+
 lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* keys, uint32_t n_annos,
                     const double* const* annos, uint32_t n_meta, const uint32_t* const* meta,
                     const uint32_t* level_order, uint32_t flags, const uint32_t* sel, uint64_t n_sel,
-                    hipStream_t s, uint32_t sorted_tail) {
+                    hipStream_t s, uint32_t sorted_tail, bool detect_sorted) {
   const uint64_t n = sel ? n_sel : n_rows;
   sorted_tail = std::min(sorted_tail, n_keys);
   if (n >= (1ull << 32) - 1) fail(LH_ERR_OVERFLOW, "trie build: 2^32 - 1 rows or more");
@@ -344,6 +381,8 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
     t->key_bits[l] = bitlen(t->key_max[l]);
   }
 
+  if (detect_sorted && sorted_tail == 0 && n > 1) sorted_tail = presorted_tail(col, n_keys, n, s);
+
   // The permutation is needed only to carry annotation and meta columns.
   // Keys that pack into one word are sorted as such and unpacked into the
   // sorted columns (no gathers); wider keys take the multi-pass sort.
@@ -353,8 +392,11 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
   lc.n_levels = n_keys;
   std::vector<DBuf<uint32_t>> sorted;
   uint32_t* sorted_p[LH_MAX_KEYS];
-  // rows already in order: a set trie reads the input columns as they are
+  // rows already in order: a set trie reads the input columns as they are;
+  // other tries copy them (a bag keeps its sorted columns) with the
+  // identity permutation
   const bool in_order = sorted_tail >= n_keys && !need_perm && !bag && !sel;
+  const bool copy_order = sorted_tail >= n_keys && !in_order;
   for (uint32_t l = 0; l < n_keys; l++) {
     if (in_order) {
       sorted.emplace_back();
@@ -368,6 +410,10 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
   }
   if (in_order) {
     // nothing to sort
+  } else if (copy_order) {
+    for (uint32_t l = 0; l < n_keys && n; l++)
+      LH_HIP(hipMemcpyAsync(sorted_p[l], col[l], n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (need_perm) iota_u32(perm.p, n, s);
   } else if (!sort_packed(col, t->key_bits, n_keys, n, need_perm ? perm.p : nullptr, sorted_p, s, sorted_tail)) {
     if (!need_perm) perm.alloc(n, s);
     // a stable sort by the leading levels keeps the presorted tail's order

@@ -141,6 +141,16 @@ class Ghd(C.Structure):
     ]
 
 
+class FeatureCol(C.Structure):
+    _fields_ = [
+        ("codes", C.c_void_p),
+        ("values", C.c_void_p),
+        ("card", C.c_uint32),
+        ("by", C.c_uint32),
+        ("n_ids", C.c_uint64),
+    ]
+
+
 # Every entry point declared in include/lh.h, with its ctypes signature.
 SIGNATURES = {
     "lh_trie_build": ([C.POINTER(RelationDesc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
@@ -178,6 +188,10 @@ SIGNATURES = {
     "lh_ghd_for_query": ([C.POINTER(Query), C.POINTER(Ghd)], C.c_int),
     "lh_ghd_join_aggregate": ([C.POINTER(Query), C.POINTER(Ghd), C.c_void_p, C.POINTER(C.POINTER(Result))],
                               C.c_int),
+    "lh_encode": ([C.c_uint64, C.c_uint32, C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32, C.POINTER(FeatureCol),
+                   C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32), C.c_void_p], C.c_int),
+    "lh_logreg_fit": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
+                       C.c_double, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
 }
 
 
@@ -387,6 +401,19 @@ def plan(n_attrs, atoms, out=(), group=(), agg="count", filters=(), attr_order=N
     return Plan(out_h.value, [a[0] for a in atoms])
 
 
+class _DevCol:
+    """A device column owned by someone else (a result's key column)."""
+
+    def __init__(self, ptr, n):
+        self.ptr, self.n = ptr, n
+
+    def data_ptr(self):
+        return self.ptr or 0
+
+    def numel(self):
+        return self.n
+
+
 class JoinResult:
     def __init__(self, ptr):
         self.ptr = ptr
@@ -394,6 +421,12 @@ class JoinResult:
     @property
     def n_rows(self):
         return self.ptr.contents.n_rows
+
+    def key_columns(self):
+        """The result's output columns as device pointers wrapped for
+        lh_encode (objects with data_ptr() and numel())."""
+        r = self.ptr.contents
+        return [_DevCol(r.out_keys[c], r.n_rows) for c in range(r.n_cols)]
 
     def to_host(self):
         r = self.ptr.contents
@@ -670,3 +703,51 @@ def run_query(query, attr_order=None, policy="plain", layout="plain", return_pla
         for t in tries.values():
             t.free()
     return out
+
+
+# --------------------------------------------------------------------------
+# the SQL + ML pipeline (section 7): encoding and logistic regression
+# --------------------------------------------------------------------------
+
+def encode(ids, row_col, cols, bias=True, stream=None):
+    """lh_encode.  ids: device id columns (e.g. JoinResult.key_columns());
+    cols: dicts {"codes": column, "card": c, "by": i} or {"values": column,
+    "by": i} with device (or numpy) columns indexed by ids[by].  Returns
+    (rows, feats, vals, n_feat) as device tensors of n * slots entries."""
+    torch = _torch()
+    n = int(ids[0].numel()) if ids else 0
+    keep = []
+    fc = (FeatureCol * max(1, len(cols)))()
+    for i, c in enumerate(cols):
+        if "codes" in c:
+            t = to_device(c["codes"], np.uint32)
+            fc[i].codes = t.data_ptr()
+            fc[i].card = int(c["card"])
+        else:
+            t = to_device(c["values"], np.float64)
+            fc[i].values = t.data_ptr()
+        keep.append(t)
+        fc[i].by = int(c["by"])
+        fc[i].n_ids = int(t.numel())
+    slots = len(cols) + (1 if bias else 0)
+    rows = torch.empty(n * slots, dtype=torch.int32, device="cuda")
+    feats = torch.empty(n * slots, dtype=torch.int32, device="cuda")
+    vals = torch.empty(n * slots, dtype=torch.float64, device="cuda")
+    ia = (C.c_void_p * max(1, len(ids)))(*[t.data_ptr() for t in ids])
+    nf = C.c_uint32()
+    _check(lib.lh_encode(n, len(ids), ia, row_col, len(cols), fc, 1 if bias else 0, rows.data_ptr(),
+                         feats.data_ptr(), vals.data_ptr(), C.byref(nf),
+                         stream if stream is not None else current_stream()))
+    return rows, feats, vals, nf.value
+
+
+def logreg_fit(x_rows, x_cols, y, w, iters, step, anno=0, loss=True, stream=None):
+    """lh_logreg_fit on two Trie handles; y and w are device float64
+    tensors (w is updated in place).  Returns the per-iteration mean
+    log-loss as a device tensor (or None)."""
+    torch = _torch()
+    lt = torch.empty(max(1, iters), dtype=torch.float64, device="cuda") if loss else None
+    _check(lib.lh_logreg_fit(x_rows.handle, x_cols.handle, anno, y.data_ptr(), int(y.numel()), int(w.numel()),
+                             iters, float(step), w.data_ptr(), lt.data_ptr() if loss else None,
+                             stream if stream is not None else current_stream()))
+    return lt[:iters] if loss else None

@@ -85,6 +85,33 @@ def test_plan_rejects_foreign_trie(lh):
     assert lh.lib.lh_plan(C.byref(q), None, C.byref(out)) == lh.LH_ERR_INVALID
 
 
+def test_encode_and_logreg_validate_without_a_gpu(lh):
+    nf = C.c_uint32(7)
+    ids = (C.c_void_p * 1)(0)
+    # NULL id array, n_id_cols 0, row_col out of range, no feature at all
+    assert lh.lib.lh_encode(0, 1, None, 0, 0, None, 1, None, None, None, C.byref(nf), None) == lh.LH_ERR_INVALID
+    assert lh.lib.lh_encode(0, 0, ids, 0, 0, None, 1, None, None, None, C.byref(nf), None) == lh.LH_ERR_INVALID
+    assert lh.lib.lh_encode(0, 1, ids, 1, 0, None, 1, None, None, None, C.byref(nf), None) == lh.LH_ERR_INVALID
+    assert lh.lib.lh_encode(0, 1, ids, 0, 0, None, 0, None, None, None, C.byref(nf), None) == lh.LH_ERR_INVALID
+    cols = (lh.FeatureCol * 2)()
+    cols[0].codes, cols[0].values, cols[0].card = 0x10, 0x20, 3   # both codes and values
+    assert lh.lib.lh_encode(0, 1, ids, 0, 1, cols, 1, None, None, None, C.byref(nf), None) == lh.LH_ERR_INVALID
+    cols[0].values = None
+    cols[0].by = 1                                                  # no id column 1
+    assert lh.lib.lh_encode(0, 1, ids, 0, 1, cols, 1, None, None, None, C.byref(nf), None) == lh.LH_ERR_INVALID
+    cols[0].by = 0
+    cols[0].card = 0                                                # empty category
+    assert lh.lib.lh_encode(0, 1, ids, 0, 1, cols, 1, None, None, None, C.byref(nf), None) == lh.LH_ERR_INVALID
+    # zero rows: only the feature count is produced
+    cols[0].card = 3
+    cols[1].values, cols[1].by = 0x30, 0
+    assert lh.lib.lh_encode(0, 1, ids, 0, 2, cols, 1, None, None, None, C.byref(nf), None) == lh.LH_OK
+    assert nf.value == 1 + 3 + 1
+    assert lh.lib.lh_logreg_fit(C.c_void_p(0xdead), C.c_void_p(0xbeef), 0, None, 0, 0, 1, 0.5, None, None,
+                                None) == lh.LH_ERR_INVALID
+    assert b"live" in lh.lib.lh_last_error()
+
+
 # --------------------------------------------------------------------------
 # section 4 worked examples
 # --------------------------------------------------------------------------

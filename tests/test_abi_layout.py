@@ -25,6 +25,7 @@ STRUCTS = {
     "Hypergraph": "lh_hypergraph",
     "Ghd": "lh_ghd",
     "ProfileEntry": "lh_profile_entry",
+    "FeatureCol": "lh_feature_col",
 }
 def _binding_module():
     from paper_1708_07859_amd import lh
