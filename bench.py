@@ -761,6 +761,14 @@ def bench_voter(args, lh, torch, synth):
     loss = out["loss"].cpu().numpy().tolist()
     log(f"  {ms:.2f} ms per pipeline; {n_rows} rows x {nf} features; loss {loss}")
 
+    # kernel scopes of one whole pipeline
+    lh.profile_reset()
+    lh.profile_enable(True)
+    pipeline.run(t, iters=5, step=0.5, **f)
+    torch.cuda.synchronize()
+    lh.profile_enable(False)
+    for k, v in sorted(lh.profile_read().items(), key=lambda kv: -kv[1]["total_ms"])[:14]:
+        log(f"  {k:22s} launches={v['launches']:5d} total={v['total_ms']:8.3f} ms")
     # phase split (one extra run, synchronised between phases)
     phases = {}
     torch.cuda.synchronize()

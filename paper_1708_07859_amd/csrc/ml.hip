@@ -21,7 +21,7 @@ namespace lh {
 namespace {
 
 constexpr int LR_NT = 256;          // threads per workgroup
-constexpr uint32_t LR_CAP = 2048;   // staged products per row workgroup (16 KB of LDS)
+constexpr uint32_t LR_CAP = 4096;   // staged products per row workgroup (32 KB of LDS)
 constexpr uint32_t LR_CHUNK = 2048; // entries of one feature per column workgroup
 
 // ---- encoding ----------------------------------------------------------------
@@ -165,16 +165,31 @@ struct LrCols {
   double* part;            // per chunk: sum of value x residual
 };
 
-// One workgroup per chunk of LR_CHUNK entries of one feature.
+// One workgroup per chunk of LR_CHUNK entries of one feature.  Thread t
+// takes entries t, t + LR_NT, ... of the chunk: all of its loads are
+// issued before the sum, which adds them in that order.
 __global__ __launch_bounds__(LR_NT) void k_lr_cols(LrCols a) {
+  constexpr uint32_t PER = LR_CHUNK / LR_NT;
   __shared__ double s_red[LR_NT];
   const uint32_t c = blockIdx.x;
   const uint32_t f = a.cfeat[c];
   const uint32_t b = a.foffs[f] + (c - a.cstart[f]) * LR_CHUNK;
   const uint32_t e = (uint32_t)min<uint64_t>(a.foffs[f + 1], (uint64_t)b + LR_CHUNK);
+  uint32_t r[PER];
+  double v[PER];
+#pragma unroll
+  for (uint32_t k = 0; k < PER; k++) {
+    const uint32_t j = b + threadIdx.x + k * LR_NT;
+    const bool in = j < e;
+    r[k] = in ? a.rkeys[j] : 0u;
+    v[k] = in ? entry_value(a.runs, a.val, j) : 0.0;
+  }
   double acc = 0.0;
-  for (uint32_t j = b + threadIdx.x; j < e; j += LR_NT)
-    acc = __dadd_rn(acc, __dmul_rn(entry_value(a.runs, a.val, j), a.res[a.rkeys[j]]));
+#pragma unroll
+  for (uint32_t k = 0; k < PER; k++) {
+    const uint32_t j = b + threadIdx.x + k * LR_NT;
+    if (j < e) acc = __dadd_rn(acc, __dmul_rn(v[k], a.res[r[k]]));
+  }
   const double sum = block_sum(acc, s_red);
   if (threadIdx.x == 0) a.part[c] = sum;
 }

@@ -23,11 +23,15 @@ struct LevelCols {
 
 __device__ __forceinline__ uint32_t head_mask(const LevelCols& c, uint64_t r) {
   // bit l set when row r starts a new node at level l
+  // (levels unrolled: constant indices keep the column pointers in registers)
   uint32_t m = 0;
   bool h = (r == 0);
-  for (uint32_t l = 0; l < c.n_levels; l++) {
-    if (!h) h = c.k[l][r] != c.k[l][r - 1];
-    if (h) m |= 1u << l;
+#pragma unroll
+  for (uint32_t l = 0; l < LH_MAX_KEYS; l++) {
+    if (l < c.n_levels) {
+      if (!h) h = c.k[l][r] != c.k[l][r - 1];
+      if (h) m |= 1u << l;
+    }
   }
   return m;
 }
@@ -38,9 +42,12 @@ __global__ __launch_bounds__(TB_NT) void k_head_counts(LevelCols c, uint64_t n, 
   uint64_t r = (uint64_t)blockIdx.x * TB_NT + threadIdx.x;
   uint32_t m = r < n ? head_mask(c, r) : 0;
   const int w = threadIdx.x / WAVE;
-  for (uint32_t l = 0; l < c.n_levels; l++) {
-    uint64_t b = ballot((m >> l) & 1u);
-    if (lane_id() == 0) w_cnt[w][l] = (uint32_t)__popcll(b);
+#pragma unroll
+  for (uint32_t l = 0; l < LH_MAX_KEYS; l++) {
+    if (l < c.n_levels) {
+      uint64_t b = ballot((m >> l) & 1u);
+      if (lane_id() == 0) w_cnt[w][l] = (uint32_t)__popcll(b);
+    }
   }
   __syncthreads();
   if (threadIdx.x < c.n_levels) {
@@ -67,17 +74,22 @@ __global__ __launch_bounds__(TB_NT) void k_emit_levels(EmitArgs a, uint64_t n) {
   uint32_t m = r < n ? head_mask(a.c, r) : 0;
   const int w = threadIdx.x / WAVE;
   uint32_t rank[LH_MAX_KEYS];
-  for (uint32_t l = 0; l < a.c.n_levels; l++) {
-    uint64_t b = ballot((m >> l) & 1u);
-    rank[l] = lanes_below(b);
-    if (lane_id() == 0) w_cnt[w][l] = (uint32_t)__popcll(b);
+#pragma unroll
+  for (uint32_t l = 0; l < LH_MAX_KEYS; l++) {
+    rank[l] = 0;
+    if (l < a.c.n_levels) {
+      uint64_t b = ballot((m >> l) & 1u);
+      rank[l] = lanes_below(b);
+      if (lane_id() == 0) w_cnt[w][l] = (uint32_t)__popcll(b);
+    }
   }
   __syncthreads();
   if (r >= n) return;
   const uint32_t L = a.c.n_levels;
   uint32_t pos_prev = 0;
-  for (uint32_t l = 0; l < L; l++) {
-    if (!((m >> l) & 1u)) continue;
+#pragma unroll
+  for (uint32_t l = 0; l < LH_MAX_KEYS; l++) {
+    if (l >= L || !((m >> l) & 1u)) continue;
     uint32_t pre = 0;
     for (int j = 0; j < w; j++) pre += w_cnt[j][l];
     uint32_t pos = a.tile_off[(uint64_t)l * a.ntiles + blockIdx.x] + pre + rank[l];
@@ -102,21 +114,36 @@ __global__ __launch_bounds__(TB_NT) void k_emit_levels(EmitArgs a, uint64_t n) {
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
 // Bit t-1 of *mask stays set while rows i-1, i are in lexicographic order
-// of the last t levels (equal tuples are in order), for every i.
+// of the last t levels (equal tuples are in order), for every i.  Bits only
+// clear: a wave publishes the bits it newly clears (one atomic each time)
+// and stops once none is left, so unsorted input costs a fraction of a
+// pass.
 __global__ void k_sorted_tails(LevelCols c, uint64_t n, uint32_t* mask) {
   const int K = (int)c.n_levels;
-  const uint32_t full = (1u << K) - 1;
-  uint32_t m = full;
-  for (uint64_t i = 1 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    bool ord = true;  // order of the suffix from level l on
-    for (int l = K - 1; l >= 0; l--) {
-      const uint32_t a = c.k[l][i - 1], b = c.k[l][i];
-      ord = a < b || (a == b && ord);
-      if (!ord) m &= ~(1u << (K - 1 - l));
+  uint32_t known = __builtin_amdgcn_readfirstlane(__hip_atomic_load(mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i0 = 1 + (uint64_t)blockIdx.x * blockDim.x; i0 < n && known; i0 += stride) {
+    const uint64_t i = i0 + threadIdx.x;
+    uint32_t m = known;
+    if (i < n) {
+      bool ord = true;  // order of the suffix from level l on
+      // constant level indices: the column pointers stay in registers
+#pragma unroll
+      for (int l = LH_MAX_KEYS - 1; l >= 0; l--) {
+        if (l < K) {
+          const uint32_t a = c.k[l][i - 1], b = c.k[l][i];
+          ord = a < b || (a == b && ord);
+          if (!ord) m &= ~(1u << (K - 1 - l));
+        }
+      }
     }
+    for (int o = 32; o > 0; o >>= 1) m &= (uint32_t)__shfl_xor((int)m, o, 64);
+    if (m != known) {  // uniform over the wave
+      if ((threadIdx.x & 63) == 0) atomicAnd(mask, m);
+      known = m;
+    }
+    known &= __builtin_amdgcn_readfirstlane(__hip_atomic_load(mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
-  for (int o = 32; o > 0; o >>= 1) m &= (uint32_t)__shfl_xor((int)m, o, 64);
-  if ((threadIdx.x & 63) == 0 && m != full) atomicAnd(mask, m);
 }
 
 __global__ void k_line_samples(const uint32_t* keys, uint64_t n_samp, uint32_t* samp) {

@@ -50,9 +50,11 @@ def sql_phase(t, age_lo, age_hi, district_lo, district_hi, policy="plain"):
 
 
 def design_tries(rows, feats, vals):
-    """The (row, feature) and (feature, row) tries of the triples."""
-    xr = lh.trie_build([rows, feats], annos=[vals], bag=True)
-    xc = lh.trie_build([rows, feats], annos=[vals], level_order=[1, 0], bag=True)
+    """The (row, feature) and (feature, row) tries of the triples.  The
+    training kernels read the sets' keys only, so every set keeps the uint
+    layout (no bitsets are built)."""
+    xr = lh.trie_build([rows, feats], annos=[vals], bag=True, layout="uint")
+    xc = lh.trie_build([rows, feats], annos=[vals], level_order=[1, 0], bag=True, layout="uint")
     return xr, xc
 
 
