@@ -204,12 +204,16 @@ __global__ void k_chunk_fill(const uint32_t* cstart, uint64_t n0, uint32_t* cfea
     for (uint32_t c = cstart[f], e = cstart[f + 1]; c < e; c++) cfeat[c] = (uint32_t)f;
 }
 
-// g = (sum of the feature's chunks, in order) / n; w -= step * g.
-__global__ void k_lr_update(const uint32_t* fkeys, const uint32_t* cstart, const double* part, uint64_t n0,
-                            double n, double step, double* w) {
-  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < n0; f += (uint64_t)gridDim.x * blockDim.x) {
-    double sum = 0.0;
-    for (uint32_t c = cstart[f], e = cstart[f + 1]; c < e; c++) sum = __dadd_rn(sum, part[c]);
+// One workgroup per feature: g = (its chunk sums, thread t adding chunks
+// t, t + LR_NT, ..., then a fixed tree) / n; w -= step * g.
+__global__ __launch_bounds__(LR_NT) void k_lr_update(const uint32_t* fkeys, const uint32_t* cstart,
+                                                     const double* part, double n, double step, double* w) {
+  __shared__ double s_red[LR_NT];
+  const uint32_t f = blockIdx.x;
+  double acc = 0.0;
+  for (uint32_t c = cstart[f] + threadIdx.x, e = cstart[f + 1]; c < e; c += LR_NT) acc = __dadd_rn(acc, part[c]);
+  const double sum = block_sum(acc, s_red);
+  if (threadIdx.x == 0) {
     const uint32_t fid = fkeys[f];
     w[fid] = __dsub_rn(w[fid], __dmul_rn(step, __ddiv_rn(sum, n)));
   }
@@ -292,6 +296,7 @@ void logreg_fit(const lh_trie* xr, const lh_trie* xc, uint32_t anno, const doubl
     fail(LH_ERR_INVALID, "logreg: the two tries' level orders are not transposes");
   if (xr->n_rows != xc->n_rows) fail(LH_ERR_INVALID, "logreg: the two tries hold different relations");
   const uint64_t n0 = xr->lv[0].n, f0 = xc->lv[0].n;
+  if (f0 >= (1ull << 31)) fail(LH_ERR_OVERFLOW, "logreg: 2^31 features or more");
   if (n0 && (xr->key_max[0] >= n_y || xc->key_max[1] >= n_y))
     fail(LH_ERR_INVALID, "logreg: a row id is not below n_y");
   if (n0 && (xr->key_max[1] >= n_feat || xc->key_max[0] >= n_feat))
@@ -360,7 +365,7 @@ void logreg_fit(const lh_trie* xr, const lh_trie* xc, uint32_t anno, const doubl
       k_lr_cols<<<nchunks, LR_NT, 0, s>>>(ca);
       LH_HIP(hipGetLastError());
     }
-    k_lr_update<<<grid_of(f0), 256, 0, s>>>(xc->lv[0].keys.p, cstart.p, part.p, f0, n, step, w);
+    k_lr_update<<<(unsigned)f0, LR_NT, 0, s>>>(xc->lv[0].keys.p, cstart.p, part.p, n, step, w);
     LH_HIP(hipGetLastError());
   }
   LH_HIP(hipStreamSynchronize(s));

@@ -293,10 +293,28 @@ __global__ void k_anno_stats(const double* v, uint64_t n, int32_t* qmin, unsigne
     m = max(m, (uint64_t)__shfl_xor((unsigned long long)m, d, WAVE));
     bad |= (uint32_t)__shfl_xor((int)bad, d, WAVE);
   }
+  // one update per workgroup, and only when it changes the result (the
+  // same three words are the target of every workgroup)
+  __shared__ int32_t s_q[8];
+  __shared__ unsigned long long s_m[8];
+  __shared__ uint32_t s_b[8];
+  const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
   if (lane_id() == 0) {
-    atomicMin(qmin, q);
-    atomicMax(maxabs, (unsigned long long)m);
-    if (bad) atomicOr(nonfinite, 1u);
+    s_q[w] = q;
+    s_m[w] = m;
+    s_b[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 1; j < nw; j++) {
+      q = min(q, s_q[j]);
+      m = max(m, (uint64_t)s_m[j]);
+      bad |= s_b[j];
+    }
+    if (q < __hip_atomic_load(qmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(qmin, q);
+    if (m > __hip_atomic_load(maxabs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(maxabs, (unsigned long long)m);
+    if (bad && !__hip_atomic_load(nonfinite, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicOr(nonfinite, 1u);
   }
 }
 

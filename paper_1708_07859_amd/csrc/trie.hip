@@ -440,7 +440,7 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
   } else if (copy_order) {
     for (uint32_t l = 0; l < n_keys && n; l++)
       LH_HIP(hipMemcpyAsync(sorted_p[l], col[l], n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    if (need_perm) iota_u32(perm.p, n, s);
+    if (need_perm && (sel || !bag)) iota_u32(perm.p, n, s);  // else the rows are copied as they are (below)
   } else if (!sort_packed(col, t->key_bits, n_keys, n, need_perm ? perm.p : nullptr, sorted_p, s, sorted_tail)) {
     if (!need_perm) perm.alloc(n, s);
     // a stable sort by the leading levels keeps the presorted tail's order
@@ -546,14 +546,26 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
     gather_u32(sel, rowsel, srcrow.p, t->n_rows, s);
     rowmap = srcrow.p;
   }
+  // a presorted bag keeps its input rows in order: plain copies
+  const bool same_rows = copy_order && bag && !sel;
   for (uint32_t a = 0; a < n_annos; a++) {
     t->annos.emplace_back(t->n_rows, s);
-    gather_f64(annos[a], rowmap, t->annos.back().p, t->n_rows, s);
+    if (same_rows) {
+      if (t->n_rows)
+        LH_HIP(hipMemcpyAsync(t->annos.back().p, annos[a], t->n_rows * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      gather_f64(annos[a], rowmap, t->annos.back().p, t->n_rows, s);
+    }
     t->astats.push_back(anno_stats(t->annos.back().p, t->n_rows, s));
   }
   for (uint32_t m = 0; m < n_meta; m++) {
     t->meta.emplace_back(t->n_rows, s);
-    gather_u32(meta[m], rowmap, t->meta.back().p, t->n_rows, s);
+    if (same_rows) {
+      if (t->n_rows)
+        LH_HIP(hipMemcpyAsync(t->meta.back().p, meta[m], t->n_rows * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    } else {
+      gather_u32(meta[m], rowmap, t->meta.back().p, t->n_rows, s);
+    }
   }
 
   uint32_t mode = flags & LH_LAYOUT_MASK;
