@@ -6,7 +6,7 @@
 // entry value as its annotation.  Its trie in (row, feature) order is a
 // row-compressed sparse matrix and its trie in (feature, row) order the
 // column-compressed one, so the training loop reads the two tries as they
-// are: no conversion into a sparse-BLAS format (section 7, Table 5's point).
+// are: no conversion into a sparse-BLAS format (section 7, Table 4's point).
 //
 // One iteration is z = X w, p = 1 / (1 + exp(-z)), g = X^T (p - y) / n and
 // w -= step * g.  Both products sum in a fixed order (ascending positions

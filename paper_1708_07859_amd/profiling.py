@@ -21,6 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = {  # kernel -> source file whose hash stamps its counters
     "k_leaf2_count": os.path.join(HERE, "csrc", "join.hip"),
     "k_elem": os.path.join(HERE, "csrc", "join.hip"),
+    "k_lr_cols": os.path.join(HERE, "csrc", "ml.hip"),
+    "k_lr_rows": os.path.join(HERE, "csrc", "ml.hip"),
 }
 COPY_BYTES = 1 << 30
 
