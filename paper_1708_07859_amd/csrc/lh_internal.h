@@ -70,12 +70,22 @@ struct DBuf {  // owning device buffer, freed on the stream it was made on
   }
 };
 
+// A 64-byte pinned host buffer per host thread, kept until the process
+// ends: a scalar read back into pinned memory skips the staging of a
+// pageable copy (about 40 us per read on the sync-heavy paths).
+inline void* pinned_scratch() {
+  thread_local void* p = nullptr;
+  if (!p) LH_HIP(hipHostMalloc(&p, 64, hipHostMallocPortable));
+  return p;
+}
+
 template <class T>
 T read_scalar(const T* dptr, hipStream_t s) {
-  T v{};
-  LH_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  static_assert(sizeof(T) <= 64, "read_scalar: at most 64 bytes");
+  T* h = static_cast<T*>(pinned_scratch());
+  LH_HIP(hipMemcpyAsync(h, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
   LH_HIP(hipStreamSynchronize(s));
-  return v;
+  return *h;
 }
 
 // ---------------------------------------------------------------------------
