@@ -194,6 +194,72 @@ __global__ __launch_bounds__(LR_NT) void k_lr_cols(LrCols a) {
   if (threadIdx.x == 0) a.part[c] = sum;
 }
 
+// ---- the blocked column pass ------------------------------------------------
+// Row ids are cut into blocks of 2^RB_SHIFT.  A feature's rows are sorted,
+// so its entries of one block are a contiguous segment.  One workgroup per
+// block stages the block's residuals in LDS and its waves take the
+// features in turn: each wave sums a feature's segment (lanes strided,
+// then a fixed shuffle tree) with every residual read from LDS.
+constexpr uint32_t RB_SHIFT = 12;
+constexpr uint32_t RB = 1u << RB_SHIFT;
+
+// seg[f * (nb + 1) + b]: first entry of feature f (level-0 position) at a
+// row id >= b * RB; seg[f * (nb + 1) + nb] = the end of f's list.
+__global__ void k_lr_segments(const uint32_t* foffs, const uint32_t* rkeys, uint64_t f0, uint32_t nb, uint32_t* seg) {
+  const uint64_t total = f0 * (nb + 1);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t f = i / (nb + 1);
+    const uint32_t b = (uint32_t)(i - f * (nb + 1));
+    uint32_t lo = foffs[f], hi = foffs[f + 1];
+    if (b < nb) {
+      const uint64_t key = (uint64_t)b << RB_SHIFT;
+      while (lo < hi) {  // first row id >= key
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if ((uint64_t)rkeys[mid] < key) lo = mid + 1;
+        else hi = mid;
+      }
+    } else {
+      lo = hi;
+    }
+    seg[i] = lo;
+  }
+}
+
+struct LrBlocked {
+  const uint32_t* seg;    // (f0, nb + 1) segment starts
+  const uint32_t* rkeys;  // level 1 of the (feature, row) trie: row ids
+  const uint32_t* runs;   // level-1 run offsets, or null
+  const double* val;      // annotation column in trie order
+  const double* res;      // p - y at the row id (n_res entries)
+  uint64_t n_res;
+  uint64_t f0;
+  uint32_t nb;
+  double* part;           // (f0, nb): per feature and block
+};
+
+__global__ __launch_bounds__(LR_NT) void k_lr_cols_blocked(LrBlocked a) {
+  __shared__ double s_res[RB];
+  const uint32_t b = blockIdx.x;
+  const uint64_t r0 = (uint64_t)b << RB_SHIFT;
+  const uint32_t nr = (uint32_t)min<uint64_t>(RB, a.n_res - r0);
+  for (uint32_t i = threadIdx.x; i < nr; i += LR_NT) s_res[i] = a.res[r0 + i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (uint64_t f = w; f < a.f0; f += LR_NT / 64) {
+    const uint32_t s = a.seg[f * (a.nb + 1) + b], e = a.seg[f * (a.nb + 1) + b + 1];
+    double acc = 0.0;
+    for (uint32_t j = s + lane; j < e; j += 64)
+      acc = __dadd_rn(acc, __dmul_rn(entry_value(a.runs, a.val, j), s_res[a.rkeys[j] - (uint32_t)r0]));
+    for (int o = 32; o > 0; o >>= 1) acc = __dadd_rn(acc, __shfl_xor(acc, o, 64));
+    if (lane == 0) a.part[f * a.nb + b] = acc;
+  }
+}
+
+__global__ void k_stride_starts(uint64_t f0, uint32_t nb, uint32_t* cstart) {
+  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f <= f0; f += (uint64_t)gridDim.x * blockDim.x)
+    cstart[f] = (uint32_t)(f * nb);
+}
+
 __global__ void k_chunk_counts(const uint32_t* foffs, uint64_t n0, uint32_t* cnt) {
   for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < n0; f += (uint64_t)gridDim.x * blockDim.x)
     cnt[f] = (uint32_t)(((uint64_t)foffs[f + 1] - foffs[f] + LR_CHUNK - 1) / LR_CHUNK);
@@ -330,15 +396,43 @@ void logreg_fit(const lh_trie* xr, const lh_trie* xc, uint32_t anno, const doubl
   DBuf<double> lpart(loss ? nb : 0, s);
   ra.lpart = loss ? lpart.p : nullptr;
 
-  // chunks of each feature's row list
-  DBuf<uint32_t> cnt(f0, s), cstart(f0 + 1, s);
-  k_chunk_counts<<<grid_of(f0), 256, 0, s>>>(xc->lv[0].offs.p, f0, cnt.p);
-  LH_HIP(hipGetLastError());
-  const uint32_t nchunks = scan_u32(cnt.p, cstart.p, f0, s);
-  DBuf<uint32_t> cfeat(nchunks, s);
-  DBuf<double> part(nchunks, s);
-  k_chunk_fill<<<grid_of(f0), 256, 0, s>>>(cstart.p, f0, cfeat.p);
-  LH_HIP(hipGetLastError());
+  // The column pass: blocked by row id when the (feature, block) partial
+  // sums stay few next to the entries, else chunks of each feature's list.
+  // Either way cstart[f] .. cstart[f + 1] are feature f's partial sums.
+  const uint64_t nnz = xr->lv[1].n;
+  const uint64_t nblk = (n_res + RB - 1) / RB;
+  const bool blocked = nblk < (1u << 24) && f0 * nblk <= std::max<uint64_t>(nnz / 4, 1u << 16);
+  DBuf<uint32_t> cnt, cstart(f0 + 1, s), cfeat, seg;
+  DBuf<double> part;
+  uint32_t nchunks = 0;
+  if (blocked) {
+    seg.alloc(f0 * (nblk + 1), s);
+    k_lr_segments<<<grid_of(f0 * (nblk + 1)), 256, 0, s>>>(xc->lv[0].offs.p, xc->lv[1].keys.p, f0, (uint32_t)nblk,
+                                                          seg.p);
+    LH_HIP(hipGetLastError());
+    k_stride_starts<<<grid_of(f0 + 1), 256, 0, s>>>(f0, (uint32_t)nblk, cstart.p);
+    LH_HIP(hipGetLastError());
+    part.alloc(f0 * nblk, s);
+  } else {
+    cnt.alloc(f0, s);
+    k_chunk_counts<<<grid_of(f0), 256, 0, s>>>(xc->lv[0].offs.p, f0, cnt.p);
+    LH_HIP(hipGetLastError());
+    nchunks = scan_u32(cnt.p, cstart.p, f0, s);
+    cfeat.alloc(nchunks, s);
+    part.alloc(nchunks, s);
+    k_chunk_fill<<<grid_of(f0), 256, 0, s>>>(cstart.p, f0, cfeat.p);
+    LH_HIP(hipGetLastError());
+  }
+  LrBlocked ba{};
+  ba.seg = seg.p;
+  ba.rkeys = xc->lv[1].keys.p;
+  ba.runs = xc->n_rows == xc->lv[1].n ? nullptr : xc->lv[1].offs.p;
+  ba.val = xc->annos[anno].p;
+  ba.res = res.p;
+  ba.n_res = n_res;
+  ba.f0 = f0;
+  ba.nb = (uint32_t)nblk;
+  ba.part = part.p;
   LrCols ca{};
   ca.foffs = xc->lv[0].offs.p;
   ca.rkeys = xc->lv[1].keys.p;
@@ -349,7 +443,6 @@ void logreg_fit(const lh_trie* xr, const lh_trie* xc, uint32_t anno, const doubl
   ca.cstart = cstart.p;
   ca.part = part.p;
 
-  const uint64_t nnz = xr->lv[1].n;
   for (uint32_t it = 0; it < iters; it++) {
     {
       ProfScope ps("lr_rows", s, n0, nnz);
@@ -360,7 +453,11 @@ void logreg_fit(const lh_trie* xr, const lh_trie* xc, uint32_t anno, const doubl
       k_lr_loss<<<1, LR_NT, 0, s>>>(lpart.p, nb, n, loss + it);
       LH_HIP(hipGetLastError());
     }
-    if (nchunks) {
+    if (blocked) {
+      ProfScope ps("lr_cols", s, f0, nnz);
+      k_lr_cols_blocked<<<(unsigned)nblk, LR_NT, 0, s>>>(ba);
+      LH_HIP(hipGetLastError());
+    } else if (nchunks) {
       ProfScope ps("lr_cols", s, f0, nnz);
       k_lr_cols<<<nchunks, LR_NT, 0, s>>>(ca);
       LH_HIP(hipGetLastError());

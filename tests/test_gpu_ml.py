@@ -113,13 +113,15 @@ def random_sparse(rng, n_rows, id_space, n_feat, long_rows=3, long_len=3000, dup
     return rows[perm], feats[perm], vals[perm]
 
 
-@pytest.mark.parametrize("dup", [False, True])
-def test_logreg_on_random_sparse_tries(lh, pipeline, dup):
+# many features over a wide row-id space take the chunked column pass; few
+# features over a narrow one take the pass blocked by row id
+@pytest.mark.parametrize("dup,n_feat,id_space", [(False, 4000, 1 << 20), (True, 4000, 1 << 20),
+                                                 (False, 64, 1 << 16), (True, 64, 1 << 16)])
+def test_logreg_on_random_sparse_tries(lh, pipeline, dup, n_feat, id_space):
     import torch
-    rng = synth.rng_for(21 + dup)
-    n_feat, id_space = 4000, 1 << 20
+    rng = synth.rng_for(21 + dup + n_feat)
     rows, feats, vals = random_sparse(rng, 3000, id_space, n_feat, dup=dup)
-    say(f"random sparse logreg dup={dup} nnz={len(rows)}")
+    say(f"random sparse logreg dup={dup} n_feat={n_feat} nnz={len(rows)}")
     y_all = (rng.random(id_space) < 0.4).astype(np.float64)
     w0 = synth.uniform_pm1(rng, n_feat) * 0.1
     xr, xc = pipeline.design_tries(lh.to_device(rows), lh.to_device(feats), lh.to_device(vals))
