@@ -247,13 +247,7 @@ lh_status lh_trie_get_info(const lh_trie* t, lh_trie_info* info) {
       info->level_order[l] = t->level_order[l];
       info->col_distinct[l] = t->col_distinct[l];
       info->col_freq_max[l] = t->col_freq_max[l];
-      uint64_t nb = 0;
-      if (t->lv[l].n_sets) {
-        std::vector<uint64_t> w(t->lv[l].n_sets);
-        LH_HIP(hipMemcpy(w.data(), t->lv[l].bs_word.p, w.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
-        for (uint64_t x : w) nb += x != UINT64_MAX;
-      }
-      info->level_bitsets[l] = nb;
+      info->level_bitsets[l] = count_bitsets(t, l, nullptr);
     }
   });
 }

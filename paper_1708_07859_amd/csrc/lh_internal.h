@@ -221,6 +221,9 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
 // Column statistics (col_distinct, col_freq_max), computed once per trie.
 void ensure_column_stats(lh_trie* t, hipStream_t s);
 
+// Sets of level l stored as bitsets (a device count).
+uint64_t count_bitsets(const lh_trie* t, uint32_t l, hipStream_t s);
+
 // Per-set layout and bitset materialization for one level.
 void build_layouts(lh_trie* t, uint32_t level, uint32_t layout_flags, const uint32_t* parent, hipStream_t s);
 

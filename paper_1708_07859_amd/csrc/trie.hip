@@ -248,6 +248,24 @@ uint32_t bitlen(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
 
 }  // namespace
 
+__global__ void k_count_bitsets(const uint64_t* bs_word, uint64_t n, unsigned long long* out) {
+  uint32_t c = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    c += bs_word[i] != UINT64_MAX;
+  for (int o = 32; o > 0; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+uint64_t count_bitsets(const lh_trie* t, uint32_t l, hipStream_t s) {
+  const Level& L = t->lv[l];
+  if (!L.n_sets || !L.pool_words) return 0;
+  DBuf<unsigned long long> c(1, s);
+  LH_HIP(hipMemsetAsync(c.p, 0, sizeof(unsigned long long), s));
+  k_count_bitsets<<<std::min<unsigned>(grid_for(L.n_sets), 1024), 256, 0, s>>>(L.bs_word.p, L.n_sets, c.p);
+  LH_HIP(hipGetLastError());
+  return read_scalar(c.p, s);
+}
+
 void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, const uint32_t* parent, hipStream_t s) {
   Level& L = t->lv[l];
   L.n_sets = (l == 0) ? 1 : t->lv[l - 1].n;
