@@ -738,7 +738,9 @@ def bench_voter(args, lh, torch, synth):
     step runs the whole application.  Roofline: the two training kernels
     against HBM, with algorithmic bytes per launch
       lr_rows: nnz * (4 B feature + 8 B value) + n * (4 B row + 4 B offset + 8 B label + 8 B residual)
-      lr_cols: nnz * (4 B row + 8 B value + 8 B residual) + chunks * 8 B."""
+      lr_cols_blocked (row-id blocks of 4096): nnz * (4 B row + 8 B value) + n_ids * 8 B residual
+                      + features * blocks * 8 B partial sums
+      lr_cols (chunks of 2048 entries): nnz * (4 B row + 8 B value + 8 B residual gather) + chunks * 8 B."""
     import numpy as np
 
     from paper_1708_07859_amd import pipeline
@@ -803,10 +805,14 @@ def bench_voter(args, lh, torch, synth):
     prof = lh.profile_read()
     _, foffs = xc.read_level(0)
     chunks = int(np.sum((np.diff(foffs.astype(np.int64)) + 2047) // 2048))
+    rk, _ = xr.read_level(0)
+    n_ids = int(rk[-1]) + 1 if len(rk) else 0
+    blocks = (n_ids + 4095) // 4096
     xr.free()
     xc.free()
     t.free()
-    alg = {"lr_rows": nnz * 12 + n0 * 24, "lr_cols": nnz * 20 + chunks * 8}
+    alg = {"lr_rows": nnz * 12 + n0 * 24, "lr_cols": nnz * 20 + chunks * 8,
+           "lr_cols_blocked": nnz * 12 + n_ids * 8 + (len(foffs) - 1) * blocks * 8}
     kern = {}
     for k, b in alg.items():
         e = prof.get(k)

@@ -454,7 +454,7 @@ void logreg_fit(const lh_trie* xr, const lh_trie* xc, uint32_t anno, const doubl
       LH_HIP(hipGetLastError());
     }
     if (blocked) {
-      ProfScope ps("lr_cols", s, f0, nnz);
+      ProfScope ps("lr_cols_blocked", s, f0, nnz);
       k_lr_cols_blocked<<<(unsigned)nblk, LR_NT, 0, s>>>(ba);
       LH_HIP(hipGetLastError());
     } else if (nchunks) {

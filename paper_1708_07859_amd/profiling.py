@@ -22,6 +22,7 @@ KERNEL_SOURCE = {  # kernel -> source file whose hash stamps its counters
     "k_leaf2_count": os.path.join(HERE, "csrc", "join.hip"),
     "k_elem": os.path.join(HERE, "csrc", "join.hip"),
     "k_lr_cols": os.path.join(HERE, "csrc", "ml.hip"),
+    "k_lr_cols_blocked": os.path.join(HERE, "csrc", "ml.hip"),
     "k_lr_rows": os.path.join(HERE, "csrc", "ml.hip"),
 }
 COPY_BYTES = 1 << 30
