@@ -19,6 +19,7 @@ both must be identical.
 Prints one JSON line.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -108,6 +109,13 @@ def main():
     from paper_1708_07859_amd import lh
 
     torch.cuda.set_device(0)
+    # Python's cyclic collector would otherwise traverse every object torch
+    # and numpy created at import, tens of milliseconds per full pass, at
+    # a moment set by allocation counts (which differ when imports compile
+    # their sources): the objects alive now are frozen out of collection,
+    # and timed loops run with the collector paused, as timeit does.
+    gc.collect()
+    gc.freeze()
     if args.workload == "batch":
         return bench_batch(args, lh, torch, synth)
     if args.workload == "learned":
@@ -226,12 +234,15 @@ def measure_triangle(args, lh, torch, lo_d, hi_d, layout, policy):
     torch.cuda.synchronize()
     lh.profile_reset()
     lh.profile_enable(True)
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    gc.enable()
     lh.profile_enable(False)
     prof = lh.profile_read()
     ms = dt * 1000 / args.steps
@@ -753,12 +764,15 @@ def bench_voter(args, lh, torch, synth):
     f = synth.VOTER_FILTER
     for _ in range(max(1, args.warmup)):
         out = pipeline.run(t, iters=5, step=0.5, **f)
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = pipeline.run(t, iters=5, step=0.5, **f)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1000 / args.steps
+    gc.enable()
     n_rows, nf = out["n_rows"], out["n_feat"]
     loss = out["loss"].cpu().numpy().tolist()
     log(f"  {ms:.2f} ms per pipeline; {n_rows} rows x {nf} features; loss {loss}")
