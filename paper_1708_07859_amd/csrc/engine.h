@@ -60,6 +60,7 @@ struct lh_plan_s {
   uint32_t agg = LH_AGG_COUNT;
   uint32_t policy = LH_POLICY_PLAIN;
   bool case_prefix = false;                 // outputs = first n_out attributes of the order
+  bool case_full = false;                   // COUNT, every attribute an output, no GROUP BY meta column
   uint32_t group_impl = 0;                  // GROUP BY outside the prefix: 0 auto, 1 sort, 2 hash, 3 dense
   uint32_t blas = 0;                        // 1: BLAS matrix-vector, 2: matrix-matrix (dense relations)
   lh::DensePlan dense;

@@ -1732,8 +1732,108 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
   return true;
 }
 
+// ---- materialized joins -----------------------------------------------------------
+
+struct FullArgs {
+  const uint32_t* pos[MAXA];  // each atom's position in its last level
+  const uint32_t* run[MAXA];  // bag atoms: run offsets of the last level; else null
+  uint32_t na;
+  uint64_t* counts;
+};
+
+__global__ void k_gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[idx[i]];
+}
+
+// Rows a tuple stands for: the product over bag atoms of its run length.
+__global__ void k_full_counts(FullArgs a, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t c = 1;
+#pragma unroll
+    for (int e = 0; e < MAXA; e++)
+      if (e < (int)a.na && a.run[e]) {
+        const uint32_t q = a.pos[e][i];
+        c *= (uint64_t)(a.run[e][q + 1] - a.run[e][q]);
+      }
+    a.counts[i] = c;
+  }
+}
+
+// COUNT with every attribute an output (a materialized join) and no GROUP
+// BY meta column: Algorithm 1 runs to the last attribute, whose frontier
+// holds each distinct output tuple once, in the lexicographic order of the
+// attribute order; a tuple's count is the product of its bag runs.  The
+// rows are re-sorted only when the declared output order is another one.
+lh_result_impl* run_full(const lh_plan_t* p, hipStream_t s) {
+  std::unique_ptr<lh_result_impl> res(new lh_result_impl());
+  memset(&res->pub, 0, sizeof(res->pub));
+  const uint32_t na = (uint32_t)p->atoms.size();
+  const uint32_t no = (uint32_t)p->out_attrs.size();
+  Frontier F;
+  F.pos.resize(na);
+  F.outv.resize(no);
+  for (uint32_t d = 0; d < p->n_attrs && F.n; d++) step(p, d, F, s);
+  const uint64_t n = F.n;
+  DBuf<uint64_t> cnt(n, s);
+  if (n) {
+    FullArgs fa{};
+    fa.na = na;
+    fa.counts = cnt.p;
+    for (uint32_t e = 0; e < na; e++) {
+      const PlanAtom& A = p->atoms[e];
+      fa.pos[e] = F.pos[e].p;
+      fa.run[e] = A.bag ? A.trie->lv[A.n_levels - 1].offs.p : nullptr;
+    }
+    k_full_counts<<<grid_for(n), 256, 0, s>>>(fa, n);
+    LH_HIP(hipGetLastError());
+  }
+  bool in_order = true;
+  for (uint32_t j = 0; j < no; j++) in_order = in_order && p->out_attrs[j] == p->order[j];
+  res->cols.resize(no);
+  if (in_order || n <= 1) {
+    for (uint32_t j = 0; j < no; j++) res->cols[j] = std::move(F.outv[j]);
+    res->counts = std::move(cnt);
+  } else {
+    std::vector<const uint32_t*> cptr(no);
+    std::vector<uint32_t> bits(no);
+    for (uint32_t j = 0; j < no; j++) {
+      cptr[j] = F.outv[j].p;
+      bits[j] = bitlen(reduce_max_u32(F.outv[j].p, n, s));
+    }
+    DBuf<uint32_t> perm(n, s);
+    lex_sort_perm(cptr.data(), bits.data(), no, n, perm.p, s);
+    for (uint32_t j = 0; j < no; j++) {
+      res->cols[j].alloc(n, s);
+      gather_u32(F.outv[j].p, perm.p, res->cols[j].p, n, s);
+    }
+    res->counts.alloc(n, s);
+    k_gather_u64<<<grid_for(n), 256, 0, s>>>(cnt.p, perm.p, res->counts.p, n);
+    LH_HIP(hipGetLastError());
+  }
+  lh_result& R = res->pub;
+  R.n_rows = n;
+  R.n_cols = no;
+  R.exact = 0;
+  R.group_impl = 0;
+  res->colptr.resize(no);
+  for (uint32_t j = 0; j < no; j++) res->colptr[j] = res->cols[j].p;
+  R.out_keys = no ? res->colptr.data() : nullptr;
+  R.counts = res->counts.p;
+  R.sums = nullptr;
+  uint64_t nj = 0;
+  if (n) {
+    DBuf<uint64_t> tmp(n + 1, s);
+    nj = scan_u64(res->counts.p, tmp.p, n, s);
+  }
+  R.n_join_tuples = nj;
+  LH_HIP(hipStreamSynchronize(s));
+  return res.release();
+}
+
 lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
   if (p->blas) return run_dense(p, s);
+  if (p->case_full) return run_full(p, s);
   std::unique_ptr<lh_result_impl> res(new lh_result_impl());
   memset(&res->pub, 0, sizeof(res->pub));
   const uint32_t na = (uint32_t)p->atoms.size();

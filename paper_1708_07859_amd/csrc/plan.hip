@@ -301,6 +301,7 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
   for (auto& g : p->groups) (void)g;
 
   // streamed groups when the output is a proper prefix of the order
+  p->case_full = p->groups.empty() && p->agg == LH_AGG_COUNT && p->n_attrs > 0 && p->out_attrs.size() == p->n_attrs;
   p->case_prefix = p->groups.empty() && p->out_attrs.size() < p->n_attrs;
   for (uint32_t j = 0; j < p->out_attrs.size() && p->case_prefix; j++)
     if (p->out_attrs[j] != p->order[j]) p->case_prefix = false;

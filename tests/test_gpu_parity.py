@@ -218,6 +218,31 @@ def test_random_queries(lh, block):
             raise
 
 
+@pytest.mark.parametrize("policy", ["plain", "learned"])
+def test_materialized_joins(lh, policy):
+    """COUNT with every attribute an output (the join materialized) in a
+    random output order: bag runs multiply, filters apply, rows come out
+    sorted by the declared columns."""
+    n = 0
+    for seed in range(3000, 3120):
+        q = queries.random_query(seed, max_atoms=3, max_attrs=4, domain=12, max_rows=60)
+        rng = synth.rng_for(seed + 7)
+        q["out"] = rng.permutation(q["n_attrs"]).tolist()
+        q["agg"] = "count"
+        q["group"] = []
+        for a in q["atoms"]:
+            a["anno"] = -1
+        want = oracle.join_aggregate(q)
+        got = lh.run_query(q, policy=policy)
+        try:
+            assert_same(got, want)
+        except AssertionError:
+            say("materialized join seed", seed, "policy", policy)
+            raise
+        n += len(want["counts"])
+    assert n > 100
+
+
 def test_random_queries_larger_domains(lh):
     for seed in range(1000, 1030):
         q = queries.random_query(seed, max_atoms=3, max_attrs=4, domain=40, max_rows=300)
