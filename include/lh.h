@@ -431,7 +431,7 @@ typedef struct {
  * are HOST arrays; X is n x d_in row-major.
  *
  * Two decisions can use a registered model (lh_use_model); without one they
- * follow the plain rules of section 4, which also remain the judge of the
+ * follow the plain rules of section 4, which also remain the yardstick of the
  * model's regret.  Join results never depend on these choices.
  *  LH_MODEL_LAYOUT: per-set layout at lh_trie_build with LH_LAYOUT_LEARNED
  *    (sets of 32+ elements); features [log2 card, log2 span, log2(card/span),
