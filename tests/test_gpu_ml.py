@@ -203,3 +203,23 @@ def test_no_device_memory_leaks(lh, pipeline):
     t.free()
     del out
     assert lh.live_allocations() == before
+
+
+def test_voter_pipeline_full_size(lh, pipeline):
+    """The benchmark's workload (7,503,555 voters, 2,751 precincts, five
+    iterations, step 0.5) against the oracle.  At this size the bound on
+    the gradient's rounding error, n * eps * max|x| per iteration, is
+    carried over the iterations: |dw| <= iters * step * n * eps * max|x|."""
+    say("voter pipeline full size")
+    d = synth.voter_schema(7_503_555, 2751, 7)
+    t = pipeline.VoterTables(d, synth.voter_features(d))
+    try:
+        out = pipeline.run(t, iters=5, step=0.5, **synth.VOTER_FILTER)
+    finally:
+        t.free()
+    vid, _, (rows, feats, vals, nf), w_ref, loss_ref = oracle_pipeline(d, 5, 0.5)
+    assert out["n_rows"] == len(vid) and out["n_feat"] == nf
+    bound = 5 * 0.5 * len(vid) * np.finfo(np.float64).eps * float(np.max(np.abs(vals)))
+    err = np.abs(out["w"].cpu().numpy() - w_ref)
+    assert np.all(err <= max(bound, W_TOL)), (float(err.max()), bound)
+    np.testing.assert_allclose(out["loss"].cpu().numpy(), loss_ref, rtol=1e-10)
