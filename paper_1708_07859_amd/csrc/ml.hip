@@ -43,11 +43,12 @@ struct EncArgs {
 
 // One thread per output triple (row r, slot k): consecutive threads write
 // consecutive triples.
+template <class I>
 __global__ void k_encode(EncArgs a, uint64_t n) {
-  const uint64_t total = n * a.slots;
-  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t r = e / a.slots;
+  // I: the index type, 32-bit when n * slots fits (a cheaper division)
+  const I total = (I)(n * a.slots);
+  for (I e = (I)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (I)gridDim.x * blockDim.x) {
+    const I r = e / a.slots;
     const uint32_t k = (uint32_t)(e - r * a.slots);
     uint32_t feat = 0;
     double val = 1.0;  // the bias slot and indicators carry 1
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(LR_NT) void k_lr_cols(LrCols a) {
 // then a fixed shuffle tree) with every residual read from LDS.
 constexpr uint32_t RB_SHIFT = 12;
 constexpr uint32_t RB = 1u << RB_SHIFT;
+constexpr int RB_NT = 512;  // 8 waves share the block's features (32 KB of LDS per workgroup)
 
 // seg[f * (nb + 1) + b]: first entry of feature f (level-0 position) at a
 // row id >= b * RB; seg[f * (nb + 1) + nb] = the end of f's list.
@@ -237,15 +239,15 @@ struct LrBlocked {
   double* part;           // (f0, nb): per feature and block
 };
 
-__global__ __launch_bounds__(LR_NT) void k_lr_cols_blocked(LrBlocked a) {
+__global__ __launch_bounds__(RB_NT) void k_lr_cols_blocked(LrBlocked a) {
   __shared__ double s_res[RB];
   const uint32_t b = blockIdx.x;
   const uint64_t r0 = (uint64_t)b << RB_SHIFT;
   const uint32_t nr = (uint32_t)min<uint64_t>(RB, a.n_res - r0);
-  for (uint32_t i = threadIdx.x; i < nr; i += LR_NT) s_res[i] = a.res[r0 + i];
+  for (uint32_t i = threadIdx.x; i < nr; i += RB_NT) s_res[i] = a.res[r0 + i];
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (uint64_t f = w; f < a.f0; f += LR_NT / 64) {
+  for (uint64_t f = w; f < a.f0; f += RB_NT / 64) {
     const uint32_t s = a.seg[f * (a.nb + 1) + b], e = a.seg[f * (a.nb + 1) + b + 1];
     double acc = 0.0;
     for (uint32_t j = s + lane; j < e; j += 64)
@@ -342,7 +344,10 @@ uint32_t encode_features(uint64_t n, uint32_t n_id_cols, const uint32_t* const* 
     a.err = err.p;
     {
       ProfScope ps("encode", s, n, n * a.slots);
-      k_encode<<<grid_of(n * a.slots), 256, 0, s>>>(a, n);
+      if (n * a.slots < (1ull << 32) - (1ull << 26))
+        k_encode<uint32_t><<<grid_of(n * a.slots), 256, 0, s>>>(a, n);
+      else
+        k_encode<uint64_t><<<grid_of(n * a.slots), 256, 0, s>>>(a, n);
       LH_HIP(hipGetLastError());
     }
     const uint32_t e = read_scalar(err.p, s);
@@ -455,7 +460,7 @@ void logreg_fit(const lh_trie* xr, const lh_trie* xc, uint32_t anno, const doubl
     }
     if (blocked) {
       ProfScope ps("lr_cols_blocked", s, f0, nnz);
-      k_lr_cols_blocked<<<(unsigned)nblk, LR_NT, 0, s>>>(ba);
+      k_lr_cols_blocked<<<(unsigned)nblk, RB_NT, 0, s>>>(ba);
       LH_HIP(hipGetLastError());
     } else if (nchunks) {
       ProfScope ps("lr_cols", s, f0, nnz);

@@ -124,17 +124,19 @@ __global__ void k_sorted_tails(LevelCols c, uint64_t n, uint32_t* mask) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i0 = 1 + (uint64_t)blockIdx.x * blockDim.x; i0 < n && known; i0 += stride) {
     const uint64_t i = i0 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     uint32_t m = known;
-    if (i < n) {
-      bool ord = true;  // order of the suffix from level l on
-      // constant level indices: the column pointers stay in registers
+    bool ord = true;  // order of the suffix from level l on
+    // constant level indices: the column pointers stay in registers; each
+    // lane loads its row once and takes row i - 1 from the lane below
 #pragma unroll
-      for (int l = LH_MAX_KEYS - 1; l >= 0; l--) {
-        if (l < K) {
-          const uint32_t a = c.k[l][i - 1], b = c.k[l][i];
-          ord = a < b || (a == b && ord);
-          if (!ord) m &= ~(1u << (K - 1 - l));
-        }
+    for (int l = LH_MAX_KEYS - 1; l >= 0; l--) {
+      if (l < K) {
+        const uint32_t b = i < n ? c.k[l][i] : 0u;
+        uint32_t a = (uint32_t)__shfl_up((int)b, 1, 64);
+        if (lane == 0 && i < n) a = c.k[l][i - 1];
+        ord = a < b || (a == b && ord);
+        if (i < n && !ord) m &= ~(1u << (K - 1 - l));
       }
     }
     for (int o = 32; o > 0; o >>= 1) m &= (uint32_t)__shfl_xor((int)m, o, 64);
