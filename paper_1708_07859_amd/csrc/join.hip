@@ -1345,6 +1345,10 @@ __global__ void k_seg_accumulate(SegAccArgs a, uint64_t n) {
 // A dispatch counts work-items in 32 bits: cap the grid and let blocks
 // stride over virtual blocks.
 unsigned elem_grid(uint64_t nvblk) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nvblk, 32768)); }
+// The two-set leaf walks its virtual blocks with more workgroups in flight
+// than the frontier kernels: 131072 (512 per CU) measured 6% faster than
+// 32768 on R-MAT-22 triangles, while larger grids lose again.
+unsigned leaf_grid(uint64_t nvblk) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nvblk, 131072)); }
 
 unsigned grid_for(uint64_t n) {
   uint64_t b = (n + 255) / 256;
@@ -1953,7 +1957,7 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         l2.ucnt = ucnt.p;
         {
           ProfScope ps("leaf_aggregate", s, F.n, total);
-          k_leaf2_count<<<elem_grid(nblk), J_NT, 0, s>>>(l2);
+          k_leaf2_count<<<leaf_grid(nblk), J_NT, 0, s>>>(l2);
         }
         LH_HIP(hipGetLastError());
         if (L.gid) {
