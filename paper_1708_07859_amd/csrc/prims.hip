@@ -193,15 +193,25 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const
     lstart[tid] = st;
     run[tid] = st;
   }
+  // all of the tile's loads are issued before the first ranking round
+  uint64_t kk[RS_ITEMS];
+  uint32_t vv[RS_ITEMS];
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; i++) {
+    const uint32_t li = (uint32_t)i * RS_NT + tid;
+    kk[i] = li < ntile ? kin[base + li] : 0;
+    vv[i] = 0;
+    if constexpr (HAS_V) vv[i] = li < ntile ? vin[base + li] : 0u;
+  }
+#pragma unroll
   for (int i = 0; i < RS_ITEMS; i++) {
 #pragma unroll
     for (int j = 0; j < RS_NW; j++) wcnt[j][tid] = 0;
     __syncthreads();
     const uint32_t li = (uint32_t)i * RS_NT + tid;
     const bool valid = li < ntile;
-    const uint64_t k = valid ? kin[base + li] : 0;
-    uint32_t v = 0;
-    if constexpr (HAS_V) v = valid ? vin[base + li] : 0u;
+    const uint64_t k = kk[i];
+    const uint32_t v = vv[i];
     const uint32_t d = (uint32_t)(k >> shift) & 255u;
     uint64_t peers = ballot(valid);
 #pragma unroll
@@ -252,8 +262,9 @@ struct UnpackCols {
 __global__ void k_unpack_cols(UnpackCols a, const uint64_t* keys, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t k = keys[i];
-    for (uint32_t c = 0; c < a.ncols; c++)
-      a.col[c][i] = a.bits[c] ? (uint32_t)((k >> a.shift[c]) & ((1ull << a.bits[c]) - 1)) : 0u;
+#pragma unroll
+    for (uint32_t c = 0; c < LH_MAX_KEYS; c++)
+      if (c < a.ncols) a.col[c][i] = a.bits[c] ? (uint32_t)((k >> a.shift[c]) & ((1ull << a.bits[c]) - 1)) : 0u;
   }
 }
 
@@ -261,7 +272,9 @@ __global__ void k_pack(PackArgs a, const uint32_t* perm, uint64_t* out, uint64_t
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t r = perm ? perm[i] : (uint32_t)i;
     uint64_t k = 0;
-    for (uint32_t c = 0; c < a.ncols; c++) k |= (uint64_t)a.col[c][r] << a.shift[c];
+#pragma unroll
+    for (uint32_t c = 0; c < LH_MAX_KEYS; c++)
+      if (c < a.ncols) k |= (uint64_t)a.col[c][r] << a.shift[c];
     out[i] = k;
   }
 }
