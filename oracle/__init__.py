@@ -101,6 +101,10 @@ def _load():
         lib.orc_result_free.restype = None
         lib.orc_exact_dot.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]
         lib.orc_exact_dot.restype = C.c_double
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_set_threads.restype = None
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -184,6 +188,16 @@ def join_aggregate(query):
                 "n_join": int(res.n_join_tuples), "n_intermediate": int(res.n_intermediate)}
     finally:
         lib.orc_result_free(C.byref(res))
+
+
+def set_threads(n):
+    """Threads of the probe side (OpenMP); 0 restores the default."""
+    _load().orc_set_threads(int(n))
+
+
+def threads():
+    """Threads the next join_aggregate call will use."""
+    return int(_load().orc_threads())
 
 
 def exact_dot(a, b=None):

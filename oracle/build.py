@@ -16,7 +16,7 @@ def build(force: bool = True) -> str:
     src = os.path.join(HERE, "oracle.c")
     tmp = LIB + ".tmp"
     subprocess.check_call([
-        "gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-ffp-contract=off",
+        "gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-ffp-contract=off", "-fopenmp",
         "-fPIC", "-shared", "-o", tmp, src, "-lm",
     ])
     os.replace(tmp, LIB)

@@ -6,6 +6,14 @@ and loss L = mean((p - y)^2) / 2.  Parameters are packed as
 [W1 (64 x d_in), b1 (64), W2 (64 x 64), b2 (64), W3 (1 x 64), b3 (1)].
 The gradient is the chain rule written out layer by layer; the tests pin
 it with central finite differences of ``loss``.
+
+Training follows Adam as Kingma and Ba define it (Adam: A Method for
+Stochastic Optimization, 2015, Algorithm 1): exponential moving averages of
+the gradient and of its square, each divided by its bias correction, and a
+step of -lr * m_hat / (sqrt(v_hat) + eps).  The tests pin it with closed
+forms: the first step from zero moments moves every parameter by
+-lr * g / (|g| + eps), and a constant gradient keeps that step at every
+iteration.
 """
 import numpy as np
 
@@ -81,3 +89,30 @@ def forward_bf16(p, X):
     a1 = bf16(np.maximum(x @ W1.T + b1, 0))
     a2 = bf16(np.maximum(a1 @ W2.T + b2, 0))
     return (a2 @ W3.T + b3)[:, 0].astype(np.float64)
+
+
+BETA1, BETA2, EPS = 0.9, 0.999, 1e-8
+
+
+def adam_step(p, g, m, v, t, lr, b1=BETA1, b2=BETA2, eps=EPS):
+    """One Adam update at step t (1-based): returns (p, m, v)."""
+    g = np.asarray(g, dtype=np.float64)
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return p - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def train_full_batch(p, X, y, steps, lr):
+    """`steps` Adam steps on the whole batch (X, y), from zero moments.
+    Returns the parameters and the loss before each step."""
+    p = np.asarray(p, dtype=np.float64).copy()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    losses = []
+    for t in range(1, steps + 1):
+        L, g = loss_grad(p, X, y)
+        losses.append(L)
+        p, m, v = adam_step(p, g, m, v, t, lr)
+    return p, losses

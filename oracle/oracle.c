@@ -1,7 +1,9 @@
 /*
  * Join-aggregate oracle: TEST INFRASTRUCTURE ONLY (see oracle.h for what it
- * computes and why it is shaped as it is).  Plain C, single-threaded, built
- * with -ffp-contract=off so no multiply is fused behind the reader's back.
+ * computes and why it is shaped as it is).  Plain C with OpenMP over the
+ * probe side of each join (thread-local intermediates and aggregation
+ * tables, merged exactly), built with -ffp-contract=off so no multiply is
+ * fused behind the reader's back.
  */
 #define _GNU_SOURCE
 #include "oracle.h"
@@ -9,6 +11,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef unsigned __int128 u128;
 
@@ -230,14 +235,12 @@ static int vec_reserve(vec* v, uint64_t need) {
 /* ------------------------------------------------------------------------
  * Query evaluation.
  * ---------------------------------------------------------------------- */
+
+/* One aggregation table: group keys, counts and exact sums.  Every thread
+ * aggregates into its own table; the tables are merged at the end, which
+ * does not depend on the order because counts and accumulators are exact
+ * integers. */
 typedef struct {
-  const orc_query* q;
-  uint32_t wu;          /* uint32 slots per intermediate tuple: attrs then groups */
-  uint32_t wf;          /* factor slots: one per annotated atom */
-  int32_t* fslot;       /* factor slot of each atom, -1 if none */
-  uint64_t** rows;      /* surviving row ids per atom */
-  uint64_t* nrows;
-  /* aggregation */
   uint32_t wk;
   vec gkeys;            /* uint32 x wk per group */
   vec gcount;           /* uint64 per group */
@@ -246,6 +249,15 @@ typedef struct {
   const uint32_t* gkeys_ptr;
   uint64_t n_join;
   int status;
+} agg_state;
+
+typedef struct {
+  const orc_query* q;
+  uint32_t wu;          /* uint32 slots per intermediate tuple: attrs then groups */
+  uint32_t wf;          /* factor slots: one per annotated atom */
+  int32_t* fslot;       /* factor slot of each atom, -1 if none */
+  uint64_t** rows;      /* surviving row ids per atom */
+  uint64_t* nrows;
 } eval_ctx;
 
 static int row_passes(const orc_query* q, uint32_t ai, uint64_t r) {
@@ -277,6 +289,9 @@ static int row_passes(const orc_query* q, uint32_t ai, uint64_t r) {
   return 1;
 }
 
+/* Widest aggregation key: output attributes plus group columns. */
+#define MAX_KEY_COLS 128
+
 static int validate(const orc_query* q) {
   if (!q || q->n_atoms == 0 || !q->atoms || q->n_attrs == 0 || q->n_attrs > 64) return ORC_E_INVALID;
   if (q->agg != ORC_COUNT && q->agg != ORC_SUM) return ORC_E_INVALID;
@@ -298,6 +313,7 @@ static int validate(const orc_query* q) {
   }
   if (seen != (q->n_attrs == 64 ? ~0ull : ((1ull << q->n_attrs) - 1))) return ORC_E_INVALID;
   if (q->agg == ORC_SUM && !annotated) return ORC_E_INVALID;
+  if (q->n_out > q->n_attrs || (uint64_t)q->n_out + q->n_group > MAX_KEY_COLS) return ORC_E_INVALID;
   uint64_t outs = 0;
   for (uint32_t i = 0; i < q->n_out; i++) {
     uint32_t v = q->out_attrs[i];
@@ -355,46 +371,78 @@ static int select_rows(const orc_query* q, uint32_t e, uint64_t** out, uint64_t*
   return ORC_OK;
 }
 
-/* Aggregate one full-join tuple (u: attr values then group values, f: the
- * factors of the annotated atoms so far, in atom order). */
-static void aggregate(eval_ctx* c, const uint32_t* u, const double* f) {
+static int agg_init(agg_state* a, uint32_t wk, int is_sum) {
+  memset(a, 0, sizeof *a);
+  a->wk = wk;
+  a->gkeys.elt = sizeof(uint32_t);
+  a->gcount.elt = sizeof(uint64_t);
+  a->gacc.elt = sizeof(acc_t);
+  if (wk) return ht_init(&a->agg, wk, 1024, &a->gkeys_ptr);
+  /* no output columns: one group, present even when nothing joins */
+  if (vec_reserve(&a->gcount, 1) || (is_sum && vec_reserve(&a->gacc, 1))) return ORC_E_NOMEM;
+  ((uint64_t*)a->gcount.p)[0] = 0;
+  a->gcount.n = 1;
+  if (is_sum) { memset(a->gacc.p, 0, sizeof(acc_t)); a->gacc.n = 1; }
+  return ORC_OK;
+}
+
+static void agg_free(agg_state* a) {
+  free(a->gkeys.p);
+  free(a->gcount.p);
+  free(a->gacc.p);
+  if (a->wk) ht_free(&a->agg);
+}
+
+/* Group index of key in table a (created empty when new), or UINT64_MAX
+ * when memory runs out. */
+static uint64_t agg_group(agg_state* a, const uint32_t* key, int is_sum) {
+  if (a->wk == 0) return 0;
+  /* the probe key is compared against stored keys only */
+  uint64_t s = ht_find(&a->agg, key);
+  if (a->agg.slot[s]) return a->agg.slot[s] - 1;
+  uint64_t g = a->gcount.n;
+  if (vec_reserve(&a->gkeys, (g + 1) * a->wk) || vec_reserve(&a->gcount, g + 1) ||
+      (is_sum && vec_reserve(&a->gacc, g + 1)))
+    return UINT64_MAX;
+  memcpy((uint32_t*)a->gkeys.p + g * a->wk, key, a->wk * sizeof(uint32_t));
+  a->gkeys_ptr = (const uint32_t*)a->gkeys.p;
+  ((uint64_t*)a->gcount.p)[g] = 0;
+  a->gcount.n = g + 1;
+  a->gkeys.n = (g + 1) * a->wk;
+  if (is_sum) {
+    memset((acc_t*)a->gacc.p + g, 0, sizeof(acc_t));
+    a->gacc.n = g + 1;
+  }
+  a->agg.slot[s] = g + 1;
+  if (++a->agg.n * 2 > a->agg.cap && ht_grow(&a->agg)) return UINT64_MAX;
+  return g;
+}
+
+/* x += y, both 512-bit two's complement (merging exact accumulators). */
+static void acc_merge(acc_t* x, const acc_t* y) {
+  uint64_t carry = 0;
+  for (int i = 0; i < ACC_W; i++) {
+    u128 s2 = (u128)x->w[i] + y->w[i] + carry;
+    x->w[i] = (uint64_t)s2;
+    carry = (uint64_t)(s2 >> 64);
+  }
+}
+
+/* Aggregate one full-join tuple into table a (u: attr values then group
+ * values, f: the factors of the annotated atoms, in atom order). */
+static void aggregate(const eval_ctx* c, agg_state* a, const uint32_t* u, const double* f) {
   const orc_query* q = c->q;
-  uint32_t key[128];
+  uint32_t key[MAX_KEY_COLS];
   for (uint32_t i = 0; i < q->n_out; i++) key[i] = u[q->out_attrs[i]];
   for (uint32_t i = 0; i < q->n_group; i++) key[q->n_out + i] = u[q->n_attrs + i];
-  uint64_t g;
-  if (c->wk == 0) {
-    g = 0;
-  } else {
-    /* the probe key is compared against stored keys only */
-    uint64_t s = ht_find(&c->agg, key);
-    if (c->agg.slot[s]) {
-      g = c->agg.slot[s] - 1;
-    } else {
-      g = c->gcount.n;
-      if (vec_reserve(&c->gkeys, (g + 1) * c->wk) || vec_reserve(&c->gcount, g + 1) ||
-          (q->agg == ORC_SUM && vec_reserve(&c->gacc, g + 1))) {
-        c->status = ORC_E_NOMEM;
-        return;
-      }
-      memcpy((uint32_t*)c->gkeys.p + g * c->wk, key, c->wk * sizeof(uint32_t));
-      c->gkeys_ptr = (const uint32_t*)c->gkeys.p;
-      ((uint64_t*)c->gcount.p)[g] = 0;
-      c->gcount.n = g + 1;
-      c->gkeys.n = (g + 1) * c->wk;
-      if (q->agg == ORC_SUM) {
-        memset((acc_t*)c->gacc.p + g, 0, sizeof(acc_t));
-        c->gacc.n = g + 1;
-      }
-      c->agg.slot[s] = g + 1;
-      if (++c->agg.n * 2 > c->agg.cap && ht_grow(&c->agg)) { c->status = ORC_E_NOMEM; return; }
-    }
-  }
-  ((uint64_t*)c->gcount.p)[g] += 1;
-  c->n_join++;
-  if (q->agg == ORC_SUM) {
-    int st = acc_add_product((acc_t*)c->gacc.p + g, f, (int)c->wf);
-    if (st) c->status = st;
+  const int is_sum = q->agg == ORC_SUM;
+  uint64_t g = agg_group(a, key, is_sum);
+  if (g == UINT64_MAX) { a->status = ORC_E_NOMEM; return; }
+  ((uint64_t*)a->gcount.p)[g] += 1;
+  a->n_join++;
+  if (is_sum) {
+    int st = acc_add_product((acc_t*)a->gacc.p + g, f, (int)c->wf);
+    if (st) a->status = st;
   }
 }
 
@@ -419,65 +467,82 @@ static int key_cmp(const void* x, const void* y, void* ctx) {
   return 0;
 }
 
+static int n_threads_set = 0;
+
+void orc_set_threads(int n) { n_threads_set = n > 0 ? n : 0; }
+
+int orc_threads(void) {
+#ifdef _OPENMP
+  return n_threads_set > 0 ? n_threads_set : omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* The running intermediate: one segment of tuples per thread that made
+ * them (their order does not matter: the join is a set of tuples and the
+ * aggregation is exact). */
+typedef struct {
+  vec u, f;
+  uint64_t n;
+} segment;
+
 int orc_join_aggregate(const orc_query* q, orc_result* out) {
   if (!out) return ORC_E_INVALID;
   memset(out, 0, sizeof *out);
   int st = validate(q);
   if (st) return st;
+  const int nthr = orc_threads();
+  const int is_sum = q->agg == ORC_SUM;
 
   eval_ctx c;
   memset(&c, 0, sizeof c);
   c.q = q;
   c.wu = q->n_attrs + q->n_group;
-  c.wk = q->n_out + q->n_group;
+  const uint32_t wk = q->n_out + q->n_group;
   c.fslot = (int32_t*)malloc(q->n_atoms * sizeof(int32_t));
   c.rows = (uint64_t**)calloc(q->n_atoms, sizeof(uint64_t*));
   c.nrows = (uint64_t*)calloc(q->n_atoms, sizeof(uint64_t));
-  c.gkeys.elt = sizeof(uint32_t);
-  c.gcount.elt = sizeof(uint64_t);
-  c.gacc.elt = sizeof(acc_t);
-  vec cur_u = {0, 0, 0, sizeof(uint32_t)}, cur_f = {0, 0, 0, sizeof(double)};
-  vec nxt_u = {0, 0, 0, sizeof(uint32_t)}, nxt_f = {0, 0, 0, sizeof(double)};
+  agg_state* tabs = (agg_state*)calloc((size_t)nthr, sizeof(agg_state));
+  segment* cur = (segment*)calloc((size_t)nthr, sizeof(segment));
+  segment* nxt = (segment*)calloc((size_t)nthr, sizeof(segment));
+  int ncur = 1;
   uint32_t* bkeys = NULL;
   uint64_t* chain = NULL;
-  uint64_t n_cur = 0;
-  if (!c.fslot || !c.rows || !c.nrows) { st = ORC_E_NOMEM; goto done; }
+  if (!c.fslot || !c.rows || !c.nrows || !tabs || !cur || !nxt) { st = ORC_E_NOMEM; goto done; }
+  for (int t = 0; t < nthr; t++) {
+    cur[t].u.elt = nxt[t].u.elt = sizeof(uint32_t);
+    cur[t].f.elt = nxt[t].f.elt = sizeof(double);
+    if ((st = agg_init(&tabs[t], wk, is_sum))) goto done;
+  }
   for (uint32_t e = 0; e < q->n_atoms; e++) {
-    c.fslot[e] = (q->agg == ORC_SUM && q->atoms[e].anno >= 0) ? (int32_t)c.wf++ : -1;
+    c.fslot[e] = (is_sum && q->atoms[e].anno >= 0) ? (int32_t)c.wf++ : -1;
     if ((st = select_rows(q, e, &c.rows[e], &c.nrows[e]))) goto done;
   }
-  c.gkeys_ptr = NULL;
-  if (c.wk && (st = ht_init(&c.agg, c.wk, 1024, &c.gkeys_ptr))) goto done;
-  if (c.wk == 0) {
-    if (vec_reserve(&c.gcount, 1) || (q->agg == ORC_SUM && vec_reserve(&c.gacc, 1))) { st = ORC_E_NOMEM; goto done; }
-    ((uint64_t*)c.gcount.p)[0] = 0;
-    c.gcount.n = 1;
-    if (q->agg == ORC_SUM) { memset(c.gacc.p, 0, sizeof(acc_t)); c.gacc.n = 1; }
-  }
+  const uint32_t wf1 = c.wf ? c.wf : 1;
 
   /* scan of atom 0 */
   {
-    uint32_t wf1 = c.wf ? c.wf : 1;
-    if (vec_reserve(&cur_u, (c.nrows[0] + 1) * c.wu) || vec_reserve(&cur_f, (c.nrows[0] + 1) * wf1)) { st = ORC_E_NOMEM; goto done; }
+    segment* s0 = &cur[0];
+    if (vec_reserve(&s0->u, (c.nrows[0] + 1) * c.wu) || vec_reserve(&s0->f, (c.nrows[0] + 1) * wf1)) { st = ORC_E_NOMEM; goto done; }
     for (uint64_t i = 0; i < c.nrows[0]; i++) {
-      uint32_t* u = (uint32_t*)cur_u.p + i * c.wu;
-      double* f = (double*)cur_f.p + i * wf1;
+      uint32_t* u = (uint32_t*)s0->u.p + i * c.wu;
+      double* f = (double*)s0->f.p + i * wf1;
       memset(u, 0, c.wu * sizeof(uint32_t));
       bind_atom(&c, 0, c.rows[0][i], u, f);
     }
-    n_cur = c.nrows[0];
-    out->n_intermediate = n_cur;
+    s0->n = c.nrows[0];
+    out->n_intermediate = s0->n;
   }
   if (q->n_atoms == 1) {
-    uint32_t wf1 = c.wf ? c.wf : 1;
-    for (uint64_t i = 0; i < n_cur && !c.status; i++)
-      aggregate(&c, (uint32_t*)cur_u.p + i * c.wu, (double*)cur_f.p + i * wf1);
+    for (uint64_t i = 0; i < cur[0].n && !tabs[0].status; i++)
+      aggregate(&c, &tabs[0], (uint32_t*)cur[0].u.p + i * c.wu, (double*)cur[0].f.p + i * wf1);
   }
 
   uint64_t bound = 0;
   for (uint32_t k = 0; k < q->atoms[0].n_keys; k++) bound |= 1ull << q->atoms[0].attr_of_key[k];
 
-  for (uint32_t e = 1; e < q->n_atoms && !c.status; e++) {
+  for (uint32_t e = 1; e < q->n_atoms; e++) {
     const orc_atom* a = &q->atoms[e];
     uint32_t shared_col[64], shared_attr[64], ns = 0;
     for (uint32_t v = 0; v < q->n_attrs; v++) {
@@ -498,7 +563,6 @@ int orc_join_aggregate(const orc_query* q, orc_result* out) {
     if ((st = ht_init(&ht, wsh, nb, &bk))) goto done;
     /* head of each key's chain lives in the slot; chain[i] links rows */
     uint64_t* head = NULL;
-    uint64_t nkeys = 0;
     {
       vec hv = {0, 0, 0, sizeof(uint64_t)};
       for (uint64_t i = 0; i < nb; i++) {
@@ -515,77 +579,119 @@ int orc_join_aggregate(const orc_query* q, orc_result* out) {
           ((uint64_t*)hv.p)[i] = i;                    /* indexed by the key's first row */
           chain[i] = UINT64_MAX;
           ht.slot[s] = i + 1;
-          nkeys++;
           if (++ht.n * 2 > ht.cap && ht_grow(&ht)) { ht_free(&ht); free(hv.p); st = ORC_E_NOMEM; goto done; }
         }
       }
       head = (uint64_t*)hv.p;
     }
-    (void)nkeys;
-    /* probe side: the running intermediate */
-    int last = (e + 1 == q->n_atoms);
-    uint32_t wf1 = c.wf ? c.wf : 1;
-    uint64_t n_nxt = 0;
-    uint32_t probe[64];
-    uint32_t* tu = (uint32_t*)malloc(c.wu * sizeof(uint32_t) + 4);
-    double* tf = (double*)malloc(wf1 * sizeof(double));
-    if (!tu || !tf) { free(tu); free(tf); free(head); ht_free(&ht); st = ORC_E_NOMEM; goto done; }
-    for (uint64_t i = 0; i < n_cur && !c.status; i++) {
-      const uint32_t* u = (const uint32_t*)cur_u.p + i * c.wu;
-      const double* f = (const double*)cur_f.p + i * wf1;
-      if (ns == 0) probe[0] = 0;
-      for (uint32_t j = 0; j < ns; j++) probe[j] = u[shared_attr[j]];
-      uint64_t s = ht_find(&ht, probe);
-      if (!ht.slot[s]) continue;
-      for (uint64_t b = head[ht.slot[s] - 1]; b != UINT64_MAX; b = chain[b]) {
-        memcpy(tu, u, c.wu * sizeof(uint32_t));
-        memcpy(tf, f, wf1 * sizeof(double));
-        bind_atom(&c, e, c.rows[e][b], tu, tf);
-        if (last) {
-          aggregate(&c, tu, tf);
-        } else {
-          if (vec_reserve(&nxt_u, (n_nxt + 1) * c.wu) || vec_reserve(&nxt_f, (n_nxt + 1) * wf1)) {
-            c.status = ORC_E_NOMEM;
-            break;
+    /* probe side: the running intermediate, split over the threads; each
+     * thread appends to its own segment or aggregates into its own table */
+    const int last = (e + 1 == q->n_atoms);
+    int fail = 0;
+    for (int t = 0; t < nthr; t++) nxt[t].n = 0;
+#pragma omp parallel num_threads(nthr)
+    {
+#ifdef _OPENMP
+      const int t = omp_get_thread_num();
+#else
+      const int t = 0;
+#endif
+      uint32_t probe[64];
+      uint32_t* tu = (uint32_t*)malloc(c.wu * sizeof(uint32_t) + 4);
+      double* tf = (double*)malloc(wf1 * sizeof(double));
+      segment* my = &nxt[t];
+      agg_state* tab = &tabs[t];
+      if (!tu || !tf) {
+#pragma omp atomic write
+        fail = 1;
+      }
+      for (int sg = 0; sg < ncur; sg++) {
+        const segment* in = &cur[sg];
+#pragma omp for schedule(dynamic, 4096) nowait
+        for (uint64_t i = 0; i < in->n; i++) {
+          int stop;
+#pragma omp atomic read
+          stop = fail;
+          if (stop || tab->status || !tu || !tf) continue;
+          const uint32_t* u = (const uint32_t*)in->u.p + i * c.wu;
+          const double* f = (const double*)in->f.p + i * wf1;
+          if (ns == 0) probe[0] = 0;
+          for (uint32_t j = 0; j < ns; j++) probe[j] = u[shared_attr[j]];
+          uint64_t s = ht_find(&ht, probe);
+          if (!ht.slot[s]) continue;
+          for (uint64_t b = head[ht.slot[s] - 1]; b != UINT64_MAX; b = chain[b]) {
+            memcpy(tu, u, c.wu * sizeof(uint32_t));
+            memcpy(tf, f, wf1 * sizeof(double));
+            bind_atom(&c, e, c.rows[e][b], tu, tf);
+            if (last) {
+              aggregate(&c, tab, tu, tf);
+            } else {
+              if (vec_reserve(&my->u, (my->n + 1) * c.wu) || vec_reserve(&my->f, (my->n + 1) * wf1)) {
+#pragma omp atomic write
+                fail = 1;
+                break;
+              }
+              memcpy((uint32_t*)my->u.p + my->n * c.wu, tu, c.wu * sizeof(uint32_t));
+              memcpy((double*)my->f.p + my->n * wf1, tf, wf1 * sizeof(double));
+              my->n++;
+            }
           }
-          memcpy((uint32_t*)nxt_u.p + n_nxt * c.wu, tu, c.wu * sizeof(uint32_t));
-          memcpy((double*)nxt_f.p + n_nxt * wf1, tf, wf1 * sizeof(double));
-          n_nxt++;
         }
       }
+      free(tu);
+      free(tf);
     }
-    free(tu);
-    free(tf);
     free(head);
     ht_free(&ht);
+    if (fail) { st = ORC_E_NOMEM; goto done; }
+    for (int t = 0; t < nthr; t++)
+      if (tabs[t].status) { st = tabs[t].status; goto done; }
     if (!last) {
-      vec t;
-      t = cur_u; cur_u = nxt_u; nxt_u = t;
-      t = cur_f; cur_f = nxt_f; nxt_f = t;
-      n_cur = n_nxt;
-      if (n_cur > out->n_intermediate) out->n_intermediate = n_cur;
+      uint64_t tot = 0;
+      for (int t = 0; t < nthr; t++) {
+        segment tmp = cur[t];
+        cur[t] = nxt[t];
+        nxt[t] = tmp;
+        tot += cur[t].n;
+      }
+      ncur = nthr;
+      if (tot > out->n_intermediate) out->n_intermediate = tot;
     }
     for (uint32_t k = 0; k < a->n_keys; k++) bound |= 1ull << a->attr_of_key[k];
   }
-  if (c.status) { st = c.status; goto done; }
+  for (int t = 0; t < nthr; t++)
+    if (tabs[t].status) { st = tabs[t].status; goto done; }
+
+  /* merge the thread tables into the first one */
+  for (int t = 1; t < nthr; t++) {
+    agg_state* src = &tabs[t];
+    for (uint64_t g = 0; g < src->gcount.n; g++) {
+      const uint64_t d = agg_group(&tabs[0], (const uint32_t*)src->gkeys.p + g * src->wk, is_sum);
+      if (d == UINT64_MAX) { st = ORC_E_NOMEM; goto done; }
+      ((uint64_t*)tabs[0].gcount.p)[d] += ((const uint64_t*)src->gcount.p)[g];
+      if (is_sum) acc_merge((acc_t*)tabs[0].gacc.p + d, (const acc_t*)src->gacc.p + g);
+    }
+    tabs[0].n_join += src->n_join;
+  }
 
   /* emit, sorted ascending by key */
   {
-    uint64_t ng = c.gcount.n;
-    if (c.wk == 0) ng = 1;
+    const agg_state* A = &tabs[0];
+    uint64_t ng = A->gcount.n;
+    if (wk == 0) ng = 1;
     uint64_t* order = (uint64_t*)malloc((ng + 1) * sizeof(uint64_t));
     if (!order) { st = ORC_E_NOMEM; goto done; }
     for (uint64_t i = 0; i < ng; i++) order[i] = i;
-    if (c.wk) {
-      key_cmp_ctx cx = {(const uint32_t*)c.gkeys.p, c.wk};
+    if (wk) {
+      key_cmp_ctx cx = {(const uint32_t*)A->gkeys.p, wk};
       qsort_r(order, ng, sizeof(uint64_t), key_cmp, &cx);
     }
     out->n_rows = ng;
-    out->n_cols = c.wk;
-    out->keys = (uint32_t*)malloc((ng * c.wk + 1) * sizeof(uint32_t));
+    out->n_cols = wk;
+    out->keys = (uint32_t*)malloc((ng * wk + 1) * sizeof(uint32_t));
     out->counts = (uint64_t*)malloc((ng + 1) * sizeof(uint64_t));
-    out->sums = q->agg == ORC_SUM ? (double*)malloc((ng + 1) * sizeof(double)) : NULL;
-    if (!out->keys || !out->counts || (q->agg == ORC_SUM && !out->sums)) {
+    out->sums = is_sum ? (double*)malloc((ng + 1) * sizeof(double)) : NULL;
+    if (!out->keys || !out->counts || (is_sum && !out->sums)) {
       free(order);
       orc_result_free(out);
       st = ORC_E_NOMEM;
@@ -593,11 +699,11 @@ int orc_join_aggregate(const orc_query* q, orc_result* out) {
     }
     for (uint64_t i = 0; i < ng; i++) {
       uint64_t g = order[i];
-      if (c.wk) memcpy(out->keys + i * c.wk, (uint32_t*)c.gkeys.p + g * c.wk, c.wk * sizeof(uint32_t));
-      out->counts[i] = ((uint64_t*)c.gcount.p)[g];
-      if (out->sums) out->sums[i] = acc_round((acc_t*)c.gacc.p + g);
+      if (wk) memcpy(out->keys + i * wk, (uint32_t*)A->gkeys.p + g * wk, wk * sizeof(uint32_t));
+      out->counts[i] = ((uint64_t*)A->gcount.p)[g];
+      if (out->sums) out->sums[i] = acc_round((acc_t*)A->gacc.p + g);
     }
-    out->n_join_tuples = c.n_join;
+    out->n_join_tuples = A->n_join;
     free(order);
   }
 
@@ -607,14 +713,15 @@ done:
   free(c.rows);
   free(c.nrows);
   free(c.fslot);
-  free(c.gkeys.p);
-  free(c.gcount.p);
-  free(c.gacc.p);
-  if (c.wk) ht_free(&c.agg);
-  free(cur_u.p);
-  free(cur_f.p);
-  free(nxt_u.p);
-  free(nxt_f.p);
+  if (tabs)
+    for (int t = 0; t < nthr; t++) agg_free(&tabs[t]);
+  free(tabs);
+  if (cur)
+    for (int t = 0; t < nthr; t++) { free(cur[t].u.p); free(cur[t].f.p); }
+  if (nxt)
+    for (int t = 0; t < nthr; t++) { free(nxt[t].u.p); free(nxt[t].f.p); }
+  free(cur);
+  free(nxt);
   free(bkeys);
   free(chain);
   return st;

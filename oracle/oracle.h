@@ -1,7 +1,7 @@
 /*
  * Join-aggregate oracle: TEST INFRASTRUCTURE ONLY.
  *
- * A plain, slow, single-threaded CPU evaluation of an aggregate-join query
+ * A plain, slow CPU evaluation of an aggregate-join query
  * over annotated relations.  It is used by the test-suite, by the smoke check
  * and by the CPU-baseline leg of the benchmark, and by nothing else: the
  * GPU library never links, loads or calls it, and it shares no code,
@@ -27,7 +27,11 @@
  * running intermediate and probed by the intermediate), followed by hash
  * aggregation keyed by the output attributes and group columns.  This is
  * deliberately NOT the paper's Generic-Join (Algorithm 1), so agreement
- * between the two is evidence.
+ * between the two is evidence.  The probe side of each join is split over
+ * OpenMP threads; each keeps its own intermediate tuples and its own
+ * aggregation table, and the tables are merged at the end.  Counts and
+ * exact accumulators are integers, so the merge does not depend on the
+ * order and the result is the same for any thread count.
  *
  * SUM semantics: every term (the product of the tuple's non-identity
  * annotations) is added EXACTLY into a 512-bit fixed-point accumulator with
@@ -75,10 +79,10 @@ typedef struct {
 typedef struct { uint32_t atom, meta_col; } orc_group;
 
 typedef struct {
-  uint32_t n_attrs;
+  uint32_t n_attrs;              /* 1..64 */
   uint32_t n_atoms;
   const orc_atom* atoms;
-  uint32_t n_out;
+  uint32_t n_out;                /* n_out + n_group <= 128 */
   const uint32_t* out_attrs;
   uint32_t n_group;
   const orc_group* groups;
@@ -98,6 +102,10 @@ typedef struct {
 } orc_result;
 
 int orc_join_aggregate(const orc_query* q, orc_result* out);
+/* Threads of the probe side: n > 0 fixes the count, 0 restores the OpenMP
+ * default; orc_threads() returns the count the next call will use. */
+void orc_set_threads(int n);
+int orc_threads(void);
 void orc_result_free(orc_result* r);
 
 /* Exact sum of products: SUM_i a[i]*b[i] (b == NULL: SUM_i a[i]) rounded

@@ -172,26 +172,10 @@ struct BatchArgs {
   uint32_t kw;                      // k values per heavy window (multiple of 64, <= KW_MAX)
 };
 
-// Exact sum held in slots (EXACT_MAXD stride) of one accumulator: add t.
-__device__ __forceinline__ bool lds_add_term(long long* slots, double v, int32_t lsb, uint32_t D, int64_t mult) {
-  if (v == 0.0) return true;
-  int32_t k0;
-  int64_t d0, d1, d2;
-  bool neg;
-  if (!split_to_digits(v, lsb, k0, d0, d1, d2, neg)) return false;
-  if (neg) mult = -mult;
-  const int64_t dd[3] = {d0 * mult, d1 * mult, d2 * mult};
-  bool ok = true;
-  for (int q = 0; q < 3; q++) {
-    if (dd[q] == 0) continue;
-    const int32_t k = k0 + q;
-    if (k >= (int32_t)D) {
-      ok = false;
-      continue;
-    }
-    atomicAdd((unsigned long long*)&slots[k], (unsigned long long)dd[q]);
-  }
-  return ok;
+// Exact sum held in LDS slots (EXACT_MAXD stride) of one accumulator: add
+// mult * v (shared slot form, so any number of terms is exact).
+__device__ __forceinline__ bool lds_add_term(long long* slots, double v, int32_t lsb, uint32_t D, uint64_t mult) {
+  return atomic_add_term((int64_t*)slots, v, lsb, D, mult);
 }
 
 // Heavy rows: one block per row.  A symbolic pass marks every k the row

@@ -1,13 +1,31 @@
 // Exact, order-independent FP64 summation on the device.
 //
 // A sum of products is accumulated as a fixed-point integer whose least
-// significant bit has weight 2^lsb, held in D signed 64-bit slots of 32-bit
-// digits (slot i has weight 2^(lsb + 32 i)).  Contributions are added to the
-// slots without carrying (each slot absorbs ~2^30 additions of 33-bit
-// values), carries are propagated before slots are merged, and the final
-// value is rounded once to the nearest double, ties to even.  Because
-// integer addition is associative, the result does not depend on the order
-// of the terms, the intersection algorithm, the set layout or the batching.
+// significant bit has weight 2^lsb, held in D 64-bit slots of 32-bit
+// digits (slot i has weight 2^(lsb + 32 i)), and rounded once to the
+// nearest double, ties to even.  Because integer addition is associative,
+// the result does not depend on the order of the terms, the intersection
+// algorithm, the set layout or the batching.
+//
+// A term v repeated mult times (mult < 2^64: rows of bag relations that
+// carry no annotation) is split into the exact words of |v| * mult / 2^lsb,
+// at most five 32-bit words, so every addition into a slot is below 2^32
+// in magnitude whatever the multiplicity.
+//
+// Two slot forms exist:
+//  - register accumulators (RegAcc) add signed words into int64 slots and
+//    carry every 2^24 additions, so no slot leaves int64;
+//  - shared accumulators (global or LDS, updated with atomics) keep every
+//    slot below the top one as an unsigned value modulo 2^64.  An atomic
+//    add returns the slot's previous value, from which the adding thread
+//    knows exactly whether its own addition wrapped; it then adds the wrap
+//    (+-2^32) into the next slot.  Atomic adds are linearizable, so the
+//    wraps counted this way are exactly those of the serial history, and
+//    the value is kept exactly for any number of additions.  The top slot
+//    is signed; the plan sizes D so that it stays far inside int64.
+// Both forms are read with the same carry rule (lower slots unsigned, top
+// slot signed), since a normalized register accumulator is also a valid
+// shared-form value.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,13 +41,24 @@ __device__ __forceinline__ void two_prod(double a, double b, double& hi, double&
   lo = __fma_rn(a, b, -hi);
 }
 
-// Digits of |v| placed relative to 2^lsb: digit index k0 and three 32-bit
-// (unnormalized, < 2^33) parts.  Returns false when v has bits below 2^lsb.
-__device__ __forceinline__ bool split_to_digits(double v, int32_t lsb, int32_t& k0, int64_t& d0, int64_t& d1,
-                                                int64_t& d2, bool& neg) {
-  uint64_t bits = (uint64_t)__double_as_longlong(v);
+// Multiply with saturation at UINT64_MAX (row multiplicities and counts).
+__device__ __forceinline__ uint64_t sat_mul_u64(uint64_t a, uint64_t b) {
+  const uint64_t hi = __umul64hi(a, b);
+  return hi ? UINT64_MAX : a * b;
+}
+__device__ __forceinline__ uint64_t sat_add_u64(uint64_t a, uint64_t b) {
+  const uint64_t s = a + b;
+  return s < a ? UINT64_MAX : s;
+}
+
+// |v| * mult / 2^lsb as five 32-bit words p[0..4] placed at digit k0.
+// Returns false when v has bits below 2^lsb.  v == 0 or mult == 0 gives
+// all-zero words.
+__device__ __forceinline__ bool term_words(double v, int32_t lsb, uint64_t mult, int32_t& k0, uint32_t* p,
+                                           bool& neg) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(v);
   neg = (bits >> 63) != 0;
-  uint32_t ex = (uint32_t)(bits >> 52) & 0x7ffu;
+  const uint32_t ex = (uint32_t)(bits >> 52) & 0x7ffu;
   uint64_t mant = bits & ((1ull << 52) - 1);
   int32_t e;
   if (ex == 0) {
@@ -38,26 +67,42 @@ __device__ __forceinline__ bool split_to_digits(double v, int32_t lsb, int32_t& 
     mant |= 1ull << 52;
     e = (int32_t)ex - 1075;
   }
-  if (mant == 0) {
-    k0 = 0;
-    d0 = d1 = d2 = 0;
-    return true;
-  }
+#pragma unroll
+  for (int j = 0; j < 5; j++) p[j] = 0;
+  k0 = 0;
+  if (mant == 0 || mult == 0) return true;
   int32_t sh = e - lsb;
   if (sh < 0) {
-    int tz = __builtin_ctzll(mant);
+    const int tz = __builtin_ctzll(mant);
     if (tz < -sh) return false;
     mant >>= -sh;
     sh = 0;
   }
   k0 = sh >> 5;
-  uint32_t off = (uint32_t)sh & 31u;
-  uint64_t ml = mant & 0xffffffffull, mh = mant >> 32;
-  uint64_t t0 = ml << off;   // < 2^64
-  uint64_t t1 = mh << off;   // < 2^53
-  d0 = (int64_t)(t0 & 0xffffffffull);
-  d1 = (int64_t)((t0 >> 32) + (t1 & 0xffffffffull));
-  d2 = (int64_t)(t1 >> 32);
+  const uint32_t off = (uint32_t)sh & 31u;
+  // the magnitude as three words: mant << off < 2^85
+  const uint64_t lo = mant << off;                       // low 64 bits
+  const uint64_t hi = off ? (mant >> (64 - off)) : 0;    // bits 64..84
+  const uint32_t w[3] = {(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi};
+  if (mult == 1) {
+    p[0] = w[0];
+    p[1] = w[1];
+    p[2] = w[2];
+    return true;
+  }
+  const uint32_t m[2] = {(uint32_t)mult, (uint32_t)(mult >> 32)};
+  // schoolbook product of 3 x 2 words; each partial sum stays below 2^64
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    uint64_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      const uint64_t t = (uint64_t)w[i] * m[j] + p[i + j] + carry;
+      p[i + j] = (uint32_t)t;
+      carry = t >> 32;
+    }
+    p[i + 2] = (uint32_t)carry;
+  }
   return true;
 }
 
@@ -66,30 +111,34 @@ __device__ __forceinline__ bool split_to_digits(double v, int32_t lsb, int32_t& 
 // slots stay in registers.
 struct RegAcc {
   int64_t s[EXACT_MAXD];
+  uint32_t pending;   // additions since the last carry
   __device__ __forceinline__ void clear() {
 #pragma unroll
     for (int i = 0; i < EXACT_MAXD; i++) s[i] = 0;
+    pending = 0;
   }
   // Adds mult * v; returns false if v does not fit the window.
-  __device__ __forceinline__ bool add(double v, int32_t lsb, uint32_t D, int64_t mult) {
+  __device__ __forceinline__ bool add(double v, int32_t lsb, uint32_t D, uint64_t mult) {
     if (v == 0.0) return true;
     int32_t k0;
-    int64_t d0, d1, d2;
+    uint32_t p[5];
     bool neg;
-    if (!split_to_digits(v, lsb, k0, d0, d1, d2, neg)) return false;
-    if (neg) mult = -mult;
-    d0 *= mult;
-    d1 *= mult;
-    d2 *= mult;
-    bool ok = (k0 < (int32_t)D) && (k0 + 1 < (int32_t)D || d1 == 0) && (k0 + 2 < (int32_t)D || d2 == 0);
+    if (!term_words(v, lsb, mult, k0, p, neg)) return false;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 5; j++) ok = ok && (k0 + j < (int32_t)D || p[j] == 0);
 #pragma unroll
     for (int i = 0; i < EXACT_MAXD; i++) {
-      int64_t add = (i == k0) ? d0 : (i == k0 + 1) ? d1 : (i == k0 + 2) ? d2 : 0;
-      s[i] += add;
+      const uint32_t w = (i == k0) ? p[0] : (i == k0 + 1) ? p[1] : (i == k0 + 2) ? p[2] : (i == k0 + 3) ? p[3]
+                       : (i == k0 + 4) ? p[4] : 0u;
+      s[i] += neg ? -(int64_t)w : (int64_t)w;
     }
+    // each addition is below 2^32 in magnitude: carry long before 2^63
+    if (++pending >= (1u << 24)) normalize(D);
     return ok;
   }
-  // Propagate carries so slots 0..D-2 hold digits in [0, 2^32).
+  // Propagate carries so slots 0..D-2 hold digits in [0, 2^32) and the top
+  // slot the signed rest.
   __device__ __forceinline__ void normalize(uint32_t D) {
     int64_t c = 0;
 #pragma unroll
@@ -102,6 +151,25 @@ struct RegAcc {
         s[i] += c;
       }
     }
+    pending = 0;
+  }
+  // Take the value of shared-form slots (below the top: unsigned modulo
+  // 2^64; top: signed), normalized.
+  __device__ __forceinline__ void load_shared(const int64_t* slot, uint32_t D) {
+    int64_t c = 0;
+#pragma unroll
+    for (int i = 0; i < EXACT_MAXD; i++) {
+      s[i] = 0;
+      if (i + 1 < (int)D) {
+        const uint64_t u = (uint64_t)slot[i];
+        const int64_t t = (int64_t)(u & 0xffffffffull) + c;
+        s[i] = t & 0xffffffffll;
+        c = (t >> 32) + (int64_t)(u >> 32);
+      } else if (i + 1 == (int)D) {
+        s[i] = slot[i] + c;
+      }
+    }
+    pending = 0;
   }
   __device__ __forceinline__ bool zero() const {
     int64_t o = 0;
@@ -111,22 +179,72 @@ struct RegAcc {
   }
 };
 
-// Round the exact value held in D slots (any carry state) to a double,
-// nearest with ties to even.  Sets *overflow if the value does not fit the
-// D-digit window.  The digits are carried into 32-bit words, the leading
-// word and the two below it give a 96-bit window holding the 53 result
-// bits, the rounding bit and the first sticky bits; words further down
-// only feed the sticky bit.  Every index is resolved with unrolled selects.
+// Atomically add the signed value v (|v| < 2^63) to slot q of a shared-form
+// accumulator (global or LDS).  A wrap of a slot below the top moves +-2^32
+// into the next slot, itself an atomic add that may wrap in turn.
+__device__ __forceinline__ void atomic_add_digit(int64_t* slots, uint32_t q, uint32_t D, int64_t v) {
+  while (v != 0 && q < D) {
+    const uint64_t old = atomicAdd((unsigned long long*)&slots[q], (unsigned long long)v);
+    if (q + 1 >= D) return;
+    const uint64_t now = old + (uint64_t)v;
+    int64_t carry = 0;
+    if (v > 0 && now < old) carry = 1;
+    else if (v < 0 && now > old) carry = -1;
+    v = carry * (1ll << 32);
+    q++;
+  }
+}
+
+// Add a normalized register accumulator (or any slots whose lower values
+// are non-negative) to a shared-form accumulator.
+__device__ __forceinline__ void atomic_add_acc(int64_t* slots, const RegAcc& t, uint32_t D) {
+  for (uint32_t q = 0; q < D; q++)
+    if (t.s[q]) atomic_add_digit(slots, q, D, t.s[q]);
+}
+
+// Add mult * v straight into a shared-form accumulator: at most five
+// atomics.  Returns false if v does not fit the window.
+__device__ __forceinline__ bool atomic_add_term(int64_t* slots, double v, int32_t lsb, uint32_t D, uint64_t mult) {
+  if (v == 0.0) return true;
+  int32_t k0;
+  uint32_t p[5];
+  bool neg;
+  if (!term_words(v, lsb, mult, k0, p, neg)) return false;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 5; j++) {
+    if (!p[j]) continue;
+    if (k0 + j >= (int32_t)D) {
+      ok = false;
+      continue;
+    }
+    atomic_add_digit(slots, (uint32_t)(k0 + j), D, neg ? -(int64_t)p[j] : (int64_t)p[j]);
+  }
+  return ok;
+}
+
+// Round the exact value held in D shared-form slots (a normalized register
+// accumulator is one too) to a double, nearest with ties to even.  Sets
+// *overflow if the value does not fit the D-digit window.  The slots are
+// carried into 32-bit words, the leading word and the two below it give a
+// 96-bit window holding the 53 result bits, the rounding bit and the first
+// sticky bits; words further down only feed the sticky bit.  Every index is
+// resolved with unrolled selects.
 __device__ inline double exact_round(const int64_t* slot, uint32_t D, int32_t lsb, uint32_t* overflow) {
   uint32_t dg[EXACT_MAXD];
   int64_t c = 0;
 #pragma unroll
   for (int i = 0; i < EXACT_MAXD; i++) {
     dg[i] = 0;
-    if (i < (int)D) {
+    if (i + 1 < (int)D) {
+      const uint64_t u = (uint64_t)slot[i];
+      const int64_t t = (int64_t)(u & 0xffffffffull) + c;
+      dg[i] = (uint32_t)t;
+      c = (t >> 32) + (int64_t)(u >> 32);
+    } else if (i + 1 == (int)D) {
       const int64_t v = slot[i] + c;
-      c = v >> 32;
       dg[i] = (uint32_t)v;
+      c = v >> 32;
     }
   }
   // c is the value above the top digit: it must be a sign extension

@@ -216,6 +216,8 @@ constexpr uint32_t SLOT_EMPTY = 0, SLOT_BUSY = 1, SLOT_READY = 2;
 // its claim, so the bound is never reached in a correct run)
 constexpr uint32_t SLOT_SPIN_MAX = 1u << 22;
 constexpr uint32_t ERR_TABLE_FULL = 2u, ERR_SLOT_SPIN = 4u;
+// a tuple count (or a row multiplicity) does not fit 64 bits
+constexpr uint32_t ERR_COUNT_OVERFLOW = 8u;
 
 __device__ __forceinline__ uint64_t key_mix(uint64_t h, uint32_t v) {
   h ^= v;
@@ -328,7 +330,7 @@ __device__ __forceinline__ void leaf_rows(const LeafArgs& L, uint64_t r, const u
     }
     h.rb[e] = b;
     h.re[e] = en;
-    if (!A.expand) h.mult *= (uint64_t)(en - b);
+    if (!A.expand) h.mult = sat_mul_u64(h.mult, (uint64_t)(en - b));
   }
 }
 
@@ -359,15 +361,22 @@ __device__ __forceinline__ void term_of(const LeafArgs& L, const uint32_t* cur, 
   }
 }
 
-// Number of row combinations of the expanding atoms.
+// Number of row combinations of the expanding atoms (UINT64_MAX when it
+// does not fit 64 bits).
 __device__ __forceinline__ uint64_t combos(const LeafArgs& L, const HitRows& h) {
   uint64_t c = 1;
 #pragma unroll
   for (int e = 0; e < MAXA; e++) {
     if (e >= (int)L.n_atoms) break;
-    if (L.at[e].expand) c *= (uint64_t)(h.re[e] - h.rb[e]);
+    if (L.at[e].expand) c = sat_mul_u64(c, (uint64_t)(h.re[e] - h.rb[e]));
   }
   return c;
+}
+
+// Add v to a tuple count; a count that leaves 64 bits flags an error.
+__device__ __forceinline__ void atomic_add_count(uint64_t* c, uint64_t v, uint32_t* err) {
+  const uint64_t old = atomicAdd((unsigned long long*)c, (unsigned long long)v);
+  if (v == UINT64_MAX || old + v < old) atomicOr(err, ERR_COUNT_OVERFLOW);
 }
 
 // Advance the odometer over expanding atoms; false when exhausted.
@@ -548,7 +557,7 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
         HitRows h;
         leaf_rows(L, r, ppos[it], h);
         const uint64_t nc = combos(L, h);
-        cnt += h.mult * nc;
+        cnt = sat_add_u64(cnt, sat_mul_u64(h.mult, nc));
         if (L.sum && nc) {
           uint32_t cur[MAXA];
 #pragma unroll
@@ -556,42 +565,49 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
           do {
             double hi, lo;
             term_of(L, cur, hi, lo);
-            bool ok = acc.add(hi, L.lsb, L.D, (int64_t)h.mult);
-            ok = acc.add(lo, L.lsb, L.D, (int64_t)h.mult) && ok;
-            if (!ok) bad = 1;
+            bool ok = acc.add(hi, L.lsb, L.D, h.mult);
+            ok = acc.add(lo, L.lsb, L.D, h.mult) && ok;
+            if (!ok) bad |= 1u;
           } while (next_combo(L, h, cur));
         }
       }
+      if (cnt == UINT64_MAX) bad |= ERR_COUNT_OVERFLOW;
       if (L.sum) acc.normalize(L.D);
       if (one_group) {
-        run_cnt += cnt;
+        run_cnt = sat_add_u64(run_cnt, cnt);
 #pragma unroll
         for (int i = 0; i < EXACT_MAXD; i++) run_acc.s[i] += acc.s[i];
         if (L.sum) run_acc.normalize(L.D);
       } else {
-        // the wave's unit belongs to one row, hence to one group
+        // the wave's unit belongs to one row, hence to one group; lane
+        // counts below 2^58 cannot wrap the wave's sum
+        if (__any(cnt >= (1ull << 58))) bad |= ERR_COUNT_OVERFLOW;
         cnt = wave_sum(cnt);
         if (wave_valid) {
           const uint64_t g = L.gid[r];
-          if (lane == 0 && cnt) atomicAdd((unsigned long long*)&L.gcount[g], (unsigned long long)cnt);
+          if (lane == 0 && cnt) atomic_add_count(&L.gcount[g], cnt, L.err);
           if (L.sum)
             for (uint32_t i = 0; i < L.D; i++) {
-              int64_t v = wave_sum(acc.s[i]);
-              if (lane == 0 && v) atomicAdd((unsigned long long*)&L.gacc[g * EXACT_MAXD + i], (unsigned long long)v);
+              // normalized lane digits: the wave's sum stays below 2^38
+              const int64_t v = wave_sum(acc.s[i]);
+              if (lane == 0 && v) atomic_add_digit(L.gacc + g * EXACT_MAXD, i, L.D, v);
             }
         }
       }
     } else if (MODE == M_LEAF_B_COUNT) {
+      // rows to materialize; a block's count saturates at UINT32_MAX, which
+      // the host's limit of 2^32 - 1 emitted rows then rejects
       uint64_t c = 0;
 #pragma unroll
       for (int it = 0; it < U_IT; it++) {
         if (!hit[it]) continue;
         HitRows h;
         leaf_rows(L, r, ppos[it], h);
-        c += combos(L, h);
+        c = sat_add_u64(c, combos(L, h));
       }
+      c = min(c, (uint64_t)UINT32_MAX);
       uint64_t t = block_sum<uint64_t, J_NT>(c, s_red);
-      if (tid == 0) a.blk_cnt[vb] = (uint32_t)t;
+      if (tid == 0) a.blk_cnt[vb] = (uint32_t)min(t, (uint64_t)UINT32_MAX);
     } else if (MODE == M_LEAF_B_FILL) {
       uint64_t m[U_IT];
       uint64_t wtot = 0;
@@ -743,21 +759,15 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
             }
           }
           if (ok) {
-            if (GAGG && L.glds) atomicAdd(&s_gcnt[slot], (unsigned long long)h.mult);
-            else atomicAdd((unsigned long long*)&L.gcount[slot], (unsigned long long)h.mult);
+            if (GAGG && L.glds) atomic_add_count((uint64_t*)&s_gcnt[slot], h.mult, L.err);
+            else atomic_add_count(&L.gcount[slot], h.mult, L.err);
             if (L.sum) {
               double hi, lo;
               term_of(L, cur, hi, lo);
-              RegAcc t;
-              t.clear();
-              bool fits = t.add(hi, L.lsb, L.D, (int64_t)h.mult);
-              fits = t.add(lo, L.lsb, L.D, (int64_t)h.mult) && fits;
-              if (!fits) bad = 1;
-              for (uint32_t q = 0; q < L.D; q++) {
-                if (!t.s[q]) continue;
-                if (GAGG && L.glds) atomicAdd((unsigned long long*)&s_gdig[slot * EXACT_MAXD + q], (unsigned long long)t.s[q]);
-                else atomicAdd((unsigned long long*)&L.gacc[slot * L.D + q], (unsigned long long)t.s[q]);
-              }
+              int64_t* dig = (GAGG && L.glds) ? (int64_t*)&s_gdig[slot * EXACT_MAXD] : L.gacc + slot * L.D;
+              bool fits = atomic_add_term(dig, hi, L.lsb, L.D, h.mult);
+              fits = atomic_add_term(dig, lo, L.lsb, L.D, h.mult) && fits;
+              if (!fits) bad |= 1u;
             }
           }
         } while (next_combo(L, h, cur));
@@ -765,50 +775,43 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
     }
   }
 
-  if (MODE == M_LEAF_B_AGG && bad) atomicOr(L.err, 1u);
+  if (MODE == M_LEAF_B_AGG && bad) atomicOr(L.err, bad);
   if constexpr (GAGG) {
     if (L.glds) {
-      // flush the block's groups; digits carried first, so every flushed
-      // digit is below 2^32 but the top one
+      // flush the block's groups, each carried into normalized digits
       __syncthreads();
       for (uint32_t i = tid; i < L.gspace; i += J_NT) {
         const unsigned long long c = s_gcnt[i];
         if (!c) continue;
-        atomicAdd((unsigned long long*)&L.gcount[i], c);
+        atomic_add_count(&L.gcount[i], c, L.err);
         if (L.sum) {
           RegAcc t;
-          t.clear();
-#pragma unroll
-          for (int q = 0; q < EXACT_MAXD; q++) t.s[q] = s_gdig[i * EXACT_MAXD + q];
-          t.normalize(L.D);
-          for (uint32_t q = 0; q < L.D; q++)
-            if (t.s[q]) atomicAdd((unsigned long long*)&L.gacc[i * L.D + q], (unsigned long long)t.s[q]);
+          t.load_shared((const int64_t*)&s_gdig[i * EXACT_MAXD], L.D);
+          atomic_add_acc(L.gacc + i * L.D, t, L.D);
         }
       }
     }
   }
   if (LEAF_AGG) {
-    if (bad) atomicOr(L.err, 1u);
+    if (bad) atomicOr(L.err, bad);
     if (one_group) {
       // reduce the block into LDS, one flush per block
       __syncthreads();
+      if (__any(run_cnt >= (1ull << 58))) atomicOr(L.err, ERR_COUNT_OVERFLOW);
       const uint64_t c = wave_sum(run_cnt);
-      if (lane == 0 && c) atomicAdd(&s_cnt, (unsigned long long)c);
+      if (lane == 0 && c) atomic_add_count((uint64_t*)&s_cnt, c, L.err);
       if (MODE == M_LEAF_A && L.sum)
         for (uint32_t i = 0; i < L.D; i++) {
-          int64_t v = wave_sum(run_acc.s[i]);
-          if (lane == 0 && v) atomicAdd((unsigned long long*)&s_acc[i], (unsigned long long)v);
+          const int64_t v = wave_sum(run_acc.s[i]);
+          if (lane == 0 && v) atomic_add_digit((int64_t*)s_acc, i, L.D, v);
         }
       __syncthreads();
       if (tid == 0) {
-        if (s_cnt) atomicAdd((unsigned long long*)&L.gcount[0], s_cnt);
+        if (s_cnt) atomic_add_count(&L.gcount[0], s_cnt, L.err);
         if (MODE == M_LEAF_A && L.sum) {
           RegAcc t;
-          t.clear();
-          for (uint32_t i = 0; i < L.D; i++) t.s[i] = s_acc[i];
-          t.normalize(L.D);
-          for (uint32_t i = 0; i < L.D; i++)
-            if (t.s[i]) atomicAdd((unsigned long long*)&L.gacc[i], (unsigned long long)t.s[i]);
+          t.load_shared((const int64_t*)s_acc, L.D);
+          atomic_add_acc(L.gacc, t, L.D);
         }
       }
     }
@@ -1329,15 +1332,12 @@ __global__ void k_seg_accumulate(SegAccArgs a, uint64_t n) {
     const uint32_t p = a.perm[i];
     if (a.segoff[i + 1] != a.segoff[i])
       for (uint32_t c = 0; c < a.cols.n; c++) a.key_out[c][g] = a.cols.c[c][p];
-    atomicAdd((unsigned long long*)&a.gcount[g], (unsigned long long)a.mult[p]);
+    atomic_add_count(&a.gcount[g], a.mult[p], a.err);
     if (a.sum) {
-      RegAcc t;
-      t.clear();
-      bool ok = t.add(a.hi[p], a.lsb, a.D, (int64_t)a.mult[p]);
-      ok = t.add(a.lo[p], a.lsb, a.D, (int64_t)a.mult[p]) && ok;
+      int64_t* dig = a.gacc + g * EXACT_MAXD;
+      bool ok = atomic_add_term(dig, a.hi[p], a.lsb, a.D, a.mult[p]);
+      ok = atomic_add_term(dig, a.lo[p], a.lsb, a.D, a.mult[p]) && ok;
       if (!ok) atomicOr(a.err, 1u);
-      for (uint32_t s = 0; s < a.D; s++)
-        if (t.s[s]) atomicAdd((unsigned long long*)&a.gacc[g * EXACT_MAXD + s], (unsigned long long)t.s[s]);
     }
   }
 }
@@ -2126,7 +2126,9 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
     }
     R.n_rows = n_seg;
   }
-  if (read_scalar(err.p, s)) fail(LH_ERR_UNSUPPORTED, "an annotation product did not fit the exact accumulator");
+  const uint32_t leaf_err = read_scalar(err.p, s);
+  if (leaf_err & ERR_COUNT_OVERFLOW) fail(LH_ERR_OVERFLOW, "join: a tuple count exceeds 2^64 - 1");
+  if (leaf_err) fail(LH_ERR_UNSUPPORTED, "an annotation product did not fit the exact accumulator");
 
   // total contributing tuples
   res->colptr.resize(n_cols);

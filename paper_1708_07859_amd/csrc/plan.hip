@@ -323,9 +323,17 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
       lsb = 0;
       maxprod = 0.0;
     }
-    // headroom for 2^40 terms and the sign
+    // headroom for every join tuple: their number is at most the product
+    // of the relations' row counts (and a count beyond 2^64 is an error of
+    // its own), each tuple adding |hi| + |lo| <= 2 * maxprod
+    int tuple_bits = 0;
+    for (auto& pa : p->atoms) {
+      const uint64_t n = std::max<uint64_t>(1, pa.trie->n_rows);
+      tuple_bits += 64 - __builtin_clzll(n);   // n < 2^bits
+    }
+    tuple_bits = std::min(tuple_bits, 64);
     int top = maxprod > 0 ? (int)std::ceil(std::log2(maxprod)) + 1 : 0;
-    top += 41;
+    top += tuple_bits + 1;
     int bits = top - lsb + 2;
     uint32_t D = (uint32_t)std::max(1, (bits + 31) / 32);
     if (D > 8) fail(LH_ERR_UNSUPPORTED, "annotation values span too many binades for exact summation");

@@ -49,3 +49,44 @@ def test_bf16_rounding():
     x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 2.0 ** -7, 1.0 + 3 * 2.0 ** -8], dtype=np.float32)
     # halfway cases round to even
     assert ref.bf16(x).tolist() == [1.0, 1.0, 1.0 + 2.0 ** -7, 1.0 + 2.0 ** -6]
+
+
+def test_adam_first_step_closed_form():
+    # from zero moments the bias corrections cancel: m_hat = g, v_hat = g^2
+    rng = synth.rng_for(4)
+    g = rng.normal(0, 1, 50) * np.logspace(-6, 3, 50)
+    p0 = rng.normal(0, 1, 50)
+    lr = 0.01
+    p1, m, v = ref.adam_step(p0, g, np.zeros(50), np.zeros(50), 1, lr)
+    assert np.allclose(p1 - p0, -lr * g / (np.abs(g) + ref.EPS), rtol=1e-12, atol=0)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_constant_gradient_keeps_its_step():
+    # with g fixed, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so every
+    # bias-corrected step is again -lr * g / (|g| + eps)
+    g = np.array([3.0, -0.5, 1e-3, -2e4])
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    lr = 1e-3
+    for t in range(1, 41):
+        p, m, v = ref.adam_step(p, g, m, v, t, lr)
+    assert np.allclose(p, -40 * lr * g / (np.abs(g) + ref.EPS), rtol=1e-9, atol=0)
+
+
+def test_adam_descends_a_quadratic():
+    # f(p) = |p - c|^2 / 2 has gradient p - c: Adam approaches c
+    c = np.array([1.0, -2.0, 0.5])
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 3001):
+        p, m, v = ref.adam_step(p, p - c, m, v, t, 0.01)
+    assert np.abs(p - c).max() < 1e-2
+
+
+def test_full_batch_training_lowers_the_loss():
+    d = 4
+    p = _params(d, 5) * 0.5
+    rng = synth.rng_for(6)
+    X = rng.normal(0, 1, (64, d))
+    y = X[:, 0] - 2 * X[:, 1]
+    p1, losses = ref.train_full_batch(p, X, y, 200, 1e-3)
+    assert ref.loss(p1, X, y) < 0.5 * losses[0]

@@ -268,3 +268,36 @@ def test_invalid_queries_rejected():
     bad["n_attrs"] = 4                       # attribute 3 in no atom
     with pytest.raises(oracle.OracleError):
         oracle.join_aggregate(bad)
+
+
+def test_too_many_group_columns_rejected():
+    # the aggregation key holds at most 128 columns (outputs + GROUP BY)
+    n = 5
+    rel = {"keys": [np.arange(n, dtype=np.uint32)], "attrs": [0], "bag": True, "anno": -1,
+           "meta": [np.zeros(n, np.uint32)]}
+    q = {"n_attrs": 1, "agg": "count", "out": [0], "atoms": [rel], "group": [(0, 0)] * 127}
+    res = oracle.join_aggregate(q)                   # 1 + 127 columns: accepted
+    assert res["keys"].shape == (n, 128)
+    q["group"] = [(0, 0)] * 128                      # 129 columns
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.join_aggregate(q)
+    assert ei.value.code == oracle.ORC_E_INVALID
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_thread_count_does_not_change_results(seed):
+    # thread-local tables merged exactly: every thread count gives the same bits
+    q = queries.random_query(seed, max_rows=40, domain=5)
+    outs = []
+    for t in (1, 3, 8):
+        oracle.set_threads(t)
+        try:
+            outs.append(oracle.join_aggregate(q))
+        finally:
+            oracle.set_threads(0)
+    for o in outs[1:]:
+        assert np.array_equal(o["keys"], outs[0]["keys"])
+        assert np.array_equal(o["counts"], outs[0]["counts"])
+        assert o["n_join"] == outs[0]["n_join"]
+        if o["sums"] is not None:
+            assert np.array_equal(o["sums"].view(np.uint64), outs[0]["sums"].view(np.uint64))
