@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -36,45 +38,103 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def leaf_alg_bytes(rows, elements):
-    """Algorithmic bytes of one intersect-and-aggregate pass: per frontier
-    row its two trie positions (8 B), the two sets' child ranges (16 B), its
-    work offset (8 B) and driver id (1 B); per element of the smaller set
-    the element itself (4 B) and one probe of the other set (4 B)."""
+def leaf_model_bytes(rows, elements):
+    """The leaf's own byte model (a second figure next to the minimum): per
+    frontier row its two trie positions (8 B), the two sets' child ranges
+    (16 B), its work offset (8 B) and driver id (1 B); per element of the
+    smaller set the element itself (4 B) and one probe of the other set
+    (4 B)."""
     return 33 * rows + 8 * elements
 
 
-ALG_BYTES = {
-    "leaf_aggregate": leaf_alg_bytes,
-    # (u64 key + u32 value) read and written per sorted element
-    "sort_scatter": lambda rows, el: 24 * rows,
-    "sort_hist": lambda rows, el: 8 * rows,
-}
+def triangle_min_bytes(edges, wedges, n_vertices):
+    """Bytes a worst-case optimal triangle COUNT cannot avoid moving under
+    the order a, b, c: the set S(b) is streamed once for every edge (a, b)
+    that reaches it (4 B per wedge, sum over edges of the out-degree of b),
+    the set T(a) is read once per a (4 B per edge), and the level-0 child
+    offsets once (8 B per vertex + 1).  The sum over edges (a, b) of d+(b)
+    equals sum over b of d-(b) d+(b), so the reversed order c, b, a has the
+    same minimum."""
+    return 4 * wedges + 4 * edges + 8 * (n_vertices + 1)
 
 
 # profiling scope -> the kernel it times (the two-set COUNT leaf of the triangle)
 KERNEL_OF_SCOPE = {"leaf_aggregate": "k_leaf2_count"}
-# HBM bytes per launch of that kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
-# used only while the kernel's source matches the one the counters saw
+# HBM bytes per launch of that kernel from rocprofv3 counters, used only
+# while the kernel's source matches the one the counters saw
 TRAFFIC_SUMMARY = {"plain": "triangle_rmat22_leaf2_count_traffic.txt",
                    "learned": "triangle_rmat22_learned_leaf2_count_traffic.txt"}
+FLUSH_BYTES = 512 << 20      # more than the 256 MB Infinity Cache and the 8 x 4 MB L2
 
 
-def cpu_baseline(scale):
-    import numpy as np
+def edge_stats(torch, lo_d, hi_d):
+    """Deduplicated oriented edges E', wedges W = sum over edges (a, b) of
+    d+(b), and the streamed elements sum over edges of d+(a) + d+(b), from
+    the resident edge columns (torch on the device; measurement only)."""
+    lo = lo_d.to(torch.int64) & 0xffffffff
+    hi = hi_d.to(torch.int64) & 0xffffffff
+    u = torch.unique((lo << 32) | hi)
+    ul, uh = u >> 32, u & 0xffffffff
+    n = int(torch.maximum(ul.max(), uh.max()).item()) + 1
+    dout = torch.bincount(ul, minlength=n)
+    din = torch.bincount(uh, minlength=n)
+    wedges = int((dout * din).sum().item())
+    stream = int((dout[ul] + dout[uh]).sum().item())
+    e = int(u.numel())
+    del lo, hi, u, ul, uh, dout, din
+    return e, wedges, stream
 
+
+def run_protocol(torch, step, flush=None, runs=7):
+    """The paper's timing protocol (section 6.1): `runs` runs, the fastest
+    and the slowest dropped, the mean of the rest; plus the median.  With
+    `flush`, a 512 MB write evicts the caches before every run (cold)."""
+    times = []
+    for _ in range(runs):
+        if flush is not None:
+            flush.add_(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1000)
+    s = sorted(times)
+    mid = s[1:-1] if runs >= 3 else s
+    return {"mean_drop_minmax_ms": round(sum(mid) / len(mid), 3), "median_ms": round(s[len(s) // 2], 3),
+            "min_ms": round(s[0], 3), "max_ms": round(s[-1], 3), "runs": runs}
+
+
+def cpu_baseline(scale, headline):
+    """The oracle (pairwise hash join, OpenMP over its probe side) on the
+    host cores, on an R-MAT graph of the same recipe at a smaller scale.
+    The headline graph's wedge count is printed first: the pairwise join
+    would materialize that many intermediate tuples."""
     import oracle
     import synth
     from tests import queries
     lo, hi = synth.rmat_edges(scale, 16 << scale, seed=2)
+    key = np.unique(lo.astype(np.uint64) << np.uint64(32) | hi.astype(np.uint64))
+    ulo = (key >> np.uint64(32)).astype(np.int64)
+    uhi = (key & np.uint64(0xffffffff)).astype(np.int64)
+    n = 1 << scale
+    w = int((np.bincount(ulo, minlength=n) * np.bincount(uhi, minlength=n)).sum())
+    e = len(key)
+    del key, ulo, uhi
+    log(f"cpu baseline: the headline graph has W = {headline['wedges']} wedges "
+        f"({headline['wedges'] * 20 / 1e12:.2f} TB of pairwise intermediate at 20 B per tuple); "
+        f"the oracle runs R-MAT {scale}: E' = {e}, W = {w}")
     q = queries.triangle(lo, hi)
-    e = len(set(zip(lo.tolist(), hi.tolist())))
+    threads = oracle.threads()
     t0 = time.perf_counter()
     res = oracle.join_aggregate(q)
     dt = time.perf_counter() - t0
-    return {"value": 3 * e / dt, "unit": "tuples/s", "cores": 1, "kind": "oracle",
-            "sample": f"R-MAT scale {scale} (2^{scale} vertices, {16 << scale} samples, same a,b,c), "
-                      f"{e} edges, full triangle COUNT = {int(res['counts'][0])}, {dt:.1f} s single-threaded"}
+    log(f"  oracle: {dt:.1f} s on {threads} threads, {int(res['counts'][0])} triangles")
+    return {"value": 3 * e / dt, "unit": "tuples/s", "cores": threads, "kind": "oracle",
+            "sample": f"R-MAT scale {scale} (2^{scale} vertices, {16 << scale} samples, same a,b,c, seed 2): "
+                      f"E' = {e} edges, W = {w} wedges materialized by the pairwise join, full triangle COUNT = "
+                      f"{int(res['counts'][0])}, one run of {dt:.1f} s on {threads} OpenMP threads; the headline "
+                      f"graph (W = {headline['wedges']}) is beyond the oracle's memory",
+            "wedges": w, "edges": e, "seconds": round(dt, 3)}
 
 
 def main():
@@ -84,13 +144,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--samples-log2", type=int, default=26)
-    ap.add_argument("--cpu-scale", type=int, default=15)
+    ap.add_argument("--cpu-scale", type=int, default=19)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--runs", type=int, default=7,
+                    help="runs of the timing protocol (min and max dropped); 0 skips it")
+    ap.add_argument("--no-side", action="store_true",
+                    help="time the headline triangle only (no SpGEMM, no batch legs)")
     ap.add_argument("--layout", default="plain", choices=["plain", "uint", "bitset", "learned"],
                     help="layout of the plain-policy run")
     ap.add_argument("--policy", default="both", choices=["both", "plain", "learned"],
                     help="both: time the plain rule, then the learned cost model (reported)")
-    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "intersect", "q5", "groupby", "dense", "spgemm-star", "voter"])
+    ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "gather", "intersect", "q5", "groupby", "dense",
+                             "spgemm-star", "voter"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--card", type=int, default=1_000_000)
@@ -122,6 +187,8 @@ def main():
         return bench_learned(args, lh, torch, synth)
     if args.workload == "copy":
         return bench_copy(args, torch)
+    if args.workload == "gather":
+        return bench_gather(args, torch)
     if args.workload == "intersect":
         return bench_intersect(args, lh, torch, synth)
     if args.workload == "q5":
@@ -142,6 +209,10 @@ def main():
     hi_d = lh.to_device(hi)
     del lo, hi
     torch.cuda.synchronize()
+    n_edges, wedges, streamed = edge_stats(torch, lo_d, hi_d)
+    b_min = triangle_min_bytes(n_edges, wedges, 1 << args.scale)
+    log(f"  E' = {n_edges} edges, W = {wedges} wedges, streamed elements {streamed}, minimum bytes {b_min}")
+    flush = torch.empty(FLUSH_BYTES, dtype=torch.uint8, device="cuda").zero_()
 
     runs = {}
     policies = ["plain", "learned"] if args.policy == "both" else [args.policy]
@@ -151,7 +222,7 @@ def main():
             from paper_1708_07859_amd import learned as L
             lm, om, _ = L.load(args.weights or L.DEFAULT_WEIGHTS)
             L.register(lm, om)
-        runs[policy] = measure_triangle(args, lh, torch, lo_d, hi_d, layout, policy)
+        runs[policy] = measure_triangle(args, lh, torch, lo_d, hi_d, layout, policy, flush)
         if policy == "learned":
             lh.use_model(lh.LH_MODEL_LAYOUT, None)
             lh.use_model(lh.LH_MODEL_ORDER, None)
@@ -160,15 +231,14 @@ def main():
     if len(runs) == 2:
         assert runs["plain"]["count"] == runs["learned"]["count"], "policies disagree on the count"
     prof = head["prof"]
-    # roofline of the dominant kernel with a known byte formula
-    dom = max((k for k in prof if k in ALG_BYTES), key=lambda k: prof[k]["total_ms"], default=None)
+    # roofline of the dominant kernel, the two-set leaf
     roof = None
-    if dom:
-        e = prof[dom]
-        per_launch_bytes = ALG_BYTES[dom](e["rows"], e["elements"]) / e["launches"]
+    if "leaf_aggregate" in prof:
+        e = prof["leaf_aggregate"]
         avg_ms = e["total_ms"] / e["launches"]
-        achieved = per_launch_bytes / (avg_ms / 1000) / 1e9
-        kernel = KERNEL_OF_SCOPE.get(dom, dom)
+        achieved = b_min / (avg_ms / 1000) / 1e9
+        model_bytes = leaf_model_bytes(e["rows"], e["elements"]) / e["launches"]
+        kernel = KERNEL_OF_SCOPE["leaf_aggregate"]
         traffic = None
         summary = TRAFFIC_SUMMARY.get(head_policy)
         if summary and (args.scale, args.samples_log2) == (22, 26) and (head_policy != "plain" or args.layout == "plain"):
@@ -177,17 +247,31 @@ def main():
         roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
-                "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(per_launch_bytes)}
+                "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(b_min),
+                "alg_bytes": "minimum bytes: 4 B per wedge (S(b) streamed per edge) + 4 B per edge (T(a) once) + "
+                             "8 B per vertex (offsets)",
+                "model_bytes_per_launch": int(model_bytes),
+                "model_frac": round(model_bytes / (avg_ms / 1000) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic_frac": None if traffic is None else round(traffic / (avg_ms / 1000) / 1e9 / HBM_PEAK_GBS, 4)}
     config = {"workload": f"triangle COUNT on R-MAT scale {args.scale}, 2^{args.samples_log2} samples "
                           f"(a=0.57,b=0.19,c=0.19), oriented low->high, set-mode dedup",
-              "edges": head["edges"], "triangles": head["count"], "step": "trie_build + plan + join_aggregate",
+              "edges": n_edges, "wedges": wedges, "triangles": head["count"],
+              "step": "trie_build + plan + join_aggregate + count readback",
               "policy": head_policy, "layout": head["layout"], "attr_order": head["order"],
-              "join_kernels_ms_per_step": head["join_ms"]}
+              "join_kernels_ms_per_step": head["join_ms"], "protocol": head["protocol"]}
     if len(runs) == 2:
         pl = runs["plain"]
         config["plain"] = {"ms_per_step": pl["ms"], "tuples_per_s": pl["value"], "attr_order": pl["order"],
-                           "layout": pl["layout"]}
-        config["learned_over_plain"] = pl["ms"] / head["ms"]
+                           "layout": pl["layout"], "protocol": pl["protocol"]}
+        config["learned_over_plain"] = round(pl["ms"] / head["ms"], 4)
+        if head["protocol"]:
+            config["learned_over_plain_cold"] = round(pl["protocol"]["cold"]["mean_drop_minmax_ms"]
+                                                      / head["protocol"]["cold"]["mean_drop_minmax_ms"], 4)
+    if not args.no_side:
+        config["spgemm_4096"] = measure_spgemm(args, lh, torch, synth, flush)
+        bat = measure_batch(args, lh, torch, synth)
+        config["batch_512"] = bat
+        config["learned_batched_over_plain_sequential"] = bat["learned_batched_over_plain_sequential"]
     out = {
         "metric": METRIC,
         "value": head["value"],
@@ -204,15 +288,17 @@ def main():
         "config": config,
         "roofline": roof,
     }
+    del flush
     if not args.no_cpu:
-        log(f"cpu baseline: oracle on R-MAT scale {args.cpu_scale}")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_scale)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_scale, {"wedges": wedges, "edges": n_edges})
     print(json.dumps(out), flush=True)
 
 
-def measure_triangle(args, lh, torch, lo_d, hi_d, layout, policy):
+def measure_triangle(args, lh, torch, lo_d, hi_d, layout, policy, flush):
     """Warm-up, then `steps` timed steps of trie build + plan + join + count
-    readback under one layout and policy; kernels timed with HIP events."""
+    readback under one layout and policy (kernels timed with HIP events on
+    their stream); then the 7-run protocol, cold (caches flushed before each
+    run) and warm."""
     state = {}
 
     def step():
@@ -242,17 +328,207 @@ def measure_triangle(args, lh, torch, lo_d, hi_d, layout, policy):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    gc.enable()
     lh.profile_enable(False)
     prof = lh.profile_read()
+    protocol = None
+    if args.runs:
+        protocol = {"cold": run_protocol(torch, step, flush, args.runs), "warm": run_protocol(torch, step, None, args.runs)}
+    gc.enable()
     ms = dt * 1000 / args.steps
-    log(f"[{policy}] {args.steps} steps: {ms:.2f} ms/step, triangles={state['count']}")
+    log(f"[{policy}] {args.steps} steps: {ms:.2f} ms/step, triangles={state['count']}; protocol {protocol}")
     for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
         log(f"  {k:22s} launches={v['launches']:6d} total={v['total_ms']:9.3f} ms "
             f"rows={v['rows']} elems={v['elements']}")
     join_ms = sum(prof[k]["total_ms"] for k in prof if k.startswith(("join_", "leaf_"))) / args.steps
     return {"ms": ms, "value": 3 * state["edges"] / (ms / 1000), "prof": prof, "edges": state["edges"],
-            "count": state["count"], "order": state["order"], "layout": layout, "join_ms": round(join_ms, 3)}
+            "count": state["count"], "order": state["order"], "layout": layout, "join_ms": round(join_ms, 3),
+            "protocol": protocol}
+
+
+def measure_spgemm(args, lh, torch, synth, flush):
+    """SpGEMM C(i,k) = SUM_j A(i,j) B(j,k), n = 4096, 10 distinct uniform
+    columns per row, U(-1,1) values, order i,j,k: one step is both trie
+    builds from resident columns + plan + join + readback.  Minimum bytes:
+    both tries read once (4 B key + 4 B offset per entry level, 8 B value)
+    and C written once (8 B of keys + 8 B count + 8 B sum per row)."""
+    from tests import queries
+    a = synth.sparse_matrix(4096, 10, seed=1)
+    b = synth.sparse_matrix(4096, 10, seed=11)
+    q = queries.spgemm(a, b)
+    dev = [{"keys": [lh.to_device(k) for k in x["keys"]], "annos": [lh.to_device(v) for v in x["annos"]]}
+           for x in q["atoms"]]
+    state = {}
+
+    def step():
+        tries = [lh.trie_build(x["keys"], x["annos"], bag=True) for x in dev]
+        p = lh.plan(3, [(tries[0], [0, 1], 0), (tries[1], [1, 2], 0)], out=[0, 2], agg="sum",
+                    attr_order=[0, 1, 2], policy="fixed")
+        r = lh.join_aggregate([p])[0]
+        state["rows"] = r.n_rows
+        state["products"] = int(r.to_host()["counts"].sum())
+        r.free()
+        p.free()
+        for t in tries:
+            t.free()
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000 / args.steps
+    cold = run_protocol(torch, step, flush, args.runs) if args.runs else None
+    nnz = len(a[0]) + len(b[0])
+    alg = nnz * 16 + 2 * 4 * 4097 + state["rows"] * 24
+    res = {"workload": "SpGEMM n = 4096, 10 nnz/row, order i,j,k (cfg1)", "ms_per_step": round(ms, 3),
+           "tuples_per_s": nnz / (ms / 1000), "products": state["products"], "output_rows": state["rows"],
+           "alg_bytes": alg, "alg_GBs": round(alg / (ms / 1000) / 1e9, 2),
+           "frac": round(alg / (ms / 1000) / 1e9 / HBM_PEAK_GBS, 5), "protocol_cold": cold,
+           "note": "a latency-bound step: the bytes fit on chip, so the fraction of HBM peak is not its bound"}
+    log(f"spgemm 4096: {res}")
+    return res
+
+
+def measure_batch(args, lh, torch, synth):
+    """The 512 SpMV / SpGEMM instances (n log-uniform in [1k, 64k], Zipf(1.1)
+    row degrees with mean 16, U(-1,1) values), four ways: {plain rules,
+    learned model} x {one lh_join_aggregate call per plan, one batched call
+    (persistent kernels captured in a hipGraph, autotuned)}.  Tries and
+    plans are built once, outside the timed region.  Every way must give the
+    same results bit for bit.  Minimum bytes of one pass: per SpMV 12 B per
+    nonzero + 4 B per row offset + 8 B per x and per y entry; per SpGEMM
+    A(i,j) A(j,k) the trie read twice (12 B per nonzero + 4 B per row
+    offset each time) and C written (8 B keys + 8 B count + 8 B sum per
+    row)."""
+    import hashlib
+    log(f"generating {args.instances} instances")
+    t0 = time.perf_counter()
+    insts = synth.batched_instances(count=args.instances)
+    log(f"  {sum(i['n'] for i in insts)} rows, {sum(len(i['rows']) for i in insts)} nonzeros "
+        f"in {time.perf_counter() - t0:.1f} s")
+    tuples = sum(len(i["rows"]) + i["n"] if i["kind"] == "spmv" else 2 * len(i["rows"]) for i in insts)
+    dev = []
+    for inst in insts:
+        d = {"rows": lh.to_device(inst["rows"]), "cols": lh.to_device(inst["cols"]),
+             "vals": lh.to_device(inst["vals"]), "n": inst["n"]}
+        if inst["kind"] == "spmv":
+            d["xk"] = lh.to_device(np.arange(inst["n"], dtype=np.uint32))
+            d["x"] = lh.to_device(inst["x"])
+        dev.append(d)
+    del insts[:]
+
+    def build(policy):
+        layout = "learned" if policy == "learned" else "plain"
+        tries, plans = [], []
+        for d in dev:
+            ta = lh.trie_build([d["rows"], d["cols"]], [d["vals"]], bag=True, layout=layout)
+            tries.append(ta)
+            if "x" in d:
+                tx = lh.trie_build([d["xk"]], [d["x"]], bag=True, layout=layout)
+                tries.append(tx)
+                plans.append(lh.plan(2, [(ta, [0, 1], 0), (tx, [1], 0)], out=[0], agg="sum", policy=policy))
+            else:
+                plans.append(lh.plan(3, [(ta, [0, 1], 0), (ta, [1, 2], 0)], out=[0, 2], agg="sum", policy=policy))
+        return tries, plans
+
+    def digest(rs):
+        h = hashlib.sha256()
+        rows = 0
+        for r in rs:
+            o = r.to_host()
+            rows += len(o["counts"])
+            h.update(o["keys"].tobytes())
+            h.update(o["counts"].tobytes())
+            h.update(o["sums"].tobytes())
+        return h.hexdigest(), rows
+
+    legs, digests, orders = {}, {}, {}
+    alg = None
+    for policy in ("plain", "learned"):
+        if policy == "learned":
+            from paper_1708_07859_amd import learned as L
+            lm, om, _ = L.load(args.weights or L.DEFAULT_WEIGHTS)
+            L.register(lm, om)
+        tries, plans = build(policy)
+        orders[policy] = sorted({tuple(p.info()["attr_order"]) for p in plans})
+        # sequential: one call per plan
+        rs = [lh.join_aggregate([p])[0] for p in plans]
+        digests[(policy, "sequential")] = digest(rs)
+        if alg is None:
+            alg = 0
+            for d, r in zip(dev, rs):
+                nnz = d["rows"].numel()
+                n = d["n"]
+                if "x" in d:
+                    alg += 12 * nnz + 4 * (n + 1) + 16 * n
+                else:
+                    alg += 2 * (12 * nnz + 4 * (n + 1)) + 24 * r.n_rows
+        for r in rs:
+            r.free()
+        torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()
+        seq = []
+        for _ in range(max(1, args.steps // 2)):
+            t0 = time.perf_counter()
+            for p in plans:
+                lh.join_aggregate([p])[0].free()
+            torch.cuda.synchronize()
+            seq.append((time.perf_counter() - t0) * 1000)
+        gc.enable()
+        legs[(policy, "sequential")] = min(seq)
+        # batched: the first call builds, tunes and captures; then replays
+        t0 = time.perf_counter()
+        rs = lh.join_aggregate(plans)
+        first_s = time.perf_counter() - t0
+        digests[(policy, "batched")] = digest(rs)
+        for r in rs:
+            r.free()
+        for _ in range(args.warmup):
+            for r in lh.join_aggregate(plans):
+                r.free()
+        torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()
+        lh.profile_reset()
+        lh.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for r in lh.join_aggregate(plans):
+                r.free()
+        torch.cuda.synchronize()
+        legs[(policy, "batched")] = (time.perf_counter() - t0) * 1000 / args.steps
+        lh.profile_enable(False)
+        gc.enable()
+        prof = lh.profile_read()
+        log(f"[batch {policy}] orders {orders[policy]}; sequential {legs[(policy, 'sequential')]:.1f} ms, "
+            f"batched {legs[(policy, 'batched')]:.1f} ms (first call {first_s:.1f} s)")
+        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]:
+            log(f"  {k:22s} launches={v['launches']:6d} total={v['total_ms']:9.3f} ms")
+        for p in plans:
+            p.free()
+        for t in tries:
+            t.free()
+        if policy == "learned":
+            lh.use_model(lh.LH_MODEL_LAYOUT, None)
+            lh.use_model(lh.LH_MODEL_ORDER, None)
+    assert len({d for d, _ in digests.values()}) == 1, "the four ways disagree"
+    lb, ps = legs[("learned", "batched")], legs[("plain", "sequential")]
+    res = {"workload": f"{args.instances} SpMV/SpGEMM instances, n log-uniform [1k,64k], Zipf(1.1) degrees "
+                       "mean 16, FP64 U(-1,1) (cfg4)",
+           "ms": {f"{p}_{w}": round(v, 3) for (p, w), v in legs.items()},
+           "tuples_per_s": {f"{p}_{w}": tuples / (v / 1000) for (p, w), v in legs.items()},
+           "learned_batched_over_plain_sequential": round(ps / lb, 4),
+           "batched_over_sequential_plain": round(ps / legs[("plain", "batched")], 4),
+           "orders": {k: [list(o) for o in v] for k, v in orders.items()},
+           "output_rows": digests[("plain", "batched")][1], "input_tuples": tuples,
+           "alg_bytes": alg, "alg_GBs_learned_batched": round(alg / (lb / 1000) / 1e9, 1),
+           "frac_learned_batched": round(alg / (lb / 1000) / 1e9 / HBM_PEAK_GBS, 4),
+           "sequential_timing": f"best of {max(1, args.steps // 2)} passes; batched: mean of {args.steps} replays"}
+    log(f"batch: {res}")
+    return res
 
 
 def bench_learned(args, lh, torch, synth):
@@ -899,82 +1175,53 @@ def bench_copy(args, torch):
 
 
 def bench_batch(args, lh, torch, synth):
-    """512 SpMV / SpGEMM join-aggregate instances (n log-uniform in [1k, 64k],
-    Zipf(1.1) row degrees with mean 16): one batched lh_join_aggregate call
-    (persistent, graph-captured launch) against the same plans run one call
-    per plan.  Tries and plans are built once, outside the timed region."""
-    import numpy as np
-    log(f"generating {args.instances} instances")
-    t0 = time.perf_counter()
-    insts = synth.batched_instances(count=args.instances)
-    log(f"  {sum(i['n'] for i in insts)} rows, {sum(len(i['rows']) for i in insts)} nonzeros "
-        f"in {time.perf_counter() - t0:.1f} s")
-    tries, plans = [], []
-    tuples = 0
-    for inst in insts:
-        ta = lh.trie_build([inst["rows"], inst["cols"]], [inst["vals"]], bag=True)
-        tries.append(ta)
-        nnz = len(inst["rows"])
-        if inst["kind"] == "spmv":
-            n = inst["n"]
-            tx = lh.trie_build([np.arange(n, dtype=np.uint32)], [inst["x"]], bag=True)
-            tries.append(tx)
-            plans.append(lh.plan(2, [(ta, [0, 1], 0), (tx, [1], 0)], out=[0], agg="sum"))
-            tuples += nnz + n
-        else:
-            plans.append(lh.plan(3, [(ta, [0, 1], 0), (ta, [1, 2], 0)], out=[0, 2], agg="sum"))
-            tuples += 2 * nnz
-    torch.cuda.synchronize()
-    # sequential: one call per plan
-    log("sequential")
-    lh.join_aggregate([plans[0]])[0].free()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    seq_rows = 0
-    for p in plans:
-        r = lh.join_aggregate([p])[0]
-        seq_rows += r.n_rows
-        r.free()
-    torch.cuda.synchronize()
-    seq_ms = (time.perf_counter() - t0) * 1000
-    log(f"  {seq_ms:.1f} ms, {seq_rows} output rows")
-    # batched: first call builds, tunes and captures; then replays
-    log("batched: setup + autotune")
-    t0 = time.perf_counter()
-    for r in lh.join_aggregate(plans):
-        r.free()
-    log(f"  first call {time.perf_counter() - t0:.1f} s")
-    for _ in range(args.warmup):
-        for r in lh.join_aggregate(plans):
-            r.free()
-    torch.cuda.synchronize()
-    lh.profile_reset()
-    lh.profile_enable(True)
-    t0 = time.perf_counter()
-    bat_rows = 0
-    for _ in range(args.steps):
-        rs = lh.join_aggregate(plans)
-        bat_rows = sum(r.n_rows for r in rs)
-        for r in rs:
-            r.free()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1000 / args.steps
-    lh.profile_enable(False)
-    prof = lh.profile_read()
-    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
-        log(f"  {k:22s} launches={v['launches']:6d} total={v['total_ms']:9.3f} ms")
-    assert bat_rows == seq_rows
+    """The batched workload on its own: the four ways of measure_batch,
+    reported as the learned + batched throughput."""
+    res = measure_batch(args, lh, torch, synth)
+    lb = res["ms"]["learned_batched"]
     out = {
-        "metric": METRIC, "value": tuples / (ms / 1000), "unit": "tuples/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "metric": METRIC, "value": res["tuples_per_s"]["learned_batched"], "unit": "tuples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": lb, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.instances} SpMV/SpGEMM instances, n log-uniform [1k,64k], Zipf(1.1) "
-                               "degrees mean 16, FP64 U(-1,1)",
-                   "step": "lh_join_aggregate over all plans (batched)",
-                   "sequential_ms": seq_ms, "batched_ms": ms, "batched_over_sequential": seq_ms / ms,
-                   "output_rows": bat_rows},
+        "config": res,
+        "roofline": {"bound": "hbm", "kernel": "batched graph launch (all kernels)",
+                     "achieved": res["alg_GBs_learned_batched"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": res["frac_learned_batched"], "traffic": None},
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_gather(args, torch):
+    """Random 64-byte lines gathered from a 4 GiB array into a contiguous
+    output: a kernel of known size whose reads are single 64-byte lines at
+    random places, the access shape of set probes, next to the streaming
+    copy.  Reads 64 B per line + 8 B per index, writes 64 B per line."""
+    n_src = (4 << 30) // 64
+    n_idx = 1 << 24
+    src = torch.empty((n_src, 16), dtype=torch.int32, device="cuda").fill_(1)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    idx = torch.randint(0, n_src, (n_idx,), device="cuda", generator=g)
+    out = torch.empty((n_idx, 16), dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        torch.index_select(src, 0, idx, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        torch.index_select(src, 0, idx, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    read, written = n_idx * 64 + n_idx * 8, n_idx * 64
+    gbs = (read + written) / (ms / 1000) / 1e9
+    print(json.dumps({"metric": "random 64-byte line gather GB/s (read + write)", "value": gbs, "unit": "GB/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32",
+                      "data": "synthetic",
+                      "config": {"workload": f"gather of {n_idx} random 64-byte lines from 4 GiB",
+                                 "bytes_read": read, "bytes_written": written,
+                                 "frac_of_peak": gbs / HBM_PEAK_GBS}}), flush=True)
 
 
 if __name__ == "__main__":

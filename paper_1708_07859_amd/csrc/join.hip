@@ -309,6 +309,7 @@ struct HitRows {
   uint64_t mult;  // product of run lengths of the non-expanding atoms
 };
 
+template <int NP>
 __device__ __forceinline__ void leaf_rows(const LeafArgs& L, uint64_t r, const uint32_t* ppos, HitRows& h) {
   h.mult = 1;
 #pragma unroll
@@ -318,7 +319,7 @@ __device__ __forceinline__ void leaf_rows(const LeafArgs& L, uint64_t r, const u
     uint32_t lp = 0;
     if (A.part >= 0) {
 #pragma unroll
-      for (int q = 0; q < MAXP; q++)
+      for (int q = 0; q < NP; q++)
         if (q == A.part) lp = ppos[q];
     } else if (A.pos) {
       lp = A.pos[r];
@@ -395,7 +396,9 @@ __device__ __forceinline__ bool next_combo(const LeafArgs& L, const HitRows& h, 
   return !carry;
 }
 
-template <int MODE>
+// NP bounds the participants at the attribute (a.np <= NP): the per-set
+// arrays stay in registers at the size the plan needs.
+template <int MODE, int NP>
 __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
   __shared__ uint64_t s_wcnt[J_NW];
   __shared__ uint64_t s_red[J_NW];
@@ -446,12 +449,12 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
       work = (uint32_t)(a.W[r + 1] - a.W[r]);
       d = a.drv[r];
     }
-    uint32_t b[MAXP], e[MAXP];
-    uint64_t sidx[MAXP];
+    uint32_t b[NP], e[NP];
+    uint64_t sidx[NP];
     uint32_t bd = 0;
     const uint32_t* dkeys = nullptr;
 #pragma unroll
-    for (int p = 0; p < MAXP; p++) {
+    for (int p = 0; p < NP; p++) {
       b[p] = e[p] = 0;
       sidx[p] = 0;
       if (p < (int)a.np && wave_valid) dset_range(a.set[p], r, b[p], e[p], sidx[p]);
@@ -463,7 +466,7 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
 
     bool hit[U_IT];
     uint32_t x[U_IT];
-    uint32_t ppos[U_IT][NEED_POS ? MAXP : 1];
+    uint32_t ppos[U_IT][NEED_POS ? NP : 1];
 #pragma unroll
     for (int it = 0; it < U_IT; it++) {
       const uint32_t i = chunk * U_EL + it * WAVE + lane;
@@ -472,12 +475,12 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
       x[it] = valid ? dkeys[bd + i] : 0u;
       if constexpr (NEED_POS) {
 #pragma unroll
-        for (int p = 0; p < MAXP; p++) ppos[it][p] = (p == (int)d) ? bd + i : 0u;
+        for (int p = 0; p < NP; p++) ppos[it][p] = (p == (int)d) ? bd + i : 0u;
       }
     }
     // probe the other sets; iterations are independent, so their loads overlap
 #pragma unroll
-    for (int p = 0; p < MAXP; p++) {
+    for (int p = 0; p < NP; p++) {
       if (p >= (int)a.np) break;
       if (p == (int)d) continue;
       const bool np_ = NEED_POS && ((a.need_pos_mask >> p) & 1u);
@@ -529,7 +532,7 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
             uint32_t v = 0;
             if (pa >= 0) {
 #pragma unroll
-              for (int q = 0; q < MAXP; q++)
+              for (int q = 0; q < NP; q++)
                 if (q == pa) v = ppos[it][q];
             } else {
               v = a.pos_in[at][r];
@@ -555,7 +558,7 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
       for (int it = 0; it < U_IT; it++) {
         if (!hit[it]) continue;
         HitRows h;
-        leaf_rows(L, r, ppos[it], h);
+        leaf_rows<NP>(L, r, ppos[it], h);
         const uint64_t nc = combos(L, h);
         cnt = sat_add_u64(cnt, sat_mul_u64(h.mult, nc));
         if (L.sum && nc) {
@@ -602,7 +605,7 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
       for (int it = 0; it < U_IT; it++) {
         if (!hit[it]) continue;
         HitRows h;
-        leaf_rows(L, r, ppos[it], h);
+        leaf_rows<NP>(L, r, ppos[it], h);
         c = sat_add_u64(c, combos(L, h));
       }
       c = min(c, (uint64_t)UINT32_MAX);
@@ -616,7 +619,7 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
         m[it] = 0;
         if (hit[it]) {
           HitRows h;
-          leaf_rows(L, r, ppos[it], h);
+          leaf_rows<NP>(L, r, ppos[it], h);
           m[it] = combos(L, h);
         }
         wtot += wave_sum(m[it]);
@@ -631,7 +634,7 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
         const uint64_t tot = __shfl(incl, WAVE - 1, WAVE);
         if (m[it]) {
           HitRows h;
-          leaf_rows(L, r, ppos[it], h);
+          leaf_rows<NP>(L, r, ppos[it], h);
           uint32_t cur[MAXA];
 #pragma unroll
           for (int at = 0; at < MAXA; at++) cur[at] = h.rb[at];
@@ -673,7 +676,7 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
       for (int it = 0; it < U_IT; it++) {
         if (!hit[it] || table_full) continue;
         HitRows h;
-        leaf_rows(L, r, ppos[it], h);
+        leaf_rows<NP>(L, r, ppos[it], h);
         if (!combos(L, h)) continue;
         uint32_t cur[MAXA];
 #pragma unroll
@@ -818,6 +821,13 @@ __global__ __launch_bounds__(J_NT) void k_elem(ElemArgs a) {
   }
 }
 
+template <int MODE>
+void launch_elem(const ElemArgs& a, unsigned grid, hipStream_t s) {
+  if (a.np <= 2) k_elem<MODE, 2><<<grid, J_NT, 0, s>>>(a);
+  else if (a.np <= 4) k_elem<MODE, 4><<<grid, J_NT, 0, s>>>(a);
+  else k_elem<MODE, MAXP><<<grid, J_NT, 0, s>>>(a);
+}
+
 // Row of every work unit.  A thread writes up to UROW_SMALL units of its
 // row; rows with more are listed and finished by whole blocks.
 constexpr uint64_t UROW_SMALL = 16;
@@ -843,6 +853,13 @@ __global__ void k_unit_rows_big(const uint64_t* U, const uint32_t* big, const ui
 }
 
 // ---- two-set COUNT leaf with per-unit descriptors ----------------------------
+// Probed keys a wave stages in LDS (4 waves x 4 KB per block keeps 8 waves
+// per SIMD; 2048 keys halved the occupancy and cost 65%).
+constexpr int L2_CAP = 1024;
+// Stage at most this many probed keys per driver key: beyond it, bisecting
+// the range's line samples reads fewer bytes than staging the range.
+constexpr uint32_t L2_STAGE_RATIO = 8;
+
 // For the common leaf of two participating sets and set semantics, every
 // work unit is described once: its driver key range, and either the probed
 // set's bitset window or the part of the probed sorted keys that the unit's
@@ -856,8 +873,14 @@ struct UnitDesc {
   uint64_t pword;    // probed set's first bitset word, or UINT64_MAX (sorted keys)
   uint32_t drv;      // driving participant (0 or 1), or DRV_AND: words [plo | phi << 32, +dcount) of
                      // participant 0's pool AND words [pword, +dcount) of participant 1's
-  uint32_t pad;
+  uint32_t top;      // 1: the unit's row is in the top bucket (run by its own launch)
 };
+
+// Rows whose two sets hold this many elements together form the top
+// bucket: the largest intersections, run as a launch of their own.
+constexpr uint32_t TOP_MIN = 1u << 14;
+// Leaves with fewer units run in one launch.
+constexpr uint64_t TOP_SPLIT_UNITS = 1u << 16;
 
 // First index in [lo, hi) whose value is > x (hi if none).
 __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t x) {
@@ -871,9 +894,11 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t 
 // One thread per unit.  Consecutive units of a row split the driver into
 // chunks of U_EL sorted keys; a chunk can only meet probed keys from the
 // lower bound of its first key up to the lower bound of the next chunk's
-// first key (the last chunk: the upper bound of its last key).
+// first key (the last chunk: the upper bound of its last key).  Units of
+// top-bucket rows are tagged and, when top_list is given, listed (in no
+// particular order: their counts add up in any order).
 __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow, const uint8_t* drv, uint64_t units,
-                            UnitDesc* desc) {
+                            UnitDesc* desc, uint32_t* top_list, uint32_t* n_top) {
   for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t r = urow[u];
     const uint64_t u0 = U[r], u1 = U[r + 1];
@@ -883,7 +908,19 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
     dset_range(wa.set[1], r, b[1], e[1], sidx[1]);
     const uint32_t d = drv[r];
     UnitDesc t;
-    t.pad = 0;
+    const bool is_top = top_list && (uint64_t)(e[0] - b[0]) + (e[1] - b[1]) >= TOP_MIN;
+    t.top = is_top ? 1u : 0u;
+    if (top_list) {
+      // one atomic per wave for the wave's top units
+      const uint64_t m = ballot(is_top);
+      if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        if (lane_id() == leader) base = atomicAdd(n_top, (uint32_t)__popcll(m));
+        base = __shfl(base, leader, WAVE);
+        if (is_top) top_list[base + lanes_below(m)] = (uint32_t)u;
+      }
+    }
     if (d == DRV_AND) {
       // word k of each window covers base + 64 k; both bases are multiples of 64
       const uint32_t base0 = wa.set[0].bs_base[sidx[0]], base1 = wa.set[1].bs_base[sidx[1]];
@@ -916,6 +953,11 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
     if (t.pword != UINT64_MAX) {
       t.plo = bsb[sq];
       t.phi = pk[pe - 1];
+    } else if (u0 + 1 == u1 && pe - pb <= (uint32_t)L2_CAP && pe - pb <= 2 * t.dcount + WAVE) {
+      // the row's only unit, against a probed set no larger than about
+      // twice its driver: the whole set is staged, no search needed
+      t.plo = pb;
+      t.phi = pe;
     } else {
       t.plo = sampled_lower_bound(pk, ps, pb, pe, dk[t.dstart]);
       if (u + 1 == u1) {
@@ -934,6 +976,8 @@ struct Leaf2Args {
   const uint32_t* samp[2];
   const uint64_t* pool[2];
   const UnitDesc* desc;
+  const uint32_t* list;   // top-bucket launch: the units to run (units = their number)
+  uint64_t n_desc;        // descriptors (all units of the leaf)
   uint64_t* ucnt;         // grouped: count of every unit; null: one group, summed into gcount[0]
   uint64_t* gcount;
   uint64_t units;
@@ -957,14 +1001,6 @@ __global__ void k_group_add(const uint64_t* gstart, const uint64_t* gend, uint64
     gcount[g] += gend[g] - gstart[g];
 }
 
-#ifndef LH_L2_CAP
-#define LH_L2_CAP 1024
-#endif
-constexpr int L2_CAP = LH_L2_CAP;  // probed keys a wave stages in LDS
-#ifndef LH_L2_RATIO
-#define LH_L2_RATIO 8
-#endif
-constexpr uint32_t L2_STAGE_RATIO = LH_L2_RATIO;  // stage at most this many probed keys per driver key
 
 // Membership of x[it] (it < nit) in the strictly increasing keys a[0, m),
 // m >= 1: a branchless bisection whose trip count depends on m only, so the
@@ -1123,10 +1159,13 @@ __device__ __forceinline__ UnitDesc load_desc(CDesc d, uint64_t u) {
   t.phi = d[u].phi;
   t.pword = d[u].pword;
   t.drv = d[u].drv;
-  t.pad = 0;
+  t.top = d[u].top;
   return t;
 }
 
+// LIST = false runs every unit but those of the top bucket; LIST = true
+// runs the top bucket's units, listed in a.list.
+template <bool LIST>
 __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
   __shared__ uint32_t s_stage[J_NW][L2_CAP];
   __shared__ unsigned long long s_cnt;
@@ -1141,47 +1180,52 @@ __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
   // on, so its latency overlaps the current unit's key loads.
   // descriptors are read-only here: read through the constant address space
   const CDesc desc = (CDesc)a.desc;
+  auto unit_of = [&](uint64_t i) -> uint64_t { return LIST ? (uint64_t)a.list[i] : i; };
   UnitDesc nt{};
+  uint64_t nu = 0;
   uint32_t nlo = 0;
   const uint64_t vb0 = xcd_block(blockIdx.x, gridDim.x);
   if (vb0 < a.nvblk && vb0 * J_NW + w < a.units) {
-    const uint64_t u0 = vb0 * J_NW + w;
-    nt = load_desc(desc, u0);
-    nlo = (u0 + 1 < a.units) ? desc[u0 + 1].plo : 0u;
+    nu = unit_of(vb0 * J_NW + w);
+    nt = load_desc(desc, nu);
+    nlo = (nu + 1 < a.n_desc) ? desc[nu + 1].plo : 0u;
   }
   for (uint64_t vb = vb0; vb < a.nvblk; vb += gridDim.x) {
-    const uint64_t u = vb * J_NW + w;
+    const uint64_t i = vb * J_NW + w;
+    const uint64_t u = nu;
     const UnitDesc t = nt;
     const uint32_t next_lo = nlo;
-    const uint64_t un = (vb + gridDim.x) * J_NW + w;
-    if (vb + gridDim.x < a.nvblk && un < a.units) {
-      nt = load_desc(desc, un);
-      nlo = (un + 1 < a.units) ? desc[un + 1].plo : 0u;
+    const uint64_t in = (vb + gridDim.x) * J_NW + w;
+    if (vb + gridDim.x < a.nvblk && in < a.units) {
+      nu = unit_of(in);
+      nt = load_desc(desc, nu);
+      nlo = (nu + 1 < a.n_desc) ? desc[nu + 1].plo : 0u;
     }
-    if (u >= a.units) continue;  // wave-uniform; no barrier inside the loop
+    if (i >= a.units) continue;      // wave-uniform; no barrier inside the loop
+    if (!LIST && t.top) continue;    // the top bucket's own launch runs it
     uint32_t c = 0;
     if (t.drv == DRV_AND) {
       const uint64_t w0 = (uint64_t)t.plo | ((uint64_t)t.phi << 32);
 #pragma unroll
       for (int it = 0; it < U_IT; it++) {
-        const uint32_t i = it * WAVE + lane;
-        if (i < t.dcount) c += (uint32_t)__popcll(a.pool[0][w0 + i] & a.pool[1][t.pword + i]);
+        const uint32_t k = it * WAVE + lane;
+        if (k < t.dcount) c += (uint32_t)__popcll(a.pool[0][w0 + k] & a.pool[1][t.pword + k]);
       }
     } else {
       c = probe_unit(a, t, next_lo, stage, lane);
     }
     if (a.ucnt) {
       // grouped: one count per unit; groups are summed by a scan afterwards
-      const uint64_t s = wave_sum((uint64_t)c);
-      if (lane == 0) a.ucnt[u] = s;
+      const uint64_t sc = wave_sum((uint64_t)c);
+      if (lane == 0) a.ucnt[u] = sc;
     } else {
       run += c;
     }
   }
   if (!a.ucnt) {
     __syncthreads();
-    const uint64_t s = wave_sum(run);
-    if (lane == 0 && s) atomicAdd(&s_cnt, (unsigned long long)s);
+    const uint64_t sc = wave_sum(run);
+    if (lane == 0 && sc) atomicAdd(&s_cnt, (unsigned long long)sc);
     __syncthreads();
     if (tid == 0 && s_cnt) atomicAdd((unsigned long long*)&a.gcount[0], s_cnt);
   }
@@ -1468,7 +1512,7 @@ void step(const lh_plan_t* p, uint32_t d, Frontier& F, hipStream_t s) {
                                       "join_count_d8", "join_count_d9", "join_count_d10", "join_count_d11",
                                       "join_count_d12", "join_count_d13", "join_count_d14", "join_count_d15"};
     ProfScope ps(names[d], s, F.n, total);
-    k_elem<M_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+    launch_elem<M_COUNT>(a, elem_grid(nblk), s);
   }
   LH_HIP(hipGetLastError());
   DBuf<uint64_t> boff(nblk + 1, s);
@@ -1519,7 +1563,7 @@ void step(const lh_plan_t* p, uint32_t d, Frontier& F, hipStream_t s) {
                                       "join_fill_d8", "join_fill_d9", "join_fill_d10", "join_fill_d11",
                                       "join_fill_d12", "join_fill_d13", "join_fill_d14", "join_fill_d15"};
     ProfScope ps(names[d], s, F.n, total);
-    k_elem<M_FILL><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+    launch_elem<M_FILL>(a, elem_grid(nblk), s);
   }
   LH_HIP(hipGetLastError());
   F = std::move(G);
@@ -1626,7 +1670,7 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
     }
     if (total) {
       ProfScope ps(impl == 3 ? "leaf_group_dense" : "leaf_group_hash", s, F.n, total);
-      k_elem<M_LEAF_B_AGG><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+      launch_elem<M_LEAF_B_AGG>(a, elem_grid(nblk), s);
       LH_HIP(hipGetLastError());
     }
     const uint32_t e = read_scalar(err.p, s);
@@ -1643,7 +1687,7 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
         a.blk_cnt = bcnt.p;
         {
           ProfScope ps("leaf_emit_count", s, F.n, total);
-          k_elem<M_LEAF_B_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+          launch_elem<M_LEAF_B_COUNT>(a, elem_grid(nblk), s);
         }
         LH_HIP(hipGetLastError());
         const uint64_t n_emit = scan_u32_to_u64(bcnt.p, boff.p, nblk, s);
@@ -1937,11 +1981,18 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         wa.np = 2;
         wa.set[0] = a.set[0];
         wa.set[1] = a.set[1];
+        // large leaves run their top bucket (rows whose two sets hold
+        // TOP_MIN elements or more) as a launch of its own
+        const bool split = dw.units >= TOP_SPLIT_UNITS;
+        DBuf<uint32_t> top_list(split ? dw.units : 0, s), n_top(1, s);
+        fill_u32(n_top.p, 0u, 1, s);
         {
           ProfScope ps("leaf_units", s, dw.units, 0);
-          k_unit_desc<<<grid_for(dw.units), 256, 0, s>>>(wa, dw.U.p, dw.urow.p, dw.drv.p, dw.units, desc.p);
+          k_unit_desc<<<grid_for(dw.units), 256, 0, s>>>(wa, dw.U.p, dw.urow.p, dw.drv.p, dw.units, desc.p,
+                                                          split ? top_list.p : nullptr, n_top.p);
         }
         LH_HIP(hipGetLastError());
+        const uint32_t top_units = split ? read_scalar(n_top.p, s) : 0u;
         Leaf2Args l2{};
         l2.keys[0] = a.set[0].keys;
         l2.keys[1] = a.set[1].keys;
@@ -1952,12 +2003,22 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         l2.desc = desc.p;
         l2.gcount = L.gcount;
         l2.units = dw.units;
+        l2.n_desc = dw.units;
         l2.nvblk = nblk;
         DBuf<uint64_t> ucnt(L.gid ? dw.units : 0, s);
         l2.ucnt = ucnt.p;
         {
           ProfScope ps("leaf_aggregate", s, F.n, total);
-          k_leaf2_count<<<leaf_grid(nblk), J_NT, 0, s>>>(l2);
+          k_leaf2_count<false><<<leaf_grid(nblk), J_NT, 0, s>>>(l2);
+        }
+        LH_HIP(hipGetLastError());
+        if (top_units) {
+          Leaf2Args lt = l2;
+          lt.list = top_list.p;
+          lt.units = top_units;
+          lt.nvblk = (top_units + J_NW - 1) / J_NW;
+          ProfScope ps("leaf_top", s, top_units, 0);
+          k_leaf2_count<true><<<leaf_grid(lt.nvblk), J_NT, 0, s>>>(lt);
         }
         LH_HIP(hipGetLastError());
         if (L.gid) {
@@ -1972,8 +2033,8 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         }
       } else {
         ProfScope ps("leaf_aggregate", s, F.n, total);
-        if (all_set) k_elem<M_LEAF_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
-        else k_elem<M_LEAF_A><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+        if (all_set) launch_elem<M_LEAF_COUNT>(a, elem_grid(nblk), s);
+        else launch_elem<M_LEAF_A>(a, elem_grid(nblk), s);
       }
       LH_HIP(hipGetLastError());
     }
@@ -2025,7 +2086,7 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
       a.blk_cnt = bcnt.p;
       {
         ProfScope ps("leaf_emit_count", s, F.n, total);
-        k_elem<M_LEAF_B_COUNT><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+        launch_elem<M_LEAF_B_COUNT>(a, elem_grid(nblk), s);
       }
       LH_HIP(hipGetLastError());
       boff.alloc(nblk + 1, s);
@@ -2052,7 +2113,7 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
     if (n_emit) {
       a.blk_off = boff.p;
       ProfScope ps("leaf_emit_fill", s, F.n, total);
-      k_elem<M_LEAF_B_FILL><<<elem_grid(nblk), J_NT, 0, s>>>(a);
+      launch_elem<M_LEAF_B_FILL>(a, elem_grid(nblk), s);
       LH_HIP(hipGetLastError());
     }
     // sort tuples by the output columns

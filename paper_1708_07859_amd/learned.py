@@ -222,10 +222,10 @@ def training_queries():
     for sc in (12, 14, 16, 18, 20, 21):
         lo, hi = synth.rmat_edges(sc, 16 << sc, seed=20 + sc)
         qs.append(("triangle rmat%d" % sc, queries.triangle(lo, hi)))
-    # the benchmark graph itself (2^22 vertices, 2^26 samples, seed 2) and
-    # one of twice its size (seed 23); 2^24 vertices are held out
-    lo, hi = synth.rmat_edges(22, 1 << 26, seed=2)
-    qs.append(("triangle rmat22", queries.triangle(lo, hi)))
+    # graphs of the benchmark's size on other seeds and one of twice its
+    # size; the benchmark graph itself (2^22 vertices, 2^26 samples, seed 2),
+    # the 2^24-vertex graph (seed 5) and the test graph of the model's gain
+    # (2^20 vertices, seed 1020) are held out
     lo, hi = synth.rmat_edges(23, 1 << 27, seed=23)
     qs.append(("triangle rmat23", queries.triangle(lo, hi)))
     for sc, seed in ((22, 102), (23, 123)):

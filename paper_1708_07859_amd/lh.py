@@ -11,8 +11,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# LH_LIBRARY names another build of the same library (for A/B timing)
-LIB_PATH = os.environ.get("LH_LIBRARY") or os.path.join(HERE, "liblh.so")
+LIB_PATH = os.path.join(HERE, "liblh.so")
 
 LH_OK, LH_ERR_INVALID, LH_ERR_OOM, LH_ERR_DEVICE, LH_ERR_UNSUPPORTED, LH_ERR_OVERFLOW = range(6)
 LH_SET, LH_BAG = 0x0, 0x1
