@@ -202,6 +202,31 @@ typedef struct lh_result {
 lh_status lh_join_aggregate(lh_plan_t* const* plans, uint32_t n_plans, void* hip_stream,
                             lh_result** out);
 
+/* ---- a join that allocates no device memory -------------------------------
+ * For callers that cannot allocate device memory: tight serving loops and
+ * harnesses that forbid allocation around their calls.  It runs one plan as
+ * lh_join_aggregate does (same kernels, identical results) but takes every
+ * temporary from a static device array of LH_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends, and writes
+ * the result into the caller's buffers instead of an lh_result.  It calls
+ * no hipMalloc, hipFree or allocating library routine.  All calls on one
+ * GPU share that GPU's array: calls that overlap on one GPU (other host
+ * threads, other streams) race and must be serialized by the caller.
+ *
+ * out_keys: HOST array of n_cols DEVICE columns (n_cols = the plan's n_out
+ * + n_group), each with room for max_rows uint32; counts: DEVICE, max_rows
+ * uint64; sums: DEVICE, max_rows doubles (SUM plans; ignored and may be NULL
+ * for COUNT); *n_rows (HOST) receives the number of rows written, in the
+ * order and format of lh_result.  The plan comes from lh_plan as usual.
+ * Errors: LH_ERR_INVALID for NULL arguments or a plan that is not live;
+ * LH_ERR_UNSUPPORTED for a plan run by BLAS (LH_DENSE_BLAS); LH_ERR_OVERFLOW
+ * when the join's temporaries do not fit the scratch or the result has more
+ * than max_rows rows (outputs are then unspecified); the errors of
+ * lh_join_aggregate otherwise. */
+#define LH_NOALLOC_SCRATCH_BYTES (64u << 20)
+lh_status lh_join_aggregate_noalloc(const lh_plan_t* plan, void* hip_stream, uint64_t max_rows,
+                                    uint32_t* const* out_keys, uint64_t* counts, double* sums, uint64_t* n_rows);
+
 /* Release an lh_trie*, lh_plan* or lh_result*.  NULL is a no-op. */
 void lh_free(void* handle);
 

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblh.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["runtime.cpp", "prims.hip", "trie.hip", "join.hip", "batch.hip", "mlp.hip", "learned.hip", "plan.hip", "ghd.hip", "dense.hip", "ml.hip", "costmodel.cpp", "capi.cpp"]
+SOURCES = ["runtime.cpp", "prims.hip", "trie.hip", "join.hip", "batch.hip", "mlp.hip", "learned.hip", "plan.hip", "ghd.hip", "dense.hip", "ml.hip", "noalloc.hip", "costmodel.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -217,6 +217,21 @@ lh_status lh_join_aggregate(lh_plan_t* const* plans, uint32_t n_plans, void* hip
   return LH_OK;
 }
 
+lh_status lh_join_aggregate_noalloc(const lh_plan_t* plan, void* hip_stream, uint64_t max_rows,
+                                    uint32_t* const* out_keys, uint64_t* counts, double* sums, uint64_t* n_rows) {
+  if (n_rows) *n_rows = 0;
+  return guard([&] {
+    if (!plan || !counts || !n_rows) fail(LH_ERR_INVALID, "NULL argument");
+    if (!tracked(g_plans, plan)) fail(LH_ERR_INVALID, "not a live lh_plan");
+    const uint32_t n_cols = (uint32_t)(plan->out_attrs.size() + plan->groups.size());
+    if (n_cols && !out_keys) fail(LH_ERR_INVALID, "NULL out_keys for a result with key columns");
+    for (uint32_t c = 0; c < n_cols; c++)
+      if (!out_keys[c]) fail(LH_ERR_INVALID, "NULL output key column");
+    if (plan->agg == LH_AGG_SUM && !sums) fail(LH_ERR_INVALID, "NULL sums for a SUM plan");
+    *n_rows = run_plan_noalloc(plan, (hipStream_t)hip_stream, max_rows, out_keys, counts, sums, nullptr);
+  });
+}
+
 void lh_free(void* h) {
   if (!h) return;
   if (untrack(g_tries, h)) {

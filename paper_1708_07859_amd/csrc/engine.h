@@ -90,6 +90,10 @@ namespace lh {
 
 lh_plan_t* make_plan(const lh_query* q, hipStream_t s);
 lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s);
+// run_plan with every temporary in the static scratch (noalloc.hip); the
+// result's rows go to the caller's buffers.  Returns the row count.
+uint64_t run_plan_noalloc(const lh_plan_t* p, hipStream_t s, uint64_t max_rows, uint32_t* const* out_keys,
+                          uint64_t* counts, double* sums, uint64_t* peak_bytes);
 // Dense relations under LH_DENSE_BLAS: mark the plan for a BLAS product.
 void plan_dense(const lh_query* q, lh_plan_t* p, hipStream_t s);
 lh_result_impl* run_dense(const lh_plan_t* p, hipStream_t s);

@@ -36,6 +36,25 @@ void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
 long live_allocations();
 
+// A caller-provided device region that stands in for allocation: while an
+// ArenaScope is alive on a host thread, dalloc on that thread bump-allocates
+// from [base, base + cap) (256-byte aligned) and fails with LH_ERR_OVERFLOW
+// when the region is full; dfree of memory inside a registered region does
+// nothing.
+struct Arena {
+  void* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  size_t peak = 0;
+};
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena& a);
+  ~ArenaScope();
+};
+void register_arena_range(void* base, size_t cap);
+bool arena_active();
+
 template <class T>
 struct DBuf {  // owning device buffer, freed on the stream it was made on
   T* p = nullptr;
@@ -82,6 +101,13 @@ inline void* pinned_scratch() {
 template <class T>
 T read_scalar(const T* dptr, hipStream_t s) {
   static_assert(sizeof(T) <= 64, "read_scalar: at most 64 bytes");
+  if (arena_active()) {
+    // no host allocation either: read into this frame
+    T v;
+    LH_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+    LH_HIP(hipStreamSynchronize(s));
+    return v;
+  }
   T* h = static_cast<T*>(pinned_scratch());
   LH_HIP(hipMemcpyAsync(h, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
   LH_HIP(hipStreamSynchronize(s));

@@ -6,6 +6,7 @@
 #include <mutex>
 #include <sstream>
 #include <unordered_map>
+#include <vector>
 
 #include "lh_internal.h"
 
@@ -81,8 +82,56 @@ void release_cache(hipStream_t s) {
 }
 }  // namespace
 
+// ---- bump arena -------------------------------------------------------------
+// While an arena is active on a host thread, device allocations of that
+// thread are carved from it in order and frees give nothing back until it
+// ends; no device memory is allocated.  Memory inside a registered arena
+// range is never handed to hipFreeAsync.
+namespace {
+thread_local Arena* t_arena = nullptr;
+std::mutex g_arena_mu;
+std::vector<std::pair<const char*, const char*>> g_arena_ranges;
+
+bool in_arena_range(const void* p) {
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  const char* c = static_cast<const char*>(p);
+  for (auto& r : g_arena_ranges)
+    if (c >= r.first && c < r.second) return true;
+  return false;
+}
+}  // namespace
+
+void register_arena_range(void* base, size_t cap) {
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  const char* b = static_cast<const char*>(base);
+  for (auto& r : g_arena_ranges)
+    if (r.first == b) return;
+  g_arena_ranges.emplace_back(b, b + cap);
+}
+
+bool arena_active() { return t_arena != nullptr; }
+
+ArenaScope::ArenaScope(Arena& a) : prev(t_arena) {
+  a.used = 0;
+  t_arena = &a;
+}
+ArenaScope::~ArenaScope() { t_arena = prev; }
+
 void* dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) return nullptr;
+  if (t_arena) {
+    Arena& a = *t_arena;
+    const size_t off = (a.used + 255) & ~size_t(255);
+    if (off > a.cap || bytes > a.cap - off) {
+      std::ostringstream os;
+      os << "the static scratch of " << (a.cap >> 20) << " MiB cannot hold this join's temporaries (" << bytes
+         << " more bytes at offset " << off << ")";
+      fail(LH_ERR_OVERFLOW, os.str());
+    }
+    a.used = off + bytes;
+    if (a.used > a.peak) a.peak = a.used;
+    return static_cast<char*>(a.base) + off;
+  }
   configure_pool();
   long fa = fail_after();
   long k = g_allocs.fetch_add(1);
@@ -123,6 +172,7 @@ void* dalloc(size_t bytes, hipStream_t s) {
 
 void dfree(void* p, hipStream_t s) {
   if (!p) return;
+  if (in_arena_range(p)) return;   // arena memory is released when the arena ends
   std::lock_guard<std::mutex> lk(g_cache_mu);
   auto it = g_cap.find(p);
   if (it == g_cap.end()) {

@@ -155,6 +155,8 @@ SIGNATURES = {
     "lh_trie_build": ([C.POINTER(RelationDesc), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "lh_plan": ([C.POINTER(Query), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "lh_join_aggregate": ([C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p, C.POINTER(C.POINTER(Result))], C.c_int),
+    "lh_join_aggregate_noalloc": ([C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p), C.c_void_p,
+                                   C.c_void_p, C.POINTER(C.c_uint64)], C.c_int),
     "lh_free": ([C.c_void_p], None),
     "lh_last_error": ([], C.c_char_p),
     "lh_trie_get_info": ([C.c_void_p, C.POINTER(TrieInfo)], C.c_int),
@@ -460,6 +462,23 @@ def join_aggregate(plans, stream=None):
     outs = (C.POINTER(Result) * n)()
     _check(lib.lh_join_aggregate(arr, n, stream if stream is not None else current_stream(), outs))
     return [JoinResult(outs[i]) for i in range(n)]
+
+
+def join_aggregate_noalloc(plan, out_keys, counts, sums=None, stream=None):
+    """lh_join_aggregate_noalloc: run one plan with no device allocation,
+    writing into caller-owned device tensors (out_keys: one uint32/int32
+    tensor per output column, counts: uint64/int64, sums: float64 or None),
+    all with the same capacity.  Returns the number of rows written."""
+    cap = counts.numel()
+    for t in list(out_keys) + ([sums] if sums is not None else []):
+        if t.numel() < cap:
+            raise ValueError("every output buffer needs the capacity of counts")
+    keys = (C.c_void_p * max(1, len(out_keys)))(*[t.data_ptr() for t in out_keys])
+    n = C.c_uint64(0)
+    _check(lib.lh_join_aggregate_noalloc(plan.handle, stream if stream is not None else current_stream(), cap,
+                                         keys, counts.data_ptr(), sums.data_ptr() if sums is not None else None,
+                                         C.byref(n)))
+    return n.value
 
 
 def live_allocations():
