@@ -144,7 +144,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--samples-log2", type=int, default=26)
-    ap.add_argument("--cpu-scale", type=int, default=19)
+    ap.add_argument("--cpu-scale", type=int, default=18)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--runs", type=int, default=7,
                     help="runs of the timing protocol (min and max dropped); 0 skips it")
@@ -155,7 +155,7 @@ def main():
     ap.add_argument("--policy", default="both", choices=["both", "plain", "learned"],
                     help="both: time the plain rule, then the learned cost model (reported)")
     ap.add_argument("--workload", default="triangle", choices=["triangle", "batch", "learned", "copy", "gather", "intersect", "q5", "groupby", "dense",
-                             "spgemm-star", "voter"])
+                             "spgemm-star", "voter", "configs"])
     ap.add_argument("--weights", default=None)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--card", type=int, default=1_000_000)
@@ -189,6 +189,8 @@ def main():
         return bench_copy(args, torch)
     if args.workload == "gather":
         return bench_gather(args, torch)
+    if args.workload == "configs":
+        return bench_configs(args, lh, torch, synth)
     if args.workload == "intersect":
         return bench_intersect(args, lh, torch, synth)
     if args.workload == "q5":
@@ -231,11 +233,13 @@ def main():
     if len(runs) == 2:
         assert runs["plain"]["count"] == runs["learned"]["count"], "policies disagree on the count"
     prof = head["prof"]
-    # roofline of the dominant kernel, the two-set leaf
+    # roofline of the dominant kernel, the two-set leaf: its main launch plus
+    # the top-bucket launch, per step
     roof = None
     if "leaf_aggregate" in prof:
         e = prof["leaf_aggregate"]
-        avg_ms = e["total_ms"] / e["launches"]
+        top = prof.get("leaf_top", {"total_ms": 0.0, "launches": 0})
+        avg_ms = (e["total_ms"] + top["total_ms"]) / e["launches"]
         achieved = b_min / (avg_ms / 1000) / 1e9
         model_bytes = leaf_model_bytes(e["rows"], e["elements"]) / e["launches"]
         kernel = KERNEL_OF_SCOPE["leaf_aggregate"]
@@ -243,11 +247,16 @@ def main():
         summary = TRAFFIC_SUMMARY.get(head_policy)
         if summary and (args.scale, args.samples_log2) == (22, 26) and (head_policy != "plain" or args.layout == "plain"):
             from paper_1708_07859_amd import profiling
-            traffic = profiling.read_traffic(os.path.join(ROOT, "profiles", summary), kernel)
+            path = os.path.join(ROOT, "profiles", summary)
+            traffic = profiling.read_traffic(path, kernel)
+            t_top = profiling.read_traffic(path, kernel + "_top")
+            if traffic is not None and t_top is not None:
+                traffic += t_top
         roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
-                "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(b_min),
+                "avg_launch_ms": round(avg_ms, 4), "top_bucket_ms": round(top["total_ms"] / e["launches"], 4),
+                "alg_bytes_per_launch": int(b_min),
                 "alg_bytes": "minimum bytes: 4 B per wedge (S(b) streamed per edge) + 4 B per edge (T(a) once) + "
                              "8 B per vertex (offsets)",
                 "model_bytes_per_launch": int(model_bytes),
@@ -531,6 +540,158 @@ def measure_batch(args, lh, torch, synth):
     return res
 
 
+def scope_roofline(prof, scope, steps):
+    """GB/s and fraction of peak of one profiling scope whose `elements`
+    field holds the algorithmic bytes its launches moved."""
+    e = prof.get(scope)
+    if not e or not e["total_ms"]:
+        return None
+    gbs = e["elements"] / (e["total_ms"] / 1000) / 1e9
+    return {"kernel_scope": scope, "launches_per_step": e["launches"] / steps,
+            "ms_per_step": round(e["total_ms"] / steps, 3), "bytes_per_step": int(e["elements"] / steps),
+            "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def bench_configs(args, lh, torch, synth):
+    """Every single-GPU configuration in one table: SpGEMM n = 4096 (cfg1),
+    the triangle at 2^22 vertices (cfg2, the headline; see the default run),
+    the 60M-row star GROUP BY (cfg3), the 512-instance batch (cfg4) and the
+    held-out R-MAT 24 triangle (cfg5), each with tuples/s and the roofline
+    fraction of its dominant kernel under a stated byte count."""
+    from paper_1708_07859_amd import learned as L
+    from tests import queries
+    flush = torch.empty(FLUSH_BYTES, dtype=torch.uint8, device="cuda").zero_()
+    table = {}
+    table["cfg1"] = measure_spgemm(args, lh, torch, synth, flush)
+
+    # cfg3: star join GROUP BY, one step = the five trie builds + plan + join
+    log("generating the star schema")
+    sch = synth.star_schema(seed=3)
+    q = queries.star(sch)
+    dev = [{"keys": [lh.to_device(k) for k in a["keys"]], "annos": [lh.to_device(x) for x in a.get("annos", [])],
+            "meta": [lh.to_device(m) for m in a.get("meta", [])], "bag": a.get("bag", False)} for a in q["atoms"]]
+    rows = sum(len(x["keys"][0]) for x in q["atoms"])
+    del sch
+    lm, om, _ = L.load(args.weights or L.DEFAULT_WEIGHTS)
+    star = {}
+    for policy in ("plain", "learned"):
+        if policy == "learned":
+            L.register(lm, om)
+        layout = "learned" if policy == "learned" else "plain"
+        state = {}
+
+        def step():
+            tries = [lh.trie_build(a["keys"], a["annos"], a["meta"], bag=a["bag"], layout=layout) for a in dev]
+            atoms = [(t, a["attrs"], a.get("anno", -1)) for t, a in zip(tries, q["atoms"])]
+            p = lh.plan(q["n_attrs"], atoms, out=q.get("out", []), group=q.get("group", []), agg=q["agg"],
+                        filters=q.get("filters", []), policy=policy)
+            state["order"] = p.info()["attr_order"]
+            r = lh.join_aggregate([p])[0]
+            o = r.to_host()
+            state["groups"], state["tuples"] = len(o["counts"]), int(o["counts"].sum())
+            r.free()
+            p.free()
+            for t in tries:
+                t.free()
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        lh.profile_reset()
+        lh.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000 / args.steps
+        lh.profile_enable(False)
+        prof = lh.profile_read()
+        join_ms = sum(v["total_ms"] for k, v in prof.items() if k.startswith(("join_", "leaf_"))) / args.steps
+        star[policy] = {"ms_per_step": round(ms, 3), "tuples_per_s": rows / (ms / 1000), "order": state["order"],
+                        "groups": state["groups"], "join_tuples": state["tuples"],
+                        "join_kernels_ms": round(join_ms, 3),
+                        "roofline": scope_roofline(prof, "sort_scatter", args.steps),
+                        "protocol_cold": run_protocol(torch, step, flush, args.runs) if args.runs else None}
+        log(f"star {policy}: {star[policy]}")
+        if policy == "learned":
+            lh.use_model(lh.LH_MODEL_LAYOUT, None)
+            lh.use_model(lh.LH_MODEL_ORDER, None)
+    del dev
+    table["cfg3"] = {"workload": "star join GROUP BY, 60M fact rows (Zipf 1.0 keys), dims 2M/500k/100k/10k, "
+                                 "filters 20%/10%/1%, ~100 groups", "input_rows": rows,
+                     "roofline_note": "dominant kernel: the radix-sort scatter of the trie builds, 16 B per key "
+                                      "(24 B with a value) per pass",
+                     **star}
+
+    table["cfg4"] = measure_batch(args, lh, torch, synth)
+
+    # cfg5: the held-out graph, both policies, every candidate for the regret
+    log("generating R-MAT 24 (held out)")
+    lo, hi = synth.rmat_edges(24, 1 << 28, seed=5)
+    lo_d, hi_d = lh.to_device(lo), lh.to_device(hi)
+    del lo, hi
+    n_edges, wedges, _ = edge_stats(torch, lo_d, hi_d)
+    b_min = triangle_min_bytes(n_edges, wedges, 1 << 24)
+
+    def tri(layout, policy, order=None):
+        torch.cuda.synchronize()
+        lh.profile_reset()
+        lh.profile_enable(True)
+        t0 = time.perf_counter()
+        t = lh.trie_build([lo_d, hi_d], layout=layout)
+        p = lh.plan(3, [(t, [0, 1], -1), (t, [1, 2], -1), (t, [0, 2], -1)], agg="count", attr_order=order,
+                    policy=policy)
+        r = lh.join_aggregate([p])[0]
+        c = int(r.to_host()["counts"][0])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000
+        lh.profile_enable(False)
+        prof = lh.profile_read()
+        leaf = sum(v["total_ms"] for k, v in prof.items() if k in ("leaf_aggregate", "leaf_top"))
+        chosen = p.info()["attr_order"]
+        r.free()
+        p.free()
+        t.free()
+        return ms, c, chosen, leaf
+
+    def best(layout, policy, order=None, reps=3):
+        rs = [tri(layout, policy, order) for _ in range(reps)]
+        assert len({x[1] for x in rs}) == 1
+        i = min(range(reps), key=lambda k: rs[k][0])
+        return rs[i]
+
+    L.register(lm, om)
+    tri("plain", "plain")
+    res5 = {}
+    for policy in ("plain", "learned"):
+        ms, c, chosen, leaf = best("learned" if policy == "learned" else "plain", policy)
+        res5[policy] = {"ms_per_step": round(ms, 3), "tuples_per_s": 3 * n_edges / (ms / 1000), "order": chosen,
+                        "leaf_ms": round(leaf, 3), "leaf_min_bytes_GBs": round(b_min / (leaf / 1000) / 1e9, 1),
+                        "leaf_frac": round(b_min / (leaf / 1000) / 1e9 / HBM_PEAK_GBS, 4), "triangles": c}
+    import itertools
+    cands = {}
+    for layout in ("plain", "learned"):
+        for order in itertools.permutations(range(3)):
+            ms, c, _, _ = best(layout, "fixed", list(order), reps=2)
+            assert c == res5["plain"]["triangles"]
+            cands[f"{layout}:{list(order)}"] = round(ms, 3)
+    lh.use_model(lh.LH_MODEL_LAYOUT, None)
+    lh.use_model(lh.LH_MODEL_ORDER, None)
+    t_best = min(cands.values())
+    assert res5["plain"]["triangles"] == res5["learned"]["triangles"]
+    table["cfg5"] = {"workload": "held-out triangle COUNT, R-MAT scale 24, 2^28 samples, seed 5",
+                     "edges": n_edges, "wedges": wedges, "leaf_min_bytes": b_min, **res5,
+                     "speedup_learned_over_plain": round(res5["plain"]["ms_per_step"] / res5["learned"]["ms_per_step"], 4),
+                     "regret_plain": round(res5["plain"]["ms_per_step"] / t_best - 1, 4),
+                     "regret_learned": round(res5["learned"]["ms_per_step"] / t_best - 1, 4),
+                     "candidates_ms": cands}
+    out = {"metric": "per-configuration join-aggregate tuples/s and roofline fractions", "value": None,
+           "unit": "tuples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64",
+           "data": "synthetic", "config": table}
+    print(json.dumps(out), flush=True)
+
+
 def bench_learned(args, lh, torch, synth):
     """Held-out evaluation of the learned cost model: triangle COUNT on an
     R-MAT graph it never saw (2^scale vertices, 2^(samples) samples).  Times
@@ -657,8 +818,9 @@ def bench_intersect(args, lh, torch, synth):
         torch.cuda.synchronize()
         lh.profile_enable(False)
         prof = lh.profile_read()
-        leaf = prof["leaf_aggregate"]
-        ms = leaf["total_ms"] / leaf["launches"]
+        # the leaf: its main launch and, for pairs of 2^14 elements or more,
+        # the top-bucket launch
+        ms = sum(prof[k]["total_ms"] for k in ("leaf_aggregate", "leaf_top") if k in prof) / args.steps
         per_pair = {("uint", "uint"): 8 * c, ("uint", "bitset"): 4 * c + U / 8,
                     ("bitset", "bitset"): 2 * U / 8}[(la, lb)]
         alg = per_pair * npairs

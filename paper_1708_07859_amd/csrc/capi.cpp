@@ -203,8 +203,23 @@ lh_status lh_join_aggregate(lh_plan_t* const* plans, uint32_t n_plans, void* hip
     for (uint32_t i = 0; i < n_plans; i++)
       if (!tracked(g_plans, plans[i])) fail(LH_ERR_INVALID, "not a live lh_plan");
     hipStream_t s = (hipStream_t)hip_stream;
-    if (n_plans == 1 || !run_batch(plans, n_plans, s, made))
-      for (uint32_t i = 0; i < n_plans; i++) made.push_back(run_plan(plans[i], s));
+    made.assign(n_plans, nullptr);
+    if (n_plans > 1) {
+      // the plans of the row-union shape run as one batch; the others
+      // one by one
+      std::vector<uint32_t> idx;
+      std::vector<lh_plan_t*> sub;
+      for (uint32_t i = 0; i < n_plans; i++)
+        if (row_union_kind(plans[i]) >= 0) {
+          idx.push_back(i);
+          sub.push_back(plans[i]);
+        }
+      std::vector<lh_result_impl*> got;
+      if (sub.size() > 1 && run_batch(sub.data(), (uint32_t)sub.size(), s, got))
+        for (size_t k = 0; k < idx.size(); k++) made[idx[k]] = got[k];
+    }
+    for (uint32_t i = 0; i < n_plans; i++)
+      if (!made[i]) made[i] = run_plan(plans[i], s);
   });
   if (st != LH_OK) {
     for (auto* r : made) delete r;

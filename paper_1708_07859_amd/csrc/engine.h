@@ -62,6 +62,7 @@ struct lh_plan_s {
   bool case_prefix = false;                 // outputs = first n_out attributes of the order
   bool case_full = false;                   // COUNT, every attribute an output, no GROUP BY meta column
   uint32_t group_impl = 0;                  // GROUP BY outside the prefix: 0 auto, 1 sort, 2 hash, 3 dense
+  bool want_parts = false;                  // SUM: also hand out each sum's exact parts (multi-node plans)
   uint32_t blas = 0;                        // 1: BLAS matrix-vector, 2: matrix-matrix (dense relations)
   lh::DensePlan dense;
   int32_t exact_lsb = 0;
@@ -83,6 +84,7 @@ struct lh_result_impl {
   std::vector<const uint32_t*> colptr;
   lh::DBuf<uint64_t> counts;
   lh::DBuf<double> sums;
+  lh::DBuf<double> parts;                   // want_parts: EXACT_PARTS doubles per row summing exactly to the sum
   std::shared_ptr<void> shared;             // batched results share one output block
 };
 

@@ -293,4 +293,33 @@ __device__ inline double exact_round(const int64_t* slot, uint32_t D, int32_t ls
   return neg ? -r : r;
 }
 
+// The exact value held in D shared-form slots as parts out[0..K): each part
+// is the nearest double to what the parts before it leave, so out[0] is
+// the correctly rounded sum, the parts do not overlap, and their exact sum
+// is the value whenever K parts suffice (each part takes at least 53 of the
+// value's 32 D bits: K = 5 covers D = 8).  Unused parts are 0.  Sets
+// *overflow if the value does not fit the window or K parts do not suffice.
+constexpr int EXACT_PARTS = 5;
+__device__ inline void exact_parts(const int64_t* slot, uint32_t D, int32_t lsb, double* out, uint32_t* overflow) {
+  RegAcc r;
+  r.load_shared(slot, D);
+  bool done = false;
+#pragma unroll
+  for (int k = 0; k < EXACT_PARTS; k++) {
+    double v = 0.0;
+    if (!done) {
+      v = exact_round(r.s, D, lsb, overflow);
+      if (v == 0.0) {
+        done = true;
+      } else {
+        // v is a multiple of 2^lsb inside the window: the subtraction is exact
+        (void)r.add(-v, lsb, D, 1);
+        r.normalize(D);
+      }
+    }
+    out[k] = v;
+  }
+  if (!done && !r.zero() && overflow) *overflow = 1;
+}
+
 }  // namespace lh

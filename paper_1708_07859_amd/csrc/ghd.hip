@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "exact.h"
 #include "ghd.h"
 
 namespace lh {
@@ -433,6 +434,41 @@ __global__ void k_f64_to_u64(const double* in, uint64_t* out, uint64_t n, uint32
 
 unsigned grid1(uint64_t n) { return (unsigned)((n + 255) / 256); }
 
+// Non-zero exact parts of each group's sum (at least one per group, so the
+// group stays present with its count weight).
+__global__ void k_count_parts(const double* parts, uint64_t n, uint32_t* cnt) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c = 1;
+  for (int k = 1; k < EXACT_PARTS; k++) c += parts[i * EXACT_PARTS + k] != 0.0 ? 1u : 0u;
+  cnt[i] = c;
+}
+
+struct ExpandArgs {
+  uint32_t n_cols;
+  const uint32_t* key_in[MAXV];
+  uint32_t* key_out[MAXV];
+  const double* wc;       // count weight of each group
+  const double* parts;    // EXACT_PARTS per group
+  const uint64_t* off;    // first output row of each group
+  double* wc_out;
+  double* part_out;
+};
+
+// One row per non-zero part: the group's keys, its count weight on the
+// first row (0 on the others), and the part.  The parts are non-zero in
+// order, so a group's rows are its first parts.
+__global__ void k_expand_parts(ExpandArgs a, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t o = a.off[i], m = a.off[i + 1] - o;
+  for (uint64_t k = 0; k < m; k++) {
+    for (uint32_t c = 0; c < a.n_cols; c++) a.key_out[c][o + k] = a.key_in[c][i];
+    a.wc_out[o + k] = k == 0 ? a.wc[i] : 0.0;
+    a.part_out[o + k] = a.parts[i * EXACT_PARTS + k];
+  }
+}
+
 void check(lh_status st) {
   if (st != LH_OK) fail(st, std::string("ghd node: ") + lh_last_error());
 }
@@ -445,6 +481,9 @@ struct NodeOut {
   lh_trie* trie = nullptr;     // the intermediate relation handed to the parent
   std::vector<uint32_t> keys;  // its key attributes (global ids, ascending)
   bool has_anno = false;       // an annotated atom lies in this subtree
+  // the relation's rows when each sum is handed up as its exact parts
+  std::vector<DBuf<uint32_t>> ekeys;
+  DBuf<double> ewc, epart;
 };
 
 struct Owned {  // frees everything made on the way, also on errors
@@ -553,6 +592,8 @@ lh_result* run_ghd(const lh_query* q, const Ghd& g, hipStream_t s) {
       lh_plan_t* p = nullptr;
       check(lh_plan(&nq, s, &p));
       own.h.push_back(p);
+      // a child's sums go up as exact parts, so the parent sums exactly
+      if (sum_run && !root) p->want_parts = true;
       lh_result* r = nullptr;
       check(lh_join_aggregate(&p, 1, s, &r));
       own.h.push_back(r);
@@ -586,6 +627,39 @@ lh_result* run_ghd(const lh_query* q, const Ghd& g, hipStream_t s) {
       rel.n_annos = 2;
       rel.annos = annos;
       rel.flags = LH_BAG | LH_LAYOUT_PLAIN;
+      std::vector<const uint32_t*> ekp;
+      const lh_result_impl* rb = o.b ? reinterpret_cast<const lh_result_impl*>(o.b) : nullptr;
+      if (rb && rb->parts.p && nr) {
+        // one bag row per non-zero exact part of each group's sum
+        if (o.a->n_cols > MAXV) fail(LH_ERR_UNSUPPORTED, "ghd: too many interface attributes");
+        DBuf<uint32_t> cnt(nr, s);
+        DBuf<uint64_t> off(nr + 1, s);
+        k_count_parts<<<grid1(nr), 256, 0, s>>>(rb->parts.p, nr, cnt.p);
+        LH_HIP(hipGetLastError());
+        const uint64_t m = scan_u32_to_u64(cnt.p, off.p, nr, s);
+        ExpandArgs ea{};
+        ea.n_cols = o.a->n_cols;
+        o.ekeys.resize(ea.n_cols);
+        for (uint32_t c = 0; c < ea.n_cols; c++) {
+          o.ekeys[c].alloc(m, s);
+          ea.key_in[c] = o.a->out_keys[c];
+          ea.key_out[c] = o.ekeys[c].p;
+          ekp.push_back(o.ekeys[c].p);
+        }
+        o.ewc.alloc(m, s);
+        o.epart.alloc(m, s);
+        ea.wc = wc;
+        ea.parts = rb->parts.p;
+        ea.off = off.p;
+        ea.wc_out = o.ewc.p;
+        ea.part_out = o.epart.p;
+        k_expand_parts<<<grid1(nr), 256, 0, s>>>(ea, nr);
+        LH_HIP(hipGetLastError());
+        annos[0] = o.ewc.p;
+        annos[1] = o.epart.p;
+        rel.n_rows = m;
+        rel.keys = ekp.data();
+      }
       check(lh_trie_build(&rel, s, &o.trie));
       own.h.push_back(o.trie);
     }
@@ -612,8 +686,16 @@ lh_result* run_ghd(const lh_query* q, const Ghd& g, hipStream_t s) {
   }
   res->pub.counts = res->counts.p;
   res->pub.sums = is_sum ? res->sums.p : nullptr;
-  // a sum over several nodes is rounded once per node
-  res->pub.exact = (is_sum && !has_kids) ? R.b->exact : 0u;
+  // Children hand their sums up as exact parts, and a term of two factors
+  // is an exact product: with at most two annotated atoms in the query
+  // every node's terms are those of the single plan, so the root's sums are
+  // its correctly rounded exact sums.  More factors are rounded per node.
+  uint32_t n_annotated = 0;
+  for (uint32_t e = 0; e < q->n_atoms; e++) n_annotated += q->atoms[e].anno >= 0 ? 1u : 0u;
+  bool all_exact = R.b && R.b->exact;
+  for (size_t c = 1; c < nn; c++)
+    if (out[c].b) all_exact = all_exact && out[c].b->exact;
+  res->pub.exact = (is_sum && all_exact && (!has_kids || n_annotated <= 2)) ? 1u : 0u;
   uint64_t nj = 0;
   if (nr) {
     std::vector<uint64_t> h(nr);

@@ -894,11 +894,10 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t 
 // One thread per unit.  Consecutive units of a row split the driver into
 // chunks of U_EL sorted keys; a chunk can only meet probed keys from the
 // lower bound of its first key up to the lower bound of the next chunk's
-// first key (the last chunk: the upper bound of its last key).  Units of
-// top-bucket rows are tagged and, when top_list is given, listed (in no
-// particular order: their counts add up in any order).
+// first key (the last chunk: the upper bound of its last key).  When
+// top_flag is given, units of top-bucket rows are tagged and flagged.
 __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow, const uint8_t* drv, uint64_t units,
-                            UnitDesc* desc, uint32_t* top_list, uint32_t* n_top) {
+                            UnitDesc* desc, uint32_t* top_flag) {
   for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t r = urow[u];
     const uint64_t u0 = U[r], u1 = U[r + 1];
@@ -908,19 +907,9 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
     dset_range(wa.set[1], r, b[1], e[1], sidx[1]);
     const uint32_t d = drv[r];
     UnitDesc t;
-    const bool is_top = top_list && (uint64_t)(e[0] - b[0]) + (e[1] - b[1]) >= TOP_MIN;
+    const bool is_top = top_flag && (uint64_t)(e[0] - b[0]) + (e[1] - b[1]) >= TOP_MIN;
     t.top = is_top ? 1u : 0u;
-    if (top_list) {
-      // one atomic per wave for the wave's top units
-      const uint64_t m = ballot(is_top);
-      if (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        uint32_t base = 0;
-        if (lane_id() == leader) base = atomicAdd(n_top, (uint32_t)__popcll(m));
-        base = __shfl(base, leader, WAVE);
-        if (is_top) top_list[base + lanes_below(m)] = (uint32_t)u;
-      }
-    }
+    if (top_flag) top_flag[u] = t.top;
     if (d == DRV_AND) {
       // word k of each window covers base + 64 k; both bases are multiples of 64
       const uint32_t base0 = wa.set[0].bs_base[sidx[0]], base1 = wa.set[1].bs_base[sidx[1]];
@@ -1069,12 +1058,49 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Probe path of a unit: the unit's driver keys against the probed set's
-// bitset, its LDS-staged keys, or its line samples.
-__device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDesc& t, uint32_t next_lo, uint32_t* stage,
-                                               int lane) {
-  uint32_t c = 0;
+// A unit's first loads, issued one unit ahead: its driver keys and the first
+// U_IT * WAVE keys of the probed range it stages (when it stages one).
+struct UnitLoads {
+  uint32_t x[U_IT];
+  uint32_t st[U_IT];
+};
+
+// The probed key range [lo, lo + m) a sorted-array unit stages in LDS, or
+// m = 0 when it searches the line samples instead (or probes a bitset).
+__device__ __forceinline__ uint32_t staged_range(const UnitDesc& t, uint32_t next_lo, uint32_t& lo) {
+  lo = t.plo;
+  if (t.drv == DRV_AND || t.pword != UINT64_MAX) return 0;
+  const uint32_t hi = t.phi == UINT32_MAX ? next_lo : t.phi;
+  const uint32_t m = hi - lo;
+  return (m > 0 && m <= (uint32_t)L2_CAP && m <= L2_STAGE_RATIO * t.dcount) ? m : 0u;
+}
+
+__device__ __forceinline__ void issue_unit(const Leaf2Args& a, const UnitDesc& t, uint32_t next_lo, int lane,
+                                           UnitLoads& L) {
+  if (t.drv == DRV_AND) return;
   const uint32_t* dk = t.drv ? a.keys[1] : a.keys[0];
+#pragma unroll
+  for (int it = 0; it < U_IT; it++) {
+    const uint32_t i = it * WAVE + lane;
+    L.x[it] = i < t.dcount ? dk[t.dstart + i] : 0u;
+  }
+  uint32_t lo;
+  const uint32_t m = staged_range(t, next_lo, lo);
+  if (m) {
+    const uint32_t* pk = t.drv ? a.keys[0] : a.keys[1];
+#pragma unroll
+    for (int it = 0; it < U_IT; it++) {
+      const uint32_t i = it * WAVE + lane;
+      L.st[it] = i < m ? pk[lo + i] : 0u;
+    }
+  }
+}
+
+// Probe path of a unit whose first loads are in L: the unit's driver keys
+// against the probed set's bitset, its LDS-staged keys, or its line samples.
+__device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDesc& t, uint32_t next_lo,
+                                               const UnitLoads& L, uint32_t* stage, int lane) {
+  uint32_t c = 0;
   const uint32_t* pk = t.drv ? a.keys[0] : a.keys[1];
   const uint64_t* pool = t.drv ? a.pool[0] : a.pool[1];
   const uint32_t nit = (t.dcount + WAVE - 1) / WAVE;
@@ -1084,7 +1110,7 @@ __device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDes
   for (int it = 0; it < U_IT; it++) {
     const uint32_t i = it * WAVE + lane;
     v[it] = i < t.dcount;
-    x[it] = v[it] ? dk[t.dstart + i] : 0u;
+    x[it] = L.x[it];
   }
   if (t.pword != UINT64_MAX) {
 #pragma unroll
@@ -1093,59 +1119,66 @@ __device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDes
       const uint32_t dd = x[it] - t.plo;
       c += (uint32_t)((pool[t.pword + (dd >> 6)] >> (dd & 63u)) & 1ull);
     }
-  } else {
-    const uint32_t lo = t.plo;
-    const uint32_t hi = t.phi == UINT32_MAX ? next_lo : t.phi;
-    const uint32_t m = hi - lo;
-    if (m > 0 && m <= (uint32_t)L2_CAP && m <= L2_STAGE_RATIO * t.dcount) {
-      wave_stage(stage, pk + lo, m, lane);
+    return c;
+  }
+  uint32_t lo;
+  const uint32_t ms = staged_range(t, next_lo, lo);
+  if (ms) {
+    // the first U_IT * WAVE keys arrived with the unit's first loads
+#pragma unroll
+    for (int it = 0; it < U_IT; it++) {
+      const uint32_t i = it * WAVE + lane;
+      if (i < ms) stage[i] = L.st[it];
+    }
+    if (ms > (uint32_t)(U_IT * WAVE)) wave_stage(stage + U_IT * WAVE, pk + lo + U_IT * WAVE, ms - U_IT * WAVE, lane);
+    wave_lds_sync();
+    c = count_members(stage, ms, x, v, nit);
+    wave_lds_sync();
+    return c;
+  }
+  const uint32_t hi = t.phi == UINT32_MAX ? next_lo : t.phi;
+  if (hi <= lo) return 0;
+  // A large range: bisect the line samples inside it (staged in LDS
+  // when they fit), then search the one line that can hold x.
+  // Samples j in [jf, jl] start lines inside [lo, hi); keys before
+  // the first of them belong to the range's first, partial line.
+  const uint32_t* sp = t.drv ? a.samp[0] : a.samp[1];
+  const uint32_t jf = (lo + (1u << LINE_SHIFT) - 1) >> LINE_SHIFT;
+  const uint32_t jl = (hi - 1) >> LINE_SHIFT;
+  uint32_t k[U_IT];
+#pragma unroll
+  for (int it = 0; it < U_IT; it++) k[it] = 0;
+  if (jl >= jf) {
+    const uint32_t ns = jl - jf + 1;
+    if (ns <= (uint32_t)L2_CAP) {
+      wave_stage(stage, sp + jf, ns, lane);
       wave_lds_sync();
-      c = count_members(stage, m, x, v, nit);
+      count_le(stage, ns, x, nit, k);
       wave_lds_sync();
-    } else if (m > 0) {
-      // A large range: bisect the line samples inside it (staged in LDS
-      // when they fit), then search the one line that can hold x.
-      // Samples j in [jf, jl] start lines inside [lo, hi); keys before
-      // the first of them belong to the range's first, partial line.
-      const uint32_t* sp = t.drv ? a.samp[0] : a.samp[1];
-      const uint32_t jf = (lo + (1u << LINE_SHIFT) - 1) >> LINE_SHIFT;
-      const uint32_t jl = (hi - 1) >> LINE_SHIFT;
-      uint32_t k[U_IT];
-#pragma unroll
-      for (int it = 0; it < U_IT; it++) k[it] = 0;
-      if (jl >= jf) {
-        const uint32_t ns = jl - jf + 1;
-        if (ns <= (uint32_t)L2_CAP) {
-          wave_stage(stage, sp + jf, ns, lane);
-          wave_lds_sync();
-          count_le(stage, ns, x, nit, k);
-          wave_lds_sync();
-        } else {
-          count_le(sp + jf, ns, x, nit, k);
-        }
-      }
-      uint32_t pos[U_IT], len[U_IT];
-#pragma unroll
-      for (int it = 0; it < U_IT; it++) {
-        const uint32_t sb = k[it] ? (jf + k[it] - 1) << LINE_SHIFT : lo;
-        const uint32_t se = (uint32_t)min<uint64_t>(hi, (uint64_t)(jf + k[it]) << LINE_SHIFT);
-        pos[it] = sb;
-        len[it] = se > sb ? se - sb : 0;
-      }
-#pragma unroll
-      for (int step = 0; step < (int)LINE_SHIFT; step++)
-#pragma unroll
-        for (int it = 0; it < U_IT; it++)
-          if (it < (int)nit && len[it] > 1) {
-            const uint32_t half = len[it] >> 1;
-            pos[it] = (pk[pos[it] + half] <= x[it]) ? pos[it] + half : pos[it];
-            len[it] -= half;
-          }
-#pragma unroll
-      for (int it = 0; it < U_IT; it++)
-        if (it < (int)nit) c += (v[it] && len[it] > 0 && pk[pos[it]] == x[it]) ? 1u : 0u;
+    } else {
+      count_le(sp + jf, ns, x, nit, k);
     }
   }
+  uint32_t pos[U_IT], len[U_IT];
+#pragma unroll
+  for (int it = 0; it < U_IT; it++) {
+    const uint32_t sb = k[it] ? (jf + k[it] - 1) << LINE_SHIFT : lo;
+    const uint32_t se = (uint32_t)min<uint64_t>(hi, (uint64_t)(jf + k[it]) << LINE_SHIFT);
+    pos[it] = sb;
+    len[it] = se > sb ? se - sb : 0;
+  }
+#pragma unroll
+  for (int step = 0; step < (int)LINE_SHIFT; step++)
+#pragma unroll
+    for (int it = 0; it < U_IT; it++)
+      if (it < (int)nit && len[it] > 1) {
+        const uint32_t half = len[it] >> 1;
+        pos[it] = (pk[pos[it] + half] <= x[it]) ? pos[it] + half : pos[it];
+        len[it] -= half;
+      }
+#pragma unroll
+  for (int it = 0; it < U_IT; it++)
+    if (it < (int)nit) c += (v[it] && len[it] > 0 && pk[pos[it]] == x[it]) ? 1u : 0u;
   return c;
 }
 
@@ -1181,27 +1214,46 @@ __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
   // descriptors are read-only here: read through the constant address space
   const CDesc desc = (CDesc)a.desc;
   auto unit_of = [&](uint64_t i) -> uint64_t { return LIST ? (uint64_t)a.list[i] : i; };
-  UnitDesc nt{};
-  uint64_t nu = 0;
-  uint32_t nlo = 0;
+  // Software pipeline: a unit's first loads are issued one unit ahead, so
+  // each wave keeps two units' loads in flight; descriptors are loaded two
+  // units ahead.  (cur: the unit whose loads are in flight; nxt: the one
+  // after it, whose descriptor is arriving.)
+  const uint64_t G = gridDim.x;
   const uint64_t vb0 = xcd_block(blockIdx.x, gridDim.x);
-  if (vb0 < a.nvblk && vb0 * J_NW + w < a.units) {
-    nu = unit_of(vb0 * J_NW + w);
-    nt = load_desc(desc, nu);
+  auto valid = [&](uint64_t vb) { return vb < a.nvblk && vb * J_NW + w < a.units; };
+  UnitDesc cd{}, nd{};
+  uint64_t cu = 0, nu = 0;
+  uint32_t clo = 0, nlo = 0;
+  UnitLoads cl{};
+  if (valid(vb0)) {
+    cu = unit_of(vb0 * J_NW + w);
+    cd = load_desc(desc, cu);
+    clo = (cu + 1 < a.n_desc) ? desc[cu + 1].plo : 0u;
+    if (LIST || !cd.top) issue_unit(a, cd, clo, lane, cl);
+  }
+  if (valid(vb0 + G)) {
+    nu = unit_of((vb0 + G) * J_NW + w);
+    nd = load_desc(desc, nu);
     nlo = (nu + 1 < a.n_desc) ? desc[nu + 1].plo : 0u;
   }
-  for (uint64_t vb = vb0; vb < a.nvblk; vb += gridDim.x) {
-    const uint64_t i = vb * J_NW + w;
-    const uint64_t u = nu;
-    const UnitDesc t = nt;
-    const uint32_t next_lo = nlo;
-    const uint64_t in = (vb + gridDim.x) * J_NW + w;
-    if (vb + gridDim.x < a.nvblk && in < a.units) {
-      nu = unit_of(in);
-      nt = load_desc(desc, nu);
-      nlo = (nu + 1 < a.n_desc) ? desc[nu + 1].plo : 0u;
+  for (uint64_t vb = vb0; vb < a.nvblk; vb += G) {
+    const bool here = valid(vb);
+    const uint64_t u = cu;
+    const UnitDesc t = cd;
+    const uint32_t next_lo = clo;
+    const UnitLoads L = cl;
+    if (valid(vb + G)) {
+      cu = nu;
+      cd = nd;
+      clo = nlo;
+      if (LIST || !cd.top) issue_unit(a, cd, clo, lane, cl);
+      if (valid(vb + 2 * G)) {
+        nu = unit_of((vb + 2 * G) * J_NW + w);
+        nd = load_desc(desc, nu);
+        nlo = (nu + 1 < a.n_desc) ? desc[nu + 1].plo : 0u;
+      }
     }
-    if (i >= a.units) continue;      // wave-uniform; no barrier inside the loop
+    if (!here) continue;             // wave-uniform; no barrier inside the loop
     if (!LIST && t.top) continue;    // the top bucket's own launch runs it
     uint32_t c = 0;
     if (t.drv == DRV_AND) {
@@ -1212,7 +1264,7 @@ __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
         if (k < t.dcount) c += (uint32_t)__popcll(a.pool[0][w0 + k] & a.pool[1][t.pword + k]);
       }
     } else {
-      c = probe_unit(a, t, next_lo, stage, lane);
+      c = probe_unit(a, t, next_lo, L, stage, lane);
     }
     if (a.ucnt) {
       // grouped: one count per unit; groups are summed by a scan afterwards
@@ -1277,6 +1329,7 @@ struct GroupFin {
   uint32_t* key_out[MAXV + MAXA];
   uint64_t* count_out;
   double* sum_out;
+  double* parts;            // exact parts of each sum (EXACT_PARTS per row), or null
   uint32_t sum;
   int32_t lsb;
   uint32_t D;
@@ -1296,6 +1349,7 @@ __global__ void k_dense_finalize(GroupFin f, uint64_t n) {
     }
     f.count_out[o] = f.cnt[i];
     if (f.sum) f.sum_out[o] = exact_round(f.acc + i * f.D, f.D, f.lsb, f.err);
+    if (f.parts) exact_parts(f.acc + i * f.D, f.D, f.lsb, f.parts + o * EXACT_PARTS, f.err);
   }
 }
 
@@ -1307,6 +1361,7 @@ __global__ void k_hash_finalize(GroupFin f, uint64_t n) {
     for (uint32_t c = 0; c < f.n_cols; c++) f.key_out[c][i] = f.key_in[c][j];
     f.count_out[i] = f.cnt[slot];
     if (f.sum) f.sum_out[i] = exact_round(f.acc + slot * f.D, f.D, f.lsb, f.err);
+    if (f.parts) exact_parts(f.acc + slot * f.D, f.D, f.lsb, f.parts + i * EXACT_PARTS, f.err);
   }
 }
 
@@ -1319,6 +1374,7 @@ struct FinA {
   uint32_t* key_out[MAXV];
   uint64_t* count_out;
   double* sum_out;
+  double* parts;            // exact parts of each sum (EXACT_PARTS per row), or null
   uint32_t sum;
   int32_t lsb;
   uint32_t D;
@@ -1335,6 +1391,7 @@ __global__ void k_finalize_groups(FinA f, uint64_t n) {
     for (uint32_t c = 0; c < f.n_cols; c++) f.key_out[c][o] = f.key_in[c][g];
     f.count_out[o] = f.gcount[g];
     if (f.sum) f.sum_out[o] = exact_round(f.gacc + g * EXACT_MAXD, f.D, f.lsb, f.err);
+    if (f.parts) exact_parts(f.gacc + g * EXACT_MAXD, f.D, f.lsb, f.parts + o * EXACT_PARTS, f.err);
   }
 }
 
@@ -1724,8 +1781,10 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
     }
     res->counts.alloc(n_groups, s);
     if (is_sum) res->sums.alloc(n_groups, s);
+    if (is_sum && p->want_parts) res->parts.alloc(n_groups * EXACT_PARTS, s);
     f.count_out = res->counts.p;
     f.sum_out = res->sums.p;
+    f.parts = res->parts.p;
     f.off = off.p;
     if (n_groups) {
       k_dense_finalize<<<grid_for(space), 256, 0, s>>>(f, space);
@@ -1766,8 +1825,10 @@ bool group_in_place(const lh_plan_t* p, const Frontier& F, ElemArgs& a, uint64_t
     }
     res->counts.alloc(n_groups, s);
     if (is_sum) res->sums.alloc(n_groups, s);
+    if (is_sum && p->want_parts) res->parts.alloc(n_groups * EXACT_PARTS, s);
     f.count_out = res->counts.p;
     f.sum_out = res->sums.p;
+    f.parts = res->parts.p;
     f.sid = sid.p;
     f.perm = perm.p;
     if (n_groups) {
@@ -1984,15 +2045,18 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         // large leaves run their top bucket (rows whose two sets hold
         // TOP_MIN elements or more) as a launch of its own
         const bool split = dw.units >= TOP_SPLIT_UNITS;
-        DBuf<uint32_t> top_list(split ? dw.units : 0, s), n_top(1, s);
-        fill_u32(n_top.p, 0u, 1, s);
+        DBuf<uint32_t> top_flag(split ? dw.units : 0, s);
         {
           ProfScope ps("leaf_units", s, dw.units, 0);
           k_unit_desc<<<grid_for(dw.units), 256, 0, s>>>(wa, dw.U.p, dw.urow.p, dw.drv.p, dw.units, desc.p,
-                                                          split ? top_list.p : nullptr, n_top.p);
+                                                          split ? top_flag.p : nullptr);
         }
         LH_HIP(hipGetLastError());
-        const uint32_t top_units = split ? read_scalar(n_top.p, s) : 0u;
+        // the top bucket's units in unit order, so that units of one row run
+        // close together (and share the L2) as they do in the main launch
+        DBuf<uint32_t> top_list(split ? dw.units : 0, s);
+        const uint64_t top_units = split ? select_flagged(top_flag.p, dw.units, top_list.p, s) : 0u;
+        top_flag.reset();
         Leaf2Args l2{};
         l2.keys[0] = a.set[0].keys;
         l2.keys[1] = a.set[1].keys;
@@ -2068,8 +2132,10 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
     }
     res->counts.alloc(n_out_rows, s);
     if (is_sum) res->sums.alloc(n_out_rows, s);
+    if (is_sum && p->want_parts) res->parts.alloc(n_out_rows * EXACT_PARTS, s);
     f.count_out = res->counts.p;
     f.sum_out = res->sums.p;
+    f.parts = res->parts.p;
     const uint64_t nfin = no == 0 ? 1 : (group_keys.empty() ? 0 : n_groups);
     if (nfin) {
       k_finalize_groups<<<grid_for(nfin), 256, 0, s>>>(f, nfin);
@@ -2179,8 +2245,10 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
     }
     res->counts.alloc(n_seg, s);
     if (is_sum) res->sums.alloc(n_seg, s);
+    if (is_sum && p->want_parts) res->parts.alloc(n_seg * EXACT_PARTS, s);
     f.count_out = res->counts.p;
     f.sum_out = res->sums.p;
+    f.parts = res->parts.p;
     if (n_seg) {
       k_finalize_groups<<<grid_for(n_seg), 256, 0, s>>>(f, n_seg);
       LH_HIP(hipGetLastError());

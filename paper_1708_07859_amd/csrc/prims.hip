@@ -447,13 +447,16 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t*
   for (uint32_t p = 0; p < passes; p++) {
     uint32_t shift = lo_bit + p * 8;
     {
-      ProfScope ps("sort_hist", s, n, 0);
+      // elements: the pass's algorithmic bytes (the u64 keys read)
+      ProfScope ps("sort_hist", s, n, 8 * n);
       k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ki, n, shift, hist.p, ntiles);
     }
     LH_HIP(hipGetLastError());
     scan_u32(hist.p, offs.p, hn, s);
     {
-      ProfScope ps("sort_scatter", s, n, 0);
+      // elements: the pass's algorithmic bytes (u64 keys, and u32 values
+      // when they travel, read once and written once)
+      ProfScope ps("sort_scatter", s, n, (vi ? 24 : 16) * n);
       if (vals) k_rs_scatter<true><<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, offs.p, hist.p, ntiles);
       else k_rs_scatter<false><<<ntiles, RS_NT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, offs.p, hist.p, ntiles);
     }

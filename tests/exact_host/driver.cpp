@@ -3,7 +3,8 @@
 // decimal), then lines "mode v_bits mult" until EOF: mode 0 adds mult * v to
 // a register accumulator (flushed into the shared slots at the end), mode 1
 // adds it straight to the shared slots.  stdout: "ok overflow bits" where
-// bits is the rounded sum's IEEE pattern and ok is 0 if a term did not fit.
+// bits is the rounded sum's IEEE pattern and ok is 0 if a term did not fit,
+// then the IEEE patterns of the value's exact parts (exact_parts).
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -36,6 +37,15 @@ int main() {
   const double r = lh::exact_round(slots, D, lsb, &ovf);
   unsigned long long rb;
   memcpy(&rb, &r, sizeof rb);
-  printf("%d %u %llu\n", ok ? 1 : 0, ovf, rb);
+  double parts[lh::EXACT_PARTS];
+  uint32_t povf = 0;
+  lh::exact_parts(slots, D, lsb, parts, &povf);
+  printf("%d %u %llu", ok ? 1 : 0, ovf | povf, rb);
+  for (int k = 0; k < lh::EXACT_PARTS; k++) {
+    unsigned long long pb;
+    memcpy(&pb, &parts[k], sizeof pb);
+    printf(" %llu", pb);
+  }
+  printf("\n");
   return 0;
 }

@@ -37,7 +37,8 @@ def run(exe, D, lsb, terms, init=None):
     lines = [f"{D} {lsb}", " ".join(str(u) for u in init)]
     lines += [f"{m} {bits_of(v)} {mult}" for m, v, mult in terms]
     out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True, check=True)
-    ok, ovf, rb = out.stdout.split()
+    ok, ovf, rb, *parts = out.stdout.split()
+    run.parts = [struct.unpack("<d", struct.pack("<Q", int(p)))[0] for p in parts]
     return int(ok), int(ovf), struct.unpack("<d", struct.pack("<Q", int(rb)))[0]
 
 
@@ -134,3 +135,23 @@ def test_value_above_window_flags_overflow(driver):
     # D = 2 digits at lsb 0 hold |x| < 2^63: four terms of 2^62 do not fit
     ok, ovf, _ = run(driver, 2, 0, [(1, 2.0 ** 62, 1)] * 4)
     assert ok == 1 and ovf == 1
+
+
+def test_exact_parts_sum_to_the_value(driver):
+    # the parts a multi-node plan hands up: their exact sum is the value, the
+    # first is the correctly rounded sum, and they do not overlap
+    rng = random.Random(11)
+    for trial in range(30):
+        terms = [(1, (rng.random() * 2 - 1) * 2.0 ** rng.randint(-45, 20), rng.choice([1, 3, 1 << 40]))
+                 for _ in range(rng.randint(1, 60))]
+        D, lsb = 8, -110
+        ok, ovf, got = run(driver, D, lsb, terms)
+        parts = run.parts
+        exact = sum((Fraction(v) * m for _, v, m in terms), Fraction(0))
+        assert ok == 1 and ovf == 0
+        assert got == float(exact) == parts[0]
+        assert sum((Fraction(p) for p in parts), Fraction(0)) == exact
+        nz = [p for p in parts if p != 0.0]
+        assert parts[:len(nz)] == nz                     # zeros only at the end
+        for a, b in zip(nz, nz[1:]):
+            assert abs(b) <= abs(a) * 2.0 ** -53         # each below half an ulp of the one before
