@@ -64,6 +64,9 @@ KERNEL_OF_SCOPE = {"leaf_aggregate": "k_leaf2_count"}
 # while the kernel's source matches the one the counters saw
 TRAFFIC_SUMMARY = {"plain": "triangle_rmat22_leaf2_count_traffic.txt",
                    "learned": "triangle_rmat22_learned_leaf2_count_traffic.txt"}
+# the two-set leaf's launches: every row but those of the two buckets, the
+# top bucket, the merged rows
+LEAF_SCOPES = ("leaf_aggregate", "leaf_top", "leaf_merge")
 FLUSH_BYTES = 512 << 20      # more than the 256 MB Infinity Cache and the 8 x 4 MB L2
 
 
@@ -148,6 +151,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--runs", type=int, default=7,
                     help="runs of the timing protocol (min and max dropped); 0 skips it")
+    ap.add_argument("--batch-policies", default="plain,learned",
+                    help="policies of the batch legs (comma-separated)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch: time the batched launch only (e.g. to profile the graph launch alone)")
     ap.add_argument("--no-side", action="store_true",
                     help="time the headline triangle only (no SpGEMM, no batch legs)")
     ap.add_argument("--layout", default="plain", choices=["plain", "uint", "bitset", "learned"],
@@ -239,7 +246,7 @@ def main():
     if "leaf_aggregate" in prof:
         e = prof["leaf_aggregate"]
         top = prof.get("leaf_top", {"total_ms": 0.0, "launches": 0})
-        avg_ms = (e["total_ms"] + top["total_ms"]) / e["launches"]
+        avg_ms = sum(prof[k]["total_ms"] for k in LEAF_SCOPES if k in prof) / e["launches"]
         achieved = b_min / (avg_ms / 1000) / 1e9
         model_bytes = leaf_model_bytes(e["rows"], e["elements"]) / e["launches"]
         kernel = KERNEL_OF_SCOPE["leaf_aggregate"]
@@ -248,14 +255,17 @@ def main():
         if summary and (args.scale, args.samples_log2) == (22, 26) and (head_policy != "plain" or args.layout == "plain"):
             from paper_1708_07859_amd import profiling
             path = os.path.join(ROOT, "profiles", summary)
-            traffic = profiling.read_traffic(path, kernel)
-            t_top = profiling.read_traffic(path, kernel + "_top")
-            if traffic is not None and t_top is not None:
-                traffic += t_top
+            # every launch of the leaf that ran needs its counters
+            parts = [profiling.read_traffic(path, kernel)]
+            for scope, name in (("leaf_top", kernel + "_top"), ("leaf_merge", "k_leaf2_merge")):
+                if scope in prof:
+                    parts.append(profiling.read_traffic(path, name))
+            traffic = None if any(x is None for x in parts) else sum(parts)
         roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
                 "avg_launch_ms": round(avg_ms, 4), "top_bucket_ms": round(top["total_ms"] / e["launches"], 4),
+                "merge_ms": round(prof.get("leaf_merge", {"total_ms": 0.0})["total_ms"] / e["launches"], 4),
                 "alg_bytes_per_launch": int(b_min),
                 "alg_bytes": "minimum bytes: 4 B per wedge (S(b) streamed per edge) + 4 B per edge (T(a) once) + "
                              "8 B per vertex (offsets)",
@@ -455,7 +465,8 @@ def measure_batch(args, lh, torch, synth):
 
     legs, digests, orders = {}, {}, {}
     alg = None
-    for policy in ("plain", "learned"):
+    policies = [p for p in args.batch_policies.split(",") if p]
+    for policy in policies:
         if policy == "learned":
             from paper_1708_07859_amd import learned as L
             lm, om, _ = L.load(args.weights or L.DEFAULT_WEIGHTS)
@@ -477,17 +488,18 @@ def measure_batch(args, lh, torch, synth):
         for r in rs:
             r.free()
         torch.cuda.synchronize()
-        gc.collect()
-        gc.disable()
-        seq = []
-        for _ in range(max(1, args.steps // 2)):
-            t0 = time.perf_counter()
-            for p in plans:
-                lh.join_aggregate([p])[0].free()
-            torch.cuda.synchronize()
-            seq.append((time.perf_counter() - t0) * 1000)
-        gc.enable()
-        legs[(policy, "sequential")] = min(seq)
+        if not args.no_sequential:
+            gc.collect()
+            gc.disable()
+            seq = []
+            for _ in range(max(1, args.steps // 2)):
+                t0 = time.perf_counter()
+                for p in plans:
+                    lh.join_aggregate([p])[0].free()
+                torch.cuda.synchronize()
+                seq.append((time.perf_counter() - t0) * 1000)
+            gc.enable()
+            legs[(policy, "sequential")] = min(seq)
         # batched: the first call builds, tunes and captures; then replays
         t0 = time.perf_counter()
         rs = lh.join_aggregate(plans)
@@ -512,7 +524,7 @@ def measure_batch(args, lh, torch, synth):
         lh.profile_enable(False)
         gc.enable()
         prof = lh.profile_read()
-        log(f"[batch {policy}] orders {orders[policy]}; sequential {legs[(policy, 'sequential')]:.1f} ms, "
+        log(f"[batch {policy}] orders {orders[policy]}; sequential {legs.get((policy, 'sequential'), 0):.1f} ms, "
             f"batched {legs[(policy, 'batched')]:.1f} ms (first call {first_s:.1f} s)")
         for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]:
             log(f"  {k:22s} launches={v['launches']:6d} total={v['total_ms']:9.3f} ms")
@@ -523,7 +535,14 @@ def measure_batch(args, lh, torch, synth):
         if policy == "learned":
             lh.use_model(lh.LH_MODEL_LAYOUT, None)
             lh.use_model(lh.LH_MODEL_ORDER, None)
-    assert len({d for d, _ in digests.values()}) == 1, "the four ways disagree"
+    assert len({d for d, _ in digests.values()}) == 1, "the ways disagree"
+    if ("learned", "batched") not in legs or ("plain", "sequential") not in legs:
+        res = {"workload": f"{args.instances} SpMV/SpGEMM instances (cfg4)",
+               "ms": {f"{p}_{w}": round(v, 3) for (p, w), v in legs.items()},
+               "tuples_per_s": {f"{p}_{w}": tuples / (v / 1000) for (p, w), v in legs.items()},
+               "alg_bytes": alg, "input_tuples": tuples}
+        log(f"batch: {res}")
+        return res
     lb, ps = legs[("learned", "batched")], legs[("plain", "sequential")]
     res = {"workload": f"{args.instances} SpMV/SpGEMM instances, n log-uniform [1k,64k], Zipf(1.1) degrees "
                        "mean 16, FP64 U(-1,1) (cfg4)",
@@ -818,9 +837,10 @@ def bench_intersect(args, lh, torch, synth):
         torch.cuda.synchronize()
         lh.profile_enable(False)
         prof = lh.profile_read()
-        # the leaf: its main launch and, for pairs of 2^14 elements or more,
-        # the top-bucket launch
-        ms = sum(prof[k]["total_ms"] for k in ("leaf_aggregate", "leaf_top") if k in prof) / args.steps
+        # the leaf: its main launch, the top-bucket launch (pairs of 2^14
+        # elements or more) and the merge launch (two sorted sets of 2^12
+        # elements or more, sizes within a factor of 4)
+        ms = sum(prof[k]["total_ms"] for k in LEAF_SCOPES if k in prof) / args.steps
         per_pair = {("uint", "uint"): 8 * c, ("uint", "bitset"): 4 * c + U / 8,
                     ("bitset", "bitset"): 2 * U / 8}[(la, lb)]
         alg = per_pair * npairs
@@ -1340,6 +1360,13 @@ def bench_batch(args, lh, torch, synth):
     """The batched workload on its own: the four ways of measure_batch,
     reported as the learned + batched throughput."""
     res = measure_batch(args, lh, torch, synth)
+    if "learned_batched_over_plain_sequential" not in res:
+        key = next(k for k in res["ms"] if k.endswith("batched"))
+        print(json.dumps({"metric": METRIC, "value": res["tuples_per_s"][key], "unit": "tuples/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms"][key],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": res}), flush=True)
+        return
     lb = res["ms"]["learned_batched"]
     out = {
         "metric": METRIC, "value": res["tuples_per_s"]["learned_batched"], "unit": "tuples/s", "n_gpus": 1,

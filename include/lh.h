@@ -266,7 +266,9 @@ typedef struct {
   uint32_t case_prefix;             /* 1: output is a prefix of the order (streamed groups) */
   uint32_t exact_digits;            /* 32-bit digits of the exact accumulator (0: COUNT) */
   int32_t exact_lsb;                /* exponent of the accumulator's least significant bit */
-  uint32_t level_alg[16];           /* intersection algorithm per attribute position */
+  uint32_t level_alg[16];           /* intersection algorithm per attribute position: 0 probe (the
+                                       two-set leaf may still AND two bitsets or merge two sorted
+                                       sets of similar size, row by row) */
   uint32_t blas;                    /* 1: run as BLAS DGEMV, 2: as DGEMM (LH_DENSE_BLAS), else 0 */
 } lh_plan_info;
 

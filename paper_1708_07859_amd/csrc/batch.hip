@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <filesystem>
 #include <fstream>
 #include <map>
 #include <memory>
@@ -871,8 +872,8 @@ bool load_tuning(const std::string& sig, Tuning& t) {
 
 void save_tuning(const std::string& sig, const Tuning& t) {
   std::string path = cache_path();
-  std::string dir = path.substr(0, path.find_last_of('/'));
-  (void)std::system(("mkdir -p '" + dir + "' 2>/dev/null").c_str());
+  std::error_code ec;  // an unwritable cache only costs the next run a re-tune
+  std::filesystem::create_directories(std::filesystem::path(path).parent_path(), ec);
   std::ofstream f(path, std::ios::app);
   f << sig << " " << t.light_max << " " << t.blocks_per_cu << " " << t.inner_ratio << "\n";
 }

@@ -13,11 +13,13 @@ constexpr int MAXA = 8;    // atoms per query
 constexpr int MAXP = 8;    // participants per attribute
 constexpr int MAXV = 16;   // attributes per query
 
-// Per-level intersection algorithm (chosen per attribute position).
+// Intersection algorithm of an attribute position.  The plan records
+// ALG_PROBE; the two-set leaf refines it per row (k_work): two bitsets may
+// be ANDed word by word, two sorted sets of similar size merged.
 enum LevelAlg : uint32_t {
   ALG_PROBE = 0,   // iterate the smallest set, probe the others (bit test or binary search)
-  ALG_MERGE = 1,   // reserved: merge-path co-iteration of two uint sets
-  ALG_BSAND = 2,   // reserved: word-wise AND of two bitsets
+  ALG_MERGE = 1,   // merge-path co-iteration of two uint sets (two-set leaf, per row)
+  ALG_BSAND = 2,   // word-wise AND of two bitsets (two-set leaf, per row)
 };
 
 struct PlanAtom {

@@ -27,6 +27,25 @@ constexpr int J_NT = 256;          // 4 waves per block, one work unit per wave
 constexpr int J_NW = J_NT / WAVE;
 constexpr int U_IT = 4;            // elements per lane per unit
 constexpr int U_EL = WAVE * U_IT;  // driver elements per unit
+// Two-set leaves: rows whose two sets hold TOP_MIN elements or more
+// together form the top bucket, the largest intersections.  They run as a
+// launch of their own, in units of TOP_IT elements per lane, so that a wave
+// has twice the loads in flight per unit.
+constexpr uint32_t TOP_MIN = 1u << 14;
+constexpr int TOP_IT = 2 * U_IT;
+constexpr int TOP_EL = WAVE * TOP_IT;
+// Rows of two sorted (uint) sets of MERGE_MIN elements or more each, the
+// larger at most MERGE_RATIO times the smaller, are merged instead of
+// probed (the co-iteration of section 4.1.1's balanced case): the merged
+// sequence is cut into tiles of MERGE_TILE elements along its diagonal
+// (merge path), and one block streams a tile's two runs through LDS and
+// counts the equal neighbours.  Both sets are read once, in order.
+constexpr int M_NT = 256;
+constexpr int M_PER = 16;                       // merged elements per thread
+constexpr uint32_t MERGE_TILE = M_NT * M_PER;
+constexpr uint32_t MERGE_MIN = 1u << 12;
+constexpr uint32_t MERGE_RATIO = 4;
+constexpr uint64_t MERGE_GRID = 8192;           // blocks of the merge launch (they loop over tiles)
 
 struct DSet {
   const uint32_t* ppos;   // frontier positions at the previous level (null: root set)
@@ -235,8 +254,17 @@ struct WorkArgs {
 // intersected word by word (AND + popcount over the overlap of their
 // windows); its work is counted in words instead of driver elements.
 constexpr uint8_t DRV_AND = 0xff;
+// Driver value DRV_MERGE: the row's two sorted sets are merged tile by tile
+// (MERGE_TILE merged elements per unit).
+constexpr uint8_t DRV_MERGE = 0xfe;
 
-__global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv, uint32_t* units, uint32_t allow_and) {
+// leaf2: the row's two sets feed the two-set leaf (word-AND and merge
+// allowed; top-bucket rows get units of TOP_EL elements, counted into
+// n_units[0]; merged rows units of MERGE_TILE, counted into n_units[1]).
+__global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv, uint32_t* units, uint32_t leaf2,
+                       unsigned long long* n_units) {
+  __shared__ uint64_t s_red[256 / WAVE];
+  uint64_t top_units = 0, merge_units = 0;
   for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (uint64_t)gridDim.x * blockDim.x) {
     // Driver: the set whose elements are cheapest to stream and probe into
     // the others; probing a bitset costs one word load, probing a sorted
@@ -279,7 +307,17 @@ __global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv,
     }
     if (empty) best = 0;
     uint8_t dv = (uint8_t)bi;
-    if (allow_and && a.np == 2 && !empty) {
+    uint32_t chunk = U_EL;
+    if (leaf2 && a.np == 2 && !empty && probe[0] > 1.0f && probe[1] > 1.0f) {
+      // two sorted sets of similar, large size: merged
+      const uint32_t lo = min(card[0], card[1]), hi = max(card[0], card[1]);
+      if (lo >= MERGE_MIN && (uint64_t)hi <= (uint64_t)MERGE_RATIO * lo) {
+        dv = DRV_MERGE;
+        best = card[0] + card[1];
+        chunk = MERGE_TILE;
+      }
+    }
+    if (leaf2 && a.np == 2 && !empty) {
       // both bitsets: AND the overlapping words when that moves fewer words
       // than the probe path moves elements and probes
       uint32_t b0, e0, b1, e1;
@@ -299,7 +337,17 @@ __global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv,
     }
     work[r] = best;
     drv[r] = dv;
-    units[r] = (best + U_EL - 1) / U_EL;
+    const bool top = leaf2 && a.np == 2 && dv != DRV_MERGE && (uint64_t)card[0] + card[1] >= TOP_MIN;
+    if (top) chunk = TOP_EL;
+    units[r] = (best + chunk - 1) / chunk;
+    if (top) top_units += units[r];
+    if (dv == DRV_MERGE) merge_units += units[r];
+  }
+  if (n_units) {
+    const uint64_t t = block_sum<uint64_t, 256>(top_units, s_red);
+    if (threadIdx.x == 0 && t) atomicAdd(&n_units[0], (unsigned long long)t);
+    const uint64_t m = block_sum<uint64_t, 256>(merge_units, s_red);
+    if (threadIdx.x == 0 && m) atomicAdd(&n_units[1], (unsigned long long)m);
   }
 }
 
@@ -867,20 +915,20 @@ constexpr uint32_t L2_STAGE_RATIO = 8;
 // streams its driver keys and that key range side by side.
 struct UnitDesc {
   uint32_t dstart;   // first driver element (index into the driver's level keys)
-  uint32_t dcount;   // driver elements in this unit (1..U_EL)
+  uint32_t dcount;   // driver elements in this unit (1..U_EL; top bucket 1..TOP_EL)
   uint32_t plo;      // uint: first probed key index; bitset: window base value
   uint32_t phi;      // uint: end of probed keys (UINT32_MAX: next unit's plo); bitset: largest value
   uint64_t pword;    // probed set's first bitset word, or UINT64_MAX (sorted keys)
   uint32_t drv;      // driving participant (0 or 1), or DRV_AND: words [plo | phi << 32, +dcount) of
-                     // participant 0's pool AND words [pword, +dcount) of participant 1's
-  uint32_t top;      // 1: the unit's row is in the top bucket (run by its own launch)
+                     // participant 0's pool AND words [pword, +dcount) of participant 1's; or
+                     // DRV_MERGE: keys [dstart, +dcount) of participant 0 and [plo, +phi) of
+                     // participant 1 form one merge tile, pword = 1 when keys[0][dstart - 1]
+                     // belongs to the row (the tile's look-back element)
+  uint32_t top;      // 1: the unit's row is in the top bucket; 2: a merge tile (each class
+                     // runs as a launch of its own)
 };
 
-// Rows whose two sets hold this many elements together form the top
-// bucket: the largest intersections, run as a launch of their own.
-constexpr uint32_t TOP_MIN = 1u << 14;
-// Leaves with fewer units run in one launch.
-constexpr uint64_t TOP_SPLIT_UNITS = 1u << 16;
+
 
 // First index in [lo, hi) whose value is > x (hi if none).
 __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t x) {
@@ -891,13 +939,28 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t 
   return lo;
 }
 
+// Merge path: the number of elements of the sorted a[0, na) among the
+// first d elements of the merge of a and b[0, nb), where an element of a
+// goes before an equal element of b.  0 <= d <= na + nb.
+__device__ __forceinline__ uint32_t merge_split(const uint32_t* a, uint32_t na, const uint32_t* b, uint32_t nb,
+                                                uint64_t d) {
+  uint32_t lo = d > nb ? (uint32_t)(d - nb) : 0u;
+  uint32_t hi = (uint32_t)min<uint64_t>(d, na);
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if (a[mid] <= b[d - mid - 1]) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 // One thread per unit.  Consecutive units of a row split the driver into
 // chunks of U_EL sorted keys; a chunk can only meet probed keys from the
 // lower bound of its first key up to the lower bound of the next chunk's
-// first key (the last chunk: the upper bound of its last key).  When
-// top_flag is given, units of top-bucket rows are tagged and flagged.
+// first key (the last chunk: the upper bound of its last key).  Units of a
+// merged row are its merge path's tiles.  When top_flag / merge_flag are
+// given, units of top-bucket rows / merge tiles are flagged.
 __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow, const uint8_t* drv, uint64_t units,
-                            UnitDesc* desc, uint32_t* top_flag) {
+                            UnitDesc* desc, uint32_t* top_flag, uint32_t* merge_flag) {
   for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t r = urow[u];
     const uint64_t u0 = U[r], u1 = U[r + 1];
@@ -907,7 +970,28 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
     dset_range(wa.set[1], r, b[1], e[1], sidx[1]);
     const uint32_t d = drv[r];
     UnitDesc t;
-    const bool is_top = top_flag && (uint64_t)(e[0] - b[0]) + (e[1] - b[1]) >= TOP_MIN;
+    if (merge_flag) merge_flag[u] = d == DRV_MERGE ? 1u : 0u;
+    if (d == DRV_MERGE) {
+      const uint32_t na = e[0] - b[0], nb = e[1] - b[1];
+      const uint64_t d0 = (u - u0) * (uint64_t)MERGE_TILE;
+      const uint64_t d1 = min<uint64_t>(d0 + MERGE_TILE, (uint64_t)na + nb);
+      const uint32_t* ka = wa.set[0].keys + b[0];
+      const uint32_t* kb = wa.set[1].keys + b[1];
+      const uint32_t i0 = merge_split(ka, na, kb, nb, d0), i1 = merge_split(ka, na, kb, nb, d1);
+      t.drv = DRV_MERGE;
+      t.dstart = b[0] + i0;
+      t.dcount = i1 - i0;
+      t.plo = b[1] + (uint32_t)(d0 - i0);
+      t.phi = (uint32_t)(d1 - i1) - (uint32_t)(d0 - i0);
+      t.pword = i0 > 0 ? 1u : 0u;
+      t.top = 2;
+      if (top_flag) top_flag[u] = 0;
+      desc[u] = t;
+      continue;
+    }
+    // the row's bucket, as k_work decided it (the units' size follows it)
+    const bool is_top = (uint64_t)(e[0] - b[0]) + (e[1] - b[1]) >= TOP_MIN;
+    const uint32_t chunk = is_top ? TOP_EL : U_EL;
     t.top = is_top ? 1u : 0u;
     if (top_flag) top_flag[u] = t.top;
     if (d == DRV_AND) {
@@ -916,11 +1000,11 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
       const uint32_t v0 = max(base0, base1);
       const uint32_t v1 = min(wa.set[0].keys[e[0] - 1], wa.set[1].keys[e[1] - 1]);
       const uint32_t words = ((v1 - v0) >> 6) + 1;
-      const uint32_t k0 = (uint32_t)(u - u0) * U_EL;
+      const uint32_t k0 = (uint32_t)(u - u0) * chunk;
       const uint64_t w0 = wa.set[0].bs_word[sidx[0]] + ((v0 - base0) >> 6) + k0;
       t.drv = DRV_AND;
       t.dstart = 0;
-      t.dcount = min((uint32_t)U_EL, words - k0);
+      t.dcount = min(chunk, words - k0);
       t.plo = (uint32_t)w0;
       t.phi = (uint32_t)(w0 >> 32);
       t.pword = wa.set[1].bs_word[sidx[1]] + ((v0 - base1) >> 6) + k0;
@@ -936,8 +1020,8 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
     const uint64_t* bsw = d ? wa.set[0].bs_word : wa.set[1].bs_word;
     const uint32_t* bsb = d ? wa.set[0].bs_base : wa.set[1].bs_base;
     t.drv = d;
-    t.dstart = db + (uint32_t)(u - u0) * U_EL;
-    t.dcount = min((uint32_t)U_EL, de - t.dstart);
+    t.dstart = db + (uint32_t)(u - u0) * chunk;
+    t.dcount = min(chunk, de - t.dstart);
     t.pword = (pe > pb) ? bsw[sq] : UINT64_MAX;
     if (t.pword != UINT64_MAX) {
       t.plo = bsb[sq];
@@ -994,42 +1078,42 @@ __global__ void k_group_add(const uint64_t* gstart, const uint64_t* gend, uint64
 // Membership of x[it] (it < nit) in the strictly increasing keys a[0, m),
 // m >= 1: a branchless bisection whose trip count depends on m only, so the
 // probes of a lane's values are issued together.  nit is wave-uniform.
-template <class Arr>
+template <int NIT, class Arr>
 __device__ __forceinline__ uint32_t count_members(Arr a, uint32_t m, const uint32_t* x, const bool* v, uint32_t nit) {
-  uint32_t lo[U_IT];
+  uint32_t lo[NIT];
 #pragma unroll
-  for (int it = 0; it < U_IT; it++) lo[it] = 0;
+  for (int it = 0; it < NIT; it++) lo[it] = 0;
   uint32_t n = m;
   while (n > 1) {
     const uint32_t half = n >> 1;
 #pragma unroll
-    for (int it = 0; it < U_IT; it++)
+    for (int it = 0; it < NIT; it++)
       if (it < (int)nit) lo[it] = (a[lo[it] + half] <= x[it]) ? lo[it] + half : lo[it];
     n -= half;
   }
   uint32_t c = 0;
 #pragma unroll
-  for (int it = 0; it < U_IT; it++)
+  for (int it = 0; it < NIT; it++)
     if (it < (int)nit) c += (v[it] && a[lo[it]] == x[it]) ? 1u : 0u;
   return c;
 }
 
 // Number of entries <= x[it] in the sorted a[0, n), n >= 1, for it < nit:
 // branchless, trip count set by n alone.
-template <class Arr>
+template <int NIT, class Arr>
 __device__ __forceinline__ void count_le(Arr a, uint32_t n0, const uint32_t* x, uint32_t nit, uint32_t* k) {
 #pragma unroll
-  for (int it = 0; it < U_IT; it++) k[it] = 0;
+  for (int it = 0; it < NIT; it++) k[it] = 0;
   uint32_t n = n0;
   while (n > 1) {
     const uint32_t half = n >> 1;
 #pragma unroll
-    for (int it = 0; it < U_IT; it++)
+    for (int it = 0; it < NIT; it++)
       if (it < (int)nit) k[it] = (a[k[it] + half - 1] <= x[it]) ? k[it] + half : k[it];
     n -= half;
   }
 #pragma unroll
-  for (int it = 0; it < U_IT; it++)
+  for (int it = 0; it < NIT; it++)
     if (it < (int)nit) k[it] += (a[k[it]] <= x[it]) ? 1u : 0u;
 }
 
@@ -1058,127 +1142,84 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// A unit's first loads, issued one unit ahead: its driver keys and the first
-// U_IT * WAVE keys of the probed range it stages (when it stages one).
-struct UnitLoads {
-  uint32_t x[U_IT];
-  uint32_t st[U_IT];
-};
-
-// The probed key range [lo, lo + m) a sorted-array unit stages in LDS, or
-// m = 0 when it searches the line samples instead (or probes a bitset).
-__device__ __forceinline__ uint32_t staged_range(const UnitDesc& t, uint32_t next_lo, uint32_t& lo) {
-  lo = t.plo;
-  if (t.drv == DRV_AND || t.pword != UINT64_MAX) return 0;
-  const uint32_t hi = t.phi == UINT32_MAX ? next_lo : t.phi;
-  const uint32_t m = hi - lo;
-  return (m > 0 && m <= (uint32_t)L2_CAP && m <= L2_STAGE_RATIO * t.dcount) ? m : 0u;
-}
-
-__device__ __forceinline__ void issue_unit(const Leaf2Args& a, const UnitDesc& t, uint32_t next_lo, int lane,
-                                           UnitLoads& L) {
-  if (t.drv == DRV_AND) return;
-  const uint32_t* dk = t.drv ? a.keys[1] : a.keys[0];
-#pragma unroll
-  for (int it = 0; it < U_IT; it++) {
-    const uint32_t i = it * WAVE + lane;
-    L.x[it] = i < t.dcount ? dk[t.dstart + i] : 0u;
-  }
-  uint32_t lo;
-  const uint32_t m = staged_range(t, next_lo, lo);
-  if (m) {
-    const uint32_t* pk = t.drv ? a.keys[0] : a.keys[1];
-#pragma unroll
-    for (int it = 0; it < U_IT; it++) {
-      const uint32_t i = it * WAVE + lane;
-      L.st[it] = i < m ? pk[lo + i] : 0u;
-    }
-  }
-}
-
-// Probe path of a unit whose first loads are in L: the unit's driver keys
-// against the probed set's bitset, its LDS-staged keys, or its line samples.
-__device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDesc& t, uint32_t next_lo,
-                                               const UnitLoads& L, uint32_t* stage, int lane) {
+// Probe path of a unit: the unit's driver keys against the probed set's
+// bitset, its LDS-staged keys, or its line samples.
+template <int NIT>
+__device__ __forceinline__ uint32_t probe_unit(const Leaf2Args& a, const UnitDesc& t, uint32_t next_lo, uint32_t* stage,
+                                               int lane) {
   uint32_t c = 0;
+  const uint32_t* dk = t.drv ? a.keys[1] : a.keys[0];
   const uint32_t* pk = t.drv ? a.keys[0] : a.keys[1];
   const uint64_t* pool = t.drv ? a.pool[0] : a.pool[1];
   const uint32_t nit = (t.dcount + WAVE - 1) / WAVE;
-  uint32_t x[U_IT];
-  bool v[U_IT];
+  uint32_t x[NIT];
+  bool v[NIT];
 #pragma unroll
-  for (int it = 0; it < U_IT; it++) {
+  for (int it = 0; it < NIT; it++) {
     const uint32_t i = it * WAVE + lane;
     v[it] = i < t.dcount;
-    x[it] = L.x[it];
+    x[it] = v[it] ? dk[t.dstart + i] : 0u;
   }
   if (t.pword != UINT64_MAX) {
 #pragma unroll
-    for (int it = 0; it < U_IT; it++) {
+    for (int it = 0; it < NIT; it++) {
       if (!v[it] || x[it] < t.plo || x[it] > t.phi) continue;
       const uint32_t dd = x[it] - t.plo;
       c += (uint32_t)((pool[t.pword + (dd >> 6)] >> (dd & 63u)) & 1ull);
     }
-    return c;
-  }
-  uint32_t lo;
-  const uint32_t ms = staged_range(t, next_lo, lo);
-  if (ms) {
-    // the first U_IT * WAVE keys arrived with the unit's first loads
-#pragma unroll
-    for (int it = 0; it < U_IT; it++) {
-      const uint32_t i = it * WAVE + lane;
-      if (i < ms) stage[i] = L.st[it];
-    }
-    if (ms > (uint32_t)(U_IT * WAVE)) wave_stage(stage + U_IT * WAVE, pk + lo + U_IT * WAVE, ms - U_IT * WAVE, lane);
-    wave_lds_sync();
-    c = count_members(stage, ms, x, v, nit);
-    wave_lds_sync();
-    return c;
-  }
-  const uint32_t hi = t.phi == UINT32_MAX ? next_lo : t.phi;
-  if (hi <= lo) return 0;
-  // A large range: bisect the line samples inside it (staged in LDS
-  // when they fit), then search the one line that can hold x.
-  // Samples j in [jf, jl] start lines inside [lo, hi); keys before
-  // the first of them belong to the range's first, partial line.
-  const uint32_t* sp = t.drv ? a.samp[0] : a.samp[1];
-  const uint32_t jf = (lo + (1u << LINE_SHIFT) - 1) >> LINE_SHIFT;
-  const uint32_t jl = (hi - 1) >> LINE_SHIFT;
-  uint32_t k[U_IT];
-#pragma unroll
-  for (int it = 0; it < U_IT; it++) k[it] = 0;
-  if (jl >= jf) {
-    const uint32_t ns = jl - jf + 1;
-    if (ns <= (uint32_t)L2_CAP) {
-      wave_stage(stage, sp + jf, ns, lane);
+  } else {
+    const uint32_t lo = t.plo;
+    const uint32_t hi = t.phi == UINT32_MAX ? next_lo : t.phi;
+    const uint32_t m = hi - lo;
+    if (m > 0 && m <= (uint32_t)L2_CAP && m <= L2_STAGE_RATIO * t.dcount) {
+      wave_stage(stage, pk + lo, m, lane);
       wave_lds_sync();
-      count_le(stage, ns, x, nit, k);
+      c = count_members<NIT>(stage, m, x, v, nit);
       wave_lds_sync();
-    } else {
-      count_le(sp + jf, ns, x, nit, k);
-    }
-  }
-  uint32_t pos[U_IT], len[U_IT];
+    } else if (m > 0) {
+      // A large range: bisect the line samples inside it (staged in LDS
+      // when they fit), then search the one line that can hold x.
+      // Samples j in [jf, jl] start lines inside [lo, hi); keys before
+      // the first of them belong to the range's first, partial line.
+      const uint32_t* sp = t.drv ? a.samp[0] : a.samp[1];
+      const uint32_t jf = (lo + (1u << LINE_SHIFT) - 1) >> LINE_SHIFT;
+      const uint32_t jl = (hi - 1) >> LINE_SHIFT;
+      uint32_t k[NIT];
 #pragma unroll
-  for (int it = 0; it < U_IT; it++) {
-    const uint32_t sb = k[it] ? (jf + k[it] - 1) << LINE_SHIFT : lo;
-    const uint32_t se = (uint32_t)min<uint64_t>(hi, (uint64_t)(jf + k[it]) << LINE_SHIFT);
-    pos[it] = sb;
-    len[it] = se > sb ? se - sb : 0;
-  }
+      for (int it = 0; it < NIT; it++) k[it] = 0;
+      if (jl >= jf) {
+        const uint32_t ns = jl - jf + 1;
+        if (ns <= (uint32_t)L2_CAP) {
+          wave_stage(stage, sp + jf, ns, lane);
+          wave_lds_sync();
+          count_le<NIT>(stage, ns, x, nit, k);
+          wave_lds_sync();
+        } else {
+          count_le<NIT>(sp + jf, ns, x, nit, k);
+        }
+      }
+      uint32_t pos[NIT], len[NIT];
 #pragma unroll
-  for (int step = 0; step < (int)LINE_SHIFT; step++)
-#pragma unroll
-    for (int it = 0; it < U_IT; it++)
-      if (it < (int)nit && len[it] > 1) {
-        const uint32_t half = len[it] >> 1;
-        pos[it] = (pk[pos[it] + half] <= x[it]) ? pos[it] + half : pos[it];
-        len[it] -= half;
+      for (int it = 0; it < NIT; it++) {
+        const uint32_t sb = k[it] ? (jf + k[it] - 1) << LINE_SHIFT : lo;
+        const uint32_t se = (uint32_t)min<uint64_t>(hi, (uint64_t)(jf + k[it]) << LINE_SHIFT);
+        pos[it] = sb;
+        len[it] = se > sb ? se - sb : 0;
       }
 #pragma unroll
-  for (int it = 0; it < U_IT; it++)
-    if (it < (int)nit) c += (v[it] && len[it] > 0 && pk[pos[it]] == x[it]) ? 1u : 0u;
+      for (int step = 0; step < (int)LINE_SHIFT; step++)
+#pragma unroll
+        for (int it = 0; it < NIT; it++)
+          if (it < (int)nit && len[it] > 1) {
+            const uint32_t half = len[it] >> 1;
+            pos[it] = (pk[pos[it] + half] <= x[it]) ? pos[it] + half : pos[it];
+            len[it] -= half;
+          }
+#pragma unroll
+      for (int it = 0; it < NIT; it++)
+        if (it < (int)nit) c += (v[it] && len[it] > 0 && pk[pos[it]] == x[it]) ? 1u : 0u;
+    }
+  }
   return c;
 }
 
@@ -1196,9 +1237,9 @@ __device__ __forceinline__ UnitDesc load_desc(CDesc d, uint64_t u) {
   return t;
 }
 
-// LIST = false runs every unit but those of the top bucket; LIST = true
-// runs the top bucket's units, listed in a.list.
-template <bool LIST>
+// LIST = false runs every unit but those of the top bucket (NIT = NIT);
+// LIST = true runs the top bucket's units, listed in a.list (NIT = TOP_IT).
+template <bool LIST, int NIT>
 __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
   __shared__ uint32_t s_stage[J_NW][L2_CAP];
   __shared__ unsigned long long s_cnt;
@@ -1214,57 +1255,38 @@ __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
   // descriptors are read-only here: read through the constant address space
   const CDesc desc = (CDesc)a.desc;
   auto unit_of = [&](uint64_t i) -> uint64_t { return LIST ? (uint64_t)a.list[i] : i; };
-  // Software pipeline: a unit's first loads are issued one unit ahead, so
-  // each wave keeps two units' loads in flight; descriptors are loaded two
-  // units ahead.  (cur: the unit whose loads are in flight; nxt: the one
-  // after it, whose descriptor is arriving.)
-  const uint64_t G = gridDim.x;
+  UnitDesc nt{};
+  uint64_t nu = 0;
+  uint32_t nlo = 0;
   const uint64_t vb0 = xcd_block(blockIdx.x, gridDim.x);
-  auto valid = [&](uint64_t vb) { return vb < a.nvblk && vb * J_NW + w < a.units; };
-  UnitDesc cd{}, nd{};
-  uint64_t cu = 0, nu = 0;
-  uint32_t clo = 0, nlo = 0;
-  UnitLoads cl{};
-  if (valid(vb0)) {
-    cu = unit_of(vb0 * J_NW + w);
-    cd = load_desc(desc, cu);
-    clo = (cu + 1 < a.n_desc) ? desc[cu + 1].plo : 0u;
-    if (LIST || !cd.top) issue_unit(a, cd, clo, lane, cl);
-  }
-  if (valid(vb0 + G)) {
-    nu = unit_of((vb0 + G) * J_NW + w);
-    nd = load_desc(desc, nu);
+  if (vb0 < a.nvblk && vb0 * J_NW + w < a.units) {
+    nu = unit_of(vb0 * J_NW + w);
+    nt = load_desc(desc, nu);
     nlo = (nu + 1 < a.n_desc) ? desc[nu + 1].plo : 0u;
   }
-  for (uint64_t vb = vb0; vb < a.nvblk; vb += G) {
-    const bool here = valid(vb);
-    const uint64_t u = cu;
-    const UnitDesc t = cd;
-    const uint32_t next_lo = clo;
-    const UnitLoads L = cl;
-    if (valid(vb + G)) {
-      cu = nu;
-      cd = nd;
-      clo = nlo;
-      if (LIST || !cd.top) issue_unit(a, cd, clo, lane, cl);
-      if (valid(vb + 2 * G)) {
-        nu = unit_of((vb + 2 * G) * J_NW + w);
-        nd = load_desc(desc, nu);
-        nlo = (nu + 1 < a.n_desc) ? desc[nu + 1].plo : 0u;
-      }
+  for (uint64_t vb = vb0; vb < a.nvblk; vb += gridDim.x) {
+    const uint64_t i = vb * J_NW + w;
+    const uint64_t u = nu;
+    const UnitDesc t = nt;
+    const uint32_t next_lo = nlo;
+    const uint64_t in = (vb + gridDim.x) * J_NW + w;
+    if (vb + gridDim.x < a.nvblk && in < a.units) {
+      nu = unit_of(in);
+      nt = load_desc(desc, nu);
+      nlo = (nu + 1 < a.n_desc) ? desc[nu + 1].plo : 0u;
     }
-    if (!here) continue;             // wave-uniform; no barrier inside the loop
+    if (i >= a.units) continue;      // wave-uniform; no barrier inside the loop
     if (!LIST && t.top) continue;    // the top bucket's own launch runs it
     uint32_t c = 0;
     if (t.drv == DRV_AND) {
       const uint64_t w0 = (uint64_t)t.plo | ((uint64_t)t.phi << 32);
 #pragma unroll
-      for (int it = 0; it < U_IT; it++) {
+      for (int it = 0; it < NIT; it++) {
         const uint32_t k = it * WAVE + lane;
         if (k < t.dcount) c += (uint32_t)__popcll(a.pool[0][w0 + k] & a.pool[1][t.pword + k]);
       }
     } else {
-      c = probe_unit(a, t, next_lo, L, stage, lane);
+      c = probe_unit<NIT>(a, t, next_lo, stage, lane);
     }
     if (a.ucnt) {
       // grouped: one count per unit; groups are summed by a scan afterwards
@@ -1281,6 +1303,137 @@ __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
     __syncthreads();
     if (tid == 0 && s_cnt) atomicAdd((unsigned long long*)&a.gcount[0], s_cnt);
   }
+}
+
+// A merge tile, listed in launch order: keys [a0, a0 + na) of participant
+// 0 and [b0, b0 + nb) of participant 1; back = 1 when keys[0][a0 - 1] is
+// in the row (the tile's look-back element); unit = the unit it belongs to.
+struct MergeTile {
+  uint32_t a0, na, b0, nb, back, unit, pad0, pad1;
+};
+constexpr int MT_WORDS = sizeof(MergeTile) / 4;
+static_assert(MT_WORDS == 8, "a merge tile is read as 8 words, one per lane");
+
+__global__ void k_merge_tiles(const UnitDesc* desc, const uint32_t* list, uint64_t n, MergeTile* out) {
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = list[j];
+    const UnitDesc t = desc[u];
+    MergeTile m{};
+    m.a0 = t.dstart;
+    m.na = t.dcount;
+    m.b0 = t.plo;
+    m.nb = t.phi;
+    m.back = (uint32_t)t.pword;
+    m.unit = u;
+    out[j] = m;
+  }
+}
+
+// Merge tiles: each block runs one contiguous range of the tile list (the
+// ranges of an XCD's blocks are contiguous too, so tiles of one row share
+// an L2).  A tile's run of participant 0's keys, after its look-back
+// element, and its run of participant 1's keys are staged in LDS; thread k
+// finds where merged position k * M_PER falls in the two runs (a merge-path
+// search in LDS) and walks M_PER merged positions from there.  In the merge
+// an element of set 0 goes before an equal one of set 1, so every common
+// value shows up as a set-1 element whose merged predecessor from set 0 is
+// equal; the tile's first set-1 elements compare with the look-back
+// element.  The next tile's keys are loaded into registers while the
+// current one is counted, and the tile after that is described by a vector
+// load of one word per lane, which the LDS waits do not wait for.
+__global__ __launch_bounds__(M_NT) void k_leaf2_merge(Leaf2Args a, const MergeTile* tiles, uint64_t n_tiles) {
+  __shared__ uint32_t s_t[MERGE_TILE + 1];
+  __shared__ uint64_t s_red[M_NT / WAVE];
+  const int tid = threadIdx.x, lane = lane_id();
+  const uint64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
+  const uint64_t k0 = lb * per, k1 = min<uint64_t>(n_tiles, k0 + per);
+  if (k0 >= k1) return;  // block-uniform, before any barrier
+  uint64_t run = 0;
+  uint32_t r[M_PER + 1];
+  auto tile_word = [&](uint64_t k) -> uint32_t {
+    return (k < k1 && lane < MT_WORDS) ? reinterpret_cast<const uint32_t*>(tiles + k)[lane] : 0u;
+  };
+  auto unpack = [&](uint32_t w) -> MergeTile {
+    MergeTile m;
+    m.a0 = __builtin_amdgcn_readlane(w, 0);
+    m.na = __builtin_amdgcn_readlane(w, 1);
+    m.b0 = __builtin_amdgcn_readlane(w, 2);
+    m.nb = __builtin_amdgcn_readlane(w, 3);
+    m.back = __builtin_amdgcn_readlane(w, 4);
+    m.unit = __builtin_amdgcn_readlane(w, 5);
+    m.pad0 = m.pad1 = 0;
+    return m;
+  };
+  // keys of a tile into r: slot 0 the look-back element, then set 0's run,
+  // then set 1's run
+  auto fetch = [&](const MergeTile& m) {
+    const uint32_t n1 = m.na + 1, n = n1 + m.nb;
+    const uint32_t* A = a.keys[0] + m.a0;
+    const uint32_t* B = a.keys[1] + m.b0;
+#pragma unroll
+    for (int k = 0; k <= M_PER; k++) {
+      const uint32_t q = (uint32_t)k * M_NT + (uint32_t)tid;
+      uint32_t v = 0;
+      if (q == 0) v = m.back ? A[-1] : 0u;
+      else if (q < n1) v = A[q - 1];
+      else if (q < n) v = B[q - n1];
+      r[k] = v;
+    }
+  };
+  MergeTile t = unpack(tile_word(k0));
+  fetch(t);
+  uint32_t wnext = tile_word(k0 + 1);
+  for (uint64_t k = k0; k < k1; k++) {
+    const MergeTile cur = t;
+    const uint32_t na = cur.na, nb = cur.nb, n1 = na + 1, n = na + nb;
+    __syncthreads();  // the previous tile's readers are done
+#pragma unroll
+    for (int j = 0; j <= M_PER; j++) {
+      const uint32_t q = (uint32_t)j * M_NT + (uint32_t)tid;
+      if (q < n1 + nb) s_t[q] = r[j];
+    }
+    __syncthreads();
+    if (k + 1 < k1) {
+      t = unpack(wnext);
+      fetch(t);
+      wnext = tile_word(k + 2);
+    }
+    uint32_t c = 0;
+    const uint32_t d = (uint32_t)tid * M_PER;
+    if (d < n) {
+      uint32_t lo = d > nb ? d - nb : 0u, hi = min(d, na);
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_t[1 + mid] <= s_t[n1 + d - mid - 1]) lo = mid + 1; else hi = mid;
+      }
+      uint32_t ia = lo, jb = d - lo;
+      bool have = ia > 0 || cur.back != 0;
+      uint32_t prev = s_t[ia];  // set 0's element before position ia (slot 0: the look-back)
+      uint32_t av = ia < na ? s_t[1 + ia] : 0u;
+      uint32_t bv = jb < nb ? s_t[n1 + jb] : 0u;
+      const uint32_t end = min(d + (uint32_t)M_PER, n);
+      for (uint32_t q = d; q < end; q++) {
+        if (ia < na && (jb >= nb || av <= bv)) {
+          prev = av;
+          have = true;
+          ia++;
+          av = ia < na ? s_t[1 + ia] : 0u;
+        } else {
+          c += (have && prev == bv) ? 1u : 0u;
+          jb++;
+          bv = jb < nb ? s_t[n1 + jb] : 0u;
+        }
+      }
+    }
+    const uint64_t sc = block_sum<uint64_t, M_NT>((uint64_t)c, s_red);
+    if (a.ucnt) {
+      if (tid == 0) a.ucnt[cur.unit] = sc;
+    } else {
+      run += sc;
+    }
+  }
+  if (!a.ucnt && tid == 0 && run) atomicAdd((unsigned long long*)&a.gcount[0], (unsigned long long)run);
 }
 
 // ---- finalization ------------------------------------------------------------
@@ -1494,13 +1647,14 @@ DSet make_dset(const lh_plan_t* p, const Participant& pt, const Frontier& F) {
 // cut of every row into work units of U_EL elements.
 struct DepthWork {
   DBuf<uint64_t> W, U;
+  DBuf<uint64_t> n_top;     // two-set leaves: units of the top bucket, then of merged rows (device)
   DBuf<uint8_t> drv;
   DBuf<uint32_t> urow;
   uint64_t total = 0, units = 0, nblk = 0;
 };
 
 void depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs& a, DepthWork& dw, hipStream_t s,
-                bool allow_and = false) {
+                bool leaf2 = false) {
   const auto& parts = p->parts[d];
   WorkArgs wa{};
   wa.np = (uint32_t)parts.size();
@@ -1515,7 +1669,12 @@ void depth_work(const lh_plan_t* p, uint32_t d, const Frontier& F, ElemArgs& a, 
   dw.U.alloc(F.n + 1, s);
   {
     ProfScope ps("join_work", s, F.n, 0);
-    k_work<<<grid_for(F.n), 256, 0, s>>>(wa, F.n, work.p, dw.drv.p, units.p, allow_and ? 1u : 0u);
+    if (leaf2) {
+      dw.n_top.alloc(2, s);
+      fill_u64(dw.n_top.p, 0, 2, s);
+    }
+    k_work<<<grid_for(F.n), 256, 0, s>>>(wa, F.n, work.p, dw.drv.p, units.p, leaf2 ? 1u : 0u,
+                                         leaf2 ? (unsigned long long*)dw.n_top.p : nullptr);
   }
   LH_HIP(hipGetLastError());
   dw.total = scan_u32_to_u64(work.p, dw.W.p, F.n, s);
@@ -2042,21 +2201,29 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         wa.np = 2;
         wa.set[0] = a.set[0];
         wa.set[1] = a.set[1];
-        // large leaves run their top bucket (rows whose two sets hold
-        // TOP_MIN elements or more) as a launch of its own
-        const bool split = dw.units >= TOP_SPLIT_UNITS;
-        DBuf<uint32_t> top_flag(split ? dw.units : 0, s);
+        // the top bucket (rows whose two sets hold TOP_MIN elements or
+        // more, in units of TOP_EL) and the merged rows each run as a launch
+        // of their own
+        struct UnitCounts {
+          uint64_t top, merge;
+        };
+        const UnitCounts nu = read_scalar(reinterpret_cast<const UnitCounts*>(dw.n_top.p), s);
+        const bool split = nu.top != 0, merged = nu.merge != 0;
+        DBuf<uint32_t> top_flag(split ? dw.units : 0, s), merge_flag(merged ? dw.units : 0, s);
         {
           ProfScope ps("leaf_units", s, dw.units, 0);
           k_unit_desc<<<grid_for(dw.units), 256, 0, s>>>(wa, dw.U.p, dw.urow.p, dw.drv.p, dw.units, desc.p,
-                                                          split ? top_flag.p : nullptr);
+                                                          split ? top_flag.p : nullptr,
+                                                          merged ? merge_flag.p : nullptr);
         }
         LH_HIP(hipGetLastError());
-        // the top bucket's units in unit order, so that units of one row run
+        // each class's units in unit order, so that units of one row run
         // close together (and share the L2) as they do in the main launch
-        DBuf<uint32_t> top_list(split ? dw.units : 0, s);
+        DBuf<uint32_t> top_list(split ? dw.units : 0, s), merge_list(merged ? dw.units : 0, s);
         const uint64_t top_units = split ? select_flagged(top_flag.p, dw.units, top_list.p, s) : 0u;
+        const uint64_t merge_units = merged ? select_flagged(merge_flag.p, dw.units, merge_list.p, s) : 0u;
         top_flag.reset();
+        merge_flag.reset();
         Leaf2Args l2{};
         l2.keys[0] = a.set[0].keys;
         l2.keys[1] = a.set[1].keys;
@@ -2073,7 +2240,7 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         l2.ucnt = ucnt.p;
         {
           ProfScope ps("leaf_aggregate", s, F.n, total);
-          k_leaf2_count<false><<<leaf_grid(nblk), J_NT, 0, s>>>(l2);
+          k_leaf2_count<false, U_IT><<<leaf_grid(nblk), J_NT, 0, s>>>(l2);
         }
         LH_HIP(hipGetLastError());
         if (top_units) {
@@ -2082,7 +2249,16 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
           lt.units = top_units;
           lt.nvblk = (top_units + J_NW - 1) / J_NW;
           ProfScope ps("leaf_top", s, top_units, 0);
-          k_leaf2_count<true><<<leaf_grid(lt.nvblk), J_NT, 0, s>>>(lt);
+          k_leaf2_count<true, TOP_IT><<<leaf_grid(lt.nvblk), J_NT, 0, s>>>(lt);
+        }
+        LH_HIP(hipGetLastError());
+        if (merge_units) {
+          DBuf<MergeTile> tiles(merge_units, s);
+          k_merge_tiles<<<grid_for(merge_units), 256, 0, s>>>(desc.p, merge_list.p, merge_units, tiles.p);
+          LH_HIP(hipGetLastError());
+          ProfScope ps("leaf_merge", s, merge_units, 0);
+          k_leaf2_merge<<<(unsigned)std::min<uint64_t>(merge_units, MERGE_GRID), M_NT, 0, s>>>(l2, tiles.p,
+                                                                                          merge_units);
         }
         LH_HIP(hipGetLastError());
         if (L.gid) {

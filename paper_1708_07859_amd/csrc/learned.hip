@@ -201,10 +201,18 @@ void order_features(const Hypergraph& h, const std::vector<uint32_t>& order, flo
   }
 }
 
+// The model overrides the plain rule's order only when it predicts the
+// override to be faster by at least this much (log2 of a time ratio, so
+// 2^0.5 = 1.41x): about its root-mean-square error on its training set.
+// Below that the predicted gain is within the model's own noise.
+constexpr float LEARNED_ORDER_MARGIN = 0.5f;
+
 // The learned order: every candidate the plain search considers, scored
-// by the registered order model; false when no model is registered.
-bool learned_order(const Hypergraph& h, const std::vector<uint32_t>& out_attrs, std::vector<uint32_t>& order,
-                   hipStream_t s) {
+// by the registered order model; the plain rule's order (plain) stays
+// unless the model's best beats it by LEARNED_ORDER_MARGIN.  False when no
+// model is registered.
+bool learned_order(const Hypergraph& h, const std::vector<uint32_t>& out_attrs, const std::vector<uint32_t>& plain,
+                   std::vector<uint32_t>& order, hipStream_t s) {
   const Mlp* m = registered_model(MODEL_ORDER);
   if (!m || h.n_attrs > 8) return false;
   const uint32_t n = h.n_attrs;
@@ -227,13 +235,16 @@ bool learned_order(const Hypergraph& h, const std::vector<uint32_t>& out_attrs, 
       cands.push_back(sw);
     }
   } while (std::next_permutation(perm.begin(), perm.end()));
+  size_t ip = 0;
+  while (ip < cands.size() && cands[ip] != plain) ip++;
+  if (ip == cands.size()) cands.push_back(plain);
   std::vector<float> X(cands.size() * ORDER_FEATURES), y(cands.size());
   for (size_t c = 0; c < cands.size(); c++) order_features(h, cands[c], X.data() + c * ORDER_FEATURES);
   m->predict(X.data(), y.data(), cands.size(), true, s);
   size_t best = 0;
   for (size_t c = 1; c < cands.size(); c++)
     if (y[c] < y[best] || (y[c] == y[best] && cands[c] < cands[best])) best = c;
-  order = cands[best];
+  order = (y[ip] - y[best] >= LEARNED_ORDER_MARGIN) ? cands[best] : plain;
   return true;
 }
 

@@ -1,12 +1,14 @@
 // The learned cost model's network: a 3-layer perceptron d_in -> H -> H -> 1
 // with ReLU, trained in FP32 (forward, backward, Adam) and evaluated in
-// BF16 for inference.  It predicts log2 of a cost (time) from features.
+// BF16 on the matrix cores for inference.  It predicts log2 of a cost
+// (time) from features.
 //
 // Parameters are packed as [W1 (H x d_in), b1 (H), W2 (H x H), b2 (H),
 // W3 (1 x H), b3 (1)], row-major, fp32.
 //
 // Training kernels compute one output per thread with a sequential sum, so
 // a training run is deterministic.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -99,46 +101,109 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// One thread per sample: weights and activations in bf16, products summed
-// in fp32, every layer's output rounded to bf16.  DP is a compile-time
-// bound on the input width so that all activations stay in registers.
-template <int DP>
-__global__ __launch_bounds__(256) void k_mlp_bf16(const uint16_t* wts, uint32_t din, const float* X, float* y,
-                                                  uint64_t n) {
+// ---- BF16 inference on the matrix cores -------------------------------------------
+// One wave evaluates 16 samples at a time with v_mfma_f32_16x16x32_bf16
+// (D[16x16] += A[16x32] B[32x16], bf16 operands, fp32 sums).  Operand
+// layouts (lane l, 64 lanes): A holds row l%16 at k = 8(l/16)..+7; B holds
+// column l%16 at k = 8(l/16)..+7; D holds column l%16 at rows 4(l/16)..+3.
+// Layer 1 is X (16 x d_in <= 32) times W1^T in four 16-column blocks; its
+// outputs (bias, ReLU, rounded to bf16) go through LDS into layer 2's A
+// layout; layer 2 takes two 32-wide k steps per block; the output layer is a
+// dot product per sample, reduced over the 16 lanes of a column group.  The
+// arithmetic is the one-thread kernel's (bf16 operands and layer outputs,
+// exact products, fp32 sums) in another summation order.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __bf16 bf16_of(uint16_t h) { return __builtin_bit_cast(__bf16, h); }
+
+constexpr int MF_NT = 256;                // 4 waves per block
+constexpr int MF_TILE = 16;               // samples per wave tile
+
+__global__ __launch_bounds__(MF_NT) void k_mlp_bf16_mfma(const uint16_t* wts, uint32_t din, const float* X, float* y,
+                                                         uint64_t n) {
   constexpr int H = MLP_H;
-  extern __shared__ uint16_t sw[];
-  const uint64_t np = (uint64_t)H * din + H + (uint64_t)H * H + H + H + 1;
-  for (uint64_t i = threadIdx.x; i < np; i += blockDim.x) sw[i] = wts[i];
-  __syncthreads();
-  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const uint16_t* W1 = sw;
-  const uint16_t* b1 = W1 + (uint64_t)H * din;
-  const uint16_t* W2 = b1 + H;
-  const uint16_t* b2 = W2 + (uint64_t)H * H;
-  const uint16_t* W3 = b2 + H;
-  const uint16_t* b3 = W3 + H;
-  float x[DP];
+  __shared__ uint16_t s_h1[MF_NT / WAVE][MF_TILE * H];
+  const int lane = lane_id();
+  const int wv = threadIdx.x / WAVE;
+  const int col = lane % 16, grp = lane / 16;
+  const uint16_t* W1 = wts;
+  const uint16_t* B1 = W1 + (uint64_t)H * din;
+  const uint16_t* W2 = B1 + H;
+  const uint16_t* B2 = W2 + (uint64_t)H * H;
+  const uint16_t* W3 = B2 + H;
+  const uint16_t* B3 = W3 + H;
+  // B operands and biases, held for the whole kernel
+  bf16x8 w1[4], w2[4][2];
+  float b1[4], b2[4], w3[4];
 #pragma unroll
-  for (int i = 0; i < DP; i++) x[i] = (i < (int)din) ? from_bf16(to_bf16(X[s * din + i])) : 0.0f;
-  float h1[H];
+  for (int nb = 0; nb < 4; nb++) {
+    const int o = 16 * nb + col;
 #pragma unroll
-  for (int o = 0; o < H; o++) {
-    float z = from_bf16(b1[o]);
-#pragma unroll
-    for (int i = 0; i < DP; i++)
-      if (i < (int)din) z = fmaf(x[i], from_bf16(W1[o * din + i]), z);
-    h1[o] = from_bf16(to_bf16(fmaxf(z, 0.0f)));
+    for (int j = 0; j < 8; j++) {
+      const uint32_t k = 8 * grp + j;
+      w1[nb][j] = bf16_of(k < din ? W1[(uint64_t)o * din + k] : (uint16_t)0);
+      w2[nb][0][j] = bf16_of(W2[(uint64_t)o * H + k]);
+      w2[nb][1][j] = bf16_of(W2[(uint64_t)o * H + 32 + k]);
+    }
+    b1[nb] = from_bf16(B1[o]);
+    b2[nb] = from_bf16(B2[o]);
+    w3[nb] = from_bf16(W3[o]);
   }
-  float out = from_bf16(b3[0]);
-  for (int o = 0; o < H; o++) {
-    float z = from_bf16(b2[o]);
+  const float b3 = from_bf16(B3[0]);
+  uint16_t* h1 = s_h1[wv];
+  const uint64_t tiles = (n + MF_TILE - 1) / MF_TILE;
+  const uint64_t waves = (uint64_t)gridDim.x * (MF_NT / WAVE);
+  for (uint64_t t = (uint64_t)blockIdx.x * (MF_NT / WAVE) + wv; t < tiles; t += waves) {
+    const uint64_t s0 = t * MF_TILE;
+    // layer 1: A = the tile's inputs, rounded to bf16, zero past d_in and n
+    bf16x8 a;
+    const uint64_t sa = s0 + col;
 #pragma unroll
-    for (int i = 0; i < H; i++) z = fmaf(h1[i], from_bf16(W2[o * H + i]), z);
-    const float h2 = from_bf16(to_bf16(fmaxf(z, 0.0f)));
-    out = fmaf(h2, from_bf16(W3[o]), out);
+    for (int j = 0; j < 8; j++) {
+      const uint32_t k = 8 * grp + j;
+      a[j] = bf16_of((sa < n && k < din) ? to_bf16(X[sa * din + k]) : (uint16_t)0);
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1[nb], c, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; j++) h1[(4 * grp + j) * H + 16 * nb + col] = to_bf16(fmaxf(c[j] + b1[nb], 0.0f));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // layer 2: A = h1 in two 32-wide k steps
+    bf16x8 a2[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ks++)
+#pragma unroll
+      for (int j = 0; j < 8; j++) a2[ks][j] = bf16_of(h1[col * H + 32 * ks + 8 * grp + j]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[0], w2[nb][0], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[1], w2[nb][1], c, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const float h2 = from_bf16(to_bf16(fmaxf(c[j] + b2[nb], 0.0f)));
+        part[j] = fmaf(h2, w3[nb], part[j]);
+      }
+    }
+    // output layer: sum the 16 columns of each row group (lanes 16 grp .. +15)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+#pragma unroll
+      for (int d = 8; d > 0; d >>= 1) part[j] += __shfl_xor(part[j], d, 16);
+      const uint64_t sy = s0 + 4 * grp + j;
+      if (col == 0 && sy < n) y[sy] = part[j] + b3;
+    }
   }
-  y[s] = out;
 }
 
 __global__ void k_to_bf16(const float* p, uint16_t* q, uint64_t n) {
@@ -282,11 +347,10 @@ void Mlp::predict_dev(const float* X, float* y, uint64_t n, bool bf16, hipStream
     DBuf<uint16_t> q(np, s);
     LH_HIP(hipMemcpyAsync(p.p, host.data(), np * sizeof(float), hipMemcpyHostToDevice, s));
     k_to_bf16<<<blocks(np), 256, 0, s>>>(p.p, q.p, np);
-    const size_t lds = np * sizeof(uint16_t);
-    if (din <= 4) k_mlp_bf16<4><<<blocks(n), 256, lds, s>>>(q.p, din, X, y, n);
-    else if (din <= 8) k_mlp_bf16<8><<<blocks(n), 256, lds, s>>>(q.p, din, X, y, n);
-    else if (din <= 16) k_mlp_bf16<16><<<blocks(n), 256, lds, s>>>(q.p, din, X, y, n);
-    else k_mlp_bf16<32><<<blocks(n), 256, lds, s>>>(q.p, din, X, y, n);
+    // 16 samples per wave, 4 waves per block; blocks stride over the tiles
+    const uint64_t tiles = (n + MF_TILE - 1) / MF_TILE;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((tiles + 3) / 4, 2048));
+    k_mlp_bf16_mfma<<<grid, MF_NT, 0, s>>>(q.p, din, X, y, n);
     LH_HIP(hipGetLastError());
   } else {
     DBuf<float> p(np, s), Z1(n * H, s), A1(n * H, s), Z2(n * H, s), A2(n * H, s);

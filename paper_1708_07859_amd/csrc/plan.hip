@@ -11,8 +11,8 @@
 
 namespace lh {
 
-bool learned_order(const Hypergraph& h, const std::vector<uint32_t>& out_attrs, std::vector<uint32_t>& order,
-                   hipStream_t s);
+bool learned_order(const Hypergraph& h, const std::vector<uint32_t>& out_attrs, const std::vector<uint32_t>& plain,
+                   std::vector<uint32_t>& order, hipStream_t s);
 
 namespace {
 
@@ -244,11 +244,14 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
       order[i] = v;
     }
     p->cost = order_cost(h, order, nullptr, nullptr);
-  } else if ((q->policy & LH_POLICY_MASK) == LH_POLICY_LEARNED && learned_order(learned_view(q, h, filt, s),
-                                                                                 p->out_attrs, order, s)) {
-    p->cost = order_cost(h, order, nullptr, nullptr);
   } else {
     p->cost = choose_order(h, p->out_attrs, order);
+    std::vector<uint32_t> learned;
+    if ((q->policy & LH_POLICY_MASK) == LH_POLICY_LEARNED &&
+        learned_order(learned_view(q, h, filt, s), p->out_attrs, order, learned, s) && learned != order) {
+      order = learned;
+      p->cost = order_cost(h, order, nullptr, nullptr);
+    }
   }
   for (uint32_t i = 0; i < q->n_attrs; i++) {
     p->order[i] = order[i];

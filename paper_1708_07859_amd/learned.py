@@ -158,7 +158,12 @@ def _edges_of(query, tries):
         lf_max = [float(np.log2(1 + f)) for f in inf["col_freq_max"]]
         mine = [f for f in query.get("filters", []) if f["atom"] == i]
         card = _selected_rows(a, mine) if mine else len(a["keys"][0])
-        out.append({"attrs": list(a["attrs"]), "card": card, "eq": i in eq_atoms,
+        # a completely dense one-column relation adds no intersection (the
+        # plan drops it from the order's set features the same way)
+        keys0 = np.asarray(a["keys"][0])
+        dense = (inf["n_levels"] == 1 and inf["level_size"][0] > 0 and not mine
+                 and inf["level_size"][0] == int(keys0.max()) + 1)
+        out.append({"attrs": list(a["attrs"]), "card": card, "eq": i in eq_atoms, "dense": dense,
                     "lf_mean": lf_mean, "lf_max": lf_max})
     return out
 

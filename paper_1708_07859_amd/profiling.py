@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = {  # kernel -> source file whose hash stamps its counters
     "k_leaf2_count": os.path.join(HERE, "csrc", "join.hip"),
     "k_leaf2_count_top": os.path.join(HERE, "csrc", "join.hip"),
+    "k_leaf2_merge": os.path.join(HERE, "csrc", "join.hip"),
     "k_elem": os.path.join(HERE, "csrc", "join.hip"),
     "k_lr_cols": os.path.join(HERE, "csrc", "ml.hip"),
     "k_lr_cols_blocked": os.path.join(HERE, "csrc", "ml.hip"),
@@ -31,14 +32,23 @@ def source_hash(kernel):
 
 def read_traffic(path, kernel):
     """HBM bytes per dispatch of `kernel` from a traffic summary, or None
-    when the summary is missing or was taken on a different source."""
+    when the summary is missing, has no block for the kernel, or was taken
+    on a different source.  A summary holds one block per kernel, each
+    opened by its `kernel:` line."""
     if not os.path.exists(path):
         return None
-    kv = {}
+    blocks, kv = [], None
     for line in open(path):
-        if ":" in line:
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
-    if kv.get("kernel") != kernel or kv.get("source_sha256_16") != source_hash(kernel):
-        return None
-    return float(kv["hbm_bytes_per_dispatch"])
+        if ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        k, v = k.strip(), v.strip()
+        if k == "kernel":
+            kv = {}
+            blocks.append(kv)
+        if kv is not None:
+            kv[k] = v.split()[0] if v else ""
+    for kv in blocks:
+        if kv.get("kernel") == kernel and kv.get("source_sha256_16") == source_hash(kernel):
+            return float(kv["hbm_bytes_per_dispatch"])
+    return None

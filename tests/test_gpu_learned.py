@@ -129,16 +129,79 @@ def test_learned_order_is_the_models_argmin_and_exact(lh):
     want = oracle.join_aggregate(q)
     # a model that scores each order by its first position's icost feature
     # (feature 5): any order with icost 0 there is "cheapest"
-    m = lh.Mlp(24, 64, seed=1)
-    H, d = 64, 24
-    W1 = np.zeros((H, d), np.float32); W1[0, 5] = 1.0   # second position's icost
-    W2 = np.zeros((H, H), np.float32); W2[0, 0] = 1.0
-    W3 = np.zeros((1, H), np.float32); W3[0, 0] = 1.0
-    m.set_params(np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), W3.ravel(), [0.0]]))
+    def model(scale):
+        # prediction = scale x the second position's icost feature (feature 5)
+        m = lh.Mlp(24, 64, seed=1)
+        H, d = 64, 24
+        W1 = np.zeros((H, d), np.float32); W1[0, 5] = 1.0
+        W2 = np.zeros((H, H), np.float32); W2[0, 0] = 1.0
+        W3 = np.zeros((1, H), np.float32); W3[0, 0] = scale
+        m.set_params(np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), W3.ravel(), [0.0]]))
+        return m
+    plain = lh.run_query(q, return_plan_info=True)["plan"]["attr_order"]
+    assert plain == [0, 1, 2]
+    m = model(10.0)
     lh.use_model(lh.LH_MODEL_ORDER, m)
     got = lh.run_query(q, policy="learned", return_plan_info=True)
     # candidates: [0,2,1], [0,1,2] (relaxed), [2,0,1], [2,1,0]; second-position
-    # icost is 0 for [0,2,1] and [2,0,1], so the tie goes to [0,2,1]
+    # icost is 0 for [0,2,1] and [2,0,1], so the tie goes to [0,2,1], which
+    # the model scores well past the plain order's
     assert got["plan"]["attr_order"] == [0, 2, 1]
     assert np.array_equal(got["keys"], want["keys"])
     assert np.array_equal(got["sums"].view(np.uint64), want["sums"].view(np.uint64))
+    # the same preference a hundred times weaker is within the model's
+    # margin: the plain rule's order stays
+    m2 = model(0.1)
+    lh.use_model(lh.LH_MODEL_ORDER, m2)
+    assert lh.run_query(q, policy="learned", return_plan_info=True)["plan"]["attr_order"] == plain
+
+
+@pytest.mark.parametrize("kind", ["spmv", "spgemm", "triangle"])
+def test_training_features_match_the_plan(lh, kind):
+    """The features the training script records for a candidate order are
+    the ones the plan scores: with the committed weights, the decision taken
+    from the training script's features (the order model's prediction on
+    every candidate, the plain order kept unless beaten by the margin of
+    2^0.5) is the plan's own, and the plain rule's order computed from those
+    features is the plain plan's.  SpMV holds a completely dense vector
+    relation, which both sides must leave out of the set features."""
+    from paper_1708_07859_amd import learned as L
+    rng = synth.rng_for(77)
+    if kind == "spmv":
+        n = 6000
+        q = queries.spmv(synth.zipf_degree_matrix(n, 1.1, 16, rng), synth.uniform_pm1(rng, n))
+    elif kind == "spgemm":
+        a = synth.zipf_degree_matrix(3000, 1.1, 16, rng)
+        q = queries.spgemm(a, a)
+    else:
+        lo, hi = synth.rmat_edges(14, 16 << 14, seed=77)
+        q = queries.triangle(lo, hi)
+    lm, om, _ = L.load(L.DEFAULT_WEIGHTS)
+    tries, uniq = L.build_tries(q)
+    try:
+        edges = L._edges_of(q, tries)
+        out = q.get("out", [])
+        plain, _ = lh.choose_order(q["n_attrs"], edges, out)
+        cands = L.candidate_orders(q["n_attrs"], out)
+        if plain not in cands:
+            cands.append(plain)
+        X = np.stack([lh.order_features(q["n_attrs"], edges, o) for o in cands])
+        y = om.predict(X, bf16=True)
+        best = min(range(len(cands)), key=lambda c: (y[c], cands[c]))
+        want = cands[best] if y[cands.index(plain)] - y[best] >= 0.5 else plain
+        atoms = [(t, list(a["attrs"]), int(a.get("anno", -1))) for t, a in zip(tries, q["atoms"])]
+        p = lh.plan(q["n_attrs"], atoms, out=out, agg=q["agg"], policy="plain")
+        assert p.info()["attr_order"] == plain
+        p.free()
+        L.register(lm, om)
+        p = lh.plan(q["n_attrs"], atoms, out=out, agg=q["agg"], policy="learned")
+        got = p.info()["attr_order"]
+        p.free()
+        assert got == want, (kind, got, want, dict(zip(map(tuple, cands), y.tolist())))
+    finally:
+        lh.use_model(lh.LH_MODEL_LAYOUT, None)
+        lh.use_model(lh.LH_MODEL_ORDER, None)
+        for t in uniq:
+            t.free()
+        lm.free()
+        om.free()

@@ -282,6 +282,63 @@ def _mixed_pairs():
     return pairs
 
 
+def _merge_pairs():
+    """Pairs for the merge path (two sorted sets of 4096 elements or more,
+    sizes within a factor of 4): the bounds of that rule on both sides,
+    identical sets (a common value on every tile boundary that falls
+    between a set-0 element and its equal set-1 element), disjoint sets in
+    both orders, tiles made of one set only, and values near 2^32."""
+    rng = synth.rng_for(11)
+
+    def draw(n, universe, base=0):
+        return (np.sort(rng.choice(universe, n, replace=False)) + base).astype(np.uint32)
+
+    pairs = [(draw(4096, 8192), draw(4096, 8192)),                # both at the size bound
+             (draw(4095, 8192), draw(9000, 20000)),               # one below it: probed
+             (draw(4096, 40000), draw(16384, 40000)),             # ratio exactly 4
+             (draw(4096, 40000), draw(16385, 40000)),             # ratio above 4: probed
+             (draw(12345, 50000), draw(23456, 50000))]
+    same = draw(20000, 1 << 20)
+    pairs.append((same, same.copy()))
+    pairs.append((np.arange(0, 10000, dtype=np.uint32), np.arange(10000, 20000, dtype=np.uint32)))
+    pairs.append((np.arange(10000, 20000, dtype=np.uint32), np.arange(0, 10000, dtype=np.uint32)))
+    pairs.append((np.arange(0, 40000, 2, dtype=np.uint32), np.arange(0, 60000, 3, dtype=np.uint32)))
+    top = np.uint32(0xFFFFFFFE)
+    pairs.append((top - np.arange(9000, dtype=np.uint32)[::-1] * 2, top - np.arange(9000, dtype=np.uint32)[::-1] * 3))
+    pairs.append((draw(6000, 1 << 31, base=1 << 31), draw(7000, 1 << 31, base=1 << 31)))
+    return pairs
+
+
+@pytest.mark.parametrize("grouped", [True, False])
+def test_merge_path_intersections(lh, grouped):
+    """Rows that take the merge path, per pair (COUNT GROUP BY pair) and in
+    total (COUNT): equal to numpy's intersect1d and to the oracle."""
+    pairs = _merge_pairs()
+    q = queries.set_pairs(pairs)
+    if not grouped:
+        q["out"] = []
+    say(f"merge pairs grouped={grouped}: {len(pairs)} pairs")
+    ta = lh.trie_build(q["atoms"][0]["keys"], layout="uint")
+    tb = lh.trie_build(q["atoms"][1]["keys"], layout="uint")
+    p = lh.plan(2, [(ta, [0, 1], -1), (tb, [0, 1], -1)], out=q["out"], agg="count", attr_order=[0, 1],
+                policy="fixed")
+    lh.profile_reset()
+    lh.profile_enable(True)
+    r = lh.join_aggregate([p])[0]
+    got = r.to_host()
+    lh.profile_enable(False)
+    prof = lh.profile_read()
+    r.free(); p.free(); ta.free(); tb.free()
+    assert prof.get("leaf_merge", {"launches": 0})["launches"] == 1
+    sizes = np.array([len(np.intersect1d(a, b)) for a, b in pairs])
+    if grouped:
+        nz = np.nonzero(sizes)[0]
+        assert np.array_equal(got["keys"][:, 0], nz) and np.array_equal(got["counts"], sizes[nz])
+    else:
+        assert int(got["counts"][0]) == int(sizes.sum())
+    assert_same(got, oracle.join_aggregate(q))
+
+
 @pytest.mark.parametrize("la,lb", [("uint", "uint"), ("uint", "bitset"), ("bitset", "uint"),
                                    ("bitset", "bitset"), ("plain", "plain")])
 def test_set_pair_intersections(lh, la, lb):
