@@ -170,13 +170,52 @@ struct BatchArgs {
   uint64_t* ub_cnt;
   double* ub_sum;
   uint32_t* err;
+  const uint64_t* prod;      // per batch row: its number of products
   uint32_t kw;                      // k values per heavy window (multiple of 64, <= KW_MAX)
 };
 
-// Exact sum held in LDS slots (EXACT_MAXD stride) of one accumulator: add
-// mult * v (shared slot form, so any number of terms is exact).
-__device__ __forceinline__ bool lds_add_term(long long* slots, double v, int32_t lsb, uint32_t D, uint64_t mult) {
-  return atomic_add_term((int64_t*)slots, v, lsb, D, mult);
+// A row with fewer products than this keeps its LDS accumulators in signed
+// slots: a product adds two terms, each at most one word below 2^32 to any
+// slot, so no slot can leave int64 (2 * 2^30 * 2^32 = 2^63).
+constexpr uint64_t BOUNDED_PRODUCTS = 1ull << 30;
+
+// Exact sum held in LDS slots (EXACT_MAXD stride) of one accumulator: add v.
+// bounded (the row has fewer than BOUNDED_PRODUCTS products): signed slots,
+// plain atomic adds whose returned values nobody waits for.  Otherwise the
+// shared slot form, which carries every wrap, so any number of terms is
+// exact.  A row uses one form for all of its accumulators.
+__device__ __forceinline__ bool lds_add_term(long long* slots, double v, int32_t lsb, uint32_t D, bool bounded) {
+  if (!bounded) return atomic_add_term((int64_t*)slots, v, lsb, D, 1);
+  if (v == 0.0) return true;
+  int32_t k0;
+  uint32_t p[5];
+  bool neg;
+  if (!term_words(v, lsb, 1, k0, p, neg)) return false;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 5; j++) {
+    if (!p[j]) continue;
+    if (k0 + j >= (int32_t)D) {
+      ok = false;
+      continue;
+    }
+    const int64_t w = neg ? -(int64_t)p[j] : (int64_t)p[j];
+    atomicAdd((unsigned long long*)&slots[k0 + j], (unsigned long long)w);
+  }
+  return ok;
+}
+
+// The correctly rounded value of an LDS accumulator in the form lds_add_term
+// used: signed slots are carried into digits first (a normalized value is
+// also a shared-form value).
+__device__ __forceinline__ double lds_round(const long long* slots, uint32_t D, int32_t lsb, bool bounded,
+                                            uint32_t* err) {
+  if (!bounded) return exact_round((const int64_t*)slots, D, lsb, err);
+  RegAcc r;
+#pragma unroll
+  for (int i = 0; i < EXACT_MAXD; i++) r.s[i] = i < (int)D ? (int64_t)slots[i] : 0;
+  r.normalize(D);
+  return exact_round(r.s, D, lsb, err);
 }
 
 // Heavy rows: one block per row.  A symbolic pass marks every k the row
@@ -246,6 +285,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
     const uint32_t p = t - (uint32_t)a.inst_row0[a.row_inst[t]];
     const uint32_t qb = I.a_off[p], qe = I.a_off[p + 1];
     const uint64_t out = a.ub_off[t];
+    const bool bounded = a.prod[t] < BOUNDED_PRODUCTS;
     uint32_t nnz = 0;
     for (uint32_t w0 = 0; w0 < I.n_k; w0 += a.kw) {
       const uint32_t wend = min(w0 + a.kw, I.n_k);
@@ -340,8 +380,8 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
                 for (uint32_t re = eb; re < ee; re++) {
                   double hi, lo;
                   two_prod(I.a_val[ra], I.e_val[re], hi, lo);
-                  bool ok = lds_add_term(sdig + sl * EXACT_MAXD, hi, I.lsb, I.D, 1);
-                  ok = lds_add_term(sdig + sl * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
+                  bool ok = lds_add_term(sdig + sl * EXACT_MAXD, hi, I.lsb, I.D, bounded);
+                  ok = lds_add_term(sdig + sl * EXACT_MAXD, lo, I.lsb, I.D, bounded) && ok;
                   if (!ok) bad = 1;
                 }
           }
@@ -353,7 +393,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
           const uint64_t o = out + nnz + r0 + sl;
           a.ub_k[o] = sk[sl];
           a.ub_cnt[o] = scnt[sl];
-          if (I.sum) a.ub_sum[o] = exact_round((const int64_t*)(sdig + sl * EXACT_MAXD), I.D, I.lsb, a.err);
+          if (I.sum) a.ub_sum[o] = lds_round(sdig + sl * EXACT_MAXD, I.D, I.lsb, bounded, a.err);
           scnt[sl] = 0;
 #pragma unroll
           for (int d = 0; d < EXACT_MAXD; d++) sdig[sl * EXACT_MAXD + d] = 0;
@@ -398,6 +438,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
     const BInst I = a.inst[a.row_inst[t]];
     const uint32_t p = t - (uint32_t)a.inst_row0[a.row_inst[t]];
     const uint32_t qb = I.a_off[p], qe = I.a_off[p + 1];
+    const bool bounded = a.prod[t] < BOUNDED_PRODUCTS;
     const uint32_t nwords = (I.n_j + 63) / 64;
     for (uint32_t s = tid; s < nwords; s += B_NT) bm[s] = 0;
     __syncthreads();
@@ -466,8 +507,8 @@ __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
             for (uint32_t re = eb; re < ee; re++) {
               double hi, lo;
               two_prod(I.a_val[ra], I.bt_val[re], hi, lo);
-              bool ok = lds_add_term(cdig + c * EXACT_MAXD, hi, I.lsb, I.D, 1);
-              ok = lds_add_term(cdig + c * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
+              bool ok = lds_add_term(cdig + c * EXACT_MAXD, hi, I.lsb, I.D, bounded);
+              ok = lds_add_term(cdig + c * EXACT_MAXD, lo, I.lsb, I.D, bounded) && ok;
               if (!ok) bad = 1;
             }
         }
@@ -480,7 +521,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
         const uint64_t o = out + nnz + r;
         a.ub_k[o] = I.bt_k[kb0 + tid];
         a.ub_cnt[o] = cnt;
-        if (I.sum) a.ub_sum[o] = exact_round((const int64_t*)(cdig + tid * EXACT_MAXD), I.D, I.lsb, a.err);
+        if (I.sum) a.ub_sum[o] = lds_round(cdig + tid * EXACT_MAXD, I.D, I.lsb, bounded, a.err);
       }
       ccnt[tid] = 0;
 #pragma unroll
@@ -564,6 +605,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_light(BatchArgs a) {
       continue;
     }
     // matrix: hash the row's products by k
+    const bool bounded = a.prod[t] < BOUNDED_PRODUCTS;
     for (int s = lane; s < HS; s += WAVE) {
       hk[s] = EMPTY_KEY;
       hc[s] = 0;
@@ -619,8 +661,8 @@ __global__ __launch_bounds__(B_NT) void k_batch_light(BatchArgs a) {
             for (uint32_t re = eb; re < ee; re++) {
               double hi, lo;
               two_prod(I.a_val[ra], I.e_val[re], hi, lo);
-              bool ok = lds_add_term(hd + slot * EXACT_MAXD, hi, I.lsb, I.D, 1);
-              ok = lds_add_term(hd + slot * EXACT_MAXD, lo, I.lsb, I.D, 1) && ok;
+              bool ok = lds_add_term(hd + slot * EXACT_MAXD, hi, I.lsb, I.D, bounded);
+              ok = lds_add_term(hd + slot * EXACT_MAXD, lo, I.lsb, I.D, bounded) && ok;
               if (!ok) bad = 1;
             }
       }
@@ -665,7 +707,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_light(BatchArgs a) {
       const uint64_t o = out + rk[c];
       a.ub_k[o] = kk[c];
       a.ub_cnt[o] = hc[s];
-      if (I.sum) a.ub_sum[o] = exact_round((const int64_t*)(hd + s * EXACT_MAXD), I.D, I.lsb, a.err);
+      if (I.sum) a.ub_sum[o] = lds_round(hd + s * EXACT_MAXD, I.D, I.lsb, bounded, a.err);
     }
     if (lane == 0) a.row_nnz[t] = m;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -966,6 +1008,7 @@ void launch_compute(BatchState& b, hipStream_t s) {
   a.ub_cnt = b.ub_cnt.p;
   a.ub_sum = b.ub_sum.p;
   a.err = b.err.p;
+  a.prod = b.prod.p;
   a.kw = b.kw;
   const unsigned grid = (unsigned)(cus * std::min(b.tune.blocks_per_cu, MAX_BLOCKS_PER_CU));
   if (b.n_inner) k_batch_inner<<<grid, B_NT, 0, s>>>(a);
