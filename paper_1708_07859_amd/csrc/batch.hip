@@ -753,12 +753,20 @@ __global__ void k_pack_rows(PackArgs2 a) {
 }
 
 // Join tuples per instance: the sum of its output counts.
-__global__ void k_inst_sums(const uint64_t* cnt, const uint64_t* lo, const uint64_t* hi, uint64_t* out) {
+// Join tuples of each instance (one block per instance): the sum of its
+// rows' product counts, which is the sum of its output counts.
+__global__ void k_inst_sums(const uint64_t* prod, const uint64_t* row0, uint64_t* out) {
   __shared__ uint64_t red[B_NW];
   uint64_t s = 0;
-  for (uint64_t e = lo[blockIdx.x] + threadIdx.x; e < hi[blockIdx.x]; e += blockDim.x) s += cnt[e];
+  for (uint64_t t = row0[blockIdx.x] + threadIdx.x; t < row0[blockIdx.x + 1]; t += blockDim.x) s += prod[t];
   s = block_sum<uint64_t, B_NT>(s, red);
   if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// Packed output offsets at the instances' first rows (n + 1 of them).
+__global__ void k_inst_offsets(const uint64_t* out_off, const uint64_t* row0, uint32_t n, uint64_t* dst) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x)
+    dst[i] = out_off[row0[i]];
 }
 
 unsigned grid_for(uint64_t n) {
@@ -794,6 +802,7 @@ struct BatchState {
   hipStream_t s = nullptr;
   DBuf<BInst> inst;
   DBuf<uint64_t> inst_row0, prod, ub_off;
+  std::vector<uint64_t> h_nj;   // join tuples per instance (fixed by the plans)
   DBuf<uint32_t> row_inst, ub, heavy_f, light_f, inner_f, heavy, light, inner, qhead, row_nnz, ub_k, err;
   std::shared_ptr<Transposes> tr;
   DBuf<uint64_t> ub_cnt;
@@ -951,6 +960,14 @@ void setup(BatchState& b, hipStream_t s) {
   }
   b.ub_off.alloc(b.R + 1, s);
   b.UB = scan_u32_to_u64(b.ub.p, b.ub_off.p, b.R, s);
+  b.h_nj.assign(n, 0);
+  if (n) {
+    DBuf<uint64_t> dnj(n, s);
+    k_inst_sums<<<n, B_NT, 0, s>>>(b.prod.p, b.inst_row0.p, dnj.p);
+    LH_HIP(hipGetLastError());
+    LH_HIP(hipMemcpyAsync(b.h_nj.data(), dnj.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    LH_HIP(hipStreamSynchronize(s));
+  }
   b.heavy.alloc(b.R, s);
   b.light.alloc(b.R, s);
   b.n_heavy = select_flagged(b.heavy_f.p, b.R, b.heavy.p, s);
@@ -1193,26 +1210,18 @@ bool run_batch(lh_plan_t* const* plans, uint32_t n, hipStream_t s, std::vector<l
     k_pack_rows<<<grid_for(b.R * WAVE), 256, 0, s>>>(pa);
     LH_HIP(hipGetLastError());
   }
-  std::vector<uint64_t> offs(b.R + 1);
-  LH_HIP(hipMemcpyAsync(offs.data(), out_off.p, (b.R + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  LH_HIP(hipStreamSynchronize(s));
-  std::vector<uint64_t> lo(n), hi(n), nj(n, 0);
-  for (uint32_t i = 0; i < n; i++) {
-    lo[i] = offs[b.h_inst_row0[i]];
-    hi[i] = offs[b.h_inst_row0[i + 1]];
-  }
+  // each instance's rows are contiguous: its outputs are [offs[i], offs[i + 1])
+  std::vector<uint64_t> offs(n + 1);
   {
-    DBuf<uint64_t> dlo(n, s), dhi(n, s), dnj(n, s);
-    LH_HIP(hipMemcpyAsync(dlo.p, lo.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    LH_HIP(hipMemcpyAsync(dhi.p, hi.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    k_inst_sums<<<n, B_NT, 0, s>>>(sh->out_cnt.p, dlo.p, dhi.p, dnj.p);
+    DBuf<uint64_t> d(n + 1, s);
+    k_inst_offsets<<<(n + 256) / 256, 256, 0, s>>>(out_off.p, b.inst_row0.p, n, d.p);
     LH_HIP(hipGetLastError());
-    LH_HIP(hipMemcpyAsync(nj.data(), dnj.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    LH_HIP(hipMemcpyAsync(offs.data(), d.p, (n + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     LH_HIP(hipStreamSynchronize(s));
   }
   for (uint32_t i = 0; i < n; i++) {
     const BInst& I = b.h_inst[i];
-    const uint64_t o0 = lo[i], o1 = hi[i];
+    const uint64_t o0 = offs[i], o1 = offs[i + 1];
     auto* r = new lh_result_impl();
     memset(&r->pub, 0, sizeof(r->pub));
     r->shared = sh;
@@ -1224,7 +1233,7 @@ bool run_batch(lh_plan_t* const* plans, uint32_t n, hipStream_t s, std::vector<l
     r->pub.counts = sh->out_cnt.p ? sh->out_cnt.p + o0 : nullptr;
     r->pub.sums = I.sum ? (sh->out_sum.p ? sh->out_sum.p + o0 : nullptr) : nullptr;
     r->pub.exact = I.sum;
-    r->pub.n_join_tuples = nj[i];
+    r->pub.n_join_tuples = b.h_nj[i];
     out.push_back(r);
   }
   return true;
