@@ -733,26 +733,73 @@ struct PackArgs2 {
   uint64_t R;
 };
 
+// A wave takes 64 consecutive rows: lane l loads row t0 + l's offsets, its
+// instance and its i, then the wave copies the rows' outputs as one flat
+// range (the rows' packed outputs are contiguous), each lane finding the
+// row of its output by bisecting the rows' output offsets across the
+// lanes.  Every lane does useful copies whatever the rows' lengths.
 __global__ void k_pack_rows(PackArgs2 a) {
   const int lane = lane_id();
   const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x / WAVE);
-  for (uint64_t t = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; t < a.R; t += nw) {
-    const uint64_t o0 = a.out_off[t], n = a.out_off[t + 1] - o0;
-    if (!n) continue;
-    const uint32_t ii = a.row_inst[t];
-    const BInst& I = a.inst[ii];
-    const uint32_t i = I.a_i[t - a.inst_row0[ii]];
-    const uint64_t u0 = a.ub_off[t];
-    for (uint64_t e = lane; e < n; e += WAVE) {
-      a.out_i[o0 + e] = i;
-      if (I.kind == 1) a.out_k[o0 + e] = a.ub_k[u0 + e];
-      a.out_cnt[o0 + e] = a.ub_cnt[u0 + e];
-      if (I.sum) a.out_sum[o0 + e] = a.ub_sum[u0 + e];
+  for (uint64_t t0 = ((uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) * WAVE; t0 < a.R;
+       t0 += nw * WAVE) {
+    const uint64_t t = t0 + lane;
+    const bool row = t < a.R;
+    // lanes past the last row start where the group ends
+    const uint64_t oo = a.out_off[row ? t : a.R];
+    const uint64_t base = a.out_off[t0], end = a.out_off[min<uint64_t>(t0 + WAVE, a.R)];
+    uint32_t iv = 0, flags = 0;
+    uint64_t uo = 0;
+    if (row) {
+      const uint32_t ii = a.row_inst[t];
+      const BInst& I = a.inst[ii];
+      iv = I.a_i[t - a.inst_row0[ii]];
+      flags = (I.kind == 1 ? 1u : 0u) | (I.sum ? 2u : 0u);
+      uo = a.ub_off[t];
+    }
+    if (end - base >= (1ull << 32)) {
+      // more than 2^32 outputs in the group: row by row
+      for (int l = 0; l < WAVE; l++) {
+        const uint64_t o0 = (uint64_t)__shfl((long long)oo, l, WAVE);
+        const uint64_t o1 = l + 1 < WAVE ? (uint64_t)__shfl((long long)oo, l + 1, WAVE) : end;
+        const uint64_t u0 = (uint64_t)__shfl((long long)uo, l, WAVE);
+        const uint32_t il = (uint32_t)__shfl((int)iv, l, WAVE), fl = (uint32_t)__shfl((int)flags, l, WAVE);
+        for (uint64_t e = o0 + lane; e < o1; e += WAVE) {
+          a.out_i[e] = il;
+          if (fl & 1u) a.out_k[e] = a.ub_k[u0 + (e - o0)];
+          a.out_cnt[e] = a.ub_cnt[u0 + (e - o0)];
+          if (fl & 2u) a.out_sum[e] = a.ub_sum[u0 + (e - o0)];
+        }
+      }
+      continue;
+    }
+    const uint32_t rel = (uint32_t)(oo - base);
+    const uint32_t uo_lo = (uint32_t)uo, uo_hi = (uint32_t)(uo >> 32);
+    for (uint64_t e0 = base; e0 < end; e0 += WAVE) {   // uniform: every lane takes part in the shuffles
+      const uint64_t e = e0 + (uint64_t)lane;
+      const uint32_t re = (uint32_t)(e - base);
+      // the row of output e: the last lane whose first output is <= e
+      uint32_t src = 0;
+#pragma unroll
+      for (int step = WAVE / 2; step > 0; step >>= 1) {
+        const uint32_t r = (uint32_t)__shfl((int)rel, (int)(src + step), WAVE);
+        src = r <= re ? src + step : src;
+      }
+      const uint32_t rs = (uint32_t)__shfl((int)rel, (int)src, WAVE);
+      const uint32_t is = (uint32_t)__shfl((int)iv, (int)src, WAVE);
+      const uint32_t fs = (uint32_t)__shfl((int)flags, (int)src, WAVE);
+      const uint64_t us = (uint64_t)(uint32_t)__shfl((int)uo_lo, (int)src, WAVE) |
+                          ((uint64_t)(uint32_t)__shfl((int)uo_hi, (int)src, WAVE) << 32);
+      if (e >= end) continue;
+      const uint64_t u = us + (re - rs);
+      a.out_i[e] = is;
+      if (fs & 1u) a.out_k[e] = a.ub_k[u];
+      a.out_cnt[e] = a.ub_cnt[u];
+      if (fs & 2u) a.out_sum[e] = a.ub_sum[u];
     }
   }
 }
 
-// Join tuples per instance: the sum of its output counts.
 // Join tuples of each instance (one block per instance): the sum of its
 // rows' product counts, which is the sum of its output counts.
 __global__ void k_inst_sums(const uint64_t* prod, const uint64_t* row0, uint64_t* out) {
@@ -1207,7 +1254,7 @@ bool run_batch(lh_plan_t* const* plans, uint32_t n, hipStream_t s, std::vector<l
   pa.R = b.R;
   if (b.R) {
     ProfScope ps("batch_pack", s, b.R, total);
-    k_pack_rows<<<grid_for(b.R * WAVE), 256, 0, s>>>(pa);
+    k_pack_rows<<<grid_for(b.R), 256, 0, s>>>(pa);
     LH_HIP(hipGetLastError());
   }
   // each instance's rows are contiguous: its outputs are [offs[i], offs[i + 1])

@@ -29,23 +29,30 @@ constexpr int U_IT = 4;            // elements per lane per unit
 constexpr int U_EL = WAVE * U_IT;  // driver elements per unit
 // Two-set leaves: rows whose two sets hold TOP_MIN elements or more
 // together form the top bucket, the largest intersections.  They run as a
-// launch of their own, in units of TOP_IT elements per lane, so that a wave
-// has twice the loads in flight per unit.
+// launch of their own, in units of TOP_IT elements per lane (units of twice
+// that size measured 3 ms slower per triangle step under the plain order).
 constexpr uint32_t TOP_MIN = 1u << 14;
-constexpr int TOP_IT = 2 * U_IT;
+constexpr int TOP_IT = U_IT;
 constexpr int TOP_EL = WAVE * TOP_IT;
 // Rows of two sorted (uint) sets of MERGE_MIN elements or more each, the
-// larger at most MERGE_RATIO times the smaller, are merged instead of
-// probed (the co-iteration of section 4.1.1's balanced case): the merged
-// sequence is cut into tiles of MERGE_TILE elements along its diagonal
-// (merge path), and one block streams a tile's two runs through LDS and
-// counts the equal neighbours.  Both sets are read once, in order.
+// larger at most MERGE_RATIO times the smaller, are co-iterated instead of
+// probed (section 4.1.1's balanced case): the merged sequence is cut into
+// tiles of MERGE_TILE elements along its diagonal (merge path), and one
+// block streams a tile's two runs and intersects them in LDS.  Both sets
+// are read once, in order.
 constexpr int M_NT = 256;
 constexpr int M_PER = 16;                       // merged elements per thread
 constexpr uint32_t MERGE_TILE = M_NT * M_PER;
 constexpr uint32_t MERGE_MIN = 1u << 12;
 constexpr uint32_t MERGE_RATIO = 4;
-constexpr uint64_t MERGE_GRID = 8192;           // blocks of the merge launch (they loop over tiles)
+// A tile is intersected through an LDS bitmap of MERGE_TILE words of 32
+// bits when its value span fits, and the span is at most MERGE_BM_SPREAD
+// values per key of the tile (clearing the bitmap then costs at most one
+// word per four keys); sparser tiles are merged.  Rows are taken by the
+// merge tiles only when their value span is that dense overall: sparser
+// pairs intersect faster by the staged probes.
+constexpr uint64_t MERGE_BM_SPAN = 32ull * MERGE_TILE;
+constexpr uint64_t MERGE_BM_SPREAD = 8;
 
 struct DSet {
   const uint32_t* ppos;   // frontier positions at the previous level (null: root set)
@@ -309,12 +316,21 @@ __global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv,
     uint8_t dv = (uint8_t)bi;
     uint32_t chunk = U_EL;
     if (leaf2 && a.np == 2 && !empty && probe[0] > 1.0f && probe[1] > 1.0f) {
-      // two sorted sets of similar, large size: merged
+      // two sorted sets of similar, large size whose values are dense
+      // enough for the merge tiles' LDS bitmaps: merged
       const uint32_t lo = min(card[0], card[1]), hi = max(card[0], card[1]);
       if (lo >= MERGE_MIN && (uint64_t)hi <= (uint64_t)MERGE_RATIO * lo) {
-        dv = DRV_MERGE;
-        best = card[0] + card[1];
-        chunk = MERGE_TILE;
+        uint32_t b0, e0, b1, e1;
+        uint64_t s0, s1;
+        dset_range(a.set[0], r, b0, e0, s0);
+        dset_range(a.set[1], r, b1, e1, s1);
+        const uint32_t vmin = min(a.set[0].keys[b0], a.set[1].keys[b1]);
+        const uint32_t vmax = max(a.set[0].keys[e0 - 1], a.set[1].keys[e1 - 1]);
+        if ((uint64_t)(vmax - vmin) + 1 <= MERGE_BM_SPREAD * ((uint64_t)card[0] + card[1])) {
+          dv = DRV_MERGE;
+          best = card[0] + card[1];
+          chunk = MERGE_TILE;
+        }
       }
     }
     if (leaf2 && a.np == 2 && !empty) {
@@ -1307,14 +1323,17 @@ __global__ __launch_bounds__(J_NT) void k_leaf2_count(Leaf2Args a) {
 
 // A merge tile, listed in launch order: keys [a0, a0 + na) of participant
 // 0 and [b0, b0 + nb) of participant 1; back = 1 when keys[0][a0 - 1] is
-// in the row (the tile's look-back element); unit = the unit it belongs to.
+// in the row (the tile's look-back element, lb); unit = the unit it belongs
+// to; [lo, hi] = the smallest and largest of the tile's keys and lb
+// (lo > hi: the tile holds no key).
 struct MergeTile {
-  uint32_t a0, na, b0, nb, back, unit, pad0, pad1;
+  uint32_t a0, na, b0, nb, back, unit, lo, hi, lb, pad[7];
 };
 constexpr int MT_WORDS = sizeof(MergeTile) / 4;
-static_assert(MT_WORDS == 8, "a merge tile is read as 8 words, one per lane");
+static_assert(MT_WORDS == 16, "a merge tile is read as 16 words, one per lane");
 
-__global__ void k_merge_tiles(const UnitDesc* desc, const uint32_t* list, uint64_t n, MergeTile* out) {
+__global__ void k_merge_tiles(const UnitDesc* desc, const uint32_t* list, const uint32_t* k0, const uint32_t* k1,
+                              uint64_t n, MergeTile* out) {
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t u = list[j];
     const UnitDesc t = desc[u];
@@ -1325,24 +1344,92 @@ __global__ void k_merge_tiles(const UnitDesc* desc, const uint32_t* list, uint64
     m.nb = t.phi;
     m.back = (uint32_t)t.pword;
     m.unit = u;
+    uint32_t lo = UINT32_MAX, hi = 0;
+    if (m.back) {
+      m.lb = k0[m.a0 - 1];
+      lo = min(lo, m.lb);
+      hi = max(hi, m.lb);
+    }
+    if (m.na) {
+      lo = min(lo, k0[m.a0]);
+      hi = max(hi, k0[m.a0 + m.na - 1]);
+    }
+    if (m.nb) {
+      lo = min(lo, k1[m.b0]);
+      hi = max(hi, k1[m.b0 + m.nb - 1]);
+    }
+    if (lo > hi) {
+      lo = 1;
+      hi = 0;
+    }
+    m.lo = lo;
+    m.hi = hi;
     out[j] = m;
   }
 }
 
+// 16-byte chunks of keys per thread per tile: the two runs' chunks on the
+// 16-byte grid, partial chunks at the ends included (at most
+// MERGE_TILE / 4 + 4 of them).
+constexpr int M_CH = (int)((MERGE_TILE / 4 + 4 + M_NT - 1) / M_NT);
+
+// Bitmap word of the value offset d: words are XOR-swizzled within groups
+// of 32 so that lanes whose values lie 32 words apart (sparse sets) hit
+// different banks.
+__device__ __forceinline__ uint32_t bm_word(uint32_t d) {
+  const uint32_t w = d >> 5;
+  return w ^ ((w >> 5) & 31u);
+}
+
+// A run of n keys at p, cut into 16-byte chunks on the 16-byte grid: chunk
+// c holds the run's elements 4c - head .. 4c - head + 3 (those in [0, n)).
+struct KeyRun {
+  const uint32_t* al;   // p rounded down to 16 bytes
+  uint32_t head, n, nch;
+};
+
+__device__ __forceinline__ KeyRun key_run(const uint32_t* p, uint32_t n) {
+  KeyRun r;
+  r.head = (uint32_t)(((uintptr_t)p & 15u) >> 2);
+  r.al = p - r.head;
+  r.n = n;
+  r.nch = n ? (r.head + n + 3) / 4 : 0u;
+  return r;
+}
+
+// Chunk c of a run: one 16-byte load when the chunk lies inside the run,
+// else its elements inside the run one by one (the rest are 0).
+__device__ __forceinline__ uint4 load_chunk(const KeyRun& r, uint32_t c) {
+  const int64_t e0 = 4 * (int64_t)c - r.head;
+  if (e0 >= 0 && e0 + 4 <= (int64_t)r.n) return *reinterpret_cast<const uint4*>(r.al + 4 * (uint64_t)c);
+  uint32_t v[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int64_t e = e0 + k;
+    v[k] = (e >= 0 && e < (int64_t)r.n) ? r.al[4 * (uint64_t)c + k] : 0u;
+  }
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+__device__ __forceinline__ uint32_t chunk_elem(const uint4& x, int k) {
+  return k == 0 ? x.x : k == 1 ? x.y : k == 2 ? x.z : x.w;
+}
+
 // Merge tiles: each block runs one contiguous range of the tile list (the
 // ranges of an XCD's blocks are contiguous too, so tiles of one row share
-// an L2).  A tile's run of participant 0's keys, after its look-back
-// element, and its run of participant 1's keys are staged in LDS; thread k
-// finds where merged position k * M_PER falls in the two runs (a merge-path
-// search in LDS) and walks M_PER merged positions from there.  In the merge
-// an element of set 0 goes before an equal one of set 1, so every common
-// value shows up as a set-1 element whose merged predecessor from set 0 is
-// equal; the tile's first set-1 elements compare with the look-back
-// element.  The next tile's keys are loaded into registers while the
-// current one is counted, and the tile after that is described by a vector
-// load of one word per lane, which the LDS waits do not wait for.
+// an L2).  A tile's two runs are loaded as 16-byte chunks, coalesced, and
+// the next tile's chunks are loaded while the current one is counted.
+// Participant 0's keys of the tile (and its look-back element: a common
+// value split across two tiles has its set-0 copy at the end of one and its
+// set-1 copy at the start of the next) set bits of an LDS bitmap over the
+// tile's value span, one atomic OR per bitmap word a chunk touches; every
+// participant-1 key then tests its bit.  The loads, bit sets and tests are
+// independent of each other.  A sparser tile is merged instead: its keys
+// are staged in LDS, thread k finds merged position k * M_PER (a merge-path
+// search) and walks M_PER positions, counting set-1 keys equal to their
+// merged set-0 predecessor.
 __global__ __launch_bounds__(M_NT) void k_leaf2_merge(Leaf2Args a, const MergeTile* tiles, uint64_t n_tiles) {
-  __shared__ uint32_t s_t[MERGE_TILE + 1];
+  __shared__ __align__(16) uint32_t s_t[MERGE_TILE + 4];
   __shared__ uint64_t s_red[M_NT / WAVE];
   const int tid = threadIdx.x, lane = lane_id();
   const uint64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -1350,79 +1437,143 @@ __global__ __launch_bounds__(M_NT) void k_leaf2_merge(Leaf2Args a, const MergeTi
   const uint64_t k0 = lb * per, k1 = min<uint64_t>(n_tiles, k0 + per);
   if (k0 >= k1) return;  // block-uniform, before any barrier
   uint64_t run = 0;
-  uint32_t r[M_PER + 1];
+  uint4 r[M_CH], rn[M_CH];
   auto tile_word = [&](uint64_t k) -> uint32_t {
     return (k < k1 && lane < MT_WORDS) ? reinterpret_cast<const uint32_t*>(tiles + k)[lane] : 0u;
   };
   auto unpack = [&](uint32_t w) -> MergeTile {
-    MergeTile m;
+    MergeTile m{};
     m.a0 = __builtin_amdgcn_readlane(w, 0);
     m.na = __builtin_amdgcn_readlane(w, 1);
     m.b0 = __builtin_amdgcn_readlane(w, 2);
     m.nb = __builtin_amdgcn_readlane(w, 3);
     m.back = __builtin_amdgcn_readlane(w, 4);
     m.unit = __builtin_amdgcn_readlane(w, 5);
-    m.pad0 = m.pad1 = 0;
+    m.lo = __builtin_amdgcn_readlane(w, 6);
+    m.hi = __builtin_amdgcn_readlane(w, 7);
+    m.lb = __builtin_amdgcn_readlane(w, 8);
     return m;
   };
-  // keys of a tile into r: slot 0 the look-back element, then set 0's run,
-  // then set 1's run
-  auto fetch = [&](const MergeTile& m) {
-    const uint32_t n1 = m.na + 1, n = n1 + m.nb;
-    const uint32_t* A = a.keys[0] + m.a0;
-    const uint32_t* B = a.keys[1] + m.b0;
+  // chunk j * M_NT + tid of the tile: set 0's run first, then set 1's
+  auto fetch = [&](const MergeTile& m, uint4* x) {
+    const KeyRun A = key_run(a.keys[0] + m.a0, m.na), B = key_run(a.keys[1] + m.b0, m.nb);
 #pragma unroll
-    for (int k = 0; k <= M_PER; k++) {
-      const uint32_t q = (uint32_t)k * M_NT + (uint32_t)tid;
-      uint32_t v = 0;
-      if (q == 0) v = m.back ? A[-1] : 0u;
-      else if (q < n1) v = A[q - 1];
-      else if (q < n) v = B[q - n1];
-      r[k] = v;
+    for (int j = 0; j < M_CH; j++) {
+      const uint32_t c = (uint32_t)j * M_NT + (uint32_t)tid;
+      x[j] = c < A.nch ? load_chunk(A, c) : c < A.nch + B.nch ? load_chunk(B, c - A.nch) : make_uint4(0, 0, 0, 0);
     }
   };
   MergeTile t = unpack(tile_word(k0));
-  fetch(t);
+  fetch(t, r);
   uint32_t wnext = tile_word(k0 + 1);
   for (uint64_t k = k0; k < k1; k++) {
     const MergeTile cur = t;
-    const uint32_t na = cur.na, nb = cur.nb, n1 = na + 1, n = na + nb;
-    __syncthreads();  // the previous tile's readers are done
-#pragma unroll
-    for (int j = 0; j <= M_PER; j++) {
-      const uint32_t q = (uint32_t)j * M_NT + (uint32_t)tid;
-      if (q < n1 + nb) s_t[q] = r[j];
-    }
-    __syncthreads();
+    // the next tile's keys are in flight while this one is counted
     if (k + 1 < k1) {
       t = unpack(wnext);
-      fetch(t);
+      fetch(t, rn);
       wnext = tile_word(k + 2);
     }
+    const KeyRun A = key_run(a.keys[0] + cur.a0, cur.na), B = key_run(a.keys[1] + cur.b0, cur.nb);
+    const uint32_t na = cur.na, nb = cur.nb, n1 = na + 1, n = na + nb;
+    const uint64_t span = cur.lo <= cur.hi ? (uint64_t)(cur.hi - cur.lo) + 1 : 0;
+    const bool bitmap = span <= MERGE_BM_SPAN && span <= MERGE_BM_SPREAD * (n + 1);  // block-uniform
     uint32_t c = 0;
-    const uint32_t d = (uint32_t)tid * M_PER;
-    if (d < n) {
-      uint32_t lo = d > nb ? d - nb : 0u, hi = min(d, na);
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_t[1 + mid] <= s_t[n1 + d - mid - 1]) lo = mid + 1; else hi = mid;
+    __syncthreads();  // the previous tile's readers are done
+    if (bitmap) {
+      const uint32_t nw = (uint32_t)((span + 31) >> 5);
+      // the swizzle permutes words within groups of 32: clear whole groups
+      const uint32_t nz = (nw + 31) & ~31u;
+      for (uint32_t i = 4 * (uint32_t)tid; i < nz; i += 4 * M_NT)
+        *reinterpret_cast<uint4*>(&s_t[i]) = make_uint4(0u, 0u, 0u, 0u);
+      __syncthreads();
+      if (tid == 0 && cur.back) {
+        const uint32_t d = cur.lb - cur.lo;
+        atomicOr(&s_t[bm_word(d)], 1u << (d & 31u));
       }
-      uint32_t ia = lo, jb = d - lo;
-      bool have = ia > 0 || cur.back != 0;
-      uint32_t prev = s_t[ia];  // set 0's element before position ia (slot 0: the look-back)
-      uint32_t av = ia < na ? s_t[1 + ia] : 0u;
-      uint32_t bv = jb < nb ? s_t[n1 + jb] : 0u;
-      const uint32_t end = min(d + (uint32_t)M_PER, n);
-      for (uint32_t q = d; q < end; q++) {
-        if (ia < na && (jb >= nb || av <= bv)) {
-          prev = av;
-          have = true;
-          ia++;
-          av = ia < na ? s_t[1 + ia] : 0u;
-        } else {
-          c += (have && prev == bv) ? 1u : 0u;
-          jb++;
-          bv = jb < nb ? s_t[n1 + jb] : 0u;
+#pragma unroll
+      for (int j = 0; j < M_CH; j++) {
+        const uint32_t ch = (uint32_t)j * M_NT + (uint32_t)tid;
+        if (ch >= A.nch) continue;
+        // the chunk's bits, one atomic per word they fall in
+        uint32_t cw = UINT32_MAX, bits = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int64_t i = 4 * (int64_t)ch - A.head + e;
+          if (i < 0 || i >= (int64_t)na) continue;
+          const uint32_t d = chunk_elem(r[j], e) - cur.lo;
+          const uint32_t w = bm_word(d);
+          if (w != cw) {
+            if (bits) atomicOr(&s_t[cw], bits);
+            cw = w;
+            bits = 0;
+          }
+          bits |= 1u << (d & 31u);
+        }
+        if (bits) atomicOr(&s_t[cw], bits);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < M_CH; j++) {
+        const uint32_t ch = (uint32_t)j * M_NT + (uint32_t)tid;
+        if (ch < A.nch || ch >= A.nch + B.nch) continue;
+        const uint32_t cb = ch - A.nch;
+        uint32_t cw = UINT32_MAX, word = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int64_t i = 4 * (int64_t)cb - B.head + e;
+          if (i < 0 || i >= (int64_t)nb) continue;
+          const uint32_t d = chunk_elem(r[j], e) - cur.lo;
+          const uint32_t w = bm_word(d);
+          if (w != cw) {
+            cw = w;
+            word = s_t[w];
+          }
+          c += (word >> (d & 31u)) & 1u;
+        }
+      }
+    } else {
+      // stage: slot 0 the look-back element, set 0's run at 1.., set 1's at n1..
+      if (tid == 0) s_t[0] = cur.back ? cur.lb : 0u;
+#pragma unroll
+      for (int j = 0; j < M_CH; j++) {
+        const uint32_t ch = (uint32_t)j * M_NT + (uint32_t)tid;
+        const bool in_a = ch < A.nch;
+        if (!in_a && ch >= A.nch + B.nch) continue;
+        const uint32_t head = in_a ? A.head : B.head, len = in_a ? na : nb;
+        const uint32_t cc = in_a ? ch : ch - A.nch;
+        const uint32_t base = in_a ? 1u : n1;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int64_t i = 4 * (int64_t)cc - head + e;
+          if (i >= 0 && i < (int64_t)len) s_t[base + (uint32_t)i] = chunk_elem(r[j], e);
+        }
+      }
+      __syncthreads();
+      const uint32_t d = (uint32_t)tid * M_PER;
+      if (d < n) {
+        uint32_t lo = d > nb ? d - nb : 0u, hi = min(d, na);
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_t[1 + mid] <= s_t[n1 + d - mid - 1]) lo = mid + 1; else hi = mid;
+        }
+        uint32_t ia = lo, jb = d - lo;
+        bool have = ia > 0 || cur.back != 0;
+        uint32_t prev = s_t[ia];  // set 0's element before position ia (slot 0: the look-back)
+        uint32_t av = ia < na ? s_t[1 + ia] : 0u;
+        uint32_t bv = jb < nb ? s_t[n1 + jb] : 0u;
+        const uint32_t end = min(d + (uint32_t)M_PER, n);
+        for (uint32_t q = d; q < end; q++) {
+          if (ia < na && (jb >= nb || av <= bv)) {
+            prev = av;
+            have = true;
+            ia++;
+            av = ia < na ? s_t[1 + ia] : 0u;
+          } else {
+            c += (have && prev == bv) ? 1u : 0u;
+            jb++;
+            bv = jb < nb ? s_t[n1 + jb] : 0u;
+          }
         }
       }
     }
@@ -1432,6 +1583,8 @@ __global__ __launch_bounds__(M_NT) void k_leaf2_merge(Leaf2Args a, const MergeTi
     } else {
       run += sc;
     }
+#pragma unroll
+    for (int j = 0; j < M_CH; j++) r[j] = rn[j];
   }
   if (!a.ucnt && tid == 0 && run) atomicAdd((unsigned long long*)&a.gcount[0], (unsigned long long)run);
 }
@@ -1602,6 +1755,15 @@ unsigned elem_grid(uint64_t nvblk) { return (unsigned)std::max<uint64_t>(1, std:
 // The two-set leaf walks its virtual blocks with more workgroups in flight
 // than the frontier kernels: 131072 (512 per CU) measured 6% faster than
 // 32768 on R-MAT-22 triangles, while larger grids lose again.
+// The merge launch: as many blocks as fit on the device at once; each loops
+// over a contiguous range of tiles, loading the next while counting one.
+unsigned merge_grid() {
+  int dev = 0, cus = 256, per = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_leaf2_merge, M_NT, 0) != hipSuccess) per = 1;
+  return (unsigned)std::max(1, cus * std::max(1, per));
+}
 unsigned leaf_grid(uint64_t nvblk) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nvblk, 131072)); }
 
 unsigned grid_for(uint64_t n) {
@@ -2254,10 +2416,11 @@ lh_result_impl* run_plan(const lh_plan_t* p, hipStream_t s) {
         LH_HIP(hipGetLastError());
         if (merge_units) {
           DBuf<MergeTile> tiles(merge_units, s);
-          k_merge_tiles<<<grid_for(merge_units), 256, 0, s>>>(desc.p, merge_list.p, merge_units, tiles.p);
+          k_merge_tiles<<<grid_for(merge_units), 256, 0, s>>>(desc.p, merge_list.p, l2.keys[0], l2.keys[1],
+                                                              merge_units, tiles.p);
           LH_HIP(hipGetLastError());
           ProfScope ps("leaf_merge", s, merge_units, 0);
-          k_leaf2_merge<<<(unsigned)std::min<uint64_t>(merge_units, MERGE_GRID), M_NT, 0, s>>>(l2, tiles.p,
+          k_leaf2_merge<<<(unsigned)std::min<uint64_t>(merge_units, merge_grid()), M_NT, 0, s>>>(l2, tiles.p,
                                                                                           merge_units);
         }
         LH_HIP(hipGetLastError());
