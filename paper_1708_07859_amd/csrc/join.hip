@@ -18,6 +18,7 @@
 #include "device_common.h"
 #include "engine.h"
 #include "exact.h"
+#include "search.h"
 
 namespace lh {
 
@@ -29,11 +30,25 @@ constexpr int U_IT = 4;            // elements per lane per unit
 constexpr int U_EL = WAVE * U_IT;  // driver elements per unit
 // Two-set leaves: rows whose two sets hold TOP_MIN elements or more
 // together form the top bucket, the largest intersections.  They run as a
-// launch of their own, in units of TOP_IT elements per lane (units of twice
-// that size measured 3 ms slower per triangle step under the plain order).
+// launch of their own.  Units of TOP_IT elements per lane (twice the loads
+// in flight per wave) are used where a unit's probes stay cheap: word-AND
+// rows, rows probing a bitset, and rows whose probed set is at most
+// TOP_BALANCE times the driver (its range for a unit still fits the LDS
+// stage).  Other top rows keep units of U_IT: a larger unit's probed range
+// would overflow the stage and fall to the line-sample search (units of 512
+// there measured 3 ms slower per plain-order triangle step).
 constexpr uint32_t TOP_MIN = 1u << 14;
-constexpr int TOP_IT = U_IT;
+constexpr int TOP_IT = 2 * U_IT;
 constexpr int TOP_EL = WAVE * TOP_IT;
+constexpr uint32_t TOP_BALANCE = 2;
+
+// Driver elements (or words) per unit of a two-set leaf row whose sets hold
+// c0 and c1 elements; wide: a word-AND row, or one probing a bitset.
+__device__ __forceinline__ uint32_t leaf2_chunk(uint32_t c0, uint32_t c1, bool wide) {
+  const bool top = (uint64_t)c0 + c1 >= TOP_MIN;
+  const bool big = wide || (uint64_t)TOP_BALANCE * min(c0, c1) >= max(c0, c1);
+  return top && big ? (uint32_t)TOP_EL : (uint32_t)U_EL;
+}
 // Rows of two sorted (uint) sets of MERGE_MIN elements or more each, the
 // larger at most MERGE_RATIO times the smaller, are co-iterated instead of
 // probed (section 4.1.1's balanced case): the merged sequence is cut into
@@ -354,7 +369,10 @@ __global__ void k_work(WorkArgs a, uint64_t nrows, uint32_t* work, uint8_t* drv,
     work[r] = best;
     drv[r] = dv;
     const bool top = leaf2 && a.np == 2 && dv != DRV_MERGE && (uint64_t)card[0] + card[1] >= TOP_MIN;
-    if (top) chunk = TOP_EL;
+    if (top) {
+      const float probed = dv == 0 ? probe[1] : probe[0];   // the probed set's cost: 1 for a bitset
+      chunk = leaf2_chunk(card[0], card[1], dv == DRV_AND || (dv < 2 && probed == 1.0f));
+    }
     units[r] = (best + chunk - 1) / chunk;
     if (top) top_units += units[r];
     if (dv == DRV_MERGE) merge_units += units[r];
@@ -1005,9 +1023,11 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
       desc[u] = t;
       continue;
     }
-    // the row's bucket, as k_work decided it (the units' size follows it)
+    // the row's bucket and unit size, as k_work decided them
     const bool is_top = (uint64_t)(e[0] - b[0]) + (e[1] - b[1]) >= TOP_MIN;
-    const uint32_t chunk = is_top ? TOP_EL : U_EL;
+    const bool probes_bitset = d < 2 && (d ? e[0] > b[0] && wa.set[0].bs_word[sidx[0]] != UINT64_MAX
+                                               : e[1] > b[1] && wa.set[1].bs_word[sidx[1]] != UINT64_MAX);
+    const uint32_t chunk = is_top ? leaf2_chunk(e[0] - b[0], e[1] - b[1], d == DRV_AND || probes_bitset) : U_EL;
     t.top = is_top ? 1u : 0u;
     if (top_flag) top_flag[u] = t.top;
     if (d == DRV_AND) {
@@ -1048,10 +1068,13 @@ __global__ void k_unit_desc(WorkArgs wa, const uint64_t* U, const uint32_t* urow
       t.plo = pb;
       t.phi = pe;
     } else {
-      t.plo = sampled_lower_bound(pk, ps, pb, pe, dk[t.dstart]);
+      // the unit's first (and, for a row's last unit, last) key, loaded
+      // together; quinary searches keep the dependent chain short
+      const uint32_t first = dk[t.dstart];
+      const uint32_t last = u + 1 == u1 ? dk[t.dstart + t.dcount - 1] : 0u;
+      t.plo = lower_bound_sampled_quinary(pk, ps, pb, pe, first);
       if (u + 1 == u1) {
-        const uint32_t last = dk[t.dstart + t.dcount - 1];
-        t.phi = last == UINT32_MAX ? pe : sampled_lower_bound(pk, ps, t.plo, pe, last + 1);
+        t.phi = last == UINT32_MAX ? pe : lower_bound_sampled_quinary(pk, ps, t.plo, pe, last + 1);
       } else {
         t.phi = UINT32_MAX;
       }
