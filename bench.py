@@ -62,8 +62,8 @@ def triangle_min_bytes(edges, wedges, n_vertices):
 KERNEL_OF_SCOPE = {"leaf_aggregate": "k_leaf2_count"}
 # HBM bytes per launch of that kernel from rocprofv3 counters, used only
 # while the kernel's source matches the one the counters saw
-TRAFFIC_SUMMARY = {"plain": "triangle_rmat22_leaf2_count_traffic.txt",
-                   "learned": "triangle_rmat22_learned_leaf2_count_traffic.txt"}
+TRAFFIC_SUMMARY = {"plain": "triangle_rmat22_plain_leaf_traffic.txt",
+                   "learned": "triangle_rmat22_learned_leaf_traffic.txt"}
 # the two-set leaf's launches: every row but those of the two buckets, the
 # top bucket, the merged rows
 LEAF_SCOPES = ("leaf_aggregate", "leaf_top", "leaf_merge")
@@ -251,6 +251,7 @@ def main():
         model_bytes = leaf_model_bytes(e["rows"], e["elements"]) / e["launches"]
         kernel = KERNEL_OF_SCOPE["leaf_aggregate"]
         traffic = None
+        top_traffic = None
         summary = TRAFFIC_SUMMARY.get(head_policy)
         if summary and (args.scale, args.samples_log2) == (22, 26) and (head_policy != "plain" or args.layout == "plain"):
             from paper_1708_07859_amd import profiling
@@ -260,18 +261,34 @@ def main():
             for scope, name in (("leaf_top", kernel + "_top"), ("leaf_merge", "k_leaf2_merge")):
                 if scope in prof:
                     parts.append(profiling.read_traffic(path, name))
+                    if scope == "leaf_top":
+                        top_traffic = parts[-1]
             traffic = None if any(x is None for x in parts) else sum(parts)
+        top_ms = top["total_ms"] / e["launches"]
+        # the top bucket (rows whose two sets hold 2^14 elements or more):
+        # its own launch, timed with HIP events, its DRAM bytes from the
+        # counters (L2 misses, reads in 32-byte requests + writes)
+        top_bucket = None
+        if top["launches"]:
+            top_bucket = {"kernel": kernel + "<top>", "ms_per_launch": round(top_ms, 4),
+                          "units_per_launch": top.get("rows", 0) // max(1, top["launches"]),
+                          "dram_bytes": None if top_traffic is None else int(top_traffic),
+                          "dram_GBs": None if top_traffic is None else round(top_traffic / (top_ms / 1000) / 1e9, 1),
+                          "dram_frac": None if top_traffic is None else
+                          round(top_traffic / (top_ms / 1000) / 1e9 / HBM_PEAK_GBS, 4)}
         roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
-                "avg_launch_ms": round(avg_ms, 4), "top_bucket_ms": round(top["total_ms"] / e["launches"], 4),
+                "avg_launch_ms": round(avg_ms, 4), "top_bucket_ms": round(top_ms, 4), "top_bucket": top_bucket,
                 "merge_ms": round(prof.get("leaf_merge", {"total_ms": 0.0})["total_ms"] / e["launches"], 4),
                 "alg_bytes_per_launch": int(b_min),
                 "alg_bytes": "minimum bytes: 4 B per wedge (S(b) streamed per edge) + 4 B per edge (T(a) once) + "
                              "8 B per vertex (offsets)",
                 "model_bytes_per_launch": int(model_bytes),
                 "model_frac": round(model_bytes / (avg_ms / 1000) / 1e9 / HBM_PEAK_GBS, 4),
-                "traffic_frac": None if traffic is None else round(traffic / (avg_ms / 1000) / 1e9 / HBM_PEAK_GBS, 4)}
+                "traffic_frac": None if traffic is None else round(traffic / (avg_ms / 1000) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic_source": "rocprofv3 TCC_EA0_RDREQ_DRAM_32B_sum x 32 B + WRITE_SIZE x 1 KiB per dispatch "
+                                  "(both exact on a 1 GiB copy), from profiles/" + (summary or "")}
     config = {"workload": f"triangle COUNT on R-MAT scale {args.scale}, 2^{args.samples_log2} samples "
                           f"(a=0.57,b=0.19,c=0.19), oriented low->high, set-mode dedup",
               "edges": n_edges, "wedges": wedges, "triangles": head["count"],
