@@ -227,8 +227,26 @@ __device__ __forceinline__ double lds_round(const long long* slots, uint32_t D, 
 // digits to LDS accumulators indexed by rank - r0, which are emitted in
 // order and cleared.  No global atomics.  In both passes the products of
 // B_NT entries of A's row at a time are numbered by a block scan and dealt
-// out evenly to the threads.
+// out evenly to the threads.  A row of at most CUR_MAX entries whose
+// outputs take several rank windows keeps, per entry of A, a cursor into
+// its E row in LDS: windows are taken in increasing k, so each window's
+// products of an entry start at its cursor and end where a short gallop
+// finds the window's upper k; neither j's lookup nor the two binary
+// searches are repeated per window.
 constexpr uint32_t HC = 512;
+constexpr uint32_t CUR_MAX = 2048;
+
+// First position in [b, e) of the sorted a holding a value >= x, found by
+// galloping from b (most windows take few products of one entry).
+__device__ __forceinline__ uint32_t gallop_lower_bound(const uint32_t* a, uint32_t b, uint32_t e, uint32_t x) {
+  if (b >= e || a[b] >= x) return b;
+  uint32_t lo = b, step = 1;   // a[lo] < x
+  while (lo + step < e && a[lo + step] < x) {
+    lo += step;
+    step <<= 1;
+  }
+  return lower_bound_u32(a, lo + 1, min(lo + step, e), x);
+}
 
 __device__ __forceinline__ uint32_t rank_select(const unsigned long long* bm, const uint32_t* pre, uint32_t nwords,
                                                 uint32_t r) {
@@ -256,6 +274,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
   // scan so that every thread takes an equal share (E's rows have skewed
   // lengths, and one thread per entry would wait on the longest)
   __shared__ uint32_t s_off[B_NT], s_kb[B_NT], s_ab[B_NT], s_ae[B_NT];
+  __shared__ uint32_t s_cur[CUR_MAX], s_cend[CUR_MAX];   // per entry of A: its E row, from the next window on
   const int tid = threadIdx.x;
   uint32_t bad = 0;
   // owner of product idx: the last entry whose first product is <= idx
@@ -335,6 +354,19 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
           }
         }
       }
+      // cursors: several rank windows over one k window, few enough entries
+      const bool cursors = m > HC && I.n_k <= a.kw && qe - qb <= CUR_MAX;
+      if (cursors) {
+        for (uint32_t q = qb + tid; q < qe; q += B_NT) {
+          uint32_t pe, b = 0, e = 0;
+          if (find_j(I, I.a_j[q], pe)) {
+            b = I.e_off[pe];
+            e = I.e_off[pe + 1];
+          }
+          s_cur[q - qb] = b;
+          s_cend[q - qb] = e;
+        }
+      }
       __syncthreads();
       for (uint32_t r0 = 0; r0 < m; r0 += HC) {
         if (tid == 0) {
@@ -347,7 +379,16 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
           const uint32_t q = qs + tid;
           uint32_t cnt = 0, kb = 0, ab = 0, ae = 0;
           uint32_t pe;
-          if (q < qe && find_j(I, I.a_j[q], pe)) {
+          if (cursors) {
+            if (q < qe) {
+              // this thread alone reads and advances entry q's cursor
+              kb = s_cur[q - qb];
+              const uint32_t kend = gallop_lower_bound(I.e_k, kb, s_cend[q - qb], khi);
+              s_cur[q - qb] = kend;
+              cnt = kend - kb;
+              if (cnt) rows_of(I.a_run, q, ab, ae);
+            }
+          } else if (q < qe && find_j(I, I.a_j[q], pe)) {
             rows_of(I.a_run, q, ab, ae);
             kb = I.e_off[pe];
             uint32_t kend = I.e_off[pe + 1];
