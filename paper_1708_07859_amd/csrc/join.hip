@@ -1404,40 +1404,6 @@ __device__ __forceinline__ uint32_t bm_word(uint32_t d) {
   return w ^ ((w >> 5) & 31u);
 }
 
-// A run of n keys at p, cut into 16-byte chunks on the 16-byte grid: chunk
-// c holds the run's elements 4c - head .. 4c - head + 3 (those in [0, n)).
-struct KeyRun {
-  const uint32_t* al;   // p rounded down to 16 bytes
-  uint32_t head, n, nch;
-};
-
-__device__ __forceinline__ KeyRun key_run(const uint32_t* p, uint32_t n) {
-  KeyRun r;
-  r.head = (uint32_t)(((uintptr_t)p & 15u) >> 2);
-  r.al = p - r.head;
-  r.n = n;
-  r.nch = n ? (r.head + n + 3) / 4 : 0u;
-  return r;
-}
-
-// Chunk c of a run: one 16-byte load when the chunk lies inside the run,
-// else its elements inside the run one by one (the rest are 0).
-__device__ __forceinline__ uint4 load_chunk(const KeyRun& r, uint32_t c) {
-  const int64_t e0 = 4 * (int64_t)c - r.head;
-  if (e0 >= 0 && e0 + 4 <= (int64_t)r.n) return *reinterpret_cast<const uint4*>(r.al + 4 * (uint64_t)c);
-  uint32_t v[4];
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const int64_t e = e0 + k;
-    v[k] = (e >= 0 && e < (int64_t)r.n) ? r.al[4 * (uint64_t)c + k] : 0u;
-  }
-  return make_uint4(v[0], v[1], v[2], v[3]);
-}
-
-__device__ __forceinline__ uint32_t chunk_elem(const uint4& x, int k) {
-  return k == 0 ? x.x : k == 1 ? x.y : k == 2 ? x.z : x.w;
-}
-
 // Merge tiles: each block runs one contiguous range of the tile list (the
 // ranges of an XCD's blocks are contiguous too, so tiles of one row share
 // an L2).  A tile's two runs are loaded as 16-byte chunks, coalesced, and
