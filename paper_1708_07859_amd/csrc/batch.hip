@@ -174,12 +174,18 @@ struct BatchArgs {
   uint32_t kw;                      // k values per heavy window (multiple of 64, <= KW_MAX)
 };
 
+// LDS accumulators of the heavy and inner kernels sit DSTRIDE 8-byte slots
+// apart: with 9 (72 bytes), the same digit of different accumulators falls
+// in different LDS banks (at 8, 64 bytes apart, every accumulator's digit k
+// shared two banks and the atomics of a wave serialized on them).
+constexpr int DSTRIDE = EXACT_MAXD + 1;
+
 // A row with fewer products than this keeps its LDS accumulators in signed
 // slots: a product adds two terms, each at most one word below 2^32 to any
 // slot, so no slot can leave int64 (2 * 2^30 * 2^32 = 2^63).
 constexpr uint64_t BOUNDED_PRODUCTS = 1ull << 30;
 
-// Exact sum held in LDS slots (EXACT_MAXD stride) of one accumulator: add v.
+// Exact sum held in the LDS slots (digits) of one accumulator: add v.
 // bounded (the row has fewer than BOUNDED_PRODUCTS products): signed slots,
 // plain atomic adds whose returned values nobody waits for.  Otherwise the
 // shared slot form, which carries every wrap, so any number of terms is
@@ -267,7 +273,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
   __shared__ uint32_t pre[KW_MAX / 64];            // set bits before each word
   __shared__ uint32_t sk[HC];
   __shared__ unsigned long long scnt[HC];
-  __shared__ long long sdig[HC * EXACT_MAXD];
+  __shared__ long long sdig[HC * DSTRIDE];
   __shared__ uint32_t s_item, s_klo, s_khi;
   __shared__ uint32_t s_wsum[B_NW];
   // products of a batch of B_NT entries of A's row, numbered by a block
@@ -290,7 +296,7 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
   for (uint32_t sl = tid; sl < HC; sl += B_NT) {
     scnt[sl] = 0;
 #pragma unroll
-    for (int d = 0; d < EXACT_MAXD; d++) sdig[sl * EXACT_MAXD + d] = 0;
+    for (int d = 0; d < EXACT_MAXD; d++) sdig[sl * DSTRIDE + d] = 0;
   }
   for (;;) {
     if (tid == 0) s_item = atomicAdd(&a.qhead[0], 1u);
@@ -421,8 +427,8 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
                 for (uint32_t re = eb; re < ee; re++) {
                   double hi, lo;
                   two_prod(I.a_val[ra], I.e_val[re], hi, lo);
-                  bool ok = lds_add_term(sdig + sl * EXACT_MAXD, hi, I.lsb, I.D, bounded);
-                  ok = lds_add_term(sdig + sl * EXACT_MAXD, lo, I.lsb, I.D, bounded) && ok;
+                  bool ok = lds_add_term(sdig + sl * DSTRIDE, hi, I.lsb, I.D, bounded);
+                  ok = lds_add_term(sdig + sl * DSTRIDE, lo, I.lsb, I.D, bounded) && ok;
                   if (!ok) bad = 1;
                 }
           }
@@ -434,10 +440,10 @@ __global__ __launch_bounds__(B_NT) void k_batch_heavy(BatchArgs a) {
           const uint64_t o = out + nnz + r0 + sl;
           a.ub_k[o] = sk[sl];
           a.ub_cnt[o] = scnt[sl];
-          if (I.sum) a.ub_sum[o] = lds_round(sdig + sl * EXACT_MAXD, I.D, I.lsb, bounded, a.err);
+          if (I.sum) a.ub_sum[o] = lds_round(sdig + sl * DSTRIDE, I.D, I.lsb, bounded, a.err);
           scnt[sl] = 0;
 #pragma unroll
-          for (int d = 0; d < EXACT_MAXD; d++) sdig[sl * EXACT_MAXD + d] = 0;
+          for (int d = 0; d < EXACT_MAXD; d++) sdig[sl * DSTRIDE + d] = 0;
         }
         __syncthreads();
       }
@@ -461,14 +467,14 @@ __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
   __shared__ uint32_t pre[KW_MAX / 64];
   __shared__ uint32_t soff[B_NT + 1];                 // the chunk's column offsets
   __shared__ unsigned long long ccnt[B_NT];           // per column of the chunk
-  __shared__ long long cdig[B_NT * EXACT_MAXD];
+  __shared__ long long cdig[B_NT * DSTRIDE];
   __shared__ uint32_t s_item;
   __shared__ uint32_t s_wsum[B_NW];
   const int tid = threadIdx.x;
   uint32_t bad = 0;
   ccnt[tid] = 0;
 #pragma unroll
-  for (int d = 0; d < EXACT_MAXD; d++) cdig[tid * EXACT_MAXD + d] = 0;
+  for (int d = 0; d < EXACT_MAXD; d++) cdig[tid * DSTRIDE + d] = 0;
   for (;;) {
     if (tid == 0) s_item = atomicAdd(&a.qhead[2], 1u);
     __syncthreads();
@@ -548,8 +554,8 @@ __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
             for (uint32_t re = eb; re < ee; re++) {
               double hi, lo;
               two_prod(I.a_val[ra], I.bt_val[re], hi, lo);
-              bool ok = lds_add_term(cdig + c * EXACT_MAXD, hi, I.lsb, I.D, bounded);
-              ok = lds_add_term(cdig + c * EXACT_MAXD, lo, I.lsb, I.D, bounded) && ok;
+              bool ok = lds_add_term(cdig + c * DSTRIDE, hi, I.lsb, I.D, bounded);
+              ok = lds_add_term(cdig + c * DSTRIDE, lo, I.lsb, I.D, bounded) && ok;
               if (!ok) bad = 1;
             }
         }
@@ -562,11 +568,11 @@ __global__ __launch_bounds__(B_NT) void k_batch_inner(BatchArgs a) {
         const uint64_t o = out + nnz + r;
         a.ub_k[o] = I.bt_k[kb0 + tid];
         a.ub_cnt[o] = cnt;
-        if (I.sum) a.ub_sum[o] = lds_round(cdig + tid * EXACT_MAXD, I.D, I.lsb, bounded, a.err);
+        if (I.sum) a.ub_sum[o] = lds_round(cdig + tid * DSTRIDE, I.D, I.lsb, bounded, a.err);
       }
       ccnt[tid] = 0;
 #pragma unroll
-      for (int d = 0; d < EXACT_MAXD; d++) cdig[tid * EXACT_MAXD + d] = 0;
+      for (int d = 0; d < EXACT_MAXD; d++) cdig[tid * DSTRIDE + d] = 0;
       nnz += tot;
       __syncthreads();
     }

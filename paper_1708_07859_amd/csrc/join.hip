@@ -1741,9 +1741,6 @@ __global__ void k_seg_accumulate(SegAccArgs a, uint64_t n) {
 // A dispatch counts work-items in 32 bits: cap the grid and let blocks
 // stride over virtual blocks.
 unsigned elem_grid(uint64_t nvblk) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nvblk, 32768)); }
-// The two-set leaf walks its virtual blocks with more workgroups in flight
-// than the frontier kernels: 131072 (512 per CU) measured 6% faster than
-// 32768 on R-MAT-22 triangles, while larger grids lose again.
 // The merge launch: as many blocks as fit on the device at once; each loops
 // over a contiguous range of tiles, loading the next while counting one.
 unsigned merge_grid() {
@@ -1753,6 +1750,9 @@ unsigned merge_grid() {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_leaf2_merge, M_NT, 0) != hipSuccess) per = 1;
   return (unsigned)std::max(1, cus * std::max(1, per));
 }
+// The two-set leaf walks its virtual blocks with more workgroups in flight
+// than the frontier kernels: 131072 (512 per CU) measured 6% faster than
+// 32768 on R-MAT-22 triangles, while larger grids lose again.
 unsigned leaf_grid(uint64_t nvblk) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nvblk, 131072)); }
 
 unsigned grid_for(uint64_t n) {
