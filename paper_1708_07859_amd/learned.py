@@ -255,6 +255,13 @@ def training_queries():
         qs.append(("spmv zipf %d" % n, queries.spmv(synth.zipf_degree_matrix(n, 1.1, 16, rng), x)))
     s = synth.star_schema(n_fact=400_000, dims=(40_000, 10_000, 2000, 200), seed=31)
     qs.append(("star", queries.star(s, u_hi=0.2, m2=0, m3=0)))
+    # larger stars, where re-sorting the fact relation for an order costs as
+    # much as the join itself; the benchmark's 60 M-row schema (seed 3) is
+    # held out
+    for n_fact, dims, seed in ((4_000_000, (400_000, 100_000, 20_000, 2000), 34),
+                               (16_000_000, (1_000_000, 250_000, 50_000, 5000), 35)):
+        s = synth.star_schema(n_fact=n_fact, dims=dims, seed=seed)
+        qs.append(("star %dM" % (n_fact // 1_000_000), queries.star(s, u_hi=0.2, m2=0, m3=0)))
     # the cycle node of a Q5-shaped multi-node plan (customer, orders with a
     # date window, lineitem, supplier, and the selected nations), at scale
     # factors 1 and 2; the sf 10 schema (seed 5) is held out

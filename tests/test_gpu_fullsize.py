@@ -30,8 +30,8 @@ SCALE, SAMPLES_LOG2 = 22, 26
 # the order the learned model picks for the triangle with the committed
 # weights: c, b, a (the plan re-sorts the edges into (high, low) order)
 LEARNED_TRIANGLE_ORDER = [2, 1, 0]
-# and for the star: k3, k0, k2, k1
-LEARNED_STAR_ORDER = [3, 0, 2, 1]
+# and for the star: k0, k1, k2, k3
+LEARNED_STAR_ORDER = [0, 1, 2, 3]
 
 
 def say(*a):
