@@ -99,11 +99,28 @@ TO scan_impl(const TI* in, TO* out, uint64_t n, hipStream_t s) {
 
 // Maximum of a column: a block reduction, then one atomic per block (the
 // grid is capped, so the atomics on the single result stay few).
+// Largest of in[0, n).  The body is read as 16-byte vectors, four rounds
+// in flight per thread; the elements before the first 16-byte boundary and
+// after the last whole vector are read singly.
 __global__ __launch_bounds__(256) void k_reduce_max_u32(const uint32_t* in, uint64_t n, uint32_t* out) {
   __shared__ uint32_t s_m[256 / WAVE];
+  const uint64_t head = min<uint64_t>(n, (4u - (((uintptr_t)in >> 2) & 3u)) & 3u);
+  const uint4* body = reinterpret_cast<const uint4*>(in + head);
+  const uint64_t nv = (n - head) / 4, tail = head + nv * 4;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
   uint32_t m = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    m = max(m, in[i]);
+  if (gid < head) m = in[gid];
+  if (gid < n - tail) m = max(m, in[tail + gid]);
+  uint64_t i = gid;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    const uint4 a = body[i], b = body[i + stride], c = body[i + 2 * stride], d = body[i + 3 * stride];
+    m = max(m, max(max(max(a.x, a.y), max(a.z, a.w)), max(max(b.x, b.y), max(b.z, b.w))));
+    m = max(m, max(max(max(c.x, c.y), max(c.z, c.w)), max(max(d.x, d.y), max(d.z, d.w))));
+  }
+  for (; i < nv; i += stride) {
+    const uint4 a = body[i];
+    m = max(m, max(max(a.x, a.y), max(a.z, a.w)));
+  }
 #pragma unroll
   for (int d = WAVE / 2; d > 0; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, WAVE));
   if (lane_id() == 0) s_m[threadIdx.x / WAVE] = m;
@@ -146,14 +163,49 @@ unsigned grid_for(uint64_t n) {
 // LSD radix sort, 8-bit digits.  Per pass: tile histograms (digit-major, so
 // an exclusive scan yields every tile's first slot per digit), then a
 // stable scatter that ranks equal digits inside a wave with eight ballots
-// and across the block's waves through LDS.
+// and across the block's waves through LDS.  A sort of key columns reads
+// the columns in its first pass (packing each row's key on the fly) and
+// writes the sorted columns in its last (unpacking them), so no pass of
+// its own packs or unpacks.
 // ---------------------------------------------------------------------------
 constexpr int RS_NT = 256;
 constexpr int RS_ITEMS = 8;
 constexpr int RS_TILE = RS_NT * RS_ITEMS;
 constexpr int RS_NW = RS_NT / WAVE;
 
-__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, uint64_t n, uint32_t shift,
+// Key columns packed into one word: column c at bit shift[c].
+struct PackArgs {
+  const uint32_t* col[LH_MAX_KEYS];
+  uint32_t shift[LH_MAX_KEYS];
+  uint32_t ncols;
+};
+
+// One word unpacked into key columns: bits[c] bits at shift[c].
+struct UnpackCols {
+  uint32_t* col[LH_MAX_KEYS];
+  uint32_t shift[LH_MAX_KEYS];
+  uint32_t bits[LH_MAX_KEYS];
+  uint32_t ncols;
+};
+
+__device__ __forceinline__ uint64_t pack_row(const PackArgs& a, uint64_t r) {
+  uint64_t k = 0;
+#pragma unroll
+  for (uint32_t c = 0; c < LH_MAX_KEYS; c++)
+    if (c < a.ncols) k |= (uint64_t)a.col[c][r] << a.shift[c];
+  return k;
+}
+
+__device__ __forceinline__ void unpack_row(const UnpackCols& a, uint64_t r, uint64_t k) {
+#pragma unroll
+  for (uint32_t c = 0; c < LH_MAX_KEYS; c++)
+    if (c < a.ncols) a.col[c][r] = a.bits[c] ? (uint32_t)((k >> a.shift[c]) & ((1ull << a.bits[c]) - 1)) : 0u;
+}
+
+// FROM_COLS: the keys are packed from the columns of `pa` (else read from
+// `keys`).
+template <bool FROM_COLS>
+__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, PackArgs pa, uint64_t n, uint32_t shift,
                                                    uint32_t* hist, uint32_t ntiles) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -162,7 +214,10 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, uint64_
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; i++) {
     uint64_t idx = base + (uint64_t)i * RS_NT + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    if (idx < n) {
+      const uint64_t k = FROM_COLS ? pack_row(pa, idx) : keys[idx];
+      atomicAdd(&h[(uint32_t)(k >> shift) & 255u], 1u);
+    }
   }
   __syncthreads();
   hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
@@ -172,11 +227,15 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, uint64_
 // a wave, LDS counts across waves), placed in LDS in digit order, then
 // written out in that order, so each digit's run of the tile goes to
 // consecutive global slots (coalesced writes).
-// HAS_V: a 32-bit value travels with each key (else keys only)
-template <bool HAS_V>
-__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
-                                                      uint32_t* vout, uint64_t n, uint32_t shift,
-                                                      const uint32_t* offs, const uint32_t* hist, uint32_t ntiles) {
+// HAS_V: a 32-bit value travels with each key (else keys only); a null
+// `vin` gives every element its input position as value.
+// FROM_COLS: keys packed from the columns of `pa` (else read from `kin`).
+// TO_COLS: sorted keys unpacked into the columns of `ua` (else to `kout`).
+template <bool HAS_V, bool FROM_COLS, bool TO_COLS>
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, PackArgs pa, const uint32_t* vin,
+                                                      uint64_t* kout, UnpackCols ua, uint32_t* vout, uint64_t n,
+                                                      uint32_t shift, const uint32_t* offs, const uint32_t* hist,
+                                                      uint32_t ntiles) {
   __shared__ uint64_t sk[RS_TILE];
   __shared__ uint32_t sv[HAS_V ? RS_TILE : 1];
   __shared__ uint32_t lstart[256];   // first slot of each digit in the tile
@@ -199,9 +258,10 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; i++) {
     const uint32_t li = (uint32_t)i * RS_NT + tid;
-    kk[i] = li < ntile ? kin[base + li] : 0;
+    if constexpr (FROM_COLS) kk[i] = li < ntile ? pack_row(pa, base + li) : 0;
+    else kk[i] = li < ntile ? kin[base + li] : 0;
     vv[i] = 0;
-    if constexpr (HAS_V) vv[i] = li < ntile ? vin[base + li] : 0u;
+    if constexpr (HAS_V) vv[i] = li < ntile ? (vin ? vin[base + li] : (uint32_t)(base + li)) : 0u;
   }
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; i++) {
@@ -241,42 +301,31 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const
     const uint64_t k = sk[t];
     const uint32_t d = (uint32_t)(k >> shift) & 255u;
     const uint32_t pos = offs[(uint64_t)d * ntiles + blockIdx.x] + (t - lstart[d]);
-    kout[pos] = k;
+    if constexpr (TO_COLS) unpack_row(ua, pos, k);
+    else kout[pos] = k;
     if constexpr (HAS_V) vout[pos] = sv[t];
   }
 }
 
-struct PackArgs {
-  const uint32_t* col[LH_MAX_KEYS];
-  uint32_t shift[LH_MAX_KEYS];
-  uint32_t ncols;
-};
-
-struct UnpackCols {
-  uint32_t* col[LH_MAX_KEYS];
-  uint32_t shift[LH_MAX_KEYS];
-  uint32_t bits[LH_MAX_KEYS];
-  uint32_t ncols;
-};
-
-__global__ void k_unpack_cols(UnpackCols a, const uint64_t* keys, uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t k = keys[i];
-#pragma unroll
-    for (uint32_t c = 0; c < LH_MAX_KEYS; c++)
-      if (c < a.ncols) a.col[c][i] = a.bits[c] ? (uint32_t)((k >> a.shift[c]) & ((1ull << a.bits[c]) - 1)) : 0u;
-  }
+template <bool HAS_V>
+void launch_rs_scatter(bool from_cols, bool to_cols, unsigned grid, hipStream_t s, const uint64_t* kin,
+                       const PackArgs& pa, const uint32_t* vin, uint64_t* kout, const UnpackCols& ua, uint32_t* vout,
+                       uint64_t n, uint32_t shift, const uint32_t* offs, const uint32_t* hist, uint32_t ntiles) {
+  if (from_cols && to_cols)
+    k_rs_scatter<HAS_V, true, true><<<grid, RS_NT, 0, s>>>(kin, pa, vin, kout, ua, vout, n, shift, offs, hist, ntiles);
+  else if (from_cols)
+    k_rs_scatter<HAS_V, true, false><<<grid, RS_NT, 0, s>>>(kin, pa, vin, kout, ua, vout, n, shift, offs, hist, ntiles);
+  else if (to_cols)
+    k_rs_scatter<HAS_V, false, true><<<grid, RS_NT, 0, s>>>(kin, pa, vin, kout, ua, vout, n, shift, offs, hist, ntiles);
+  else
+    k_rs_scatter<HAS_V, false, false><<<grid, RS_NT, 0, s>>>(kin, pa, vin, kout, ua, vout, n, shift, offs, hist,
+                                                             ntiles);
+  LH_HIP(hipGetLastError());
 }
 
 __global__ void k_pack(PackArgs a, const uint32_t* perm, uint64_t* out, uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t r = perm ? perm[i] : (uint32_t)i;
-    uint64_t k = 0;
-#pragma unroll
-    for (uint32_t c = 0; c < LH_MAX_KEYS; c++)
-      if (c < a.ncols) k |= (uint64_t)a.col[c][r] << a.shift[c];
-    out[i] = k;
-  }
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = pack_row(a, perm ? perm[i] : (uint32_t)i);
 }
 
 __device__ __forceinline__ int32_t lowest_bit_exp(double v) {
@@ -347,7 +396,7 @@ uint32_t reduce_max_u32(const uint32_t* in, uint64_t n, hipStream_t s) {
   DBuf<uint32_t> r(1, s);
   LH_HIP(hipMemsetAsync(r.p, 0, sizeof(uint32_t), s));
   if (n) {
-    k_reduce_max_u32<<<std::min(grid_for(n), 1024u), 256, 0, s>>>(in, n, r.p);
+    k_reduce_max_u32<<<std::min(grid_for((n + 3) / 4), 2048u), 256, 0, s>>>(in, n, r.p);
     LH_HIP(hipGetLastError());
   }
   return read_scalar(r.p, s);
@@ -431,42 +480,68 @@ void gather_f64(const double* src, const uint32_t* idx, double* dst, uint64_t n,
   LH_HIP(hipGetLastError());
 }
 
+namespace {
+
+// The passes of one radix sort over bits [lo_bit, lo_bit + 8 * passes) of
+// the keys.  The first pass reads `pa`'s columns when from_cols (else
+// kin) and, when vals are wanted, `vin` (null: input positions).  Pass p
+// writes kbuf[(p + phase) & 1] and vbuf[(p + phase) & 1], except that
+// the last writes `ua`'s columns instead of keys when to_cols.
+void radix_passes(const uint64_t* kin, const PackArgs& pa, bool from_cols, const uint32_t* vin, bool vals,
+                  uint64_t* const kbuf[2], const UnpackCols& ua, bool to_cols, uint32_t* const vbuf[2],
+                  uint32_t phase, uint64_t n, uint32_t lo_bit, uint32_t passes, hipStream_t s) {
+  const uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
+  const uint64_t hn = (uint64_t)ntiles * 256;
+  DBuf<uint32_t> hist(hn, s), offs(hn + 1, s);
+  const uint64_t in_bytes = from_cols ? 4ull * pa.ncols : 8ull, out_bytes = to_cols ? 4ull * ua.ncols : 8ull;
+  const uint64_t* ki = kin;
+  const uint32_t* vi = vin;
+  for (uint32_t p = 0; p < passes; p++) {
+    const uint32_t shift = lo_bit + p * 8;
+    const bool first = p == 0, last = p + 1 == passes;
+    const bool fc = first && from_cols, tc = last && to_cols;
+    {
+      // elements: the pass's algorithmic bytes (its keys read)
+      ProfScope ps("sort_hist", s, n, (fc ? in_bytes : 8) * n);
+      if (fc) k_rs_hist<true><<<ntiles, RS_NT, 0, s>>>(nullptr, pa, n, shift, hist.p, ntiles);
+      else k_rs_hist<false><<<ntiles, RS_NT, 0, s>>>(ki, pa, n, shift, hist.p, ntiles);
+    }
+    LH_HIP(hipGetLastError());
+    scan_u32(hist.p, offs.p, hn, s);
+    uint64_t* ko = tc ? nullptr : kbuf[(p + phase) & 1];
+    uint32_t* vo = vals ? vbuf[(p + phase) & 1] : nullptr;
+    {
+      // elements: the pass's algorithmic bytes (keys, and values when they
+      // travel, read once and written once; values made from positions
+      // are written only)
+      const uint64_t vb = vals ? (vi ? 8 : 4) : 0;
+      ProfScope ps("sort_scatter", s, n, ((fc ? in_bytes : 8) + (tc ? out_bytes : 8) + vb) * n);
+      if (vals) launch_rs_scatter<true>(fc, tc, ntiles, s, ki, pa, vi, ko, ua, vo, n, shift, offs.p, hist.p, ntiles);
+      else launch_rs_scatter<false>(fc, tc, ntiles, s, ki, pa, nullptr, ko, ua, nullptr, n, shift, offs.p, hist.p,
+                                    ntiles);
+    }
+    ki = ko;
+    vi = vo;
+  }
+}
+
+}  // namespace
+
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tkeys, uint32_t* tvals, uint64_t n,
                       uint32_t bits, hipStream_t s, uint32_t lo_bit) {
   // vals == nullptr: keys only
   if (n <= 1 || bits <= lo_bit) return;
   if (n >= (1ull << 32)) fail(LH_ERR_OVERFLOW, "radix sort: more than 2^32 - 1 keys");
-  uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
-  uint64_t hn = (uint64_t)ntiles * 256;
-  DBuf<uint32_t> hist(hn, s), offs(hn + 1, s);
-  uint64_t* ki = keys;
-  uint32_t* vi = vals;
-  uint64_t* ko = tkeys;
-  uint32_t* vo = tvals;
-  uint32_t passes = (bits - lo_bit + 7) / 8;
-  for (uint32_t p = 0; p < passes; p++) {
-    uint32_t shift = lo_bit + p * 8;
-    {
-      // elements: the pass's algorithmic bytes (the u64 keys read)
-      ProfScope ps("sort_hist", s, n, 8 * n);
-      k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ki, n, shift, hist.p, ntiles);
-    }
-    LH_HIP(hipGetLastError());
-    scan_u32(hist.p, offs.p, hn, s);
-    {
-      // elements: the pass's algorithmic bytes (u64 keys, and u32 values
-      // when they travel, read once and written once)
-      ProfScope ps("sort_scatter", s, n, (vi ? 24 : 16) * n);
-      if (vals) k_rs_scatter<true><<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, offs.p, hist.p, ntiles);
-      else k_rs_scatter<false><<<ntiles, RS_NT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, offs.p, hist.p, ntiles);
-    }
-    LH_HIP(hipGetLastError());
-    std::swap(ki, ko);
-    std::swap(vi, vo);
-  }
-  if (ki != keys) {
-    LH_HIP(hipMemcpyAsync(keys, ki, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    if (vals) LH_HIP(hipMemcpyAsync(vals, vi, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  const uint32_t passes = (bits - lo_bit + 7) / 8;
+  // pass p writes buffer (p + 1) & 1: the first writes the temporaries,
+  // the last the caller's buffers when the count is even
+  uint64_t* const kbuf[2] = {keys, tkeys};
+  uint32_t* const vbuf[2] = {vals, tvals};
+  radix_passes(keys, PackArgs{}, false, vals, vals != nullptr, kbuf, UnpackCols{}, false, vbuf, 1, n, lo_bit, passes,
+               s);
+  if (passes & 1) {
+    LH_HIP(hipMemcpyAsync(keys, tkeys, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    if (vals) LH_HIP(hipMemcpyAsync(vals, tvals, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   }
 }
 
@@ -506,8 +581,8 @@ bool sort_packed(const uint32_t* const* cols, const uint32_t* bits, uint32_t nco
   uint32_t tot = 0;
   for (uint32_t c = 0; c < ncols; c++) tot += bits[c];
   if (tot > 64 || ncols > LH_MAX_KEYS) return false;
-  DBuf<uint64_t> k(n, s), tk(n, s);
-  DBuf<uint32_t> tv(perm ? n : 0, s);
+  if (!n) return true;
+  if (n >= (1ull << 32)) fail(LH_ERR_OVERFLOW, "radix sort: more than 2^32 - 1 keys");
   PackArgs a{};
   UnpackCols u{};
   a.ncols = u.ncols = ncols;
@@ -519,16 +594,28 @@ bool sort_packed(const uint32_t* const* cols, const uint32_t* bits, uint32_t nco
     u.col[c] = sorted[c];
     sh += bits[c];
   }
-  if (perm) iota_u32(perm, n, s);
-  if (n) {
-    k_pack<<<grid_for(n), 256, 0, s>>>(a, nullptr, k.p, n);
-    LH_HIP(hipGetLastError());
-    uint32_t tail_bits = 0;
-    for (uint32_t c = ncols - std::min(sorted_tail, ncols); c < ncols; c++) tail_bits += bits[c];
-    radix_sort_pairs(k.p, perm, tk.p, tv.p, n, tot, s, tail_bits);
-    k_unpack_cols<<<grid_for(n), 256, 0, s>>>(u, k.p, n);
-    LH_HIP(hipGetLastError());
+  uint32_t tail_bits = 0;
+  for (uint32_t c = ncols - std::min(sorted_tail, ncols); c < ncols; c++) tail_bits += bits[c];
+  const uint32_t passes = tot > tail_bits ? (tot - tail_bits + 7) / 8 : 0;
+  if (!passes) {
+    // in order already: every value fits its column's bits, so the sorted
+    // columns are copies
+    for (uint32_t c = 0; c < ncols; c++)
+      LH_HIP(hipMemcpyAsync(sorted[c], cols[c], n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (perm) iota_u32(perm, n, s);
+    return true;
   }
+  // the first pass packs the columns, the last unpacks into `sorted`; the
+  // permutation starts as the input positions and ends in perm
+  DBuf<uint64_t> k(passes > 1 ? n : 0, s), tk(passes > 2 ? n : 0, s);
+  DBuf<uint32_t> tv(perm && passes > 1 ? n : 0, s);
+  uint64_t* const kbuf[2] = {k.p, tk.p};
+  uint32_t* const vbuf[2] = {perm, tv.p};
+  // pass p writes buffer (p + phase) & 1: the last writes vbuf[0] = perm,
+  // the first writes kbuf[0] = k
+  const uint32_t phase = (passes - 1) & 1;
+  uint64_t* const kb[2] = {kbuf[phase], kbuf[phase ^ 1]};
+  radix_passes(nullptr, a, true, nullptr, perm != nullptr, kb, u, true, vbuf, phase, n, tail_bits, passes, s);
   return true;
 }
 

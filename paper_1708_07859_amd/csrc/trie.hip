@@ -63,6 +63,7 @@ struct EmitArgs {
   uint32_t* offs_out[LH_MAX_KEYS];   // level child offsets (levels 0..L-2)
   uint32_t* run_out;                 // bag: leaf run starts (sorted-row index); may be null
   uint32_t* kept_out;                // set: sorted-row index of each kept row; may be null
+  uint32_t* rowkeys_out[LH_MAX_KEYS]; // set: every level's key of each kept row; null when not wanted
   uint32_t* parent_out[LH_MAX_KEYS]; // level l >= 1: the level l-1 node above each node; may be null
   const uint32_t* tile_off;          // [l * ntiles + tile]
   uint32_t ntiles;
@@ -106,6 +107,11 @@ __global__ __launch_bounds__(TB_NT) void k_emit_levels(EmitArgs a, uint64_t n) {
     if (l + 1 == L) {
       if (a.run_out) a.run_out[pos] = (uint32_t)r;
       if (a.kept_out) a.kept_out[pos] = (uint32_t)r;
+      if (a.rowkeys_out[0]) {
+#pragma unroll
+        for (uint32_t j = 0; j < LH_MAX_KEYS; j++)
+          if (j < L) a.rowkeys_out[j][pos] = a.c.k[j][r];
+      }
     }
     pos_prev = pos;
   }
@@ -505,8 +511,16 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
     t->lv[n_keys - 1].offs.alloc(n_leaf + 1, s);
     ea.run_out = t->lv[n_keys - 1].offs.p;
   } else {
-    kept.alloc(n_leaf, s);
-    ea.kept_out = kept.p;
+    // a set keeps the leaf heads' rows: their keys are written as the
+    // heads are found (the row positions only when columns follow them)
+    for (uint32_t l = 0; l < n_keys; l++) {
+      t->skeys[l].alloc(n_leaf, s);
+      ea.rowkeys_out[l] = t->skeys[l].p;
+    }
+    if (need_perm) {
+      kept.alloc(n_leaf, s);
+      ea.kept_out = kept.p;
+    }
   }
   // parents of each level's nodes, for the bitset fill of levels below 0
   std::vector<DBuf<uint32_t>> parent(n_keys);
@@ -541,23 +555,17 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
 
   // Rows in trie order: bag keeps every sorted row, set keeps leaf heads.
   // Their keys are the sorted columns themselves (bag), or the sorted
-  // columns at the leaf heads, an increasing, nearly sequential gather (set).
+  // columns at the leaf heads, written by the level emission (set).
   t->n_rows = bag ? n : n_leaf;
   const uint32_t* rowsel = perm.p;  // sorted position -> input row
   DBuf<uint32_t> keptrows;
-  if (!bag && (n_annos || n_meta)) {  // (a set relation carries neither; kept for safety)
+  if (!bag && need_perm) {  // (a set relation carries neither; kept for safety)
     keptrows.alloc(n_leaf, s);
     gather_u32(perm.p, kept.p, keptrows.p, n_leaf, s);
     rowsel = keptrows.p;
   }
-  for (uint32_t l = 0; l < n_keys; l++) {
-    if (bag) {
-      t->skeys[l] = std::move(sorted[l]);
-    } else {
-      t->skeys[l].alloc(t->n_rows, s);
-      gather_u32(lc.k[l], kept.p, t->skeys[l].p, t->n_rows, s);
-    }
-  }
+  if (bag)
+    for (uint32_t l = 0; l < n_keys; l++) t->skeys[l] = std::move(sorted[l]);
   // annotation / meta columns (bag relations only); `sel` maps rows first
   DBuf<uint32_t> srcrow;
   const uint32_t* rowmap = rowsel;
