@@ -203,25 +203,41 @@ __global__ void k_layout_desc(SetRange sr, const uint32_t* keys, uint64_t n_sets
   }
 }
 
-// Bitset words from the keys: the first key of each (set, word) pair ORs in
-// the bits of the keys that follow it in the same word (at most 64) and
-// writes the word; words without keys stay zero.
-__global__ void k_layout_fill(const uint32_t* keys, const uint32_t* parent, uint64_t n, const uint64_t* bs_word,
-                              const uint32_t* bs_base, uint64_t* pool) {
-  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t st = parent ? parent[j] : 0u;
-    const uint64_t w0 = bs_word[st];
-    if (w0 == UINT64_MAX) continue;
-    const uint32_t base = bs_base[st];
-    const uint32_t word = (keys[j] - base) >> 6;
-    if (j > 0 && (!parent || parent[j - 1] == st) && ((keys[j - 1] - base) >> 6) == word) continue;
-    uint64_t bits = 0;
-    for (uint64_t t = j; t < n && (!parent || parent[t] == st); t++) {
-      const uint32_t d = keys[t] - base;
-      if ((d >> 6) != word) break;
-      bits |= 1ull << (d & 63u);
+// Bitset words from the keys.  A wave takes 64 consecutive keys; the keys
+// of one (set, word) pair are consecutive (keys are sorted within a set, and
+// sets follow each other), so a suffix OR over the lanes of each pair
+// gathers a word's bits in the pair's first lane, which writes it.  A pair
+// whose keys reach the wave's first or last lane may go on in the
+// neighbouring wave: that part is ORed atomically into the word (the pool
+// starts zeroed); words without keys stay zero.  Null bs_word: the keys
+// form one set whose window starts at 0 at word 0 (the root index).
+__global__ __launch_bounds__(256) void k_layout_fill(const uint32_t* keys, const uint32_t* parent, uint64_t n,
+                                                     const uint64_t* bs_word, const uint32_t* bs_base, uint64_t* pool) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); j0 < n; j0 += stride) {
+    const uint64_t j = j0 + lane;
+    uint64_t tag = ~0ull, bits = 0, w = 0;  // tag: set << 32 | word (words < 2^26), ~0 for no key
+    if (j < n) {
+      const uint32_t st = parent ? parent[j] : 0u;
+      const uint64_t w0 = bs_word ? bs_word[st] : 0u;
+      if (w0 != UINT64_MAX) {
+        const uint32_t d = keys[j] - (bs_word ? bs_base[st] : 0u);
+        tag = ((uint64_t)st << 32) | (d >> 6);
+        bits = 1ull << (d & 63u);
+        w = w0 + (d >> 6);
+      }
     }
-    pool[w0 + word] = bits;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const uint64_t ob = __shfl_down(bits, o, WAVE), ot = __shfl_down(tag, o, WAVE);
+      if (lane + o < WAVE && ot == tag) bits |= ob;
+    }
+    const uint64_t prev = __shfl_up(tag, 1, WAVE), last = __shfl(tag, WAVE - 1, WAVE);
+    if (tag != ~0ull && (lane == 0 || prev != tag)) {
+      if ((lane == 0 && j > 0) || last == tag) atomicOr((unsigned long long*)&pool[w], (unsigned long long)bits);
+      else pool[w] = bits;
+    }
   }
 }
 
@@ -237,13 +253,6 @@ __global__ void k_rank_delta(SetRange sr, uint64_t n_sets, const uint64_t* bs_wo
     set_range(sr, s, b, e);
     const uint64_t w = bs_word[s];
     delta[s] = w != UINT64_MAX ? b - rank[w] : 0u;
-  }
-}
-
-__global__ void k_root_bits(const uint32_t* keys, uint64_t n, uint64_t* bits) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = keys[i];
-    atomicOr((unsigned long long*)&bits[k >> 6], 1ull << (k & 63u));
   }
 }
 
@@ -608,7 +617,7 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
       t->root_bits.alloc(words, s);
       t->root_rank.alloc(words + 1, s);
       LH_HIP(hipMemsetAsync(t->root_bits.p, 0, words * sizeof(uint64_t), s));
-      k_root_bits<<<grid_for(n0), 256, 0, s>>>(t->lv[0].keys.p, n0, t->root_bits.p);
+      k_layout_fill<<<grid_for(n0), 256, 0, s>>>(t->lv[0].keys.p, nullptr, n0, nullptr, nullptr, t->root_bits.p);
       LH_HIP(hipGetLastError());
       DBuf<uint32_t> pc(words, s);
       k_word_popc<<<grid_for(words), 256, 0, s>>>(t->root_bits.p, words, pc.p);
