@@ -958,7 +958,7 @@ BInst describe(const lh_plan_t* p) {
 
 // E transposed: the same rows keyed (k, j), bag semantics, sorted arrays.
 lh_trie* transpose_e(const lh_trie* te, int32_t anno, hipStream_t s) {
-  const uint32_t* keys[2] = {te->skeys[0].p, te->skeys[1].p};
+  const uint32_t* keys[2] = {row_keys(te, 0), row_keys(te, 1)};
   const double* annos[1] = {anno >= 0 ? te->annos[anno].p : nullptr};
   const uint32_t level_order[2] = {1, 0};
   return build_trie(te->n_rows, 2, keys, anno >= 0 ? 1u : 0u, annos, 0, nullptr, level_order,

@@ -218,14 +218,21 @@ struct lh_trie {
   // two-level tries whose column statistics were taken: the rows sorted by
   // (level 1, level 0), as level-1 and level-0 keys
   lh::DBuf<uint32_t> tsorted[2];
-  // rows in trie order (bag: every row; set: one per distinct tuple)
-  lh::DBuf<uint32_t> skeys[LH_MAX_KEYS];   // per level
+  // rows in trie order (bag: every row; set: one per distinct tuple), per
+  // level; a set's last level is not kept here (its rows' last keys are
+  // that level's keys): read columns through lh::row_keys
+  lh::DBuf<uint32_t> skeys[LH_MAX_KEYS];
   std::vector<lh::DBuf<double>> annos;      // per annotation column
   std::vector<lh::DBuf<uint32_t>> meta;     // per meta column
   std::vector<lh::AnnoStats> astats;
 };
 
 namespace lh {
+
+// Level l's column of the trie's rows, in trie order.
+inline const uint32_t* row_keys(const lh_trie* t, uint32_t l) {
+  return (!(t->flags & LH_BAG) && l + 1 == t->n_levels) ? t->lv[l].keys.p : t->skeys[l].p;
+}
 
 constexpr uint32_t TRIE_MAGIC = 0x54524945u;
 constexpr uint32_t PLAN_MAGIC = 0x504c414eu;

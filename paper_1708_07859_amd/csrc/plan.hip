@@ -71,7 +71,7 @@ lh_trie* filtered_or_reordered(const lh_trie* t, const uint32_t* level_order, co
                                hipStream_t s) {
   // columns of the trie's rows in the relation's own column order
   const uint32_t* keys[LH_MAX_KEYS];
-  for (uint32_t l = 0; l < t->n_levels; l++) keys[t->level_order[l]] = t->skeys[l].p;
+  for (uint32_t l = 0; l < t->n_levels; l++) keys[t->level_order[l]] = row_keys(t, l);
   // the swapped order of a two-level trie whose rows were already sorted
   // that way (by the column statistics): no sort at all
   if (filt.empty() && t->n_levels == 2 && t->tsorted[0].p && level_order[0] == t->level_order[1] &&
@@ -193,7 +193,7 @@ lh_plan_t* make_plan(const lh_query* q, hipStream_t s) {
       case LH_EQ_KEY: {
         if (f.col >= t->n_levels) fail(LH_ERR_INVALID, "filter key column out of range");
         for (uint32_t l = 0; l < t->n_levels; l++)
-          if (t->level_order[l] == f.col) d.ucol = t->skeys[l].p;
+          if (t->level_order[l] == f.col) d.ucol = row_keys(t, l);
         eqsel[f.atom] = true;
         break;
       }

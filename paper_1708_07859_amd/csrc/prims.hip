@@ -412,17 +412,125 @@ uint64_t select_flagged(const uint32_t* flags, uint64_t n, uint32_t* out, hipStr
   return m;
 }
 
-// Histogram of a column.  Runs of equal values inside a wave (the sorted
-// first column is long runs) are added with one atomic per run.
-__global__ void k_run_heads(const uint32_t* v, uint64_t n, uint32_t* head) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    head[i] = (i == 0 || v[i] != v[i - 1]) ? 1u : 0u;
+// Runs of a sorted column: their number and the longest.  A wave takes
+// RS_GROUPS groups of 64 consecutive values, all loads issued together; a
+// ballot of each group's run heads gives every run that ends inside the
+// group its length, and a run still going at a group's end is carried into
+// the next group.  One still going at the wave's last value is followed
+// into the next 64 values with one more load and a ballot; only a run
+// longer than that gallops to its end (probes 1, 2, 4, ... past them, then
+// bisects the last step).  Each block writes its count and longest run
+// (atomics of every block on one address would serialize).
+constexpr int RS_GROUPS = 8;
+
+struct RunStats {
+  unsigned long long distinct;
+  unsigned int longest;
+  unsigned int pad;
+};
+
+__global__ __launch_bounds__(256) void k_run_stats(const uint32_t* v, uint64_t n, RunStats* part) {
+  __shared__ uint32_t s_red[256 / WAVE];
+  const int lane = lane_id();
+  uint32_t heads = 0, longest = 0;
+  constexpr uint64_t span = (uint64_t)RS_GROUPS * WAVE;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const uint64_t nwaves = (uint64_t)gridDim.x * blockDim.x / WAVE;
+  for (uint64_t c0 = wave * span; c0 < n; c0 += nwaves * span) {
+    uint32_t xs[RS_GROUPS];
+#pragma unroll
+    for (int g = 0; g < RS_GROUPS; g++) {
+      const uint64_t i = c0 + (uint64_t)g * WAVE + lane;
+      xs[g] = i < n ? v[i] : 0u;
+    }
+    const uint32_t before = c0 > 0 ? v[c0 - 1] : 0u;
+    bool open = false;      // a run started at os (value xo) is still going (uniform over the wave)
+    uint64_t os = 0;
+    uint32_t xo = 0;
+#pragma unroll
+    for (int g = 0; g < RS_GROUPS; g++) {
+      const uint64_t g0 = c0 + (uint64_t)g * WAVE, i = g0 + lane;
+      const uint32_t x = xs[g];
+      const uint32_t last_before = g ? (uint32_t)__shfl((int)xs[g > 0 ? g - 1 : 0], WAVE - 1, WAVE) : before;
+      uint32_t p = (uint32_t)__shfl_up((int)x, 1, WAVE);
+      if (lane == 0) p = last_before;
+      const bool head = i < n && (i == 0 || p != x);
+      const uint64_t Hh = ballot(head);
+      // lanes past the end count as heads: a run ends at the next set bit
+      const uint64_t H = Hh | ballot(i >= n);
+      if (open && H) {
+        if (lane == 0) longest = max(longest, (uint32_t)(g0 + (uint64_t)__builtin_ctzll(H) - os));
+        open = false;
+      }
+      if (head) heads++;
+      const uint64_t above = lane < WAVE - 1 ? H >> (lane + 1) : 0ull;
+      if (head && above) longest = max(longest, (uint32_t)__builtin_ctzll(above) + 1u);
+      // the last head's run reaches the group's last lane (every lane in range)
+      if (Hh && !((H >> (63 - __builtin_clzll(Hh))) >> 1)) {
+        open = true;
+        os = g0 + (uint64_t)(63 - __builtin_clzll(Hh));
+        xo = (uint32_t)__shfl((int)x, WAVE - 1, WAVE);
+      }
+    }
+    if (open) {  // it reaches c0 + span - 1 < n
+      const uint64_t e0 = c0 + span, k = e0 + lane;
+      const uint64_t D = ballot(k >= n || v[k] != xo);
+      uint64_t end = e0 + (D ? (uint64_t)__builtin_ctzll(D) : 0u);
+      if (!D && lane == 0) {
+        uint64_t lo = e0 + WAVE - 1, step = 1;  // v[lo] == xo
+        while (lo + step < n && v[lo + step] == xo) {
+          lo += step;
+          step <<= 1;
+        }
+        uint64_t hi = min<uint64_t>(lo + step, n);  // v[hi] != xo, or hi == n
+        while (hi - lo > 1) {
+          const uint64_t mid = lo + (hi - lo) / 2;
+          if (v[mid] == xo) lo = mid;
+          else hi = mid;
+        }
+        end = hi;
+      }
+      if (lane == 0) longest = max(longest, (uint32_t)(end - os));
+    }
+  }
+  const uint32_t h = block_sum<uint32_t, 256>(heads, s_red);  // ends with a barrier: s_red is free
+#pragma unroll
+  for (int d = WAVE / 2; d > 0; d >>= 1) longest = max(longest, (uint32_t)__shfl_xor((int)longest, d, WAVE));
+  if (lane == 0) s_red[threadIdx.x / WAVE] = longest;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (int w = 0; w < 256 / WAVE; w++) m = max(m, s_red[w]);
+    part[blockIdx.x] = RunStats{h, m, 0u};
+  }
 }
 
-// run k spans [pos[k], pos[k+1]) (the last ends at n)
-__global__ void k_run_lengths(const uint32_t* pos, uint64_t d, uint64_t n, uint32_t* len) {
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < d; k += (uint64_t)gridDim.x * blockDim.x)
-    len[k] = (uint32_t)((k + 1 < d ? (uint64_t)pos[k + 1] : n) - pos[k]);
+// The blocks' partial run statistics summed and maximized by one block.
+__global__ __launch_bounds__(256) void k_run_stats_total(const RunStats* part, uint32_t nb, RunStats* out) {
+  __shared__ unsigned long long s_d[256 / WAVE];
+  __shared__ uint32_t s_m[256 / WAVE];
+  unsigned long long d = 0;
+  uint32_t m = 0;
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+    d += part[b].distinct;
+    m = max(m, part[b].longest);
+  }
+  d = wave_sum(d);
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, WAVE));
+  if (lane_id() == 0) {
+    s_d[threadIdx.x / WAVE] = d;
+    s_m[threadIdx.x / WAVE] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    RunStats r{0ull, 0u, 0u};
+    for (int w = 0; w < 256 / WAVE; w++) {
+      r.distinct += s_d[w];
+      r.longest = max(r.longest, s_m[w]);
+    }
+    *out = r;
+  }
 }
 
 void column_freq(const uint32_t* col, uint64_t n, uint32_t range, uint64_t& distinct, uint64_t& freq_max,
@@ -444,14 +552,15 @@ void sorted_run_stats(const uint32_t* sorted, uint64_t n, uint64_t& distinct, ui
   distinct = 0;
   freq_max = 0;
   if (!n) return;
-  DBuf<uint32_t> heads(n, s), pos(n, s);
-  k_run_heads<<<grid_for(n), 256, 0, s>>>(sorted, n, heads.p);
+  const unsigned nb = grid_for((n + RS_GROUPS - 1) / RS_GROUPS);
+  DBuf<RunStats> part(nb, s), r(1, s);
+  k_run_stats<<<nb, 256, 0, s>>>(sorted, n, part.p);
   LH_HIP(hipGetLastError());
-  const uint64_t d = select_flagged(heads.p, n, pos.p, s);
-  k_run_lengths<<<grid_for(d), 256, 0, s>>>(pos.p, d, n, heads.p);
+  k_run_stats_total<<<1, 256, 0, s>>>(part.p, nb, r.p);
   LH_HIP(hipGetLastError());
-  distinct = d;
-  freq_max = reduce_max_u32(heads.p, d, s);
+  const RunStats h = read_scalar(r.p, s);
+  distinct = h.distinct;
+  freq_max = h.longest;
 }
 
 void iota_u32(uint32_t* out, uint64_t n, hipStream_t s) {

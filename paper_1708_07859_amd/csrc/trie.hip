@@ -63,7 +63,7 @@ struct EmitArgs {
   uint32_t* offs_out[LH_MAX_KEYS];   // level child offsets (levels 0..L-2)
   uint32_t* run_out;                 // bag: leaf run starts (sorted-row index); may be null
   uint32_t* kept_out;                // set: sorted-row index of each kept row; may be null
-  uint32_t* rowkeys_out[LH_MAX_KEYS]; // set: every level's key of each kept row; null when not wanted
+  uint32_t* rowkeys_out[LH_MAX_KEYS]; // set: each kept row's keys of the levels above the last; null when not wanted
   uint32_t* parent_out[LH_MAX_KEYS]; // level l >= 1: the level l-1 node above each node; may be null
   const uint32_t* tile_off;          // [l * ntiles + tile]
   uint32_t ntiles;
@@ -107,11 +107,9 @@ __global__ __launch_bounds__(TB_NT) void k_emit_levels(EmitArgs a, uint64_t n) {
     if (l + 1 == L) {
       if (a.run_out) a.run_out[pos] = (uint32_t)r;
       if (a.kept_out) a.kept_out[pos] = (uint32_t)r;
-      if (a.rowkeys_out[0]) {
 #pragma unroll
-        for (uint32_t j = 0; j < LH_MAX_KEYS; j++)
-          if (j < L) a.rowkeys_out[j][pos] = a.c.k[j][r];
-      }
+      for (uint32_t j = 0; j < LH_MAX_KEYS; j++)
+        if (j + 1 < L && a.rowkeys_out[j]) a.rowkeys_out[j][pos] = a.c.k[j][r];
     }
     pos_prev = pos;
   }
@@ -119,14 +117,16 @@ __global__ __launch_bounds__(TB_NT) void k_emit_levels(EmitArgs a, uint64_t n) {
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
-// Bit t-1 of *mask stays set while rows i-1, i are in lexicographic order
-// of the last t levels (equal tuples are in order), for every i.  Bits only
-// clear: a wave publishes the bits it newly clears (one atomic each time)
-// and stops once none is left, so unsorted input costs a fraction of a
-// pass.
-__global__ void k_sorted_tails(LevelCols c, uint64_t n, uint32_t* mask) {
+// Bit t-1 of a block's mask stays set while rows i-1, i are in
+// lexicographic order of the last t levels (equal tuples are in order),
+// for every i the block visits.  Bits only clear, and a wave stops once
+// none is left, so unsorted input costs a fraction of a pass.  Each block
+// writes its mask (atomics of every block on one address would serialize);
+// k_and_total combines them.
+__global__ __launch_bounds__(256) void k_sorted_tails(LevelCols c, uint64_t n, uint32_t all, uint32_t* part) {
+  __shared__ uint32_t s_m[256 / WAVE];
   const int K = (int)c.n_levels;
-  uint32_t known = __builtin_amdgcn_readfirstlane(__hip_atomic_load(mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  uint32_t known = all;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i0 = 1 + (uint64_t)blockIdx.x * blockDim.x; i0 < n && known; i0 += stride) {
     const uint64_t i = i0 + threadIdx.x;
@@ -146,11 +146,29 @@ __global__ void k_sorted_tails(LevelCols c, uint64_t n, uint32_t* mask) {
       }
     }
     for (int o = 32; o > 0; o >>= 1) m &= (uint32_t)__shfl_xor((int)m, o, 64);
-    if (m != known) {  // uniform over the wave
-      if ((threadIdx.x & 63) == 0) atomicAnd(mask, m);
-      known = m;
-    }
-    known &= __builtin_amdgcn_readfirstlane(__hip_atomic_load(mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    known = m;  // uniform over the wave
+  }
+  if ((threadIdx.x & 63) == 0) s_m[threadIdx.x / WAVE] = known;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = all;
+    for (int w = 0; w < 256 / WAVE; w++) m &= s_m[w];
+    part[blockIdx.x] = m;
+  }
+}
+
+// AND of the blocks' masks, by one block.
+__global__ __launch_bounds__(256) void k_and_total(const uint32_t* part, uint32_t nb, uint32_t all, uint32_t* out) {
+  __shared__ uint32_t s_m[256 / WAVE];
+  uint32_t m = all;
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) m &= part[b];
+  for (int o = 32; o > 0; o >>= 1) m &= (uint32_t)__shfl_xor((int)m, o, 64);
+  if ((threadIdx.x & 63) == 0) s_m[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = all;
+    for (int w = 0; w < 256 / WAVE; w++) r &= s_m[w];
+    *out = r;
   }
 }
 
@@ -373,7 +391,7 @@ void ensure_column_stats(lh_trie* t, hipStream_t s) {
   // copy of the trie in the swapped level order takes the rows unsorted.
   if (t->n_levels == 2 && t->annos.empty() && t->meta.empty() && t->key_bits[0] + t->key_bits[1] <= 64 &&
       t->n_rows) {
-    const uint32_t* cols[2] = {t->skeys[1].p, t->skeys[0].p};
+    const uint32_t* cols[2] = {row_keys(t, 1), row_keys(t, 0)};
     const uint32_t bits[2] = {t->key_bits[1], t->key_bits[0]};
     t->tsorted[0].alloc(t->n_rows, s);
     t->tsorted[1].alloc(t->n_rows, s);
@@ -385,7 +403,7 @@ void ensure_column_stats(lh_trie* t, hipStream_t s) {
   }
   for (uint32_t l = 1; l < t->n_levels; l++) {
     if (t->key_max[l] < (1u << 28)) {
-      column_freq(t->skeys[l].p, t->n_rows, t->key_max[l], t->col_distinct[l], t->col_freq_max[l], s);
+      column_freq(row_keys(t, l), t->n_rows, t->key_max[l], t->col_distinct[l], t->col_freq_max[l], s);
     } else {
       t->col_distinct[l] = t->n_rows;
       t->col_freq_max[l] = 1;
@@ -400,11 +418,14 @@ static uint32_t presorted_tail(const uint32_t* const* col, uint32_t n_keys, uint
   LevelCols c{};
   c.n_levels = n_keys;
   for (uint32_t l = 0; l < n_keys; l++) c.k[l] = col[l];
-  DBuf<uint32_t> m(1, s);
-  fill_u32(m.p, (1u << n_keys) - 1, 1, s);
+  const uint32_t all = (1u << n_keys) - 1;
+  const unsigned nb = grid_for(n);
+  DBuf<uint32_t> part(nb, s), m(1, s);
   {
     ProfScope ps("trie_presorted", s, n, 0);
-    k_sorted_tails<<<grid_for(n), 256, 0, s>>>(c, n, m.p);
+    k_sorted_tails<<<nb, 256, 0, s>>>(c, n, all, part.p);
+    LH_HIP(hipGetLastError());
+    k_and_total<<<1, 256, 0, s>>>(part.p, nb, all, m.p);
     LH_HIP(hipGetLastError());
   }
   const uint32_t mask = read_scalar(m.p, s);
@@ -521,8 +542,9 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
     ea.run_out = t->lv[n_keys - 1].offs.p;
   } else {
     // a set keeps the leaf heads' rows: their keys are written as the
-    // heads are found (the row positions only when columns follow them)
-    for (uint32_t l = 0; l < n_keys; l++) {
+    // heads are found (the row positions only when columns follow them);
+    // their last keys are the last level's keys
+    for (uint32_t l = 0; l + 1 < n_keys; l++) {
       t->skeys[l].alloc(n_leaf, s);
       ea.rowkeys_out[l] = t->skeys[l].p;
     }

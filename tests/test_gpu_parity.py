@@ -380,3 +380,32 @@ def test_column_stats(lh, bag, nk):
         vals, cnt = np.unique(rows[:, l], return_counts=True)
         assert inf["col_distinct"][l] == len(vals)
         assert inf["col_freq_max"][l] == cnt.max()
+
+
+@pytest.mark.parametrize("case", ["one value", "all distinct", "one row", "hub"])
+def test_column_stats_edge_runs(lh, case):
+    """Column statistics where the runs of a column are extreme: one run
+    over every row, runs of one row, a single row, and one hub value over
+    most rows (a run far longer than the rest)."""
+    rng = synth.rng_for(70)
+    n = 1 if case == "one row" else 40_000
+    a = rng.integers(0, 500, n).astype(np.uint32)
+    if case == "one value":
+        b = np.full(n, 7, np.uint32)
+    elif case == "all distinct":
+        b = rng.permutation(n).astype(np.uint32)
+    elif case == "hub":
+        b = np.where(rng.random(n) < 0.9, 12345, rng.integers(0, 1 << 20, n)).astype(np.uint32)
+    else:
+        b = np.array([3], np.uint32)
+    for bag in (False, True):
+        t = lh.trie_build([a, b], bag=bag)
+        inf = t.info()
+        t.free()
+        rows = np.stack([a, b], 1)
+        if not bag:
+            rows = np.unique(rows, axis=0)
+        for l in range(2):
+            vals, cnt = np.unique(rows[:, l], return_counts=True)
+            assert inf["col_distinct"][l] == len(vals), (case, bag, l)
+            assert inf["col_freq_max"][l] == cnt.max(), (case, bag, l)
