@@ -223,12 +223,15 @@ __global__ void k_layout_desc(SetRange sr, const uint32_t* keys, uint64_t n_sets
 
 // Bitset words from the keys.  A wave takes 64 consecutive keys; the keys
 // of one (set, word) pair are consecutive (keys are sorted within a set, and
-// sets follow each other), so a suffix OR over the lanes of each pair
-// gathers a word's bits in the pair's first lane, which writes it.  A pair
-// whose keys reach the wave's first or last lane may go on in the
-// neighbouring wave: that part is ORed atomically into the word (the pool
-// starts zeroed); words without keys stay zero.  Null bs_word: the keys
-// form one set whose window starts at 0 at word 0 (the root index).
+// sets follow each other), so the pairs are runs of lanes, marked by a
+// ballot.  When some run holds more than one key, an OR over each lane's
+// rest of its run (doubling steps, bounded by the run's end) gathers each
+// word's bits in the run's first lane, which writes the word.  A run that
+// goes on in the neighbouring wave (its first or last key's neighbour there
+// is in the same word) ORs its part atomically into the word (the pool
+// starts zeroed); words without keys stay zero.  Waves without a bitset key do no
+// lane exchange at all.  Null bs_word: the keys form one set whose window
+// starts at 0 at word 0 (the root index).
 __global__ __launch_bounds__(256) void k_layout_fill(const uint32_t* keys, const uint32_t* parent, uint64_t n,
                                                      const uint64_t* bs_word, const uint32_t* bs_base, uint64_t* pool) {
   const int lane = threadIdx.x & 63;
@@ -246,14 +249,34 @@ __global__ __launch_bounds__(256) void k_layout_fill(const uint32_t* keys, const
         w = w0 + (d >> 6);
       }
     }
+    const bool live = tag != ~0ull;
+    const uint64_t L = ballot(live);
+    if (!L) continue;  // uniform: no bitset key in the wave
+    const uint64_t prev = __shfl_up(tag, 1, WAVE);
+    const bool head = live && (lane == 0 || prev != tag);
+    // runs start at heads; lanes without a key are runs of their own
+    const uint64_t S = ballot(head) | ~L;
+    const uint64_t above = lane < WAVE - 1 ? S >> (lane + 1) : 0ull;
+    const uint32_t end = above ? (uint32_t)lane + 1u + (uint32_t)__builtin_ctzll(above) : (uint32_t)WAVE;
+    if (L & ~S) {  // uniform: some run holds two keys or more
 #pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-      const uint64_t ob = __shfl_down(bits, o, WAVE), ot = __shfl_down(tag, o, WAVE);
-      if (lane + o < WAVE && ot == tag) bits |= ob;
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const uint64_t ob = __shfl_down(bits, o, WAVE);
+        if ((uint32_t)lane + (uint32_t)o < end) bits |= ob;
+      }
     }
-    const uint64_t prev = __shfl_up(tag, 1, WAVE), last = __shfl(tag, WAVE - 1, WAVE);
-    if (tag != ~0ull && (lane == 0 || prev != tag)) {
-      if ((lane == 0 && j > 0) || last == tag) atomicOr((unsigned long long*)&pool[w], (unsigned long long)bits);
+    if (head) {
+      // does the run go on in the wave before (lane 0) or after (a run
+      // reaching the last lane)?  The neighbouring key shares the word when
+      // it has the same set and the same offset >> 6.
+      const uint32_t st = (uint32_t)(tag >> 32), word = (uint32_t)tag;
+      const uint32_t base = bs_word ? bs_base[st] : 0u;
+      bool shared = false;
+      if (lane == 0 && j > 0)
+        shared = (parent ? parent[j - 1] : 0u) == st && ((keys[j - 1] - base) >> 6) == word;
+      if (end == (uint32_t)WAVE && j0 + WAVE < n)
+        shared = shared || ((parent ? parent[j0 + WAVE] : 0u) == st && ((keys[j0 + WAVE] - base) >> 6) == word);
+      if (shared) atomicOr((unsigned long long*)&pool[w], (unsigned long long)bits);
       else pool[w] = bits;
     }
   }
