@@ -223,10 +223,15 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, PackArg
   hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile: elements are ranked by digit (ballots inside
-// a wave, LDS counts across waves), placed in LDS in digit order, then
-// written out in that order, so each digit's run of the tile goes to
-// consecutive global slots (coalesced writes).
+// Stable scatter of one tile.  Wave w holds the tile's elements
+// [w * RS_ITEMS * 64, (w + 1) * RS_ITEMS * 64), item i of lane l at offset
+// i * 64 + l, so a wave's items in order are the input order.  A wave ranks
+// its items one after another against digit counters of its own (eight
+// ballots find a lane's equal-digit peers; no barrier between items, the
+// wave's LDS operations run in order), then one prefix over the waves per
+// digit places every element in LDS in digit order, and the tile is written
+// out in that order, so each digit's run of the tile goes to consecutive
+// global slots (coalesced writes).
 // HAS_V: a 32-bit value travels with each key (else keys only); a null
 // `vin` gives every element its input position as value.
 // FROM_COLS: keys packed from the columns of `pa` (else read from `kin`).
@@ -238,41 +243,37 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, PackA
                                                       uint32_t ntiles) {
   __shared__ uint64_t sk[RS_TILE];
   __shared__ uint32_t sv[HAS_V ? RS_TILE : 1];
-  __shared__ uint32_t lstart[256];   // first slot of each digit in the tile
-  __shared__ uint32_t run[256];      // next slot of each digit in the tile
-  __shared__ uint32_t wcnt[RS_NW][256];
+  __shared__ uint32_t lstart[256];       // first slot of each digit in the tile
+  __shared__ uint32_t wcnt[RS_NW][256];  // each wave's digit counts, then its first slot per digit
   __shared__ uint32_t s_red[RS_NW];
-  const int tid = threadIdx.x, w = tid / WAVE;
+  const int tid = threadIdx.x, w = tid / WAVE, lane = tid & (WAVE - 1);
   const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
   const uint32_t ntile = (uint32_t)min<uint64_t>(RS_TILE, n - base);
-  {
-    const uint32_t c = hist[(uint64_t)tid * ntiles + blockIdx.x];
-    uint32_t tot;
-    const uint32_t st = block_excl_scan<uint32_t, RS_NT>(c, s_red, tot);
-    lstart[tid] = st;
-    run[tid] = st;
-  }
-  // all of the tile's loads are issued before the first ranking round
+  const uint32_t wbase = (uint32_t)w * RS_ITEMS * WAVE;
+  // all of the wave's loads are issued first
   uint64_t kk[RS_ITEMS];
   uint32_t vv[RS_ITEMS];
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; i++) {
-    const uint32_t li = (uint32_t)i * RS_NT + tid;
+    const uint32_t li = wbase + (uint32_t)i * WAVE + lane;
     if constexpr (FROM_COLS) kk[i] = li < ntile ? pack_row(pa, base + li) : 0;
     else kk[i] = li < ntile ? kin[base + li] : 0;
     vv[i] = 0;
     if constexpr (HAS_V) vv[i] = li < ntile ? (vin ? vin[base + li] : (uint32_t)(base + li)) : 0u;
   }
+  {
+    const uint32_t c = hist[(uint64_t)tid * ntiles + blockIdx.x];
+    uint32_t tot;
+    lstart[tid] = block_excl_scan<uint32_t, RS_NT>(c, s_red, tot);
+  }
+#pragma unroll
+  for (int j = 0; j < RS_NW; j++) wcnt[j][tid] = 0;
+  __syncthreads();
+  uint32_t rank[RS_ITEMS];
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; i++) {
-#pragma unroll
-    for (int j = 0; j < RS_NW; j++) wcnt[j][tid] = 0;
-    __syncthreads();
-    const uint32_t li = (uint32_t)i * RS_NT + tid;
-    const bool valid = li < ntile;
-    const uint64_t k = kk[i];
-    const uint32_t v = vv[i];
-    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const bool valid = wbase + (uint32_t)i * WAVE + lane < ntile;
+    const uint32_t d = (uint32_t)(kk[i] >> shift) & 255u;
     uint64_t peers = ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; b++) {
@@ -280,21 +281,31 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, PackA
       const uint64_t m = ballot(valid && bit);
       peers &= bit ? m : ~m;
     }
-    const uint32_t rank = lanes_below(peers);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pre = 0;
-      for (int j = 0; j < w; j++) pre += wcnt[j][d];
-      const uint32_t lp = run[d] + pre + rank;
-      sk[lp] = k;
-      if constexpr (HAS_V) sv[lp] = v;
-    }
-    __syncthreads();
-    uint32_t add = 0;
+    const uint32_t below = lanes_below(peers);
+    const uint32_t pre = valid ? wcnt[w][d] : 0u;
+    rank[i] = pre + below;
+    // the lowest peer moves the wave's count on, after every peer has read it
+    if (valid && below == 0) wcnt[w][d] = pre + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  {
+    // digit tid: the first slot of each wave's run of it
+    uint32_t slot = lstart[tid];
 #pragma unroll
-    for (int j = 0; j < RS_NW; j++) add += wcnt[j][tid];
-    run[tid] += add;
+    for (int j = 0; j < RS_NW; j++) {
+      const uint32_t c = wcnt[j][tid];
+      wcnt[j][tid] = slot;
+      slot += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; i++) {
+    if (wbase + (uint32_t)i * WAVE + lane < ntile) {
+      const uint32_t lp = wcnt[w][(uint32_t)(kk[i] >> shift) & 255u] + rank[i];
+      sk[lp] = kk[i];
+      if constexpr (HAS_V) sv[lp] = vv[i];
+    }
   }
   __syncthreads();
   for (uint32_t t = tid; t < ntile; t += RS_NT) {
