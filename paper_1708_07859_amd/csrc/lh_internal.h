@@ -123,7 +123,11 @@ uint64_t scan_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, hipStrea
 uint64_t scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s);
 // Exclusive scan, uint32 -> uint32 (caller guarantees the total fits); out has n+1.
 uint32_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s);
+// The same without reading the total back (it stays in out[n]).
+void scan_u32_dev(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s);
 uint32_t reduce_max_u32(const uint32_t* in, uint64_t n, hipStream_t s);
+// Raise *out (device, set beforehand) to the largest of in[0, n); nothing is read back.
+void max_u32_into(const uint32_t* in, uint64_t n, uint32_t* out, hipStream_t s);
 // Distinct values and the largest value frequency of a column whose values
 // are below `range` (a histogram pass).
 void column_freq(const uint32_t* col, uint64_t n, uint32_t range, uint64_t& distinct, uint64_t& freq_max,

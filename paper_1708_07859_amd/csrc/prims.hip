@@ -75,11 +75,13 @@ __global__ void k_set_total(TO* out, uint64_t n, const TO* tile_off, const TO* t
   out[n] = tile_off[ntiles - 1] + tile_sums[ntiles - 1];
 }
 
+// Exclusive scan of in[0, n) into out[0, n) and the total into out[n], all
+// on the device (the tile sums' own scan included): no host round trip.
 template <class TI, class TO>
-TO scan_impl(const TI* in, TO* out, uint64_t n, hipStream_t s) {
+void scan_dev(const TI* in, TO* out, uint64_t n, hipStream_t s) {
   if (n == 0) {
     LH_HIP(hipMemsetAsync(out, 0, sizeof(TO), s));
-    return 0;
+    return;
   }
   uint64_t ntiles = (n + SC_TILE - 1) / SC_TILE;
   DBuf<TO> sums(ntiles, s), offs(ntiles + 1, s);
@@ -88,17 +90,21 @@ TO scan_impl(const TI* in, TO* out, uint64_t n, hipStream_t s) {
   if (ntiles == 1) {
     LH_HIP(hipMemsetAsync(offs.p, 0, sizeof(TO), s));
   } else {
-    scan_impl<TO, TO>(sums.p, offs.p, ntiles, s);
+    scan_dev<TO, TO>(sums.p, offs.p, ntiles, s);
   }
   k_tile_scan<TI, TO><<<(unsigned)ntiles, SC_NT, 0, s>>>(in, n, offs.p, out);
   LH_HIP(hipGetLastError());
   k_set_total<TO><<<1, 1, 0, s>>>(out, n, offs.p, sums.p, ntiles);
   LH_HIP(hipGetLastError());
+}
+
+// The same, and the total read back to the host.
+template <class TI, class TO>
+TO scan_impl(const TI* in, TO* out, uint64_t n, hipStream_t s) {
+  scan_dev<TI, TO>(in, out, n, s);
   return read_scalar(out + n, s);
 }
 
-// Maximum of a column: a block reduction, then one atomic per block (the
-// grid is capped, so the atomics on the single result stay few).
 // Largest of in[0, n).  The body is read as 16-byte vectors, four rounds
 // in flight per thread; the elements before the first 16-byte boundary and
 // after the last whole vector are read singly.
@@ -402,14 +408,20 @@ uint64_t scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s) 
 uint32_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s) {
   return scan_impl<uint32_t, uint32_t>(in, out, n, s);
 }
+void scan_u32_dev(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t s) {
+  scan_dev<uint32_t, uint32_t>(in, out, n, s);
+}
+
+void max_u32_into(const uint32_t* in, uint64_t n, uint32_t* out, hipStream_t s) {
+  if (!n) return;
+  k_reduce_max_u32<<<std::min(grid_for((n + 3) / 4), 2048u), 256, 0, s>>>(in, n, out);
+  LH_HIP(hipGetLastError());
+}
 
 uint32_t reduce_max_u32(const uint32_t* in, uint64_t n, hipStream_t s) {
   DBuf<uint32_t> r(1, s);
   LH_HIP(hipMemsetAsync(r.p, 0, sizeof(uint32_t), s));
-  if (n) {
-    k_reduce_max_u32<<<std::min(grid_for((n + 3) / 4), 2048u), 256, 0, s>>>(in, n, r.p);
-    LH_HIP(hipGetLastError());
-  }
+  max_u32_into(in, n, r.p, s);
   return read_scalar(r.p, s);
 }
 
@@ -627,7 +639,7 @@ void radix_passes(const uint64_t* kin, const PackArgs& pa, bool from_cols, const
       else k_rs_hist<false><<<ntiles, RS_NT, 0, s>>>(ki, pa, n, shift, hist.p, ntiles);
     }
     LH_HIP(hipGetLastError());
-    scan_u32(hist.p, offs.p, hn, s);
+    scan_u32_dev(hist.p, offs.p, hn, s);
     uint64_t* ko = tc ? nullptr : kbuf[(p + phase) & 1];
     uint32_t* vo = vals ? vbuf[(p + phase) & 1] : nullptr;
     {

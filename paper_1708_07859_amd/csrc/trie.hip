@@ -356,7 +356,7 @@ void build_layouts(lh_trie* t, uint32_t l, uint32_t mode, const uint32_t* parent
     k_word_popc<<<grid_for(L.pool_words), 256, 0, s>>>(L.pool.p, L.pool_words, pc.p);
     LH_HIP(hipGetLastError());
     L.bs_rank.alloc(L.pool_words + 1, s);
-    scan_u32(pc.p, L.bs_rank.p, L.pool_words, s);
+    scan_u32_dev(pc.p, L.bs_rank.p, L.pool_words, s);
     L.bs_delta.alloc(L.n_sets, s);
     k_rank_delta<<<grid_for(L.n_sets), 256, 0, s>>>(sr, L.n_sets, L.bs_word.p, L.bs_rank.p, L.bs_delta.p);
     LH_HIP(hipGetLastError());
@@ -435,23 +435,25 @@ void ensure_column_stats(lh_trie* t, hipStream_t s) {
   t->col_stats = true;
 }
 
-// The most trailing levels whose lexicographic order the rows already
-// follow (0: not even the last level's).
-static uint32_t presorted_tail(const uint32_t* const* col, uint32_t n_keys, uint64_t n, hipStream_t s) {
+// The presorted-tail mask of the rows into *mask (device): bit t-1 set when
+// the rows are in lexicographic order of their last t levels.
+static void presorted_mask(const uint32_t* const* col, uint32_t n_keys, uint64_t n, uint32_t* mask, hipStream_t s) {
   LevelCols c{};
   c.n_levels = n_keys;
   for (uint32_t l = 0; l < n_keys; l++) c.k[l] = col[l];
   const uint32_t all = (1u << n_keys) - 1;
   const unsigned nb = grid_for(n);
-  DBuf<uint32_t> part(nb, s), m(1, s);
-  {
-    ProfScope ps("trie_presorted", s, n, 0);
-    k_sorted_tails<<<nb, 256, 0, s>>>(c, n, all, part.p);
-    LH_HIP(hipGetLastError());
-    k_and_total<<<1, 256, 0, s>>>(part.p, nb, all, m.p);
-    LH_HIP(hipGetLastError());
-  }
-  const uint32_t mask = read_scalar(m.p, s);
+  DBuf<uint32_t> part(nb, s);
+  ProfScope ps("trie_presorted", s, n, 0);
+  k_sorted_tails<<<nb, 256, 0, s>>>(c, n, all, part.p);
+  LH_HIP(hipGetLastError());
+  k_and_total<<<1, 256, 0, s>>>(part.p, nb, all, mask);
+  LH_HIP(hipGetLastError());
+}
+
+// The most trailing levels whose order a presorted-tail mask shows (0: not
+// even the last level's).
+static uint32_t tail_of_mask(uint32_t mask, uint32_t n_keys) {
   for (uint32_t t = n_keys; t >= 1; t--)
     if (mask >> (t - 1) & 1u) return t;
   return 0;
@@ -483,11 +485,26 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
       src = selcols.back().p;
     }
     col[l] = src;
-    t->key_max[l] = n ? reduce_max_u32(src, n, s) : 0;
-    t->key_bits[l] = bitlen(t->key_max[l]);
   }
-
-  if (detect_sorted && sorted_tail == 0 && n > 1) sorted_tail = presorted_tail(col, n_keys, n, s);
+  // every level's largest key and, when asked, the presorted tail: one
+  // read back for all of them
+  struct InputStats {
+    uint32_t key_max[LH_MAX_KEYS];
+    uint32_t tail_mask;
+  };
+  {
+    DBuf<InputStats> st(1, s);
+    LH_HIP(hipMemsetAsync(st.p, 0, sizeof(InputStats), s));
+    for (uint32_t l = 0; l < n_keys; l++) max_u32_into(col[l], n, &st.p->key_max[l], s);
+    const bool detect = detect_sorted && sorted_tail == 0 && n > 1;
+    if (detect) presorted_mask(col, n_keys, n, &st.p->tail_mask, s);
+    const InputStats h = read_scalar(st.p, s);
+    for (uint32_t l = 0; l < n_keys; l++) {
+      t->key_max[l] = h.key_max[l];
+      t->key_bits[l] = bitlen(t->key_max[l]);
+    }
+    if (detect) sorted_tail = tail_of_mask(h.tail_mask, n_keys);
+  }
 
   // The permutation is needed only to carry annotation and meta columns.
   // Keys that pack into one word are sorted as such and unpacked into the
@@ -667,7 +684,7 @@ lh_trie* build_trie(uint64_t n_rows, uint32_t n_keys, const uint32_t* const* key
       DBuf<uint32_t> pc(words, s);
       k_word_popc<<<grid_for(words), 256, 0, s>>>(t->root_bits.p, words, pc.p);
       LH_HIP(hipGetLastError());
-      scan_u32(pc.p, t->root_rank.p, words, s);
+      scan_u32_dev(pc.p, t->root_rank.p, words, s);
     }
   }
   LH_HIP(hipStreamSynchronize(s));
