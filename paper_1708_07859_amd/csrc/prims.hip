@@ -217,12 +217,30 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, PackArg
   h[threadIdx.x] = 0;
   __syncthreads();
   uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+  if (!FROM_COLS && !((uintptr_t)keys & 15u)) {
+    // packed keys, two per 16-byte load (the order of a histogram's keys
+    // does not matter)
+    const uint64_t ntile = min<uint64_t>(RS_TILE, n - base);
+    const ulonglong2* k2 = reinterpret_cast<const ulonglong2*>(keys + base);
 #pragma unroll
-  for (int i = 0; i < RS_ITEMS; i++) {
-    uint64_t idx = base + (uint64_t)i * RS_NT + threadIdx.x;
-    if (idx < n) {
-      const uint64_t k = FROM_COLS ? pack_row(pa, idx) : keys[idx];
-      atomicAdd(&h[(uint32_t)(k >> shift) & 255u], 1u);
+    for (int i = 0; i < RS_ITEMS / 2; i++) {
+      const uint64_t j = (uint64_t)i * RS_NT + threadIdx.x;  // pair index in the tile
+      if (2 * j + 1 < ntile) {
+        const ulonglong2 v = k2[j];
+        atomicAdd(&h[(uint32_t)(v.x >> shift) & 255u], 1u);
+        atomicAdd(&h[(uint32_t)(v.y >> shift) & 255u], 1u);
+      } else if (2 * j < ntile) {
+        atomicAdd(&h[(uint32_t)(keys[base + 2 * j] >> shift) & 255u], 1u);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; i++) {
+      uint64_t idx = base + (uint64_t)i * RS_NT + threadIdx.x;
+      if (idx < n) {
+        const uint64_t k = FROM_COLS ? pack_row(pa, idx) : keys[idx];
+        atomicAdd(&h[(uint32_t)(k >> shift) & 255u], 1u);
+      }
     }
   }
   __syncthreads();
